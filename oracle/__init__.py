@@ -1,0 +1,241 @@
+"""CPU oracle of the RTSDF hot path -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import this
+package.  It wraps `liboracle.so` (plain C, built by `oracle/build.py`) with numpy
+arrays and shares nothing with the GPU library.  Each wrapper names the part of the
+paper (arXiv 2210.06160) it follows; the C source documents the readings in full.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+EMPTY = -1
+
+_lib = None
+
+
+class Grid(ctypes.Structure):
+    """Uniform grid: voxel (i, j, k) has centre org + h * (i + 1/2, j + 1/2, k + 1/2)."""
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("org", ctypes.c_float * 3), ("h", ctypes.c_float)]
+
+
+def make_grid(dims, org, h):
+    g = Grid()
+    g.nx, g.ny, g.nz = (int(d) for d in dims)
+    for a in range(3):
+        g.org[a] = float(org[a])
+    g.h = float(h)
+    return g
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        L = ctypes.CDLL(path)
+        vp, i32, i64, u32, u64, f32 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                       ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float)
+        L.orc_voxelize.argtypes = [vp, i32, vp, i32, Grid, vp]
+        L.orc_voxelize.restype = ctypes.c_int
+        L.orc_jfa_pass.argtypes = [vp, vp, Grid, i32]
+        L.orc_jfa.argtypes = [vp, vp, Grid, vp, i32]
+        L.orc_seed_d2.argtypes = [vp, Grid, vp]
+        L.orc_band.argtypes = [vp, Grid, i32, vp]
+        L.orc_band.restype = i64
+        L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_direction.argtypes = [u64, u32, u32, u32, u32, vp]
+        L.orc_direction.restype = ctypes.c_int
+        L.orc_ray_tri.argtypes = [vp, vp, vp, vp, vp, f32, vp, vp]
+        L.orc_ray_tri.restype = ctypes.c_int
+        L.orc_closest_brute.argtypes = [vp, vp, i32, vp, vp, f32, vp, vp, vp]
+        L.orc_closest_brute.restype = ctypes.c_int
+        L.orc_bvh_build.argtypes = [vp, vp, i32, f32]
+        L.orc_bvh_build.restype = vp
+        L.orc_bvh_free.argtypes = [vp]
+        L.orc_bvh_closest.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.orc_bvh_closest.restype = ctypes.c_int
+        L.orc_voxel_centre.argtypes = [Grid, i64, vp]
+        L.orc_raysample.argtypes = [vp, Grid, vp, i64, i32, u64, u32, u32, vp, vp, vp]
+        L.orc_combine.argtypes = [vp, vp, vp, Grid, vp, i64, i32, f32, f32, i32, f32, i32, vp, vp]
+        L.orc_pack_id.argtypes = [i32, i32, i32]
+        L.orc_pack_id.restype = i32
+        _lib = L
+    return _lib
+
+
+def nvox(g):
+    return g.nx * g.ny * g.nz
+
+
+def pack_id(i, j, k):
+    return int(lib().orc_pack_id(i, j, k))
+
+
+def hit_pad(g):
+    """Widening of a triangle's box used by the hit test: 1/256 of a voxel."""
+    return np.float32(g.h) * np.float32(1.0 / 256.0)
+
+
+def voxelize(verts, tris, g):
+    """Section 2.2 voxelization: seed ids (own packed id) of overlapped voxels, else EMPTY."""
+    verts = np.ascontiguousarray(verts, np.float32)
+    tris = np.ascontiguousarray(tris, np.int32)
+    seeds = np.empty(nvox(g), np.int32)
+    rc = lib().orc_voxelize(_p(verts), len(verts), _p(tris), len(tris), g, _p(seeds))
+    if rc != 0:
+        raise ValueError("triangle index out of range")
+    return seeds
+
+
+def jfa_pass(seeds, g, k):
+    """One section 2.2 jump-flooding pass with offset k."""
+    seeds = np.ascontiguousarray(seeds, np.int32)
+    out = np.empty_like(seeds)
+    lib().orc_jfa_pass(_p(seeds), _p(out), g, int(k))
+    return out
+
+
+def jfa(seeds, g, steps):
+    """Section 2.2 jump flooding over the given offsets, in order."""
+    a = np.array(seeds, np.int32, copy=True)
+    tmp = np.empty_like(a)
+    st = np.ascontiguousarray(steps, np.int32)
+    lib().orc_jfa(_p(a), _p(tmp), g, _p(st), len(st))
+    return a
+
+
+def jfa_steps(dims, extra=0):
+    """Offsets n/2, n/4, ..., 1 (section 2.2) with n the next power of two of the largest
+    side, followed by `extra` additional passes with offset 1."""
+    n = max(dims)
+    k = 1
+    while k < n:
+        k *= 2
+    out = []
+    k //= 2
+    while k >= 1:
+        out.append(k)
+        k //= 2
+    if not out:
+        out = [1]
+    return out + [1] * extra
+
+
+def seed_d2(seeds, g):
+    d2 = np.empty(nvox(g), np.int32)
+    lib().orc_seed_d2(_p(np.ascontiguousarray(seeds, np.int32)), g, _p(d2))
+    return d2
+
+
+def band(seeds, g, band_vox):
+    """Section 2.3 ray mask as an increasing list of voxel ids."""
+    seeds = np.ascontiguousarray(seeds, np.int32)
+    n = lib().orc_band(_p(seeds), g, int(band_vox), None)
+    out = np.empty(n, np.int32)
+    lib().orc_band(_p(seeds), g, int(band_vox), _p(out))
+    return out
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.empty(4, np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def direction(seed, vid, frame, ray, obj=0):
+    """Section 2.1 uniform sphere direction; returns (w, philox calls used)."""
+    w = np.empty(3, np.float32)
+    n = lib().orc_direction(int(seed), int(vid), int(frame), int(ray), int(obj), _p(w))
+    return w, n
+
+
+def ray_tri(o, w, v0, v1, v2, pad):
+    o, w, v0, v1, v2 = (np.ascontiguousarray(a, np.float32) for a in (o, w, v0, v1, v2))
+    t = np.zeros(1, np.float32)
+    fr = np.zeros(1, np.int32)
+    hit = lib().orc_ray_tri(_p(o), _p(w), _p(v0), _p(v1), _p(v2), float(pad), _p(t), _p(fr))
+    return bool(hit), float(t[0]), bool(fr[0])
+
+
+def closest_brute(verts, tris, o, w, pad):
+    verts = np.ascontiguousarray(verts, np.float32)
+    tris = np.ascontiguousarray(tris, np.int32)
+    o, w = np.ascontiguousarray(o, np.float32), np.ascontiguousarray(w, np.float32)
+    t = np.zeros(1, np.float32)
+    tri = np.zeros(1, np.int32)
+    fr = np.zeros(1, np.int32)
+    hit = lib().orc_closest_brute(_p(verts), _p(tris), len(tris), _p(o), _p(w), float(pad),
+                                  _p(t), _p(tri), _p(fr))
+    return bool(hit), t[0], int(tri[0]), bool(fr[0])
+
+
+class BVH:
+    """Median-split hierarchy whose closest hit equals brute force (tested)."""
+
+    def __init__(self, verts, tris, pad):
+        self.verts = np.ascontiguousarray(verts, np.float32)
+        self.tris = np.ascontiguousarray(tris, np.int32)
+        self.ptr = lib().orc_bvh_build(_p(self.verts), _p(self.tris), len(self.tris), float(pad))
+
+    def closest(self, o, w):
+        o, w = np.ascontiguousarray(o, np.float32), np.ascontiguousarray(w, np.float32)
+        t = np.zeros(1, np.float32)
+        tri = np.zeros(1, np.int32)
+        fr = np.zeros(1, np.int32)
+        hit = lib().orc_bvh_closest(self.ptr, _p(o), _p(w), _p(t), _p(tri), _p(fr))
+        return bool(hit), t[0], int(tri[0]), bool(fr[0])
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.orc_bvh_free(self.ptr)
+            self.ptr = None
+
+
+def voxel_centre(g, vid):
+    o = np.empty(3, np.float32)
+    lib().orc_voxel_centre(g, int(vid), _p(o))
+    return o
+
+
+def new_accum(n):
+    return (np.full(n, np.inf, np.float32), np.zeros(n, np.uint32),
+            np.full(n, np.iinfo(np.uint64).max, np.uint64))
+
+
+def raysample(bvh, g, vids, x, seed, frame, obj=0, acc=None):
+    """Section 2.1 ray sampling of the listed voxels for one frame (accumulating)."""
+    vids = np.ascontiguousarray(vids, np.int32)
+    if acc is None:
+        acc = new_accum(len(vids))
+    dmin, hits, argmin = acc
+    lib().orc_raysample(bvh.ptr, g, _p(vids), len(vids), int(x), int(seed), int(frame), int(obj),
+                        _p(dmin), _p(hits), _p(argmin))
+    return acc
+
+
+def combine(seeds, dmin, hits, g, band_vox, beta, bias, mode, alpha=0.95, reset=True,
+            state=None, vids=None):
+    """Coarse/fine combination: mode 0 running minimum (section 2.1), mode 1 decay (Eq. 1)."""
+    seeds = np.ascontiguousarray(seeds, np.int32)
+    dmin = np.ascontiguousarray(dmin, np.float32)
+    hits = np.ascontiguousarray(hits, np.uint32)
+    n = len(vids) if vids is not None else nvox(g)
+    if vids is not None:
+        vids = np.ascontiguousarray(vids, np.int32)
+    if state is None:
+        state = np.zeros(n, np.float32)
+    fine = np.empty(n, np.float32)
+    lib().orc_combine(_p(seeds), _p(dmin), _p(hits), g, _p(vids), n, int(band_vox),
+                      float(beta), float(bias), int(mode), float(alpha), int(bool(reset)),
+                      _p(state), _p(fine))
+    return fine, state

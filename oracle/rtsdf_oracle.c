@@ -1,0 +1,702 @@
+/*
+ * rtsdf_oracle.c -- plain, slow CPU reference of the RTSDF signed-distance hot path
+ * (Tan, Chua, Koh, Bhojan, "RTSDF: Real-time Signed Distance Fields for Soft Shadow
+ * Approximation in Games", arXiv 2210.06160).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library.  It shares no code, header, table or
+ * helper with the GPU library; both are written from the paper.
+ *
+ * Precision: the paper fixes no precision.  Where floating point decides an integer
+ * (a voxel snap, a ray/triangle hit, a rejection-sampling accept) the oracle uses
+ * IEEE binary32 with a fixed expression order and no contraction (build with
+ * -ffp-contract=off, no fast-math), the same precision the GPU path uses, so the
+ * integer outcomes are comparable exactly.  Everything else that is checked by
+ * tolerance (BVH culling) is done in binary64.
+ *
+ * Parity pins live in tests/ (closed forms, brute force, an exact EDT, an independent
+ * numpy JFA, rocRAND's Philox).  Every function below is pinned; none is
+ * "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_EMPTY (-1)
+
+typedef struct {
+    int32_t nx, ny, nz;
+    float org[3];
+    float h;
+} orc_grid;
+
+static int64_t orc_nvox(orc_grid g) { return (int64_t)g.nx * g.ny * g.nz; }
+
+/* Grid point ids (section 2.2: every grid point may hold "seed information").
+ * A seed is identified by the packed coordinates of the voxel it lives in. */
+static int32_t orc_pack(int32_t i, int32_t j, int32_t k) { return i | (j << 10) | (k << 20); }
+static void orc_unpack(int32_t s, int32_t* i, int32_t* j, int32_t* k)
+{
+    *i = s & 1023;
+    *j = (s >> 10) & 1023;
+    *k = (s >> 20) & 1023;
+}
+
+int32_t orc_pack_id(int32_t i, int32_t j, int32_t k) { return orc_pack(i, j, k); }
+
+/* ------------------------------------------------------------------------------------
+ * Voxelization (section 2.2: "voxelize the scene with voxel resolution equal to our
+ * final distance field"; a grid point whose voxel holds a piece of a triangle is a
+ * seed).  The paper does not state a method; the reading used here is conservative
+ * closed-cell overlap: a voxel is a seed iff the closed cube of the voxel intersects
+ * the closed triangle.  Vertices are first snapped to 1/256-voxel fixed point,
+ *   X = rint(((v - org) / h) * 256)    (binary32 ops, round-half-even),
+ * and the overlap is decided by the separating-axis theorem over the 13 candidate
+ * axes of a box and a triangle, in exact 64-bit integers.
+ * A triangle with a snapped coordinate beyond +-2^19 (2048 voxels) is not voxelized.
+ * ---------------------------------------------------------------------------------- */
+#define ORC_SNAP_LIMIT 524288.0f
+
+static int64_t orc_floor_div256(int64_t x)
+{
+    int64_t q = x / 256;
+    if ((x % 256) != 0 && x < 0) q -= 1;
+    return q;
+}
+
+static int64_t orc_min3(int64_t a, int64_t b, int64_t c)
+{
+    int64_t m = a < b ? a : b;
+    return m < c ? m : c;
+}
+static int64_t orc_max3(int64_t a, int64_t b, int64_t c)
+{
+    int64_t m = a > b ? a : b;
+    return m > c ? m : c;
+}
+static int64_t orc_abs64(int64_t a) { return a < 0 ? -a : a; }
+
+/* Is the projection of the triangle (three points a[0..2]) onto axis A disjoint from
+ * the projection of the box centred at the origin with half-width 128? */
+static int orc_axis_separates(const int64_t A[3], int64_t a[3][3])
+{
+    int64_t p[3];
+    for (int v = 0; v < 3; ++v) p[v] = A[0] * a[v][0] + A[1] * a[v][1] + A[2] * a[v][2];
+    int64_t r = 128 * (orc_abs64(A[0]) + orc_abs64(A[1]) + orc_abs64(A[2]));
+    return orc_min3(p[0], p[1], p[2]) > r || orc_max3(p[0], p[1], p[2]) < -r;
+}
+
+static int orc_tri_cell_overlap(int64_t X[3][3], int64_t ci, int64_t cj, int64_t ck)
+{
+    const int64_t c[3] = {256 * ci + 128, 256 * cj + 128, 256 * ck + 128};
+    int64_t a[3][3];
+    for (int v = 0; v < 3; ++v)
+        for (int d = 0; d < 3; ++d) a[v][d] = X[v][d] - c[d];
+    /* the three box face normals */
+    for (int d = 0; d < 3; ++d) {
+        int64_t e[3] = {0, 0, 0};
+        e[d] = 1;
+        if (orc_axis_separates(e, a)) return 0;
+    }
+    /* the triangle's plane normal */
+    int64_t f[3][3];
+    for (int d = 0; d < 3; ++d) {
+        f[0][d] = a[1][d] - a[0][d];
+        f[1][d] = a[2][d] - a[1][d];
+        f[2][d] = a[0][d] - a[2][d];
+    }
+    int64_t n[3] = {f[0][1] * f[1][2] - f[0][2] * f[1][1], f[0][2] * f[1][0] - f[0][0] * f[1][2],
+                    f[0][0] * f[1][1] - f[0][1] * f[1][0]};
+    if (orc_axis_separates(n, a)) return 0;
+    /* the nine cross products of triangle edges with box edges */
+    for (int m = 0; m < 3; ++m) {
+        int64_t ax0[3] = {0, -f[m][2], f[m][1]};
+        int64_t ax1[3] = {f[m][2], 0, -f[m][0]};
+        int64_t ax2[3] = {-f[m][1], f[m][0], 0};
+        if (orc_axis_separates(ax0, a) || orc_axis_separates(ax1, a) || orc_axis_separates(ax2, a))
+            return 0;
+    }
+    return 1;
+}
+
+/* Snap one vertex; returns 0 if it is out of the representable range (or not finite). */
+static int orc_snap(const float* v, orc_grid g, int64_t X[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        float q = ((v[d] - g.org[d]) / g.h) * 256.0f;
+        if (!(fabsf(q) <= ORC_SNAP_LIMIT)) return 0;
+        X[d] = (int64_t)rintf(q);
+    }
+    return 1;
+}
+
+/* Returns 0 on success, -1 on a bad triangle index. */
+int orc_voxelize(const float* verts, int32_t nv, const int32_t* tris, int32_t nt, orc_grid g,
+                 int32_t* seeds)
+{
+    const int64_t N = orc_nvox(g);
+    for (int64_t p = 0; p < N; ++p) seeds[p] = ORC_EMPTY;
+    const int32_t dims[3] = {g.nx, g.ny, g.nz};
+    for (int32_t t = 0; t < nt; ++t) {
+        int64_t X[3][3];
+        int ok = 1;
+        for (int v = 0; v < 3; ++v) {
+            int32_t vi = tris[3 * t + v];
+            if (vi < 0 || vi >= nv) return -1;
+            if (!orc_snap(verts + 3 * (int64_t)vi, g, X[v])) ok = 0;
+        }
+        if (!ok) continue;
+        int64_t lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = orc_floor_div256(orc_min3(X[0][d], X[1][d], X[2][d]) - 1);
+            hi[d] = orc_floor_div256(orc_max3(X[0][d], X[1][d], X[2][d]));
+            if (lo[d] < 0) lo[d] = 0;
+            if (hi[d] > dims[d] - 1) hi[d] = dims[d] - 1;
+            if (lo[d] > hi[d]) ok = 0;
+        }
+        if (!ok) continue;
+        for (int64_t k = lo[2]; k <= hi[2]; ++k)
+            for (int64_t j = lo[1]; j <= hi[1]; ++j)
+                for (int64_t i = lo[0]; i <= hi[0]; ++i)
+                    if (orc_tri_cell_overlap(X, i, j, k))
+                        seeds[i + (int64_t)g.nx * (j + (int64_t)g.ny * k)] =
+                            orc_pack((int32_t)i, (int32_t)j, (int32_t)k);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Jump flooding (section 2.2).  One pass with offset k: every grid point keeps the seed
+ * it already stores and then queries the grid points at p + k*e, e in {-1,0,1}^3 \ {0},
+ * in the fixed order ez, ey, ex ascending (-1 < 0 < 1); a queried point that is inside
+ * the grid and holds a seed replaces the stored seed only if that seed is strictly
+ * closer (squared voxel distance).  Each pass reads only the previous pass's buffer.
+ * ---------------------------------------------------------------------------------- */
+static int32_t orc_d2(int32_t s, int32_t x, int32_t y, int32_t z)
+{
+    int32_t sx, sy, sz;
+    orc_unpack(s, &sx, &sy, &sz);
+    return (sx - x) * (sx - x) + (sy - y) * (sy - y) + (sz - z) * (sz - z);
+}
+
+void orc_jfa_pass(const int32_t* in, int32_t* out, orc_grid g, int32_t k)
+{
+#pragma omp parallel for schedule(static)
+    for (int32_t z = 0; z < g.nz; ++z)
+        for (int32_t y = 0; y < g.ny; ++y)
+            for (int32_t x = 0; x < g.nx; ++x) {
+                int64_t p = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+                int32_t best = in[p];
+                int32_t bestd2 = best == ORC_EMPTY ? 0 : orc_d2(best, x, y, z);
+                for (int ez = -1; ez <= 1; ++ez)
+                    for (int ey = -1; ey <= 1; ++ey)
+                        for (int ex = -1; ex <= 1; ++ex) {
+                            if (ex == 0 && ey == 0 && ez == 0) continue;
+                            int32_t qx = x + k * ex, qy = y + k * ey, qz = z + k * ez;
+                            if (qx < 0 || qy < 0 || qz < 0 || qx >= g.nx || qy >= g.ny || qz >= g.nz)
+                                continue;
+                            int32_t s = in[qx + (int64_t)g.nx * (qy + (int64_t)g.ny * qz)];
+                            if (s == ORC_EMPTY) continue;
+                            int32_t d2 = orc_d2(s, x, y, z);
+                            if (best == ORC_EMPTY || d2 < bestd2) {
+                                best = s;
+                                bestd2 = d2;
+                            }
+                        }
+                out[p] = best;
+            }
+}
+
+/* Runs the passes in order; the result is left in `seeds`.  `tmp` holds N ints. */
+void orc_jfa(int32_t* seeds, int32_t* tmp, orc_grid g, const int32_t* steps, int32_t nsteps)
+{
+    const int64_t N = orc_nvox(g);
+    int32_t* a = seeds;
+    int32_t* b = tmp;
+    for (int32_t s = 0; s < nsteps; ++s) {
+        orc_jfa_pass(a, b, g, steps[s]);
+        int32_t* t = a;
+        a = b;
+        b = t;
+    }
+    if (a != seeds) memcpy(seeds, a, (size_t)N * sizeof(int32_t));
+}
+
+/* Squared voxel distance from each grid point to the seed it stores (-1 if none). */
+void orc_seed_d2(const int32_t* seeds, orc_grid g, int32_t* d2)
+{
+    for (int32_t z = 0; z < g.nz; ++z)
+        for (int32_t y = 0; y < g.ny; ++y)
+            for (int32_t x = 0; x < g.nx; ++x) {
+                int64_t p = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+                d2[p] = seeds[p] == ORC_EMPTY ? -1 : orc_d2(seeds[p], x, y, z);
+            }
+}
+
+/* ------------------------------------------------------------------------------------
+ * Ray mask (section 2.3).  A grid point is ray traced iff the jump-flooded distance is
+ * within the mask width; the width is given in voxels, so the test is the exact integer
+ * comparison d2 <= band^2 on the stored seed.  The list is in increasing voxel order.
+ * ---------------------------------------------------------------------------------- */
+int64_t orc_band(const int32_t* seeds, orc_grid g, int32_t band, int32_t* list)
+{
+    int64_t n = 0;
+    const int32_t b2 = band * band;
+    for (int32_t z = 0; z < g.nz; ++z)
+        for (int32_t y = 0; y < g.ny; ++y)
+            for (int32_t x = 0; x < g.nx; ++x) {
+                int64_t p = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+                int32_t s = seeds[p];
+                if (s != ORC_EMPTY && orc_d2(s, x, y, z) <= b2) {
+                    if (list) list[n] = (int32_t)p;
+                    ++n;
+                }
+            }
+    return n;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Random ray directions (section 2.1: a uniformly distributed point on the unit sphere).
+ * Counter-based generator: Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC 2011).  The counter is
+ * (voxel, frame, ray, object<<8 | attempt) and the key is the 64-bit seed.
+ * Direction: Marsaglia (1972) -- draw (v1, v2) uniform in [-1,1)^2, reject unless
+ * s = v1^2 + v2^2 < 1, then w = (2 v1 sqrt(1-s), 2 v2 sqrt(1-s), 1 - 2 s).
+ * Uniforms are u = (word >> 8) * 2^-24 so that v = 2u - 1 is exact in binary32.
+ * ---------------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+#define ORC_MAX_ATTEMPTS 256
+
+/* Returns the number of Philox calls used (1..256); w = (0,0,1) if all were rejected. */
+int orc_direction(uint64_t seed, uint32_t vid, uint32_t frame, uint32_t ray, uint32_t obj, float w[3])
+{
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (uint32_t attempt = 0; attempt < ORC_MAX_ATTEMPTS; ++attempt) {
+        const uint32_t ctr[4] = {vid, frame, ray, (obj << 8) | attempt};
+        uint32_t r[4];
+        orc_philox4x32_10(ctr, key, r);
+        for (int pr = 0; pr < 2; ++pr) {
+            float u1 = (float)(r[2 * pr] >> 8) * 0x1p-24f;
+            float u2 = (float)(r[2 * pr + 1] >> 8) * 0x1p-24f;
+            float v1 = 2.0f * u1 - 1.0f;
+            float v2 = 2.0f * u2 - 1.0f;
+            float s = v1 * v1 + v2 * v2;
+            if (s < 1.0f) {
+                float q = sqrtf(1.0f - s);
+                w[0] = (2.0f * v1) * q;
+                w[1] = (2.0f * v2) * q;
+                w[2] = 1.0f - 2.0f * s;
+                return (int)attempt + 1;
+            }
+        }
+    }
+    w[0] = 0.0f;
+    w[1] = 0.0f;
+    w[2] = 1.0f;
+    return ORC_MAX_ATTEMPTS;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Ray / triangle hit (section 2.1: minimum traced distance; front or back face from
+ * the dot product of the ray direction with the primitive's normal).  Moller & Trumbore
+ * (1997) in binary32 with the operation order spelled out below; the geometric normal
+ * is (v1-v0) x (v2-v0) with counter-clockwise = outward, so det > 0 <=> dot(w, n) < 0
+ * <=> front face.  A hit also requires the computed hit point o + t*w to lie inside the
+ * triangle's axis-aligned box widened by `pad` on every side (this only rejects
+ * numerically meaningless grazing hits and makes hierarchy culling provably exact).
+ * ---------------------------------------------------------------------------------- */
+static float orc_dotf(const float a[3], const float b[3]) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+static void orc_crossf(const float a[3], const float b[3], float c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static float orc_min3f(float a, float b, float c)
+{
+    float m = a < b ? a : b;
+    return m < c ? m : c;
+}
+static float orc_max3f(float a, float b, float c)
+{
+    float m = a > b ? a : b;
+    return m > c ? m : c;
+}
+
+int orc_ray_tri(const float o[3], const float w[3], const float v0[3], const float v1[3],
+                const float v2[3], float pad, float* t_out, int* front)
+{
+    float e1[3], e2[3], P[3], T[3], Q[3];
+    for (int d = 0; d < 3; ++d) {
+        e1[d] = v1[d] - v0[d];
+        e2[d] = v2[d] - v0[d];
+    }
+    orc_crossf(w, e2, P);
+    float det = orc_dotf(e1, P);
+    if (det == 0.0f) return 0;
+    float inv = 1.0f / det;
+    for (int d = 0; d < 3; ++d) T[d] = o[d] - v0[d];
+    float u = orc_dotf(T, P) * inv;
+    if (!(u >= 0.0f && u <= 1.0f)) return 0;
+    orc_crossf(T, e1, Q);
+    float v = orc_dotf(w, Q) * inv;
+    if (!(v >= 0.0f && u + v <= 1.0f)) return 0;
+    float t = orc_dotf(e2, Q) * inv;
+    if (!(t > 0.0f)) return 0;
+    for (int d = 0; d < 3; ++d) {
+        float q = o[d] + t * w[d];
+        float lo = orc_min3f(v0[d], v1[d], v2[d]) - pad;
+        float hi = orc_max3f(v0[d], v1[d], v2[d]) + pad;
+        if (!(q >= lo && q <= hi)) return 0;
+    }
+    *t_out = t;
+    *front = det > 0.0f;
+    return 1;
+}
+
+/* Closest hit by brute force: lexicographic minimum of (t, triangle index). */
+int orc_closest_brute(const float* verts, const int32_t* tris, int32_t nt, const float o[3],
+                      const float w[3], float pad, float* t_out, int32_t* tri_out, int* front_out)
+{
+    int found = 0;
+    float bt = INFINITY;
+    int32_t btri = -1;
+    int bfront = 0;
+    for (int32_t t = 0; t < nt; ++t) {
+        float th;
+        int fr;
+        if (orc_ray_tri(o, w, verts + 3 * (int64_t)tris[3 * t], verts + 3 * (int64_t)tris[3 * t + 1],
+                        verts + 3 * (int64_t)tris[3 * t + 2], pad, &th, &fr)) {
+            if (!found || th < bt) {
+                found = 1;
+                bt = th;
+                btri = t;
+                bfront = fr;
+            }
+        }
+    }
+    *t_out = bt;
+    *tri_out = btri;
+    *front_out = bfront;
+    return found;
+}
+
+/* ------------------------------------------------------------------------------------
+ * A plain median-split bounding volume hierarchy, used only to make the oracle fast
+ * enough; its closest hit is exactly the brute-force one (tested), because boxes are
+ * widened by 2*pad and culled only when the (binary64) slab entry exceeds the best t.
+ * ---------------------------------------------------------------------------------- */
+typedef struct {
+    float lo[3], hi[3];
+    int32_t left, right; /* children, or -1 for a leaf */
+    int32_t first, count; /* leaf range into the index array */
+} orc_node;
+
+typedef struct {
+    orc_node* nodes;
+    int32_t nnodes;
+    int32_t* idx;
+    const float* verts;
+    const int32_t* tris;
+    int32_t nt;
+    float pad;
+    float* cen; /* centroids, 3 per triangle */
+    int sort_axis;
+} orc_bvh;
+
+static orc_bvh* g_sort_bvh;
+static int orc_cmp_centroid(const void* a, const void* b)
+{
+    int32_t ia = *(const int32_t*)a, ib = *(const int32_t*)b;
+    float ca = g_sort_bvh->cen[3 * ia + g_sort_bvh->sort_axis];
+    float cb = g_sort_bvh->cen[3 * ib + g_sort_bvh->sort_axis];
+    if (ca < cb) return -1;
+    if (ca > cb) return 1;
+    return ia < ib ? -1 : (ia > ib);
+}
+
+static int32_t orc_bvh_build_rec(orc_bvh* b, int32_t first, int32_t count)
+{
+    int32_t me = b->nnodes++;
+    orc_node* n = &b->nodes[me];
+    for (int d = 0; d < 3; ++d) {
+        n->lo[d] = INFINITY;
+        n->hi[d] = -INFINITY;
+    }
+    float clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t q = first; q < first + count; ++q) {
+        int32_t t = b->idx[q];
+        for (int v = 0; v < 3; ++v) {
+            const float* p = b->verts + 3 * (int64_t)b->tris[3 * t + v];
+            for (int d = 0; d < 3; ++d) {
+                float lo = p[d] - 2.0f * b->pad, hi = p[d] + 2.0f * b->pad;
+                if (lo < n->lo[d]) n->lo[d] = lo;
+                if (hi > n->hi[d]) n->hi[d] = hi;
+            }
+        }
+        for (int d = 0; d < 3; ++d) {
+            float c = b->cen[3 * t + d];
+            if (c < clo[d]) clo[d] = c;
+            if (c > chi[d]) chi[d] = c;
+        }
+    }
+    n->first = first;
+    n->count = count;
+    n->left = n->right = -1;
+    if (count <= 4) return me;
+    int axis = 0;
+    float ext = chi[0] - clo[0];
+    for (int d = 1; d < 3; ++d)
+        if (chi[d] - clo[d] > ext) {
+            ext = chi[d] - clo[d];
+            axis = d;
+        }
+    b->sort_axis = axis;
+    g_sort_bvh = b;
+    qsort(b->idx + first, (size_t)count, sizeof(int32_t), orc_cmp_centroid);
+    int32_t half = count / 2;
+    int32_t l = orc_bvh_build_rec(b, first, half);
+    int32_t r = orc_bvh_build_rec(b, first + half, count - half);
+    b->nodes[me].left = l;
+    b->nodes[me].right = r;
+    return me;
+}
+
+void* orc_bvh_build(const float* verts, const int32_t* tris, int32_t nt, float pad)
+{
+    orc_bvh* b = (orc_bvh*)calloc(1, sizeof(orc_bvh));
+    b->verts = verts;
+    b->tris = tris;
+    b->nt = nt;
+    b->pad = pad;
+    if (nt == 0) return b;
+    b->nodes = (orc_node*)malloc(sizeof(orc_node) * (size_t)(2 * nt));
+    b->idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)nt);
+    b->cen = (float*)malloc(sizeof(float) * 3 * (size_t)nt);
+    for (int32_t t = 0; t < nt; ++t) {
+        b->idx[t] = t;
+        for (int d = 0; d < 3; ++d) {
+            float s = 0.0f;
+            for (int v = 0; v < 3; ++v) s += verts[3 * (int64_t)tris[3 * t + v] + d];
+            b->cen[3 * t + d] = s / 3.0f;
+        }
+    }
+    orc_bvh_build_rec(b, 0, nt);
+    return b;
+}
+
+void orc_bvh_free(void* p)
+{
+    orc_bvh* b = (orc_bvh*)p;
+    if (!b) return;
+    free(b->nodes);
+    free(b->idx);
+    free(b->cen);
+    free(b);
+}
+
+/* Slab test in binary64 against a box; returns 1 and the entry parameter if the ray
+ * (t >= 0) meets the box. */
+static int orc_slab(const orc_node* n, const float o[3], const float w[3], double* tenter)
+{
+    double t0 = 0.0, t1 = INFINITY;
+    for (int d = 0; d < 3; ++d) {
+        if (w[d] == 0.0f) {
+            if (o[d] < n->lo[d] || o[d] > n->hi[d]) return 0;
+            continue;
+        }
+        double a = ((double)n->lo[d] - (double)o[d]) / (double)w[d];
+        double c = ((double)n->hi[d] - (double)o[d]) / (double)w[d];
+        if (a > c) {
+            double s = a;
+            a = c;
+            c = s;
+        }
+        if (a > t0) t0 = a;
+        if (c < t1) t1 = c;
+    }
+    if (t0 > t1) return 0;
+    *tenter = t0;
+    return 1;
+}
+
+int orc_bvh_closest(const void* bp, const float o[3], const float w[3], float* t_out,
+                    int32_t* tri_out, int* front_out)
+{
+    const orc_bvh* b = (const orc_bvh*)bp;
+    float bt = INFINITY;
+    int32_t btri = -1;
+    int bfront = 0;
+    if (b->nt > 0) {
+        int32_t stack[256];
+        int sp = 0;
+        stack[sp++] = 0;
+        while (sp > 0) {
+            const orc_node* n = &b->nodes[stack[--sp]];
+            double te;
+            if (!orc_slab(n, o, w, &te)) continue;
+            if (btri >= 0 && te > (double)bt) continue;
+            if (n->left < 0) {
+                for (int32_t q = n->first; q < n->first + n->count; ++q) {
+                    int32_t t = b->idx[q];
+                    float th;
+                    int fr;
+                    if (orc_ray_tri(o, w, b->verts + 3 * (int64_t)b->tris[3 * t],
+                                    b->verts + 3 * (int64_t)b->tris[3 * t + 1],
+                                    b->verts + 3 * (int64_t)b->tris[3 * t + 2], b->pad, &th, &fr)) {
+                        if (btri < 0 || th < bt || (th == bt && t < btri)) {
+                            bt = th;
+                            btri = t;
+                            bfront = fr;
+                        }
+                    }
+                }
+            } else {
+                stack[sp++] = n->right;
+                stack[sp++] = n->left;
+            }
+        }
+    }
+    *t_out = bt;
+    *tri_out = btri;
+    *front_out = bfront;
+    return btri >= 0;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Ray sampling of listed grid points (section 2.1).  For each listed voxel, ray j of
+ * this frame starts at the voxel centre org + h*(i + 0.5) and goes along the Philox /
+ * Marsaglia direction.  Every ray that hits counts one front or one back hit (front in
+ * the low 16 bits, back in the high 16 bits), lowers the stored minimum distance, and
+ * lowers the 64-bit record  bits(t) << 32 | (frame * x + j)  that names the ray which
+ * produced the minimum.  Outputs are indexed like the list and are accumulated into.
+ * ---------------------------------------------------------------------------------- */
+void orc_voxel_centre(orc_grid g, int64_t vid, float o[3])
+{
+    int64_t i = vid % g.nx, j = (vid / g.nx) % g.ny, k = vid / ((int64_t)g.nx * g.ny);
+    o[0] = g.org[0] + g.h * ((float)i + 0.5f);
+    o[1] = g.org[1] + g.h * ((float)j + 0.5f);
+    o[2] = g.org[2] + g.h * ((float)k + 0.5f);
+}
+
+void orc_raysample(const void* bvh, orc_grid g, const int32_t* vids, int64_t n, int32_t x,
+                   uint64_t seed, uint32_t frame, uint32_t obj, float* dmin, uint32_t* hits,
+                   uint64_t* argmin)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < n; ++q) {
+        float o[3];
+        orc_voxel_centre(g, vids[q], o);
+        for (int32_t j = 0; j < x; ++j) {
+            float w[3], t;
+            int32_t tri;
+            int fr;
+            orc_direction(seed, (uint32_t)vids[q], frame, (uint32_t)j, obj, w);
+            if (!orc_bvh_closest(bvh, o, w, &t, &tri, &fr)) continue;
+            if (t < dmin[q]) dmin[q] = t;
+            hits[q] += fr ? 1u : 65536u;
+            uint32_t tb;
+            memcpy(&tb, &t, 4);
+            uint64_t rec = ((uint64_t)tb << 32) | (uint64_t)(frame * (uint32_t)x + (uint32_t)j);
+            if (argmin && rec < argmin[q]) argmin[q] = rec;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------------------
+ * Combining the coarse and the ray-traced field.
+ *   coarse magnitude  u = h * sqrt(d2)   (binary32, correctly rounded sqrt; +inf if no seed)
+ *   coarse SDF        c = u - beta       (section 2.2: subtract a small beta for a sign)
+ *   in band           d2 <= band^2       (section 2.3)
+ *   sign              negative iff back hits > front hits (section 2.1)
+ * mode 0, running minimum (section 2.1): in band with at least one hit the value is
+ *   +-dmin, otherwise c.
+ * mode 1, decay (section 2.5.1, Eq. 1) on magnitudes: in band
+ *   m_t = min(alpha * m_{t-1} + (1 - alpha) * u_t, r_t), r_t = this frame's dmin or
+ *   +inf without hits; the sign is this frame's majority, or the previous sign on a tie;
+ *   state = sign * m_t.  Outside the band state = +u_t.  `reset` (or a non-finite
+ *   previous state) starts from m_{-1} = u_t with a positive sign.
+ * Both modes then subtract `bias` (section 2.5.3: thicken surfaces).
+ * The voxels combined are vids[0..n) (all voxels if vids is NULL); the outputs dmin,
+ * hits, state and fine are indexed like vids.
+ * ---------------------------------------------------------------------------------- */
+void orc_combine(const int32_t* seeds, const float* dmin, const uint32_t* hits, orc_grid g,
+                 const int32_t* vids, int64_t n, int32_t band, float beta, float bias, int32_t mode,
+                 float alpha, int32_t reset, float* state, float* fine)
+{
+    const float oma = 1.0f - alpha;
+    if (!vids) n = orc_nvox(g);
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t p = vids ? vids[q] : q;
+        int32_t x = (int32_t)(p % g.nx), y = (int32_t)((p / g.nx) % g.ny),
+                z = (int32_t)(p / ((int64_t)g.nx * g.ny));
+        int32_t s = seeds[p];
+        float u;
+        int inband;
+        if (s == ORC_EMPTY) {
+            u = INFINITY;
+            inband = 0;
+        } else {
+            int32_t d2 = orc_d2(s, x, y, z);
+            u = g.h * sqrtf((float)d2);
+            inband = d2 <= band * band;
+        }
+        float c = u - beta;
+        uint32_t front = hits[q] & 0xFFFFu, back = hits[q] >> 16;
+        float val;
+        if (mode == 0) {
+            if (inband && (front + back) > 0)
+                val = back > front ? -dmin[q] : dmin[q];
+            else
+                val = c;
+        } else {
+            if (!inband) {
+                state[q] = u;
+                val = c;
+            } else {
+                float prev = state[q];
+                float mprev, sprev;
+                if (reset || !isfinite(prev)) {
+                    mprev = u;
+                    sprev = 1.0f;
+                } else {
+                    mprev = fabsf(prev);
+                    sprev = signbit(prev) ? -1.0f : 1.0f;
+                }
+                float blend = alpha * mprev + oma * u;
+                float r = (front + back) > 0 ? dmin[q] : INFINITY;
+                float m = blend < r ? blend : r;
+                float sg = back > front ? -1.0f : (front > back ? 1.0f : sprev);
+                state[q] = copysignf(m, sg);
+                val = state[q];
+            }
+        }
+        fine[q] = val - bias;
+    }
+}

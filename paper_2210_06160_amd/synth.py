@@ -1,0 +1,203 @@
+"""Seeded synthetic scenes (inputs only; none of the method's arithmetic lives here).
+
+The paper measures on a living-room scene that is not available here (section 3); these
+generators stand in for it with meshes of the shapes and sizes its 400 x 200 x 400 ray
+texture implies (section 2.1).  Every mesh is a list of float32 vertices and int32
+triangles wound counter-clockwise when seen from outside (geometric normal
+(v1 - v0) x (v2 - v0) points out).  Both the GPU path and the CPU oracle consume these
+arrays unchanged.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Scene:
+    verts: np.ndarray          # float32 [V, 3]
+    tris: np.ndarray           # int32 [T, 3]
+    dims: tuple                # (nx, ny, nz)
+    org: tuple                 # grid origin (world units)
+    h: float                   # voxel size (world units)
+    steps: list                # jump-flooding offsets, in order
+    band: int                  # ray-mask width in voxels
+    rays: int                  # rays per masked voxel per frame
+    frames: int                # frames accumulated
+    name: str = ""
+    extra: dict = field(default_factory=dict)
+
+
+def merge(meshes):
+    vs, ts, off = [], [], 0
+    for v, t in meshes:
+        vs.append(np.asarray(v, np.float32))
+        ts.append(np.asarray(t, np.int64) + off)
+        off += len(v)
+    if not vs:
+        return np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32)
+    return np.concatenate(vs).astype(np.float32), np.concatenate(ts).astype(np.int32)
+
+
+def signed_volume(verts, tris):
+    """Enclosed volume of a closed mesh; positive when the winding is outward."""
+    v = np.asarray(verts, np.float64)
+    a, b, c = v[tris[:, 0]], v[tris[:, 1]], v[tris[:, 2]]
+    return float(np.einsum("ij,ij->i", a, np.cross(b, c)).sum() / 6.0)
+
+
+def icosphere(subdiv, radius=1.0, centre=(0.0, 0.0, 0.0)):
+    """Subdivided icosahedron with vertices on the sphere (10 * 4^s + 2 vertices)."""
+    p = (1.0 + 5.0 ** 0.5) / 2.0
+    v = [(-1, p, 0), (1, p, 0), (-1, -p, 0), (1, -p, 0), (0, -1, p), (0, 1, p), (0, -1, -p),
+         (0, 1, -p), (p, 0, -1), (p, 0, 1), (-p, 0, -1), (-p, 0, 1)]
+    f = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4),
+         (11, 10, 2), (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8),
+         (3, 8, 9), (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    verts = [np.array(x, np.float64) / np.linalg.norm(x) for x in v]
+    faces = list(f)
+    for _ in range(subdiv):
+        cache = {}
+
+        def mid(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in cache:
+                m = verts[a] + verts[b]
+                verts.append(m / np.linalg.norm(m))
+                cache[key] = len(verts) - 1
+            return cache[key]
+
+        nf = []
+        for a, b, c in faces:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = nf
+    V = np.array(verts) * radius + np.asarray(centre, np.float64)
+    return V.astype(np.float32), np.array(faces, np.int32)
+
+
+def uv_sphere(radius, centre, nseg=32, nring=16, rot=None):
+    """Latitude/longitude sphere: 2 poles + (nring - 1) rings; 2*nseg*(nring-1) triangles."""
+    pts = [(0.0, 0.0, 1.0)]
+    for r in range(1, nring):
+        th = np.pi * r / nring
+        for s in range(nseg):
+            ph = 2.0 * np.pi * s / nseg
+            pts.append((np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)))
+    pts.append((0.0, 0.0, -1.0))
+    V = np.array(pts, np.float64)
+    bottom = len(pts) - 1
+
+    def ring(r, s):
+        return 1 + (r - 1) * nseg + (s % nseg)
+
+    T = []
+    for s in range(nseg):
+        T.append((0, ring(1, s), ring(1, s + 1)))
+    for r in range(1, nring - 1):
+        for s in range(nseg):
+            a, b = ring(r, s), ring(r, s + 1)
+            c, d = ring(r + 1, s), ring(r + 1, s + 1)
+            T += [(a, c, d), (a, d, b)]
+    for s in range(nseg):
+        T.append((bottom, ring(nring - 1, s + 1), ring(nring - 1, s)))
+    if rot is not None:
+        V = V @ rot.T
+    V = V * radius + np.asarray(centre, np.float64)
+    return V.astype(np.float32), np.array(T, np.int32)
+
+
+def torus(R, r, centre, nmaj=24, nmin=12, rot=None):
+    """Ring torus around the z axis (before rotation): nmaj * nmin * 2 triangles."""
+    pts = []
+    for i in range(nmaj):
+        u = 2.0 * np.pi * i / nmaj
+        for j in range(nmin):
+            v = 2.0 * np.pi * j / nmin
+            pts.append(((R + r * np.cos(v)) * np.cos(u), (R + r * np.cos(v)) * np.sin(u), r * np.sin(v)))
+    V = np.array(pts, np.float64)
+
+    def idx(i, j):
+        return (i % nmaj) * nmin + (j % nmin)
+
+    T = []
+    for i in range(nmaj):
+        for j in range(nmin):
+            a, b, c, d = idx(i, j), idx(i + 1, j), idx(i + 1, j + 1), idx(i, j + 1)
+            T += [(a, b, c), (a, c, d)]
+    if rot is not None:
+        V = V @ rot.T
+    V = V + np.asarray(centre, np.float64)
+    return V.astype(np.float32), np.array(T, np.int32)
+
+
+def box(half, centre, rot=None):
+    """Closed box with half extents `half`: 8 vertices, 12 triangles."""
+    hx, hy, hz = half
+    V = np.array([[sx * hx, sy * hy, sz * hz] for sz in (-1, 1) for sy in (-1, 1) for sx in (-1, 1)],
+                 np.float64)
+    # vertex index = (sx>0) + 2 (sy>0) + 4 (sz>0)
+    quads = [(0, 2, 3, 1), (4, 5, 7, 6), (0, 1, 5, 4), (2, 6, 7, 3), (0, 4, 6, 2), (1, 3, 7, 5)]
+    T = []
+    for a, b, c, d in quads:
+        T += [(a, b, c), (a, c, d)]
+    if rot is not None:
+        V = V @ rot.T
+    V = V + np.asarray(centre, np.float64)
+    return V.astype(np.float32), np.array(T, np.int32)
+
+
+def random_rotation(rng):
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def jfa_offsets(dims, extra=0):
+    n = max(dims)
+    k = 1
+    while k < n:
+        k *= 2
+    out = []
+    k //= 2
+    while k >= 1:
+        out.append(k)
+        k //= 2
+    return (out or [1]) + [1] * extra
+
+
+def scene_tiny():
+    """One icosphere (subdivision 1, 80 triangles, radius 0.3) centred in the unit cube,
+    32^3 grid, offsets 16..1, 2-voxel mask, 16 rays, one frame."""
+    v, t = icosphere(1, 0.3, (0.5, 0.5, 0.5))
+    return Scene(v, t, (32, 32, 32), (0.0, 0.0, 0.0), 1.0 / 32, [16, 8, 4, 2, 1], 2, 16, 1,
+                 name="icosphere80-32^3")
+
+
+def scene_static(dims=(400, 200, 400), nprims=200, seed=0):
+    """Paper-shaped static scene over the box [0,2] x [0,1] x [0,2]: a ground quad at
+    y = 0.05 (on a voxel face at the full resolution) plus `nprims` boxes, UV spheres and
+    tori at uniform random positions with log-normal scales (median 0.1 = 0.05 of the box
+    extent, sigma 0.5).  Offsets n/2..1 plus one extra pass of 1, 4-voxel mask, 8 rays per
+    voxel per frame, 16 frames.  `dims` may be reduced (same world box) for fast tests."""
+    rng = np.random.default_rng(seed)
+    meshes = []
+    g = np.array([[0.0, 0.05, 0.0], [0.0, 0.05, 2.0], [2.0, 0.05, 2.0], [2.0, 0.05, 0.0]], np.float32)
+    meshes.append((g, np.array([[0, 1, 2], [0, 2, 3]], np.int32)))
+    for _ in range(nprims):
+        kind = rng.integers(0, 3)
+        c = (rng.uniform(0.0, 2.0), rng.uniform(0.05, 1.0), rng.uniform(0.0, 2.0))
+        s = rng.lognormal(np.log(0.1), 0.5)
+        rot = random_rotation(rng)
+        if kind == 0:
+            meshes.append(box(s * rng.uniform(0.5, 1.0, size=3), c, rot))
+        elif kind == 1:
+            meshes.append(uv_sphere(s, c, rot=rot))
+        else:
+            meshes.append(torus(s, 0.35 * s, c, rot=rot))
+    v, t = merge(meshes)
+    h = 2.0 / dims[0]
+    return Scene(v, t, tuple(dims), (0.0, 0.0, 0.0), h, jfa_offsets(dims, extra=1), 4, 8, 16,
+                 name="ground+%d-prims-%dx%dx%d" % (nprims, *dims))
