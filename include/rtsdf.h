@@ -1,0 +1,181 @@
+/*
+ * rtsdf.h -- C ABI of the RTSDF signed-distance hot path for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Tan, Chua, Koh, Bhojan, "RTSDF: Real-time Signed Distance Fields for Soft Shadow
+ * Approximation in Games" (arXiv 2210.06160).  A triangle scene is voxelized into seed
+ * voxels (section 2.2), jump-flooded into a coarse unsigned field (section 2.2), and the
+ * grid points within a mask width of a surface (section 2.3) are refined by ray sampling
+ * (section 2.1): minimum hit distance, front/back hit counts for the sign.  Frames are
+ * combined by a running minimum (section 2.1) or the decay rule of Eq. 1 (section 2.5.1),
+ * and a bias thickens surfaces (section 2.5.3).
+ *
+ * Conventions shared by every entry point
+ *  - Every array pointer is a DEVICE pointer owned by the caller unless marked HOST.  The
+ *    library never allocates or frees device memory and never synchronises the host: work
+ *    is enqueued on `stream` (a hipStream_t passed as void*; NULL = the null stream).
+ *  - Arguments are validated on the host before anything is enqueued; a non-OK status
+ *    means nothing was enqueued, except RTSDF_E_DEVICE (a launch failed; outputs are
+ *    unspecified).  rtsdf_last_error() returns a thread-local message for the last error.
+ *  - Grids: voxel (i, j, k) has centre org + h * (i + 1/2, j + 1/2, k + 1/2) and linear
+ *    index i + nx * (j + ny * k); 1 <= nx, ny, nz <= 1024; h finite and > 0.
+ *  - Seed ids pack the voxel coordinates of a seed: i | j << 10 | k << 20.  RTSDF_EMPTY
+ *    marks a grid point that holds no seed.
+ *  - Meshes: verts float[nv][3], tris int32[nt][3] (indices into verts), wound
+ *    counter-clockwise seen from outside, so (v1 - v0) x (v2 - v0) points out.
+ *  - Workspaces (`work`) are caller-owned device scratch of at least the size the
+ *    matching *_work_bytes() query returns; they carry nothing between calls.
+ *  - Calls that overlap in time must not share output or workspace buffers.
+ */
+#ifndef RTSDF_H
+#define RTSDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RTSDF_EMPTY (-1)
+#define RTSDF_MAX_DIM 1024
+#define RTSDF_MAX_RAYS 65535
+
+typedef struct rtsdf_grid {
+    int32_t nx, ny, nz; /* grid points per axis */
+    float org[3];       /* world position of the grid's lower corner */
+    float h;            /* voxel edge length (cubic voxels) */
+} rtsdf_grid;
+
+typedef int32_t rtsdf_status;
+#define RTSDF_OK 0
+#define RTSDF_E_ARG (-1)    /* null / aliased pointer, non-finite or non-positive parameter */
+#define RTSDF_E_RANGE (-2)  /* a size or count outside its documented range */
+#define RTSDF_E_SIZE (-3)   /* a workspace or output buffer smaller than required */
+#define RTSDF_E_DEVICE (-4) /* a HIP call failed; see rtsdf_last_error() */
+
+#define RTSDF_ACCUM 0 /* running minimum over frames (section 2.1) */
+#define RTSDF_DECAY 1 /* Eq. 1 decay (section 2.5.1) */
+
+/* Thread-local description of the last non-OK status ("" if none). */
+const char* rtsdf_last_error(void);
+/* ABI version of this header: 1. */
+int32_t rtsdf_abi_version(void);
+
+/* ---------------------------------------------------------------------------------------
+ * rtsdf_voxelize -- section 2.2 "voxelize the scene with voxel resolution equal to our
+ * final distance field": every grid point whose closed voxel cube meets a closed triangle
+ * becomes a seed holding its own id; every other grid point is set to RTSDF_EMPTY.
+ * Vertices are snapped to 1/256 voxel, X = rint(((v - org) / h) * 256) in binary32, and the
+ * overlap is decided exactly in integers (separating axes of a box and a triangle).
+ * Triangles with a snapped coordinate beyond +-2^19 (2048 voxels from org) are skipped.
+ *   verts  [nv*3] float     tris [nt*3] int32 (each index in [0, nv); not checked on device)
+ *   seeds  [N] int32 out    work [rtsdf_voxelize_work_bytes(nt)]
+ * nt = 0 is legal (all RTSDF_EMPTY).  Errors: E_ARG (null pointers, bad grid), E_RANGE
+ * (dims, nv/nt < 0), E_SIZE (work too small).
+ * ------------------------------------------------------------------------------------- */
+size_t rtsdf_voxelize_work_bytes(int32_t nt);
+rtsdf_status rtsdf_voxelize(const float* verts, int32_t nv, const int32_t* tris, int32_t nt,
+                            rtsdf_grid g, int32_t* seeds, void* work, size_t work_bytes,
+                            void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * rtsdf_jfa -- section 2.2 jump flooding.  Pass s uses offset k = steps[s]: every grid
+ * point p keeps its stored seed, then queries p + k*e for the 26 offsets
+ * e in {-1,0,1}^3 \ {0} in the order ez, ey, ex ascending; a query inside the grid that
+ * holds a seed replaces the stored seed only if that seed is strictly closer (squared
+ * voxel distance).  Each pass reads one buffer and writes the other (ping-pong), so the
+ * result does not depend on scheduling.
+ *   seeds    [N] int32 in: voxelize output; also ping-pong buffer
+ *   scratch  [N] int32 ping-pong buffer, must not alias seeds
+ *   steps    HOST int32[nsteps], each in [1, 1024]; nsteps in [0, 64]
+ *   result_in_scratch  HOST int32 out: 1 if the result is in scratch (nsteps odd), else 0
+ * Errors: E_ARG (null / aliased pointers, bad grid, step < 1), E_RANGE (dims, nsteps).
+ * ------------------------------------------------------------------------------------- */
+rtsdf_status rtsdf_jfa(int32_t* seeds, int32_t* scratch, rtsdf_grid g, const int32_t* steps,
+                       int32_t nsteps, int32_t* result_in_scratch, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * rtsdf_band -- section 2.3 ray mask: the grid points whose stored seed is within
+ * band_vox voxels (d2 <= band_vox^2, exact integers), listed in increasing linear index.
+ *   seeds      [N] int32 jump-flooding result
+ *   band_list  [N] int32 out: voxel linear indices; entries past the count are unspecified
+ *   band_count [1] int32 out (device): number of listed voxels
+ *   work       [rtsdf_band_work_bytes(g)]
+ * Errors: E_ARG, E_RANGE (band_vox outside [0, 2048]), E_SIZE.
+ * ------------------------------------------------------------------------------------- */
+size_t rtsdf_band_work_bytes(rtsdf_grid g);
+rtsdf_status rtsdf_band(const int32_t* seeds, rtsdf_grid g, int32_t band_vox, int32_t* band_list,
+                        int32_t* band_count, void* work, size_t work_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * rtsdf_build_bvh -- acceleration structure for the ray sampling of section 2.1 (the
+ * paper uses the graphics driver's hierarchy; CDNA has no ray-tracing units, so this is
+ * a software linear BVH: 30-bit Morton codes of triangle centroids, stable radix sort,
+ * Karras (2012) binary radix tree, bottom-up box refit).  Triangle boxes are widened by
+ * 2 * h/256 so that traversal returns exactly the brute-force closest hit of the hit test
+ * described at rtsdf_raysample.  The blob is self-contained (it copies the triangles).
+ *   bvh   [rtsdf_bvh_bytes(nt)] out      work [rtsdf_bvh_work_bytes(nt)]
+ * Errors: E_ARG, E_RANGE (nt outside [0, 2^26]), E_SIZE.
+ * ------------------------------------------------------------------------------------- */
+size_t rtsdf_bvh_bytes(int32_t nt);
+size_t rtsdf_bvh_work_bytes(int32_t nt);
+rtsdf_status rtsdf_build_bvh(const float* verts, int32_t nv, const int32_t* tris, int32_t nt,
+                             rtsdf_grid g, void* bvh, size_t bvh_bytes, void* work,
+                             size_t work_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * rtsdf_reset_accum -- sets dmin = +inf, hits = 0 and (if non-NULL) argmin = ~0 for n
+ * entries (a kernel, not a memset, so it may be captured into a graph).
+ * ------------------------------------------------------------------------------------- */
+rtsdf_status rtsdf_reset_accum(float* dmin, uint32_t* hits, uint64_t* argmin, int64_t n,
+                               void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * rtsdf_raysample -- section 2.1 ray sampling of the masked grid points for one frame.
+ * For listed voxel p and ray j < rays_per_voxel: the direction is uniform on the sphere
+ * (Philox4x32-10 with key rng_key and counter (p, frame, j, obj << 8 | attempt), then
+ * Marsaglia's 1972 rejection method); the ray starts at p's centre; the hit is
+ * Moller-Trumbore in binary32 (t > 0, and the computed hit point inside the triangle's
+ * box widened by h/256); the closest hit is the least (t, triangle index).  With no
+ * maximum distance, every ray that hits votes: front face (dot(dir, normal) < 0) adds 1,
+ * back face adds 1 << 16 to hits[p]; dmin[p] = min(dmin[p], t); argmin[p] =
+ * min(argmin[p], bits(t) << 32 | (frame * rays_per_voxel + j)).  Results do not depend on
+ * scheduling.  The caller keeps (front + back) <= 65535 across frames.
+ *   band_list/band_count  rtsdf_band output; band_capacity HOST bound on the count
+ *   dmin [N] float, hits [N] uint32, argmin [N] uint64 or NULL: accumulated in place
+ *   obj  object index (< 2^24) mixed into the counter; 0 for a single scene
+ * Errors: E_ARG, E_RANGE (rays_per_voxel outside [1, 65535], obj >= 2^24).
+ * ------------------------------------------------------------------------------------- */
+rtsdf_status rtsdf_raysample(const void* bvh, rtsdf_grid g, const int32_t* band_list,
+                             const int32_t* band_count, int64_t band_capacity,
+                             int32_t rays_per_voxel, uint64_t rng_key, uint32_t frame,
+                             uint32_t obj, float* dmin, uint32_t* hits, uint64_t* argmin,
+                             void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * rtsdf_combine -- the fine field, elementwise over all N grid points.
+ *   u = h * sqrt(d2) (binary32; +inf without a seed), c = u - beta (section 2.2), in band
+ *   iff d2 <= band_vox^2 (section 2.3), sign negative iff back hits > front hits (2.1).
+ *   RTSDF_ACCUM: in band with hits, +-dmin; otherwise c.
+ *   RTSDF_DECAY (Eq. 1 on magnitudes): in band m = min(alpha * m_prev + (1 - alpha) * u,
+ *     r) with r = dmin or +inf without hits, sign = majority or the previous sign on a tie,
+ *     state = sign * m; outside the band state = +u and the value is c.  first_frame != 0
+ *     (or a non-finite state) starts from m_prev = u with a positive sign.
+ *   fine = value - bias (section 2.5.3: a positive bias thickens surfaces).
+ *   consume != 0: after reading, grid points with hits != 0 are reset to dmin = +inf,
+ *   hits = 0, ready for the next frame.
+ *   seeds [N] int32; dmin [N] float, hits [N] uint32 (written only if consume);
+ *   state [N] float inout (DECAY only; may be NULL for ACCUM); fine [N] float out
+ * Errors: E_ARG (alpha outside [0, 1] in DECAY, non-finite beta/bias, NULL state in
+ * DECAY), E_RANGE (band_vox outside [0, 2048], mode).
+ * ------------------------------------------------------------------------------------- */
+rtsdf_status rtsdf_combine(const int32_t* seeds, float* dmin, uint32_t* hits, rtsdf_grid g,
+                           int32_t band_vox, float beta, float bias, int32_t mode, float alpha,
+                           int32_t first_frame, int32_t consume, float* state, float* fine,
+                           void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTSDF_H */

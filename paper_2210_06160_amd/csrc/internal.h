@@ -1,0 +1,90 @@
+// Internal declarations shared by the HIP translation units of librtsdf.so.
+// Host-side launchers return hipError_t; the C ABI layer (capi.cpp) validates arguments
+// and turns errors into rtsdf_status codes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/rtsdf.h"
+
+namespace rtsdf {
+
+constexpr int kWave = 64;
+
+inline int64_t nvox(const rtsdf_grid& g) { return (int64_t)g.nx * g.ny * g.nz; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Number of work-groups that keeps every CU of the device busy for grid-stride kernels.
+int persistent_groups(int threads_per_group);
+
+// ---- exclusive prefix sums (scan.hip) -------------------------------------------------
+// out[i] = sum(in[0..i)); *total = sum(in[0..n)) if total != nullptr.  out may alias in.
+size_t scan_work_bytes_u32(int64_t n);
+size_t scan_work_bytes_u64(int64_t n);
+hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                              void* work, hipStream_t s);
+hipError_t scan_exclusive_u64(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total,
+                              void* work, hipStream_t s);
+
+// ---- module launchers -----------------------------------------------------------------
+size_t voxelize_work_bytes(int32_t nt);
+hipError_t voxelize(const float* verts, const int32_t* tris, int32_t nt, const rtsdf_grid& g,
+                    int32_t* seeds, void* work, hipStream_t s);
+
+hipError_t jfa_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k,
+                    hipStream_t s);
+
+size_t band_work_bytes(const rtsdf_grid& g);
+hipError_t band(const int32_t* seeds, const rtsdf_grid& g, int32_t band_vox, int32_t* list,
+                int32_t* count, void* work, hipStream_t s);
+
+size_t bvh_bytes(int32_t nt);
+size_t bvh_work_bytes(int32_t nt);
+hipError_t build_bvh(const float* verts, const int32_t* tris, int32_t nt, const rtsdf_grid& g,
+                     void* bvh, void* work, hipStream_t s);
+
+hipError_t reset_accum(float* dmin, uint32_t* hits, uint64_t* argmin, int64_t n, hipStream_t s);
+hipError_t raysample(const void* bvh, const rtsdf_grid& g, const int32_t* list,
+                     const int32_t* count, int64_t capacity, int32_t x, uint64_t key,
+                     uint32_t frame, uint32_t obj, float* dmin, uint32_t* hits, uint64_t* argmin,
+                     hipStream_t s);
+
+hipError_t combine(const int32_t* seeds, float* dmin, uint32_t* hits, const rtsdf_grid& g,
+                   int32_t band_vox, float beta, float bias, int32_t mode, float alpha,
+                   int32_t first_frame, int32_t consume, float* state, float* fine,
+                   hipStream_t s);
+
+// ---- BVH blob layout (lbvh.hip writes it, raysample.hip reads it) ----------------------
+// [header 256 B][internal nodes: (nt-1) x BvhNode][triangles: nt x BvhTri]
+struct BvhHeader {
+    int32_t nt;
+    int32_t root;     // >= 0 internal node, < 0 leaf ~root (nt == 1); unused if nt == 0
+    float pad;        // hit-test widening (h / 256)
+    int32_t reserved[61];
+};
+struct alignas(16) BvhNode {  // both children's boxes, so one fetch tests two children
+    float4 a_lo;  // xyz = child a box min, w = bits of child a index
+    float4 a_hi;  // xyz = child a box max
+    float4 b_lo;  // child b box min, w = bits of child b index
+    float4 b_hi;
+};
+struct alignas(16) BvhTri {   // triangle in sorted order, with what the hit test needs
+    float4 v0;    // xyz = v0, w = bits of the original triangle index
+    float4 e1;    // v1 - v0
+    float4 e2;    // v2 - v0
+    float4 lo;    // xyz = min(v) - pad
+    float4 hi;    // xyz = max(v) + pad
+    float4 unused;
+};
+// child index encoding: c >= 0 internal node c; c < 0 leaf at sorted position ~c.
+
+inline BvhHeader* bvh_header(void* b) { return (BvhHeader*)b; }
+inline BvhNode* bvh_nodes(void* b) { return (BvhNode*)((char*)b + 256); }
+inline BvhTri* bvh_tris(void* b, int32_t nt) {
+    return (BvhTri*)((char*)b + 256 + sizeof(BvhNode) * (size_t)(nt > 1 ? nt - 1 : 0));
+}
+
+}  // namespace rtsdf

@@ -1,0 +1,238 @@
+"""Thin ctypes binding of librtsdf.so (the C ABI in include/rtsdf.h).
+
+Each `rtsdf_*` function marshals torch CUDA tensors into device pointers and the current
+HIP stream and calls the C entry point of the same name; all computation happens in the
+HIP kernels.  There is no fallback: if the library is missing or a call fails, an
+exception is raised.  `StaticSDF` chains the calls into the paper's static pipeline
+(voxelize -> jump flood -> mask -> BVH -> frames of ray sampling -> combine).
+"""
+import ctypes
+import os
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librtsdf.so")
+EMPTY = -1
+ACCUM, DECAY = 0, 1
+_lib = None
+
+
+class RtsdfError(RuntimeError):
+    pass
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("org", ctypes.c_float * 3), ("h", ctypes.c_float)]
+
+    @property
+    def n(self):
+        return self.nx * self.ny * self.nz
+
+
+def make_grid(dims, org, h):
+    g = Grid()
+    g.nx, g.ny, g.nz = (int(d) for d in dims)
+    for a in range(3):
+        g.org[a] = float(org[a])
+    g.h = float(h)
+    return g
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RtsdfError("librtsdf.so is not built (run paper_2210_06160_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u32, u64, f32, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                           ctypes.c_uint64, ctypes.c_float, ctypes.c_size_t)
+        sig = {
+            "rtsdf_last_error": ([], ctypes.c_char_p),
+            "rtsdf_abi_version": ([], i32),
+            "rtsdf_voxelize_work_bytes": ([i32], sz),
+            "rtsdf_voxelize": ([vp, i32, vp, i32, Grid, vp, vp, sz, vp], i32),
+            "rtsdf_jfa": ([vp, vp, Grid, vp, i32, vp, vp], i32),
+            "rtsdf_band_work_bytes": ([Grid], sz),
+            "rtsdf_band": ([vp, Grid, i32, vp, vp, vp, sz, vp], i32),
+            "rtsdf_bvh_bytes": ([i32], sz),
+            "rtsdf_bvh_work_bytes": ([i32], sz),
+            "rtsdf_build_bvh": ([vp, i32, vp, i32, Grid, vp, sz, vp, sz, vp], i32),
+            "rtsdf_reset_accum": ([vp, vp, vp, i64, vp], i32),
+            "rtsdf_raysample": ([vp, Grid, vp, vp, i64, i32, u64, u32, u32, vp, vp, vp, vp], i32),
+            "rtsdf_combine": ([vp, vp, vp, Grid, i32, f32, f32, i32, f32, i32, i32, vp, vp, vp], i32),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["rtsdf_last_error", "rtsdf_abi_version", "rtsdf_voxelize_work_bytes", "rtsdf_voxelize",
+            "rtsdf_jfa", "rtsdf_band_work_bytes", "rtsdf_band", "rtsdf_bvh_bytes", "rtsdf_bvh_work_bytes",
+            "rtsdf_build_bvh", "rtsdf_reset_accum", "rtsdf_raysample", "rtsdf_combine"]
+
+
+def _ptr(t, dtype=None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise RtsdfError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise RtsdfError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise RtsdfError("expected %s, got %s" % (dtype, t.dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(status, what):
+    if status != 0:
+        msg = lib().rtsdf_last_error().decode()
+        raise RtsdfError("%s failed (status %d): %s" % (what, status, msg))
+
+
+def workspace(nbytes, device="cuda"):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def rtsdf_abi_version():
+    return lib().rtsdf_abi_version()
+
+
+def rtsdf_voxelize_work_bytes(nt):
+    return lib().rtsdf_voxelize_work_bytes(int(nt))
+
+
+def rtsdf_voxelize(verts, tris, grid, seeds, work, stream=None):
+    _check(lib().rtsdf_voxelize(_ptr(verts, torch.float32), verts.shape[0], _ptr(tris, torch.int32),
+                                tris.shape[0], grid, _ptr(seeds, torch.int32), _ptr(work), work.numel(),
+                                _stream(stream)), "rtsdf_voxelize")
+
+
+def rtsdf_jfa(seeds, scratch, grid, steps, stream=None):
+    """Returns the tensor holding the result (seeds or scratch)."""
+    st = (ctypes.c_int32 * max(len(steps), 1))(*[int(k) for k in steps])
+    flag = ctypes.c_int32(0)
+    _check(lib().rtsdf_jfa(_ptr(seeds, torch.int32), _ptr(scratch, torch.int32), grid,
+                           ctypes.cast(st, ctypes.c_void_p), len(steps), ctypes.byref(flag), _stream(stream)),
+           "rtsdf_jfa")
+    return scratch if flag.value else seeds
+
+
+def rtsdf_band_work_bytes(grid):
+    return lib().rtsdf_band_work_bytes(grid)
+
+
+def rtsdf_band(seeds, grid, band_vox, band_list, band_count, work, stream=None):
+    _check(lib().rtsdf_band(_ptr(seeds, torch.int32), grid, int(band_vox), _ptr(band_list, torch.int32),
+                            _ptr(band_count, torch.int32), _ptr(work), work.numel(), _stream(stream)),
+           "rtsdf_band")
+
+
+def rtsdf_bvh_bytes(nt):
+    return lib().rtsdf_bvh_bytes(int(nt))
+
+
+def rtsdf_bvh_work_bytes(nt):
+    return lib().rtsdf_bvh_work_bytes(int(nt))
+
+
+def rtsdf_build_bvh(verts, tris, grid, bvh, work, stream=None):
+    _check(lib().rtsdf_build_bvh(_ptr(verts, torch.float32), verts.shape[0], _ptr(tris, torch.int32),
+                                 tris.shape[0], grid, _ptr(bvh), bvh.numel(), _ptr(work), work.numel(),
+                                 _stream(stream)), "rtsdf_build_bvh")
+
+
+def rtsdf_reset_accum(dmin, hits, argmin=None, stream=None):
+    _check(lib().rtsdf_reset_accum(_ptr(dmin, torch.float32), _ptr(hits, torch.int32),
+                                   _ptr(argmin, torch.int64) if argmin is not None else None, dmin.numel(),
+                                   _stream(stream)), "rtsdf_reset_accum")
+
+
+def rtsdf_raysample(bvh, grid, band_list, band_count, rays_per_voxel, rng_key, frame, dmin, hits,
+                    argmin=None, obj=0, stream=None):
+    """hits is an int32 tensor holding the uint32 counters; argmin an int64 tensor holding
+    the uint64 records (reinterpret with .view or `& 0xffffffff`)."""
+    _check(lib().rtsdf_raysample(_ptr(bvh), grid, _ptr(band_list, torch.int32), _ptr(band_count, torch.int32),
+                                 band_list.numel(), int(rays_per_voxel), int(rng_key) & (2 ** 64 - 1),
+                                 int(frame), int(obj), _ptr(dmin, torch.float32), _ptr(hits, torch.int32),
+                                 _ptr(argmin, torch.int64) if argmin is not None else None, _stream(stream)),
+           "rtsdf_raysample")
+
+
+def rtsdf_combine(seeds, dmin, hits, grid, band_vox, beta, bias, mode, fine, alpha=0.95, first_frame=True,
+                  consume=False, state=None, stream=None):
+    _check(lib().rtsdf_combine(_ptr(seeds, torch.int32), _ptr(dmin, torch.float32), _ptr(hits, torch.int32),
+                               grid, int(band_vox), float(beta), float(bias), int(mode), float(alpha),
+                               int(bool(first_frame)), int(bool(consume)),
+                               _ptr(state, torch.float32) if state is not None else None,
+                               _ptr(fine, torch.float32), _stream(stream)), "rtsdf_combine")
+
+
+class StaticSDF:
+    """Device buffers and the call chain for one static scene (sections 2.1-2.3).
+
+    run() = voxelize, jump flood, mask, BVH, `frames` x ray sampling (running minimum),
+    combine.  Every buffer is allocated once in __init__; run() only enqueues kernels.
+    """
+
+    def __init__(self, verts, tris, dims, org, h, steps, band, rays, frames, beta=None, bias=0.0,
+                 rng_key=0, keep_argmin=True, device="cuda"):
+        self.g = make_grid(dims, org, h)
+        N = self.g.n
+        self.verts = torch.as_tensor(verts, dtype=torch.float32).reshape(-1, 3).contiguous().to(device)
+        self.tris = torch.as_tensor(tris, dtype=torch.int32).reshape(-1, 3).contiguous().to(device)
+        nt = self.tris.shape[0]
+        self.steps, self.band, self.rays, self.frames = list(steps), int(band), int(rays), int(frames)
+        self.beta = float(h) / 2 if beta is None else float(beta)
+        self.bias, self.rng_key = float(bias), int(rng_key)
+        self.seeds = torch.empty(N, dtype=torch.int32, device=device)
+        self.scratch = torch.empty(N, dtype=torch.int32, device=device)
+        self.band_list = torch.empty(N, dtype=torch.int32, device=device)
+        self.band_count = torch.zeros(1, dtype=torch.int32, device=device)
+        self.dmin = torch.empty(N, dtype=torch.float32, device=device)
+        self.hits = torch.empty(N, dtype=torch.int32, device=device)
+        self.argmin = torch.empty(N, dtype=torch.int64, device=device) if keep_argmin else None
+        self.fine = torch.empty(N, dtype=torch.float32, device=device)
+        self.bvh = torch.empty(rtsdf_bvh_bytes(nt), dtype=torch.uint8, device=device)
+        wb = max(rtsdf_voxelize_work_bytes(nt), rtsdf_band_work_bytes(self.g), rtsdf_bvh_work_bytes(nt))
+        self.work = workspace(wb, device)
+        self.jfa_out = None
+
+    def voxelize(self):
+        rtsdf_voxelize(self.verts, self.tris, self.g, self.seeds, self.work)
+
+    def jfa(self):
+        self.jfa_out = rtsdf_jfa(self.seeds, self.scratch, self.g, self.steps)
+
+    def mask(self):
+        rtsdf_band(self.jfa_out, self.g, self.band, self.band_list, self.band_count, self.work)
+
+    def build_bvh(self):
+        rtsdf_build_bvh(self.verts, self.tris, self.g, self.bvh, self.work)
+
+    def trace(self, frame):
+        rtsdf_raysample(self.bvh, self.g, self.band_list, self.band_count, self.rays, self.rng_key, frame,
+                        self.dmin, self.hits, self.argmin)
+
+    def combine(self):
+        rtsdf_combine(self.jfa_out, self.dmin, self.hits, self.g, self.band, self.beta, self.bias, ACCUM,
+                      self.fine)
+
+    def run(self):
+        self.voxelize()
+        self.jfa()
+        self.mask()
+        self.build_bvh()
+        rtsdf_reset_accum(self.dmin, self.hits, self.argmin)
+        for f in range(self.frames):
+            self.trace(f)
+        self.combine()
+        return self.fine

@@ -1,0 +1,97 @@
+"""The C ABI library loads without a GPU, exports every entry point the header declares,
+and rejects bad arguments on the host before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rtsdf.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rtsdf_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2210_06160_amd import rtsdf
+    if not os.path.exists(rtsdf.LIB_PATH):
+        pytest.skip("librtsdf.so not built")
+    return rtsdf
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared()
+    assert len(names) >= 12
+    raw = ctypes.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+    assert set(names) == set(L.EXPORTED)
+    assert L.rtsdf_abi_version() == 1
+
+
+def fake(v=0x1000):
+    return ctypes.c_void_p(v)
+
+
+def test_host_validation(L):
+    lib = L.lib()
+    g = L.make_grid((8, 8, 8), (0, 0, 0), 0.1)
+    bad = L.make_grid((0, 8, 8), (0, 0, 0), 0.1)
+    big = L.make_grid((1025, 8, 8), (0, 0, 0), 0.1)
+    nanh = L.make_grid((8, 8, 8), (0, 0, 0), float("nan"))
+    E_ARG, E_RANGE, E_SIZE = -1, -2, -3
+    st = (ctypes.c_int32 * 2)(4, 1)
+    flag = ctypes.c_int32(0)
+    assert lib.rtsdf_jfa(fake(), fake(), bad, st, 2, ctypes.byref(flag), None) == E_RANGE
+    assert lib.rtsdf_jfa(fake(), fake(), big, st, 2, ctypes.byref(flag), None) == E_RANGE
+    assert lib.rtsdf_jfa(fake(), fake(), nanh, st, 2, ctypes.byref(flag), None) == E_ARG
+    assert lib.rtsdf_jfa(fake(), fake(), g, st, 2, ctypes.byref(flag), None) == E_ARG  # aliased
+    assert b"alias" in lib.rtsdf_last_error()
+    st0 = (ctypes.c_int32 * 2)(0, 1)
+    assert lib.rtsdf_jfa(fake(), fake(0x2000), g, st0, 2, ctypes.byref(flag), None) == E_ARG
+    assert lib.rtsdf_jfa(fake(), fake(0x2000), g, st, 65, ctypes.byref(flag), None) == E_RANGE
+    assert lib.rtsdf_jfa(None, fake(0x2000), g, st, 2, ctypes.byref(flag), None) == E_ARG
+    # voxelize
+    assert lib.rtsdf_voxelize(fake(), 3, fake(), -1, g, fake(), fake(), 1 << 20, None) == E_RANGE
+    assert lib.rtsdf_voxelize(fake(), 3, fake(), 1, g, fake(), fake(), 1, None) == E_SIZE
+    assert lib.rtsdf_voxelize(fake(), 3, fake(), 1, g, None, fake(), 1 << 20, None) == E_ARG
+    # band
+    assert lib.rtsdf_band(fake(), g, -1, fake(), fake(), fake(), 1 << 20, None) == E_RANGE
+    assert lib.rtsdf_band(fake(), g, 2, fake(), fake(), fake(), 0, None) == E_SIZE
+    # bvh
+    assert lib.rtsdf_build_bvh(fake(), 3, fake(), 1, g, fake(), 10, fake(), 1 << 20, None) == E_SIZE
+    assert lib.rtsdf_build_bvh(fake(), 3, fake(), (1 << 26) + 1, g, fake(), 1 << 40, fake(), 1 << 40,
+                               None) == E_RANGE
+    # raysample
+    for rays in (0, 65536):
+        assert lib.rtsdf_raysample(fake(), g, fake(), fake(), 10, rays, 0, 0, 0, fake(), fake(), None,
+                                   None) == E_RANGE
+    assert lib.rtsdf_raysample(fake(), g, fake(), fake(), 10, 4, 0, 0, 1 << 24, fake(), fake(), None,
+                               None) == E_RANGE
+    assert lib.rtsdf_raysample(fake(), g, fake(), fake(), 513, 4, 0, 0, 0, fake(), fake(), None,
+                               None) == E_RANGE
+    # combine
+    assert lib.rtsdf_combine(fake(), fake(), fake(), g, 2, 0.0, 0.0, 7, 0.9, 1, 0, fake(), fake(),
+                             None) == E_RANGE
+    assert lib.rtsdf_combine(fake(), fake(), fake(), g, 2, 0.0, 0.0, 1, 1.5, 1, 0, fake(), fake(),
+                             None) == E_ARG
+    assert lib.rtsdf_combine(fake(), fake(), fake(), g, 2, 0.0, 0.0, 1, 0.9, 1, 0, None, fake(),
+                             None) == E_ARG
+    assert lib.rtsdf_combine(fake(), fake(), fake(), g, 2, float("inf"), 0.0, 0, 0.9, 1, 0, None,
+                             fake(), None) == E_ARG
+    assert lib.rtsdf_reset_accum(fake(), fake(), None, -1, None) == E_RANGE
+
+
+def test_workspace_queries(L):
+    lib = L.lib()
+    g = L.make_grid((400, 200, 400), (0, 0, 0), 0.005)
+    assert lib.rtsdf_voxelize_work_bytes(103000) >= 8 * 103001
+    assert lib.rtsdf_band_work_bytes(g) > 0
+    assert lib.rtsdf_bvh_bytes(103000) >= 256 + 64 * 102999 + 96 * 103000
+    assert lib.rtsdf_bvh_work_bytes(103000) >= 16 * 103000
+    assert lib.rtsdf_voxelize_work_bytes(-1) == 0
