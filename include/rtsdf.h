@@ -144,13 +144,17 @@ rtsdf_status rtsdf_reset_accum(float* dmin, uint32_t* hits, uint64_t* argmin, in
  *   band_list/band_count  rtsdf_band output; band_capacity HOST bound on the count
  *   dmin [N] float, hits [N] uint32, argmin [N] uint64 or NULL: accumulated in place
  *   obj  object index (< 2^24) mixed into the counter; 0 for a single scene
- * Errors: E_ARG, E_RANGE (rays_per_voxel outside [1, 65535], obj >= 2^24).
+ *   work [rtsdf_raysample_work_bytes(band_capacity, rays_per_voxel)]: a work cursor and the
+ *        frame's ray directions (12 bytes per ray); nothing is carried between calls
+ * The listed voxels must be distinct (rtsdf_band lists are).
+ * Errors: E_ARG, E_RANGE (rays_per_voxel outside [1, 65535], obj >= 2^24), E_SIZE.
  * ------------------------------------------------------------------------------------- */
+size_t rtsdf_raysample_work_bytes(int64_t band_capacity, int32_t rays_per_voxel);
 rtsdf_status rtsdf_raysample(const void* bvh, rtsdf_grid g, const int32_t* band_list,
                              const int32_t* band_count, int64_t band_capacity,
                              int32_t rays_per_voxel, uint64_t rng_key, uint32_t frame,
                              uint32_t obj, float* dmin, uint32_t* hits, uint64_t* argmin,
-                             void* stream);
+                             void* work, size_t work_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------
  * rtsdf_combine -- the fine field, elementwise over all N grid points.

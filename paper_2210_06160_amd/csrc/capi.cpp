@@ -135,20 +135,28 @@ rtsdf_status rtsdf_reset_accum(float* dmin, uint32_t* hits, uint64_t* argmin, in
     return device(rtsdf::reset_accum(dmin, hits, argmin, n, as_stream(stream)), "reset_accum");
 }
 
+size_t rtsdf_raysample_work_bytes(int64_t band_capacity, int32_t rays_per_voxel)
+{
+    return rtsdf::raysample_work_bytes(band_capacity, rays_per_voxel);
+}
+
 rtsdf_status rtsdf_raysample(const void* bvh, rtsdf_grid g, const int32_t* band_list,
                              const int32_t* band_count, int64_t band_capacity, int32_t rays_per_voxel,
                              uint64_t rng_key, uint32_t frame, uint32_t obj, float* dmin, uint32_t* hits,
-                             uint64_t* argmin, void* stream)
+                             uint64_t* argmin, void* work, size_t work_bytes, void* stream)
 {
     if (rtsdf_status st = check_grid(g)) return st;
-    if (!bvh || !band_list || !band_count || !dmin || !hits) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (!bvh || !band_list || !band_count || !dmin || !hits || !work) return fail(RTSDF_E_ARG, "NULL pointer");
     if (rays_per_voxel < 1 || rays_per_voxel > RTSDF_MAX_RAYS)
         return fail(RTSDF_E_RANGE, "rays_per_voxel %d outside [1, %d]", rays_per_voxel, RTSDF_MAX_RAYS);
-    if (obj >= (1u << 24)) return fail(RTSDF_E_RANGE, "obj %u >= 2^24", obj);
     if (band_capacity < 0 || band_capacity > rtsdf::nvox(g))
         return fail(RTSDF_E_RANGE, "band_capacity outside [0, N]");
+    if (obj >= (1u << 24)) return fail(RTSDF_E_RANGE, "obj %u >= 2^24", obj);
+    if (work_bytes < rtsdf::raysample_work_bytes(band_capacity, rays_per_voxel))
+        return fail(RTSDF_E_SIZE, "raysample work %zu < %zu bytes", work_bytes,
+                    rtsdf::raysample_work_bytes(band_capacity, rays_per_voxel));
     return device(rtsdf::raysample(bvh, g, band_list, band_count, band_capacity, rays_per_voxel, rng_key,
-                                   frame, obj, dmin, hits, argmin, as_stream(stream)),
+                                   frame, obj, dmin, hits, argmin, work, as_stream(stream)),
                   "raysample");
 }
 

@@ -47,10 +47,11 @@ hipError_t build_bvh(const float* verts, const int32_t* tris, int32_t nt, const 
                      void* bvh, void* work, hipStream_t s);
 
 hipError_t reset_accum(float* dmin, uint32_t* hits, uint64_t* argmin, int64_t n, hipStream_t s);
+size_t raysample_work_bytes(int64_t capacity, int32_t x);
 hipError_t raysample(const void* bvh, const rtsdf_grid& g, const int32_t* list,
                      const int32_t* count, int64_t capacity, int32_t x, uint64_t key,
                      uint32_t frame, uint32_t obj, float* dmin, uint32_t* hits, uint64_t* argmin,
-                     hipStream_t s);
+                     void* work, hipStream_t s);
 
 hipError_t combine(const int32_t* seeds, float* dmin, uint32_t* hits, const rtsdf_grid& g,
                    int32_t band_vox, float beta, float bias, int32_t mode, float alpha,
@@ -71,13 +72,10 @@ struct alignas(16) BvhNode {  // both children's boxes, so one fetch tests two c
     float4 b_lo;  // child b box min, w = bits of child b index
     float4 b_hi;
 };
-struct alignas(16) BvhTri {   // triangle in sorted order, with what the hit test needs
+struct alignas(16) BvhTri {   // triangle in sorted (leaf) order
     float4 v0;    // xyz = v0, w = bits of the original triangle index
-    float4 e1;    // v1 - v0
-    float4 e2;    // v2 - v0
-    float4 lo;    // xyz = min(v) - pad
-    float4 hi;    // xyz = max(v) + pad
-    float4 unused;
+    float4 v1;    // xyz = v1
+    float4 v2;    // xyz = v2
 };
 // child index encoding: c >= 0 internal node c; c < 0 leaf at sorted position ~c.
 

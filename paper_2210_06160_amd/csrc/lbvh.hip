@@ -234,11 +234,8 @@ __global__ __launch_bounds__(256) void k_leaves_refit(const float* __restrict__ 
                                   fmaxf(fmaxf(a.z, b.z), c.z));
     BvhTri tri;
     tri.v0 = make_float4(a.x, a.y, a.z, __int_as_float(id));
-    tri.e1 = make_float4(b.x - a.x, b.y - a.y, b.z - a.z, 0.0f);
-    tri.e2 = make_float4(c.x - a.x, c.y - a.y, c.z - a.z, 0.0f);
-    tri.lo = make_float4(mn.x - pad, mn.y - pad, mn.z - pad, 0.0f);
-    tri.hi = make_float4(mx.x + pad, mx.y + pad, mx.z + pad, 0.0f);
-    tri.unused = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    tri.v1 = make_float4(b.x, b.y, b.z, 0.0f);
+    tri.v2 = make_float4(c.x, c.y, c.z, 0.0f);
     out[pos] = tri;
     if (n == 1) return;
     const float pad2 = 2.0f * pad;

@@ -51,12 +51,25 @@ __device__ inline float3 cross3(float3 a, float3 b)
     return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 
+__device__ inline float min3f(float a, float b, float c)
+{
+    const float m = a < b ? a : b;
+    return m < c ? m : c;
+}
+__device__ inline float max3f(float a, float b, float c)
+{
+    const float m = a > b ? a : b;
+    return m > c ? m : c;
+}
+
 // Moller-Trumbore (1997).  Returns t > 0 on a hit (and sets front = det > 0, i.e. the ray
 // meets the outward face), or a negative value on a miss.  A hit also needs the computed
-// point o + t*w inside [lo, hi] (the triangle's box widened by the hit pad).
-__device__ inline float hit_triangle(float3 o, float3 w, float3 v0, float3 e1, float3 e2, float3 lo,
-                                     float3 hi, bool& front)
+// point o + t*w inside the triangle's box widened by `pad` on every side.
+__device__ inline float hit_triangle(float3 o, float3 w, float3 v0, float3 v1, float3 v2, float pad,
+                                     bool& front)
 {
+    const float3 e1 = make_float3(v1.x - v0.x, v1.y - v0.y, v1.z - v0.z);
+    const float3 e2 = make_float3(v2.x - v0.x, v2.y - v0.y, v2.z - v0.z);
     const float3 P = cross3(w, e2);
     const float det = dot3(e1, P);
     if (det == 0.0f) return -1.0f;
@@ -70,7 +83,9 @@ __device__ inline float hit_triangle(float3 o, float3 w, float3 v0, float3 e1, f
     const float t = dot3(e2, Q) * inv;
     if (!(t > 0.0f)) return -1.0f;
     const float qx = o.x + t * w.x, qy = o.y + t * w.y, qz = o.z + t * w.z;
-    if (!(qx >= lo.x && qx <= hi.x && qy >= lo.y && qy <= hi.y && qz >= lo.z && qz <= hi.z))
+    if (!(qx >= min3f(v0.x, v1.x, v2.x) - pad && qx <= max3f(v0.x, v1.x, v2.x) + pad &&
+          qy >= min3f(v0.y, v1.y, v2.y) - pad && qy <= max3f(v0.y, v1.y, v2.y) + pad &&
+          qz >= min3f(v0.z, v1.z, v2.z) - pad && qz <= max3f(v0.z, v1.z, v2.z) + pad))
         return -1.0f;
     front = det > 0.0f;
     return t;

@@ -59,7 +59,8 @@ def lib():
             "rtsdf_bvh_work_bytes": ([i32], sz),
             "rtsdf_build_bvh": ([vp, i32, vp, i32, Grid, vp, sz, vp, sz, vp], i32),
             "rtsdf_reset_accum": ([vp, vp, vp, i64, vp], i32),
-            "rtsdf_raysample": ([vp, Grid, vp, vp, i64, i32, u64, u32, u32, vp, vp, vp, vp], i32),
+            "rtsdf_raysample_work_bytes": ([i64, i32], sz),
+            "rtsdf_raysample": ([vp, Grid, vp, vp, i64, i32, u64, u32, u32, vp, vp, vp, vp, sz, vp], i32),
             "rtsdf_combine": ([vp, vp, vp, Grid, i32, f32, f32, i32, f32, i32, i32, vp, vp, vp], i32),
         }
         for name, (args, res) in sig.items():
@@ -72,7 +73,8 @@ def lib():
 
 EXPORTED = ["rtsdf_last_error", "rtsdf_abi_version", "rtsdf_voxelize_work_bytes", "rtsdf_voxelize",
             "rtsdf_jfa", "rtsdf_band_work_bytes", "rtsdf_band", "rtsdf_bvh_bytes", "rtsdf_bvh_work_bytes",
-            "rtsdf_build_bvh", "rtsdf_reset_accum", "rtsdf_raysample", "rtsdf_combine"]
+            "rtsdf_build_bvh", "rtsdf_reset_accum", "rtsdf_raysample_work_bytes", "rtsdf_raysample",
+            "rtsdf_combine"]
 
 
 def _ptr(t, dtype=None):
@@ -156,14 +158,21 @@ def rtsdf_reset_accum(dmin, hits, argmin=None, stream=None):
                                    _stream(stream)), "rtsdf_reset_accum")
 
 
-def rtsdf_raysample(bvh, grid, band_list, band_count, rays_per_voxel, rng_key, frame, dmin, hits,
-                    argmin=None, obj=0, stream=None):
+def rtsdf_raysample_work_bytes(band_capacity, rays_per_voxel):
+    return lib().rtsdf_raysample_work_bytes(int(band_capacity), int(rays_per_voxel))
+
+
+def rtsdf_raysample(bvh, grid, band_list, band_count, rays_per_voxel, rng_key, frame, dmin, hits, work,
+                    argmin=None, obj=0, band_capacity=None, stream=None):
     """hits is an int32 tensor holding the uint32 counters; argmin an int64 tensor holding
-    the uint64 records (reinterpret with .view or `& 0xffffffff`)."""
+    the uint64 records (reinterpret with .view or `& 0xffffffff`).  band_capacity bounds the
+    device-side count (default: the list length)."""
+    cap = band_list.numel() if band_capacity is None else int(band_capacity)
     _check(lib().rtsdf_raysample(_ptr(bvh), grid, _ptr(band_list, torch.int32), _ptr(band_count, torch.int32),
-                                 band_list.numel(), int(rays_per_voxel), int(rng_key) & (2 ** 64 - 1),
+                                 cap, int(rays_per_voxel), int(rng_key) & (2 ** 64 - 1),
                                  int(frame), int(obj), _ptr(dmin, torch.float32), _ptr(hits, torch.int32),
-                                 _ptr(argmin, torch.int64) if argmin is not None else None, _stream(stream)),
+                                 _ptr(argmin, torch.int64) if argmin is not None else None, _ptr(work),
+                                 work.numel(), _stream(stream)),
            "rtsdf_raysample")
 
 
@@ -180,7 +189,9 @@ class StaticSDF:
     """Device buffers and the call chain for one static scene (sections 2.1-2.3).
 
     run() = voxelize, jump flood, mask, BVH, `frames` x ray sampling (running minimum),
-    combine.  Every buffer is allocated once in __init__; run() only enqueues kernels.
+    combine.  Buffers are allocated in __init__, except the ray-direction workspace, which
+    mask() sizes from the mask count (one device-to-host read of the count; it grows only
+    when a larger mask appears).
     """
 
     def __init__(self, verts, tris, dims, org, h, steps, band, rays, frames, beta=None, bias=0.0,
@@ -204,6 +215,9 @@ class StaticSDF:
         self.bvh = torch.empty(rtsdf_bvh_bytes(nt), dtype=torch.uint8, device=device)
         wb = max(rtsdf_voxelize_work_bytes(nt), rtsdf_band_work_bytes(self.g), rtsdf_bvh_work_bytes(nt))
         self.work = workspace(wb, device)
+        self.ray_work = workspace(rtsdf_raysample_work_bytes(0, self.rays), device)
+        self.band_n = 0
+        self.device = device
         self.jfa_out = None
 
     def voxelize(self):
@@ -214,13 +228,17 @@ class StaticSDF:
 
     def mask(self):
         rtsdf_band(self.jfa_out, self.g, self.band, self.band_list, self.band_count, self.work)
+        self.band_n = int(self.band_count.item())
+        need = rtsdf_raysample_work_bytes(self.band_n, self.rays)
+        if self.ray_work.numel() < need:
+            self.ray_work = workspace(need, self.device)
 
     def build_bvh(self):
         rtsdf_build_bvh(self.verts, self.tris, self.g, self.bvh, self.work)
 
     def trace(self, frame):
         rtsdf_raysample(self.bvh, self.g, self.band_list, self.band_count, self.rays, self.rng_key, frame,
-                        self.dmin, self.hits, self.argmin)
+                        self.dmin, self.hits, self.ray_work, self.argmin, band_capacity=self.band_n)
 
     def combine(self):
         rtsdf_combine(self.jfa_out, self.dmin, self.hits, self.g, self.band, self.beta, self.bias, ACCUM,

@@ -70,11 +70,15 @@ def test_host_validation(L):
     # raysample
     for rays in (0, 65536):
         assert lib.rtsdf_raysample(fake(), g, fake(), fake(), 10, rays, 0, 0, 0, fake(), fake(), None,
-                                   None) == E_RANGE
+                                   fake(), 256, None) == E_RANGE
     assert lib.rtsdf_raysample(fake(), g, fake(), fake(), 10, 4, 0, 0, 1 << 24, fake(), fake(), None,
-                               None) == E_RANGE
+                               fake(), 256, None) == E_RANGE
     assert lib.rtsdf_raysample(fake(), g, fake(), fake(), 513, 4, 0, 0, 0, fake(), fake(), None,
-                               None) == E_RANGE
+                               fake(), 256, None) == E_RANGE
+    assert lib.rtsdf_raysample(fake(), g, fake(), fake(), 10, 4, 0, 0, 0, fake(), fake(), None,
+                               fake(), lib.rtsdf_raysample_work_bytes(10, 4) - 1, None) == E_SIZE
+    assert lib.rtsdf_raysample(fake(), g, fake(), fake(), 10, 4, 0, 0, 0, fake(), fake(), None,
+                               None, 256, None) == E_ARG
     # combine
     assert lib.rtsdf_combine(fake(), fake(), fake(), g, 2, 0.0, 0.0, 7, 0.9, 1, 0, fake(), fake(),
                              None) == E_RANGE
@@ -92,6 +96,7 @@ def test_workspace_queries(L):
     g = L.make_grid((400, 200, 400), (0, 0, 0), 0.005)
     assert lib.rtsdf_voxelize_work_bytes(103000) >= 8 * 103001
     assert lib.rtsdf_band_work_bytes(g) > 0
-    assert lib.rtsdf_bvh_bytes(103000) >= 256 + 64 * 102999 + 96 * 103000
+    assert lib.rtsdf_bvh_bytes(103000) >= 256 + 64 * 102999 + 48 * 103000
     assert lib.rtsdf_bvh_work_bytes(103000) >= 16 * 103000
     assert lib.rtsdf_voxelize_work_bytes(-1) == 0
+    assert lib.rtsdf_raysample_work_bytes(1000, 8) >= 32
