@@ -2,74 +2,155 @@
 //
 // Query order: the stored seed first (rank 0), then the 26 offsets e in {-1,0,1}^3 \ {0}
 // in the order ez, ey, ex ascending (ranks 1..26).  A later query replaces the incumbent
-// only when strictly closer, which is the same as taking the minimum of the 32-bit key
-// (d2 << 5) | rank: d2 < 2^22 for grids up to 1024^3, so the key never overflows and
-// the reduction is order-free (v_min3_u32 on gfx950).
+// only when strictly closer, which is the same as taking the minimum of (d2, rank).
+//
+// Kernel: each thread owns one (x, y) column and walks the z positions of one residue
+// class z = r + m*k (the only planes a pass with offset k couples), holding the 3 x 3
+// neighbourhoods of planes m-1, m, m+1 in registers, so each output loads one new plane
+// (9 values) instead of 27.  For every loaded seed s the thread precomputes
+//     w = (sx - px)^2 + (sy - py)^2 + sz^2,
+// and for output z = pz a candidate's key is the signed 32-bit value
+//     key = (w - 2 pz sz) * 32 + rank = (d2 - pz^2) * 32 + rank,
+// an order-preserving image of (d2, rank) (one v_mad_i32_i24 and one v_lshl_add_u32),
+// reduced with v_min3_i32.  The winner's id is reloaded from its (recently cached)
+// position.  EMPTY (-1) unpacks to (1023, 1023, 4095), which makes w - 2 pz sz >= 8.39e6
+// > any real d2 (<= 3 * 1023^2), so it never wins against a seed; out-of-grid queries load
+// EMPTY.  Keys stay within +-2^30.
 #include "internal.h"
 
 namespace rtsdf {
 
 namespace {
 
-constexpr int kBX = 64, kBY = 4;
+constexpr int kBX = 64, kBY = 4;   // threads per block: 64 x-columns x 4 y-columns
+constexpr int kChunk = 16;          // lattice points per block along z
+constexpr int32_t kEmptyV = 8000000;  // v >= this only for EMPTY
 
-__device__ inline uint32_t sq_dist(int32_t s, int32_t x, int32_t y, int32_t z)
+struct Cand {
+    int32_t w;   // (sx-px)^2 + (sy-py)^2 + sz^2
+    int32_t sz;
+};
+
+typedef short short2_t __attribute__((ext_vector_type(2)));
+
+// (dx, dy) as packed int16 (|d| <= 1023) so that dx^2 + dy^2 + sz^2 is one v_dot2c_i32_i16
+// on top of sz^2; all other factors are below 2^23, so the 24-bit multiplier is exact.
+__device__ inline Cand prep(int32_t s, short2_t pxy)
 {
-    const int32_t dx = (s & 1023) - x;
-    const int32_t dy = ((s >> 10) & 1023) - y;
-    const int32_t dz = ((s >> 20) & 1023) - z;
-    return (uint32_t)(dx * dx + dy * dy + dz * dz);
+    const uint32_t u = (uint32_t)s;
+    const int32_t sz = (int32_t)(u >> 20);
+    const short2_t sxy = __builtin_bit_cast(short2_t, (u & 1023u) | (((u >> 10) & 1023u) << 16));
+    const short2_t d = sxy - pxy;
+    return Cand{__builtin_amdgcn_sdot2(d, d, __mul24(sz, sz), false), sz};
 }
 
-__global__ __launch_bounds__(kBX * kBY) void k_jfa_direct(const int32_t* __restrict__ in,
+__device__ inline int32_t cand_key(Cand c, int32_t m2pz, int32_t rank)
+{
+    return (c.w + __mul24(c.sz, m2pz)) * 32 + rank;
+}
+
+// query rank of offset (ex, ey, ez): self 0, others their position in (ez, ey, ex) order
+__host__ __device__ constexpr int32_t rank_of(int ex, int ey, int ez)
+{
+    return (ex == 0 && ey == 0 && ez == 0) ? 0
+           : (9 * (ez + 1) + 3 * (ey + 1) + (ex + 1)) < 13 ? 9 * (ez + 1) + 3 * (ey + 1) + (ex + 1) + 1
+                                                             : 9 * (ez + 1) + 3 * (ey + 1) + (ex + 1);
+}
+
+__global__ __launch_bounds__(kBX * kBY) void k_jfa_stream(const int32_t* __restrict__ in,
                                                           int32_t* __restrict__ out, int32_t nx,
-                                                          int32_t ny, int32_t nz, int32_t k)
+                                                          int32_t ny, int32_t nz, int32_t k,
+                                                          int32_t chunks_per_residue)
 {
     const int32_t x = blockIdx.x * kBX + threadIdx.x;
     const int32_t y = blockIdx.y * kBY + threadIdx.y;
-    const int32_t z = blockIdx.z;
-    if (x >= nx || y >= ny) return;
-    const int64_t plane = (int64_t)nx * ny;
-    const int64_t p = x + (int64_t)nx * y + plane * z;
-    uint32_t best = 0xFFFFFFFFu;
-    int32_t bid = RTSDF_EMPTY;
-    {
-        const int32_t s = in[p];
-        if (s != RTSDF_EMPTY) {
-            best = sq_dist(s, x, y, z) << 5;
-            bid = s;
+    const int32_t r = blockIdx.z / chunks_per_residue;
+    const int32_t c = blockIdx.z - r * chunks_per_residue;
+    if (x >= nx || y >= ny || r >= nz) return;
+    const int32_t mcount = (nz - r + k - 1) / k;  // lattice points z = r + m k < nz
+    const int32_t m0 = c * kChunk;
+    if (m0 >= mcount) return;
+    const int32_t m1 = min(m0 + kChunk, mcount);
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;  // grids hold at most 2^30 points
+
+    // byte offsets of the 3 x 3 neighbourhood columns; out-of-grid columns read EMPTY
+    uint32_t off[9];
+    bool ok[9];
+#pragma unroll
+    for (int ey = -1; ey <= 1; ++ey)
+#pragma unroll
+        for (int ex = -1; ex <= 1; ++ex) {
+            const int q = 3 * (ey + 1) + (ex + 1);
+            const int32_t qx = x + ex * k, qy = y + ey * k;
+            ok[q] = qx >= 0 && qx < nx && qy >= 0 && qy < ny;
+            off[q] = ok[q] ? 4u * ((uint32_t)qx + (uint32_t)nx * (uint32_t)qy) : 0u;  // bytes
         }
-    }
-    uint32_t rank = 0;
+
+    const short2_t pxy = __builtin_bit_cast(short2_t, (uint32_t)x | ((uint32_t)y << 16));
+    auto load_plane = [&](int32_t m, Cand* dst) {
+        const int32_t z = r + m * k;
+        if (m >= 0 && z < nz) {  // wave-uniform
+            const char* pb = (const char*)(in + plane * (uint32_t)z);
 #pragma unroll
-    for (int ez = -1; ez <= 1; ++ez) {
-#pragma unroll
-        for (int ey = -1; ey <= 1; ++ey) {
-#pragma unroll
-            for (int ex = -1; ex <= 1; ++ex) {
-                if (ex == 0 && ey == 0 && ez == 0) continue;
-                ++rank;
-                const int32_t qx = x + ex * k, qy = y + ey * k, qz = z + ez * k;
-                if (qx < 0 || qx >= nx || qy < 0 || qy >= ny || qz < 0 || qz >= nz) continue;
-                const int32_t s = in[qx + (int64_t)nx * qy + plane * qz];
-                if (s == RTSDF_EMPTY) continue;
-                const uint32_t key = (sq_dist(s, x, y, z) << 5) | rank;
-                if (key < best) {
-                    best = key;
-                    bid = s;
-                }
+            for (int q = 0; q < 9; ++q) {
+                const int32_t v = *(const int32_t*)(pb + off[q]);
+                dst[q] = prep(ok[q] ? v : RTSDF_EMPTY, pxy);
             }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) dst[q] = prep(RTSDF_EMPTY, pxy);
         }
+    };
+    // output for lattice point m from planes m-1 (lo), m (mid), m+1 (hi)
+    auto emit = [&](int32_t m, const Cand* lo, const Cand* mid, const Cand* hi) {
+        const int32_t pz = r + m * k;
+        const int32_t m2pz = -2 * pz;
+        const Cand* P[3] = {lo, mid, hi};
+        int32_t best = 0x7FFFFFFF;
+#pragma unroll
+        for (int ez = -1; ez <= 1; ++ez)
+#pragma unroll
+            for (int ey = -1; ey <= 1; ++ey) {
+                const int q = 3 * (ey + 1);
+                const int32_t a = cand_key(P[ez + 1][q], m2pz, rank_of(-1, ey, ez));
+                const int32_t b = cand_key(P[ez + 1][q + 1], m2pz, rank_of(0, ey, ez));
+                const int32_t d = cand_key(P[ez + 1][q + 2], m2pz, rank_of(1, ey, ez));
+                best = min(best, min(min(a, b), d));
+            }
+        int32_t id = RTSDF_EMPTY;
+        if ((best >> 5) < kEmptyV) {
+            const int32_t rk = best & 31;
+            const int32_t L = rk == 0 ? 13 : (rk <= 13 ? rk - 1 : rk);
+            const int32_t ez = L / 9 - 1, ey = (L / 3) % 3 - 1, ex = L % 3 - 1;
+            id = in[(uint32_t)(x + ex * k) + (uint32_t)nx * (uint32_t)(y + ey * k) + plane * (uint32_t)(pz + ez * k)];
+        }
+        out[(uint32_t)x + (uint32_t)nx * (uint32_t)y + plane * (uint32_t)pz] = id;
+    };
+
+    Cand A[9], B[9], C[9];
+    load_plane(m0 - 1, A);
+    load_plane(m0, B);
+    // rotate the three plane buffers by unrolling three outputs per trip
+    for (int32_t m = m0; m < m1; m += 3) {
+        load_plane(m + 1, C);
+        emit(m, A, B, C);
+        if (m + 1 >= m1) break;
+        load_plane(m + 2, A);
+        emit(m + 1, B, C, A);
+        if (m + 2 >= m1) break;
+        load_plane(m + 3, B);
+        emit(m + 2, C, A, B);
     }
-    out[p] = bid;
 }
 
 }  // namespace
 
 hipError_t jfa_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, hipStream_t s)
 {
-    dim3 grid((unsigned)ceil_div(g.nx, kBX), (unsigned)ceil_div(g.ny, kBY), (unsigned)g.nz);
-    hipLaunchKernelGGL(k_jfa_direct, grid, dim3(kBX, kBY), 0, s, in, out, g.nx, g.ny, g.nz, k);
+    const int64_t residues = std::min<int64_t>(k, g.nz);
+    const int64_t per_res = ceil_div(ceil_div(g.nz, k), kChunk);
+    dim3 grid((unsigned)ceil_div(g.nx, kBX), (unsigned)ceil_div(g.ny, kBY), (unsigned)(residues * per_res));
+    hipLaunchKernelGGL(k_jfa_stream, grid, dim3(kBX, kBY), 0, s, in, out, g.nx, g.ny, g.nz, k, (int32_t)per_res);
     return hipGetLastError();
 }
 
