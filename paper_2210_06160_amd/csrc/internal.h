@@ -59,30 +59,44 @@ hipError_t combine(const int32_t* seeds, float* dmin, uint32_t* hits, const rtsd
                    hipStream_t s);
 
 // ---- BVH blob layout (lbvh.hip writes it, raysample.hip reads it) ----------------------
-// [header 256 B][internal nodes: (nt-1) x BvhNode][triangles: nt x BvhTri]
+// [header 256 B][4-wide nodes: max(nt-1, 1) x Bvh4Node][triangles: nt x BvhTri]
+// A 4-wide node is stored at the index of the binary radix-tree node it was collapsed
+// from (only some indices are reachable).  Child codes: c >= 0 is a node index,
+// kBvhEmptySlot an unused slot, any other c < 0 a leaf range ~c = first | (count-1) << 26
+// of `count` (1..kLeafMax) consecutive triangles in sorted order.
+constexpr int32_t kBvhEmptySlot = (int32_t)0x80000000;
+constexpr int kLeafMax = 3;
+
 struct BvhHeader {
     int32_t nt;
-    int32_t root;     // >= 0 internal node, < 0 leaf ~root (nt == 1); unused if nt == 0
+    int32_t root;     // child code of the root (a node, or a leaf range when nt <= kLeafMax)
     float pad;        // hit-test widening (h / 256)
     int32_t reserved[61];
 };
-struct alignas(16) BvhNode {  // both children's boxes, so one fetch tests two children
-    float4 a_lo;  // xyz = child a box min, w = bits of child a index
-    float4 a_hi;  // xyz = child a box max
-    float4 b_lo;  // child b box min, w = bits of child b index
-    float4 b_hi;
+struct alignas(16) Bvh4Node {  // structure of arrays over the 4 children
+    float4 lox, loy, loz;
+    float4 hix, hiy, hiz;
+    int4 child;
+    int4 unused;
 };
 struct alignas(16) BvhTri {   // triangle in sorted (leaf) order
     float4 v0;    // xyz = v0, w = bits of the original triangle index
     float4 v1;    // xyz = v1
     float4 v2;    // xyz = v2
 };
-// child index encoding: c >= 0 internal node c; c < 0 leaf at sorted position ~c.
 
+__host__ __device__ inline int32_t leaf_code(int32_t first, int32_t count)
+{
+    return ~(first | ((count - 1) << 26));
+}
+__host__ __device__ inline int32_t leaf_first(int32_t code) { return (~code) & 0x3FFFFFF; }
+__host__ __device__ inline int32_t leaf_count(int32_t code) { return ((~code) >> 26) + 1; }
+
+inline size_t bvh_node_count(int32_t nt) { return (size_t)(nt > 1 ? nt - 1 : 1); }
 inline BvhHeader* bvh_header(void* b) { return (BvhHeader*)b; }
-inline BvhNode* bvh_nodes(void* b) { return (BvhNode*)((char*)b + 256); }
+inline Bvh4Node* bvh_nodes(void* b) { return (Bvh4Node*)((char*)b + 256); }
 inline BvhTri* bvh_tris(void* b, int32_t nt) {
-    return (BvhTri*)((char*)b + 256 + sizeof(BvhNode) * (size_t)(nt > 1 ? nt - 1 : 0));
+    return (BvhTri*)((char*)b + 256 + sizeof(Bvh4Node) * bvh_node_count(nt));
 }
 
 }  // namespace rtsdf

@@ -166,6 +166,15 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* __rest
 }
 
 // ---- binary radix tree ------------------------------------------------------------------
+// Binary nodes live in the workspace; each stores both children's boxes, and in the spare
+// lanes its own range of sorted triangles (a_hi.w = first, b_hi.w = count).
+struct alignas(16) BinNode {
+    float4 a_lo;  // xyz = child a box min, w = bits of child a (>= 0 node, < 0 leaf ~position)
+    float4 a_hi;  // xyz = child a box max, w = bits of this node's first triangle
+    float4 b_lo;  // child b
+    float4 b_hi;  // w = bits of this node's triangle count
+};
+
 __device__ inline int delta(const uint32_t* __restrict__ k, int32_t n, int32_t i, int32_t j)
 {
     if (j < 0 || j >= n) return -1;
@@ -175,7 +184,7 @@ __device__ inline int delta(const uint32_t* __restrict__ k, int32_t n, int32_t i
 }
 
 __global__ __launch_bounds__(256) void k_tree(const uint32_t* __restrict__ k, int32_t n,
-                                              BvhNode* __restrict__ nodes,
+                                              BinNode* __restrict__ nodes,
                                               int32_t* __restrict__ parent)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -200,9 +209,9 @@ __global__ __launch_bounds__(256) void k_tree(const uint32_t* __restrict__ k, in
     const int32_t right = (max(i, j) == gamma + 1) ? ~(gamma + 1) : gamma + 1;
     const float inf = __int_as_float(0x7f800000);
     nodes[i].a_lo = make_float4(inf, inf, inf, __int_as_float(left));
-    nodes[i].a_hi = make_float4(-inf, -inf, -inf, 0.0f);
+    nodes[i].a_hi = make_float4(-inf, -inf, -inf, __int_as_float(min(i, j)));
     nodes[i].b_lo = make_float4(inf, inf, inf, __int_as_float(right));
-    nodes[i].b_hi = make_float4(-inf, -inf, -inf, 0.0f);
+    nodes[i].b_hi = make_float4(-inf, -inf, -inf, __int_as_float(max(i, j) - min(i, j) + 1));
     parent[left >= 0 ? left : (n - 1) + ~left] = i;
     parent[right >= 0 ? right : (n - 1) + ~right] = i;
 }
@@ -213,10 +222,15 @@ __device__ inline float ld_coherent(const float* p)
                                              __HIP_MEMORY_SCOPE_AGENT));
 }
 
+__device__ inline void st_coherent(float* p, float v)
+{
+    __hip_atomic_store((uint32_t*)p, __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ __launch_bounds__(256) void k_leaves_refit(const float* __restrict__ v,
                                                       const int32_t* __restrict__ t, int32_t n,
                                                       const uint32_t* __restrict__ order,
-                                                      float pad, BvhNode* nodes,
+                                                      float pad, BinNode* nodes,
                                                       BvhTri* __restrict__ out,
                                                       const int32_t* __restrict__ parent,
                                                       uint32_t* flags)
@@ -244,16 +258,16 @@ __global__ __launch_bounds__(256) void k_leaves_refit(const float* __restrict__ 
     int32_t me = ~pos;
     int32_t p = parent[(n - 1) + pos];
     while (true) {
-        BvhNode* node = &nodes[p];
+        BinNode* node = &nodes[p];
         const bool is_a = __float_as_int(node->a_lo.w) == me;
         float* slo = is_a ? &node->a_lo.x : &node->b_lo.x;
         float* shi = is_a ? &node->a_hi.x : &node->b_hi.x;
-        __hip_atomic_store((uint32_t*)&slo[0], __float_as_uint(blo.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store((uint32_t*)&slo[1], __float_as_uint(blo.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store((uint32_t*)&slo[2], __float_as_uint(blo.z), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store((uint32_t*)&shi[0], __float_as_uint(bhi.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store((uint32_t*)&shi[1], __float_as_uint(bhi.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store((uint32_t*)&shi[2], __float_as_uint(bhi.z), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st_coherent(slo, blo.x);
+        st_coherent(slo + 1, blo.y);
+        st_coherent(slo + 2, blo.z);
+        st_coherent(shi, bhi.x);
+        st_coherent(shi + 1, bhi.y);
+        st_coherent(shi + 2, bhi.z);
         const uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (old == 0u) return;  // the sibling will finish this node
         const float* alo = &node->a_lo.x;
@@ -272,16 +286,103 @@ __global__ __launch_bounds__(256) void k_leaves_refit(const float* __restrict__ 
     }
 }
 
+// ---- collapse into a 4-wide hierarchy ---------------------------------------------------
+// For every binary node: start from its two children and repeatedly open the child with
+// the largest surface area that holds more than kLeafMax triangles, until there are 4
+// children or nothing left to open; children with at most kLeafMax triangles become leaf
+// ranges (a radix-tree subtree always covers consecutive sorted triangles).  Each node's
+// result depends only on its own subtree, so all nodes are collapsed in parallel; the ones
+// reachable from the root form the hierarchy.
+struct Slot {
+    int32_t code;   // binary code: >= 0 node, < 0 leaf ~position
+    int32_t first, count;
+    float3 lo, hi;
+};
+
+__device__ inline Slot child_slot(const BinNode* __restrict__ nodes, const BinNode& par, bool a)
+{
+    Slot s;
+    const float4 lo = a ? par.a_lo : par.b_lo, hi = a ? par.a_hi : par.b_hi;
+    s.code = __float_as_int(lo.w);
+    s.lo = make_float3(lo.x, lo.y, lo.z);
+    s.hi = make_float3(hi.x, hi.y, hi.z);
+    if (s.code >= 0) {
+        s.first = __float_as_int(nodes[s.code].a_hi.w);
+        s.count = __float_as_int(nodes[s.code].b_hi.w);
+    } else {
+        s.first = ~s.code;
+        s.count = 1;
+    }
+    return s;
+}
+
+__device__ inline float half_area(const Slot& s)
+{
+    const float dx = s.hi.x - s.lo.x, dy = s.hi.y - s.lo.y, dz = s.hi.z - s.lo.z;
+    return dx * dy + dy * dz + dz * dx;
+}
+
+__global__ __launch_bounds__(256) void k_collapse4(const BinNode* __restrict__ nodes, int32_t n,
+                                                   Bvh4Node* __restrict__ out)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    Slot s[4];
+    const BinNode me = nodes[i];
+    s[0] = child_slot(nodes, me, true);
+    s[1] = child_slot(nodes, me, false);
+    int m = 2;
+    while (m < 4) {
+        int best = -1;
+        float area = -1.0f;
+        for (int q = 0; q < m; ++q)
+            if (s[q].code >= 0 && s[q].count > kLeafMax && half_area(s[q]) > area) {
+                area = half_area(s[q]);
+                best = q;
+            }
+        if (best < 0) break;
+        const BinNode c = nodes[s[best].code];
+        s[m] = child_slot(nodes, c, false);
+        s[best] = child_slot(nodes, c, true);
+        ++m;
+    }
+    const float inf = __int_as_float(0x7f800000);
+    float lx[4], ly[4], lz[4], hx[4], hy[4], hz[4];
+    int32_t cc[4];
+    for (int q = 0; q < 4; ++q) {
+        if (q < m) {
+            lx[q] = s[q].lo.x; ly[q] = s[q].lo.y; lz[q] = s[q].lo.z;
+            hx[q] = s[q].hi.x; hy[q] = s[q].hi.y; hz[q] = s[q].hi.z;
+            cc[q] = s[q].count <= kLeafMax ? leaf_code(s[q].first, s[q].count) : s[q].code;
+        } else {
+            lx[q] = ly[q] = lz[q] = inf;
+            hx[q] = hy[q] = hz[q] = -inf;
+            cc[q] = kBvhEmptySlot;
+        }
+    }
+    Bvh4Node o;
+    o.lox = make_float4(lx[0], lx[1], lx[2], lx[3]);
+    o.loy = make_float4(ly[0], ly[1], ly[2], ly[3]);
+    o.loz = make_float4(lz[0], lz[1], lz[2], lz[3]);
+    o.hix = make_float4(hx[0], hx[1], hx[2], hx[3]);
+    o.hiy = make_float4(hy[0], hy[1], hy[2], hy[3]);
+    o.hiz = make_float4(hz[0], hz[1], hz[2], hz[3]);
+    o.child = make_int4(cc[0], cc[1], cc[2], cc[3]);
+    o.unused = make_int4(0, 0, 0, 0);
+    out[i] = o;
+}
+
 __global__ void k_header(BvhHeader* h, int32_t nt, float pad)
 {
     h->nt = nt;
-    h->root = nt == 1 ? ~0 : 0;
+    h->root = nt <= kLeafMax ? (nt > 0 ? leaf_code(0, nt) : kBvhEmptySlot) : 0;
     h->pad = pad;
 }
 
 struct SortWork {
     uint32_t *k0, *v0, *k1, *v1, *counts, *bounds, *flags;
     int32_t* parent;
+    BinNode* bin;
     void* scan;
     int32_t ntiles;
 };
@@ -308,6 +409,8 @@ SortWork carve(void* work, int32_t nt)
     p += align256((size_t)nt * 4);
     w.parent = (int32_t*)p;
     p += align256((size_t)(2 * (int64_t)nt) * 4);
+    w.bin = (BinNode*)p;
+    p += align256(sizeof(BinNode) * (size_t)nt);
     w.scan = p;
     return w;
 }
@@ -316,7 +419,7 @@ SortWork carve(void* work, int32_t nt)
 
 size_t bvh_bytes(int32_t nt)
 {
-    return 256 + sizeof(BvhNode) * (size_t)(nt > 1 ? nt - 1 : 0) + sizeof(BvhTri) * (size_t)nt;
+    return 256 + sizeof(Bvh4Node) * bvh_node_count(nt) + sizeof(BvhTri) * (size_t)nt;
 }
 
 size_t bvh_work_bytes(int32_t nt)
@@ -324,7 +427,7 @@ size_t bvh_work_bytes(int32_t nt)
     const int64_t ntiles = ceil_div(nt, kSortTile);
     return 4 * align256((size_t)nt * 4) + align256((size_t)ntiles * 256 * 4) + 256 +
            align256((size_t)nt * 4) + align256((size_t)(2 * (int64_t)nt) * 4) +
-           scan_work_bytes_u32(ntiles * 256);
+           align256(sizeof(BinNode) * (size_t)nt) + scan_work_bytes_u32(ntiles * 256);
 }
 
 hipError_t build_bvh(const float* verts, const int32_t* tris, int32_t nt, const rtsdf_grid& g,
@@ -351,13 +454,15 @@ hipError_t build_bvh(const float* verts, const int32_t* tris, int32_t nt, const 
         std::swap(ka, kb);
         std::swap(va, vb);
     }
-    BvhNode* nodes = bvh_nodes(bvh);
     BvhTri* out = bvh_tris(bvh, nt);
     if (nt > 1)
-        hipLaunchKernelGGL(k_tree, dim3((unsigned)ceil_div(nt - 1, 256)), dim3(256), 0, s, ka, nt, nodes,
+        hipLaunchKernelGGL(k_tree, dim3((unsigned)ceil_div(nt - 1, 256)), dim3(256), 0, s, ka, nt, w.bin,
                            w.parent);
-    hipLaunchKernelGGL(k_leaves_refit, dim3(tb), dim3(256), 0, s, verts, tris, nt, va, pad, nodes, out,
+    hipLaunchKernelGGL(k_leaves_refit, dim3(tb), dim3(256), 0, s, verts, tris, nt, va, pad, w.bin, out,
                        w.parent, w.flags);
+    if (nt > 1)
+        hipLaunchKernelGGL(k_collapse4, dim3((unsigned)ceil_div(nt - 1, 256)), dim3(256), 0, s,
+                           (const BinNode*)w.bin, nt, bvh_nodes(bvh));
     return hipGetLastError();
 }
 

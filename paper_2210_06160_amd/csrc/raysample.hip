@@ -5,8 +5,9 @@
 // record in registers, and folds them into the voxel's accumulators once at the end
 // (min / add are order-free, so the result does not depend on scheduling).  A lane whose
 // ray ends starts its next ray at once, and a lane whose voxel is done takes the next
-// voxel from a cursor (one atomic per wave per refill), so divergent ray lengths neither
-// idle lanes nor leave a tail of busy waves.  The mask list is split into one contiguous
+// voxel from its wave's chunk of the mask list (one cursor atomic per kChunk voxels: device-
+// scope atomics on one address serialise across the chip), so divergent ray lengths
+// neither idle lanes nor leave a tail of busy waves.  The mask list is split into one contiguous
 // range per XCD (work-groups are dealt to the 8 XCDs round-robin); a wave takes voxels
 // from its own XCD's range first, so list reads and the hierarchy working set stay in
 // that XCD's L2, and steals from the other ranges when its own is exhausted.
@@ -15,8 +16,11 @@
 // HBM-latency load would stall every later node fetch of the wave.
 // Each loop iteration does at most one node visit and one triangle test per lane.
 //
-// Traversal keeps a per-lane stack of (entry, box entry t) in LDS, spilling to private
-// memory past kLdsDepth; entries are internal nodes (>= 0) or leaves (~position).  A box
+// Traversal of the 4-wide hierarchy: the four child boxes are tested at once, the hits are
+// sorted by entry distance (packed into uint keys with the slot in the two low bits, the
+// distance rounded down, which can only keep more boxes), the nearest node is visited next
+// and the others go on a per-lane stack of (child code, entry t) in LDS that spills to
+// private memory past kLdsDepth.  Leaf ranges are tested one triangle per iteration.  A box
 // is culled only when its entry parameter exceeds the best hit so far (ties are still
 // visited, because the tie-break is the triangle index).  Box tests may round freely:
 // every triangle box is widened by 2*pad while a hit's computed point must lie within pad
@@ -29,20 +33,30 @@ namespace rtsdf {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kLdsDepth = 8;
-constexpr int kMaxDepth = 64;  // one push per level; radix-tree depth <= 30 code bits + 26 index bits
+constexpr int kLdsDepth = 12;
+constexpr int kMaxStack = 176;  // <= 3 pushes per level + 1; tree depth <= 56
 constexpr int kXcds = 8;
+constexpr int32_t kChunk = 128;  // mask entries a wave takes per cursor atomic
 constexpr int32_t kNone = 0x7FFFFFFF;
-constexpr int32_t kNoLeaf = 0x7FFFFFFF;
+constexpr uint32_t kMiss = 0xFFFFFFFFu;
 
-__device__ inline float box_entry(float4 lo, float4 hi, float3 inv, float3 oinv, float tbest)
+__device__ inline float box_entry(float lx, float ly, float lz, float hx, float hy, float hz, float3 inv,
+                                  float3 oinv, float tbest)
 {
-    const float x0 = fmaf(lo.x, inv.x, -oinv.x), x1 = fmaf(hi.x, inv.x, -oinv.x);
-    const float y0 = fmaf(lo.y, inv.y, -oinv.y), y1 = fmaf(hi.y, inv.y, -oinv.y);
-    const float z0 = fmaf(lo.z, inv.z, -oinv.z), z1 = fmaf(hi.z, inv.z, -oinv.z);
+    const float x0 = fmaf(lx, inv.x, -oinv.x), x1 = fmaf(hx, inv.x, -oinv.x);
+    const float y0 = fmaf(ly, inv.y, -oinv.y), y1 = fmaf(hy, inv.y, -oinv.y);
+    const float z0 = fmaf(lz, inv.z, -oinv.z), z1 = fmaf(hz, inv.z, -oinv.z);
     const float tmin = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
     const float tmax = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tbest));
     return tmin <= tmax ? tmin : __int_as_float(0x7f800000);
+}
+
+// sort key of child `slot`: entry distance (>= 0, so its bits are ordered) rounded down to a
+// multiple of 4 ulp, slot in the low two bits; kMiss if the box is missed or the slot empty
+__device__ inline uint32_t child_key(float t, int32_t code, uint32_t slot)
+{
+    return (t == __int_as_float(0x7f800000) || code == kBvhEmptySlot) ? kMiss
+                                                                      : ((__float_as_uint(t) & ~3u) | slot);
 }
 
 // reciprocal for slab tests only (rounding there is harmless; see the file comment)
@@ -83,17 +97,16 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
                                                         uint64_t* __restrict__ argmin,
                                                         int32_t* __restrict__ cursors)
 {
-    __shared__ int32_t s_node[kLdsDepth][kThreads];
-    __shared__ float s_t[kLdsDepth][kThreads];
-    int32_t p_node[kMaxDepth - kLdsDepth];
-    float p_t[kMaxDepth - kLdsDepth];
+    __shared__ uint64_t s_stk[kLdsDepth][kThreads];  // (t bits << 32) | child code
+    int32_t p_code[kMaxStack - kLdsDepth];
+    float p_t[kMaxStack - kLdsDepth];
 
     const BvhHeader* H = (const BvhHeader*)bvh;
     const int32_t nt = H->nt, root = H->root;
     const float pad = H->pad;
-    const BvhNode* __restrict__ nodes = (const BvhNode*)(bvh + 256);
+    const Bvh4Node* __restrict__ nodes = (const Bvh4Node*)(bvh + 256);
     const BvhTri* __restrict__ tris =
-        (const BvhTri*)(bvh + 256 + sizeof(BvhNode) * (size_t)(nt > 1 ? nt - 1 : 0));
+        (const BvhTri*)(bvh + 256 + sizeof(Bvh4Node) * (size_t)(nt > 1 ? nt - 1 : 1));
     const int32_t count = *count_p;
     const float inf = __int_as_float(0x7f800000);
     const int tid = threadIdx.x;
@@ -103,6 +116,7 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
     const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny;
     int xcd = (int)(blockIdx.x % kXcds);  // the range this wave takes voxels from
     int tried = 0;                        // ranges found exhausted
+    int32_t q_next = 0, q_end = 0;        // the wave's current chunk of the mask list
 
     int32_t vid = -1;
     uint32_t j = 0;
@@ -115,8 +129,19 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
     float tb = inf;
     int32_t bid = kNone;
     bool bfr = false;
-    int32_t node = -1, pend = kNoLeaf;
+    int32_t node = -1;
+    int32_t pfirst = 0, pcount = 0;  // pending leaf range
     int sp = 0;
+
+    auto push = [&](int32_t code, float t) {
+        if (sp < kLdsDepth) {
+            s_stk[sp][tid] = ((uint64_t)__float_as_uint(t) << 32) | (uint32_t)code;
+        } else {
+            p_code[sp - kLdsDepth] = code;
+            p_t[sp - kLdsDepth] = t;
+        }
+        ++sp;
+    };
 
     while (true) {
         // retire a finished ray; fold a finished voxel into its accumulators
@@ -140,36 +165,43 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
             }
             need = vid < 0;
         }
-        // wave-cooperative refill of voxels from this XCD's range, then the others'
+        // wave-cooperative refill: lanes take voxels from the wave's current chunk of the mask
+        // list; an empty chunk is replaced by one atomic on this XCD's cursor, and an
+        // exhausted range moves the wave on to the next XCD's range
         uint64_t needers = __ballot(need);
         while (needers && tried < kXcds) {
-            const int leader = __ffsll((unsigned long long)needers) - 1;
-            const int32_t lo = (int32_t)(((int64_t)count * xcd) / kXcds);
-            const int32_t hi = (int32_t)(((int64_t)count * (xcd + 1)) / kXcds);
-            int32_t base = 0;
-            if (lane == leader) base = atomicAdd(&cursors[xcd], (int32_t)__popcll(needers));
-            base = __shfl(base, leader) + lo;
-            if (need) {
-                const int32_t idx = base + (int32_t)__popcll(needers & lt_mask);
-                if (idx < hi) {
-                    vid = list[idx];
-                    need = false;
-                    j = 0;
-                    acc_d = inf;
-                    acc_h = 0u;
-                    acc_a = ~0ull;
-                    const uint32_t uv = (uint32_t)vid;
-                    const uint32_t row = uv / nx;
-                    const uint32_t i0 = uv - row * nx, i1 = row % ny, i2 = row / ny;
-                    o = make_float3(g.org[0] + g.h * ((float)i0 + 0.5f), g.org[1] + g.h * ((float)i1 + 0.5f),
-                                    g.org[2] + g.h * ((float)i2 + 0.5f));
+            if (q_next >= q_end) {
+                const int32_t lo = (int32_t)(((int64_t)count * xcd) / kXcds);
+                const int32_t hi = (int32_t)(((int64_t)count * (xcd + 1)) / kXcds);
+                int32_t base = 0;
+                if (lane == 0) base = atomicAdd(&cursors[xcd], kChunk);
+                base = __shfl(base, 0) + lo;
+                if (base >= hi) {
+                    xcd = (xcd + 1) % kXcds;
+                    ++tried;
+                    continue;
                 }
+                q_next = base;
+                q_end = min(base + kChunk, hi);
             }
+            const int32_t rank = (int32_t)__popcll(needers & lt_mask);
+            const int32_t take = min((int32_t)__popcll(needers), q_end - q_next);
+            if (need && rank < take) {
+                const int32_t idx = q_next + rank;
+                vid = list[idx];
+                need = false;
+                j = 0;
+                acc_d = inf;
+                acc_h = 0u;
+                acc_a = ~0ull;
+                const uint32_t uv = (uint32_t)vid;
+                const uint32_t row = uv / nx;
+                const uint32_t i0 = uv - row * nx, i1 = row % ny, i2 = row / ny;
+                o = make_float3(g.org[0] + g.h * ((float)i0 + 0.5f), g.org[1] + g.h * ((float)i1 + 0.5f),
+                                g.org[2] + g.h * ((float)i2 + 0.5f));
+            }
+            q_next += take;
             needers = __ballot(need);
-            if (needers) {  // this range is exhausted: move on to the next one
-                xcd = (xcd + 1) % kXcds;
-                ++tried;
-            }
         }
         if (need) alive = false;
         // start the next ray
@@ -181,47 +213,60 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
             bid = kNone;
             sp = 0;
             node = -1;
-            pend = kNoLeaf;
-            if (nt == 1) {
-                pend = ~root;
-                active = true;
-            } else if (nt > 1) {
-                node = root;
+            pcount = 0;
+            if (nt > 0) {
+                if (root >= 0) {
+                    node = root;
+                } else {
+                    pfirst = leaf_first(root);
+                    pcount = leaf_count(root);
+                }
                 active = true;
             }
         }
         if (__ballot(alive) == 0ull) break;
         if (!active) continue;
         // at most one triangle test ...
-        if (pend != kNoLeaf) {
-            test_leaf(tris, pend, o, w, pad, tb, bid, bfr);
-            pend = kNoLeaf;
+        if (pcount > 0) {
+            test_leaf(tris, pfirst, o, w, pad, tb, bid, bfr);
+            ++pfirst;
+            --pcount;
         }
         // ... and one node visit per iteration
         if (node >= 0) {
-            const BvhNode n = nodes[node];
-            const float ta = box_entry(n.a_lo, n.a_hi, inv, oinv, tb);
-            const float tc = box_entry(n.b_lo, n.b_hi, inv, oinv, tb);
-            const int32_t ca = __float_as_int(n.a_lo.w), cc = __float_as_int(n.b_lo.w);
-            const bool a_first = ta <= tc;
-            const int32_t c1 = a_first ? ca : cc, c2 = a_first ? cc : ca;  // near, far
-            const float t1 = a_first ? ta : tc, t2 = a_first ? tc : ta;
+            const Bvh4Node* N = nodes + node;
+            const float4 lx = N->lox, ly = N->loy, lz = N->loz, hx = N->hix, hy = N->hiy, hz = N->hiz;
+            const int4 ch = N->child;
+            uint32_t s0 = child_key(box_entry(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, inv, oinv, tb), ch.x, 0u);
+            uint32_t s1 = child_key(box_entry(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, inv, oinv, tb), ch.y, 1u);
+            uint32_t s2 = child_key(box_entry(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, inv, oinv, tb), ch.z, 2u);
+            uint32_t s3 = child_key(box_entry(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, inv, oinv, tb), ch.w, 3u);
+            // sorting network: s0 <= s1 <= s2 <= s3
+            uint32_t u;
+            u = min(s0, s1); s1 = max(s0, s1); s0 = u;
+            u = min(s2, s3); s3 = max(s2, s3); s2 = u;
+            u = min(s0, s2); s2 = max(s0, s2); s0 = u;
+            u = min(s1, s3); s3 = max(s1, s3); s1 = u;
+            u = min(s1, s2); s2 = max(s1, s2); s1 = u;
+            auto code_of = [&](uint32_t key) {
+                const uint32_t q = key & 3u;
+                return q == 0u ? ch.x : (q == 1u ? ch.y : (q == 2u ? ch.z : ch.w));
+            };
+            auto t_of = [](uint32_t key) { return __uint_as_float(key & ~3u); };
+            if (s3 != kMiss) push(code_of(s3), t_of(s3));
+            if (s2 != kMiss) push(code_of(s2), t_of(s2));
+            if (s1 != kMiss) push(code_of(s1), t_of(s1));
             node = -1;
-            // the near child goes to `node` (internal) or `pend` (leaf); the far one is pushed.
-            // A child that misses has t = inf, so a single hit is always the near one.
-            if (t1 != inf) {
-                if (c1 >= 0) node = c1;
-                else pend = ~c1;
-            }
-            if (t2 != inf) {
-                if (sp < kLdsDepth) {
-                    s_node[sp][tid] = c2;
-                    s_t[sp][tid] = t2;
+            if (s0 != kMiss) {
+                const int32_t c0 = code_of(s0);
+                if (c0 >= 0) {
+                    node = c0;
+                } else if (pcount == 0) {
+                    pfirst = leaf_first(c0);
+                    pcount = leaf_count(c0);
                 } else {
-                    p_node[sp - kLdsDepth] = c2;
-                    p_t[sp - kLdsDepth] = t2;
+                    push(c0, t_of(s0));
                 }
-                ++sp;
             }
         }
         // refill node / pending leaf from the stack
@@ -230,10 +275,11 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
             int32_t e;
             float t;
             if (top < kLdsDepth) {
-                e = s_node[top][tid];
-                t = s_t[top][tid];
+                const uint64_t v = s_stk[top][tid];
+                e = (int32_t)(uint32_t)v;
+                t = __uint_as_float((uint32_t)(v >> 32));
             } else {
-                e = p_node[top - kLdsDepth];
+                e = p_code[top - kLdsDepth];
                 t = p_t[top - kLdsDepth];
             }
             if (t > tb) {
@@ -243,14 +289,15 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
             if (e >= 0) {
                 node = e;
                 sp = top;
-            } else if (pend == kNoLeaf) {
-                pend = ~e;
+            } else if (pcount == 0) {
+                pfirst = leaf_first(e);
+                pcount = leaf_count(e);
                 sp = top;
             } else {
                 break;
             }
         }
-        if (node < 0 && pend == kNoLeaf && sp == 0) active = false;
+        if (node < 0 && pcount == 0 && sp == 0) active = false;
     }
 }
 
