@@ -29,6 +29,11 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=20000, help="masked voxels ray-sampled by the oracle")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain 1 GiB device copy three times (to scale HBM counters)")
+    p.add_argument("--traffic-kib", type=float, nargs=2, default=None, metavar=("FETCH", "WRITE"),
+                   help="FETCH_SIZE and WRITE_SIZE (KiB per ray-sampling dispatch, already scaled by the "
+                        "copy calibration) to report as roofline traffic")
     return p.parse_args()
 
 
@@ -123,6 +128,16 @@ def main():
     import torch
     from paper_2210_06160_amd import rtsdf, synth
 
+    if args.copy_calibration:
+        n = 1 << 30
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty(n, dtype=torch.uint8, device="cuda")
+        a.fill_(1)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n, "copy_calibration_bytes_written": n, "dispatches": 3}))
+        return
     sc = synth.scene_static()
     S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
     N = S.g.n
@@ -147,11 +162,15 @@ def main():
     launch_ms = stages["raysample"] / sc.frames
     # ray sampling: bound by plain ALU work and cache latency (no dense contraction, no
     # streaming); algorithmic ops per ray are the estimate stated in the design doc
-    ops_per_ray = 1400.0
+    ops_per_ray = 2500.0
     achieved = band * sc.rays * ops_per_ray / (launch_ms / 1e3) / 1e12
+    traffic = None
+    if args.traffic_kib:
+        traffic = round((args.traffic_kib[0] + args.traffic_kib[1]) * 1024.0)
     roof = {"kernel": "raysample", "bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
-            "unit": "T lane-ops/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
-            "launch_ms": round(launch_ms, 4), "units_per_launch": band * sc.rays}
+            "unit": "T lane-ops/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic,
+            "launch_ms": round(launch_ms, 4), "units_per_launch": band * sc.rays,
+            "ops_per_unit": ops_per_ray}
     jfa_ms = stages["jfa"]
     passes = len(sc.steps)
     jfa_gbs = 8.0 * N * passes / (jfa_ms / 1e3) / 1e9

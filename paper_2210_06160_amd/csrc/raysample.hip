@@ -37,6 +37,7 @@ constexpr int kLdsDepth = 12;
 constexpr int kMaxStack = 176;  // <= 3 pushes per level + 1; tree depth <= 56
 constexpr int kXcds = 8;
 constexpr int32_t kChunk = 128;  // mask entries a wave takes per cursor atomic
+constexpr int32_t kStartBatch = 12;  // idle lanes restarted together
 constexpr int32_t kNone = 0x7FFFFFFF;
 constexpr uint32_t kMiss = 0xFFFFFFFFu;
 
@@ -144,9 +145,14 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
     };
 
     while (true) {
+        // Lanes whose ray ended wait until kStartBatch of them (or the whole wave) can be
+        // retired, refilled and restarted together: that code is long (Philox, Marsaglia,
+        // set-up) and a wave pays for it whenever any lane runs it.
+        const int32_t idle = (int32_t)__popcll(__ballot(alive && !active));
+        const bool batch = idle >= kStartBatch || __ballot(active) == 0ull;
         // retire a finished ray; fold a finished voxel into its accumulators
         bool need = false;
-        if (alive && !active) {
+        if (batch && alive && !active) {
             if (vid >= 0) {
                 if (bid != kNone) {
                     acc_d = fminf(acc_d, tb);
@@ -205,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
         }
         if (need) alive = false;
         // start the next ray
-        if (alive && !active) {
+        if (batch && alive && !active) {
             w = sphere_direction(k0, k1, (uint32_t)vid, frame, j, obj);
             inv = make_float3(slab_rcp(w.x), slab_rcp(w.y), slab_rcp(w.z));
             oinv = make_float3(o.x * inv.x, o.y * inv.y, o.z * inv.z);
