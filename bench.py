@@ -31,10 +31,30 @@ def parse():
     p.add_argument("--cpu-sample", type=int, default=20000, help="masked voxels ray-sampled by the oracle")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy three times (to scale HBM counters)")
-    p.add_argument("--traffic-kib", type=float, nargs=2, default=None, metavar=("FETCH", "WRITE"),
-                   help="FETCH_SIZE and WRITE_SIZE (KiB per ray-sampling dispatch, already scaled by the "
-                        "copy calibration) to report as roofline traffic")
     return p.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "raysample_static_400x200x400_counters.md")
+TRAFFIC_SOURCES = ["raysample.hip", "sampling.h", "lbvh.hip", "internal.h"]
+
+
+def recorded_traffic():
+    """HBM-side bytes per ray-sampling dispatch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (scaled by the plain-copy calibration), or None when the kernel
+    sources have changed since those counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_sha256"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    csrc = os.path.join(ROOT, "paper_2210_06160_amd", "csrc")
+    sha = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in TRAFFIC_SOURCES)).hexdigest()
+    if fields.get("source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 class StageTimer:
@@ -164,9 +184,7 @@ def main():
     # streaming); algorithmic ops per ray are the estimate stated in the design doc
     ops_per_ray = 2500.0
     achieved = band * sc.rays * ops_per_ray / (launch_ms / 1e3) / 1e12
-    traffic = None
-    if args.traffic_kib:
-        traffic = round((args.traffic_kib[0] + args.traffic_kib[1]) * 1024.0)
+    traffic = recorded_traffic()
     roof = {"kernel": "raysample", "bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
             "unit": "T lane-ops/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic,
             "launch_ms": round(launch_ms, 4), "units_per_launch": band * sc.rays,
