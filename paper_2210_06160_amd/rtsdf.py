@@ -254,3 +254,63 @@ class StaticSDF:
             self.trace(f)
         self.combine()
         return self.fine
+
+
+class DeformSDF:
+    """The per-frame chain for a deforming mesh (section 2.5.1): every frame re-voxelizes,
+    re-floods, re-masks, rebuilds the hierarchy, ray-samples the mask and folds the frame
+    into the field with the decay rule of Eq. 1 (RTSDF_DECAY, `consume` resets the frame's
+    ray accumulators).  All frames' vertices are resident on the device.  frame(f) only
+    enqueues kernels and never synchronizes, so capture() can record each frame's chain
+    into a HIP graph once and replay() runs it; frame 0 also clears the accumulators.
+    """
+
+    def __init__(self, frame_verts, tris, dims, org, h, steps, band, rays, alpha=0.95, beta=None, bias=0.0,
+                 rng_key=0, device="cuda"):
+        self.g = make_grid(dims, org, h)
+        N = self.g.n
+        self.verts = torch.as_tensor(frame_verts, dtype=torch.float32).contiguous().to(device)
+        self.nframes = self.verts.shape[0]
+        self.tris = torch.as_tensor(tris, dtype=torch.int32).reshape(-1, 3).contiguous().to(device)
+        nt = self.tris.shape[0]
+        self.steps, self.band, self.rays = list(steps), int(band), int(rays)
+        self.alpha = float(alpha)
+        self.beta = float(h) / 2 if beta is None else float(beta)
+        self.bias, self.rng_key = float(bias), int(rng_key)
+        self.seeds = torch.empty(N, dtype=torch.int32, device=device)
+        self.scratch = torch.empty(N, dtype=torch.int32, device=device)
+        self.band_list = torch.empty(N, dtype=torch.int32, device=device)
+        self.band_count = torch.zeros(1, dtype=torch.int32, device=device)
+        self.dmin = torch.empty(N, dtype=torch.float32, device=device)
+        self.hits = torch.empty(N, dtype=torch.int32, device=device)
+        self.state = torch.zeros(N, dtype=torch.float32, device=device)
+        self.fine = torch.empty(N, dtype=torch.float32, device=device)
+        self.bvh = torch.empty(rtsdf_bvh_bytes(nt), dtype=torch.uint8, device=device)
+        wb = max(rtsdf_voxelize_work_bytes(nt), rtsdf_band_work_bytes(self.g), rtsdf_bvh_work_bytes(nt))
+        self.work = workspace(wb, device)
+        self.ray_work = workspace(rtsdf_raysample_work_bytes(N, self.rays), device)
+        self.graphs = {}
+        self.jfa_out = None
+
+    def frame(self, f):
+        v = self.verts[f]
+        if f == 0:
+            rtsdf_reset_accum(self.dmin, self.hits)
+        rtsdf_voxelize(v, self.tris, self.g, self.seeds, self.work)
+        self.jfa_out = rtsdf_jfa(self.seeds, self.scratch, self.g, self.steps)
+        rtsdf_band(self.jfa_out, self.g, self.band, self.band_list, self.band_count, self.work)
+        rtsdf_build_bvh(v, self.tris, self.g, self.bvh, self.work)
+        rtsdf_raysample(self.bvh, self.g, self.band_list, self.band_count, self.rays, self.rng_key, f, self.dmin,
+                        self.hits, self.ray_work)
+        rtsdf_combine(self.jfa_out, self.dmin, self.hits, self.g, self.band, self.beta, self.bias, DECAY,
+                      self.fine, alpha=self.alpha, first_frame=(f == 0), consume=True, state=self.state)
+
+    def capture(self, frames=None):
+        for f in (range(self.nframes) if frames is None else frames):
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr):
+                self.frame(f)
+            self.graphs[f] = gr
+
+    def replay(self, f):
+        self.graphs[f].replay()

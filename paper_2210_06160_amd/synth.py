@@ -176,6 +176,78 @@ def scene_tiny():
                  name="icosphere80-32^3")
 
 
+def torus_knot_tube(p=2, q=3, R=0.6, a=0.25, tube=0.08, nseg=500, nring=50, centre=(1.0, 0.5, 1.0)):
+    """Tube of radius `tube` around the (p, q) torus knot with radii R, a, lying in the
+    x-z plane (so its height is +-(a + tube) around centre[1]); nseg x nring vertices,
+    2 nseg nring triangles.  Returns (verts, tris, normals) in binary64 before rounding."""
+    phi = 2.0 * np.pi * np.arange(nseg) / nseg
+
+    def curve(f):
+        r = R + a * np.cos(q * f)
+        return np.stack([r * np.cos(p * f), -a * np.sin(q * f), r * np.sin(p * f)], -1)
+
+    def d1(f):
+        r = R + a * np.cos(q * f)
+        dr = -a * q * np.sin(q * f)
+        return np.stack([dr * np.cos(p * f) - r * p * np.sin(p * f), -a * q * np.cos(q * f),
+                         dr * np.sin(p * f) + r * p * np.cos(p * f)], -1)
+
+    eps = 1e-4
+    c = curve(phi)
+    T = d1(phi)
+    T /= np.linalg.norm(T, axis=1, keepdims=True)
+    Tn = d1(phi + eps)
+    Tn /= np.linalg.norm(Tn, axis=1, keepdims=True)
+    N = Tn - T                      # Frenet normal (the knot's curvature never vanishes)
+    N /= np.linalg.norm(N, axis=1, keepdims=True)
+    B = np.cross(T, N)
+    th = 2.0 * np.pi * np.arange(nring) / nring
+    nrm = (np.cos(th)[None, :, None] * N[:, None, :] + np.sin(th)[None, :, None] * B[:, None, :])
+    V = (c[:, None, :] + tube * nrm).reshape(-1, 3) + np.asarray(centre)
+    nrm = nrm.reshape(-1, 3)
+    T_ = []
+    for i in range(nseg):
+        for j in range(nring):
+            a0 = i * nring + j
+            a1 = i * nring + (j + 1) % nring
+            b0 = ((i + 1) % nseg) * nring + j
+            b1 = ((i + 1) % nseg) * nring + (j + 1) % nring
+            T_ += [(a0, b0, b1), (a0, b1, a1)]
+    tris = np.array(T_, np.int32)
+    if signed_volume(V, tris) < 0:
+        tris = tris[:, [0, 2, 1]].copy()
+    return V, tris, nrm
+
+
+def deform_frames(V, nrm, frames, amplitude=0.02, freqs=(2.0, 3.0, 5.0), periods=(60.0, 45.0, 30.0), seed=1):
+    """Vertices of each frame: V + n * sum_i (amplitude/3) sin(2 pi (f_i (u_i . V) + t/P_i) + phi_i)
+    along the undeformed normals n, with unit u_i and phases phi_i from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    u = rng.normal(size=(3, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=3)
+    out = np.empty((frames, len(V), 3), np.float32)
+    for t in range(frames):
+        d = np.zeros(len(V))
+        for i in range(3):
+            d += (amplitude / 3.0) * np.sin(2.0 * np.pi * (freqs[i] * (V @ u[i]) + t / periods[i]) + ph[i])
+        out[t] = (V + nrm * d[:, None]).astype(np.float32)
+    return out
+
+
+def scene_deform(dims=(400, 200, 400), frames=60):
+    """Deforming mesh over the box [0,2] x [0,1] x [0,2]: a (2,3) torus-knot tube (R 0.6,
+    a 0.25, tube radius 0.08, 500 x 50 segments: 25,000 vertices, 50,000 triangles) centred
+    at (1, 0.5, 1), displaced every frame by three sinusoids along its normals (amplitude
+    0.02).  Offsets n/2..1 plus one extra pass of 1, 4-voxel mask, 4 rays per masked voxel,
+    Eq. 1 decay with alpha 0.95.  `extra["frames"]` holds the per-frame vertices."""
+    V, tris, nrm = torus_knot_tube()
+    fr = deform_frames(V, nrm, frames)
+    h = 2.0 / dims[0]
+    return Scene(fr[0], tris, tuple(dims), (0.0, 0.0, 0.0), h, jfa_offsets(dims, extra=1), 4, 4, frames,
+                 name="torus-knot-50k-deforming-%dx%dx%d" % tuple(dims), extra={"frames": fr, "alpha": 0.95})
+
+
 def scene_static(dims=(400, 200, 400), nprims=200, seed=0):
     """Paper-shaped static scene over the box [0,2] x [0,1] x [0,2]: a ground quad at
     y = 0.05 (on a voxel face at the full resolution) plus `nprims` boxes, UV spheres and
