@@ -23,6 +23,24 @@ class Grid(ctypes.Structure):
                 ("org", ctypes.c_float * 3), ("h", ctypes.c_float)]
 
 
+class Shadow(ctypes.Structure):
+    """Receiver plane y = const; pixel (a, b) at (x0 + (a+1/2) dx, y, z0 + (b+1/2) dz)."""
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("x0", ctypes.c_float),
+                ("z0", ctypes.c_float), ("dx", ctypes.c_float), ("dz", ctypes.c_float), ("y", ctypes.c_float),
+                ("light", ctypes.c_float * 3), ("k", ctypes.c_float), ("steps", ctypes.c_int32),
+                ("smin", ctypes.c_float), ("smax", ctypes.c_float), ("t0", ctypes.c_float)]
+
+
+def make_shadow(width, height, x0, z0, dx, dz, y, light, k, steps, smin, smax, t0):
+    s = Shadow()
+    s.width, s.height = int(width), int(height)
+    s.x0, s.z0, s.dx, s.dz, s.y = float(x0), float(z0), float(dx), float(dz), float(y)
+    for a in range(3):
+        s.light[a] = float(light[a])
+    s.k, s.steps, s.smin, s.smax, s.t0 = float(k), int(steps), float(smin), float(smax), float(t0)
+    return s
+
+
 def make_grid(dims, org, h):
     g = Grid()
     g.nx, g.ny, g.nz = (int(d) for d in dims)
@@ -67,6 +85,11 @@ def lib():
         L.orc_combine.argtypes = [vp, vp, vp, Grid, vp, i64, i32, f32, f32, i32, f32, i32, vp, vp]
         L.orc_pack_id.argtypes = [i32, i32, i32]
         L.orc_pack_id.restype = i32
+        L.orc_shadow_forward.argtypes = [vp, Grid, ctypes.POINTER(Shadow), vp]
+        L.orc_shadow_backward.argtypes = [vp, Grid, ctypes.POINTER(Shadow), vp, vp]
+        L.orc_sdf_backward.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, Grid, i32, u64, u32, vp]
+        L.orc_sdf_backward.restype = ctypes.c_int
+        L.orc_sample.argtypes = [vp, Grid, vp, i64, vp, vp]
         _lib = L
     return _lib
 
@@ -239,3 +262,47 @@ def combine(seeds, dmin, hits, g, band_vox, beta, bias, mode, alpha=0.95, reset=
                       float(beta), float(bias), int(mode), float(alpha), int(bool(reset)),
                       _p(state), _p(fine))
     return fine, state
+
+
+def sample(fine, g, X):
+    """Trilinear value and positional gradient of the fine field at points X [n, 3]."""
+    f = np.ascontiguousarray(fine, np.float64)
+    X = np.ascontiguousarray(X, np.float64)
+    val = np.empty(len(X), np.float64)
+    grad = np.empty((len(X), 3), np.float64)
+    lib().orc_sample(_p(f), g, _p(X), len(X), _p(val), _p(grad))
+    return val, grad
+
+
+def shadow_forward(fine, g, s):
+    """Section 2.4 soft shadow by sphere tracing the fine field (binary64)."""
+    f = np.ascontiguousarray(fine, np.float64)
+    img = np.empty(s.width * s.height, np.float64)
+    lib().orc_shadow_forward(_p(f), g, ctypes.byref(s), _p(img))
+    return img
+
+
+def shadow_backward(fine, g, s, grad_img):
+    """(d img / d fine)^T grad_img by reverse-mode differentiation of the march (binary64)."""
+    f = np.ascontiguousarray(fine, np.float64)
+    gi = np.ascontiguousarray(grad_img, np.float64)
+    gf = np.zeros(len(f), np.float64)
+    lib().orc_shadow_backward(_p(f), g, ctypes.byref(s), _p(gi), _p(gf))
+    return gf
+
+
+def sdf_backward(grad_fine, hits, argmin, vids, bvh, verts, tris, g, x, seed, obj=0):
+    """Adjoint of the running-minimum fine field with respect to vertex positions
+    (binary64); hits/argmin are indexed like vids, grad_fine by voxel."""
+    gf = np.ascontiguousarray(grad_fine, np.float64)
+    h = np.ascontiguousarray(hits, np.uint32)
+    a = np.ascontiguousarray(argmin, np.uint64)
+    v = np.ascontiguousarray(vids, np.int32)
+    verts = np.ascontiguousarray(verts, np.float32)
+    tris = np.ascontiguousarray(tris, np.int32)
+    gv = np.zeros(3 * len(verts), np.float64)
+    bad = lib().orc_sdf_backward(_p(gf), _p(h), _p(a), _p(v), len(v), bvh.ptr, _p(verts), _p(tris), g,
+                                 int(x), int(seed), int(obj), _p(gv))
+    if bad:
+        raise RuntimeError("%d argmin rays found no hit" % bad)
+    return gv.reshape(-1, 3)

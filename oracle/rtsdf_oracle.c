@@ -700,3 +700,264 @@ void orc_combine(const int32_t* seeds, const float* dmin, const uint32_t* hits, 
         fine[q] = val - bias;
     }
 }
+
+/* ------------------------------------------------------------------------------------
+ * Soft shadows by sphere tracing the fine field (section 2.4).  The paper prints no
+ * formula; the reading used: from a receiver point P march towards the light along the
+ * unit direction l, starting at t = t0 (at least one voxel, section 2.5.3), for a fixed
+ * number of steps; each step samples s = trilinear(fine, P + t l), keeps
+ * res = min(res, k s / t) (penumbra estimate of the closest approach, section 2.4) and
+ * advances t by s clamped to [smin, smax] (section 2.5.2 caps the step at 0.05).  The
+ * pixel value is clamp(res, 0, 1) with res starting at 1.  Binary64 throughout.
+ * Trilinear sampling: grid coordinate g = (X - org)/h - 1/2 (voxel centres are integers),
+ * clamped to [0, n-1]; i0 = min(floor(g), n-2); f = g - i0; interpolate in x, then y, then
+ * z with a + f (b - a).
+ * ---------------------------------------------------------------------------------- */
+typedef struct {
+    int32_t width, height;  /* pixel (a, b): P = (x0 + (a+1/2) dx, y, z0 + (b+1/2) dz); img[b*width + a] */
+    float x0, z0, dx, dz, y;
+    float light[3];          /* unit direction towards the light */
+    float k;                 /* penumbra sharpness */
+    int32_t steps;
+    float smin, smax, t0;
+} orc_shadow;
+
+static double orc_fetch(const double* f, orc_grid g, int64_t i, int64_t j, int64_t k)
+{
+    return f[i + (int64_t)g.nx * (j + (int64_t)g.ny * k)];
+}
+
+/* value and gradient (with respect to the world position) of the trilinear interpolant */
+static double orc_trilinear(const double* f, orc_grid g, const double X[3], double grad[3])
+{
+    const int32_t n[3] = {g.nx, g.ny, g.nz};
+    int64_t i0[3];
+    double fr[3];
+    int inside[3];
+    for (int a = 0; a < 3; ++a) {
+        double c = (X[a] - (double)g.org[a]) / (double)g.h - 0.5;
+        inside[a] = c > 0.0 && c < (double)(n[a] - 1);
+        if (c < 0.0) c = 0.0;
+        if (c > (double)(n[a] - 1)) c = (double)(n[a] - 1);
+        int64_t b = (int64_t)floor(c);
+        if (b > n[a] - 2) b = n[a] - 2;
+        if (b < 0) b = 0;
+        i0[a] = b;
+        fr[a] = n[a] > 1 ? c - (double)b : 0.0;
+    }
+    const int64_t i1[3] = {n[0] > 1 ? i0[0] + 1 : i0[0], n[1] > 1 ? i0[1] + 1 : i0[1], n[2] > 1 ? i0[2] + 1 : i0[2]};
+    double c[2][2][2];
+    for (int z = 0; z < 2; ++z)
+        for (int y = 0; y < 2; ++y)
+            for (int x = 0; x < 2; ++x)
+                c[z][y][x] = orc_fetch(f, g, x ? i1[0] : i0[0], y ? i1[1] : i0[1], z ? i1[2] : i0[2]);
+    double cx[2][2], dcx[2][2];
+    for (int z = 0; z < 2; ++z)
+        for (int y = 0; y < 2; ++y) {
+            cx[z][y] = c[z][y][0] + fr[0] * (c[z][y][1] - c[z][y][0]);
+            dcx[z][y] = c[z][y][1] - c[z][y][0];
+        }
+    double cy[2], dcyx[2], dcyy[2];
+    for (int z = 0; z < 2; ++z) {
+        cy[z] = cx[z][0] + fr[1] * (cx[z][1] - cx[z][0]);
+        dcyx[z] = dcx[z][0] + fr[1] * (dcx[z][1] - dcx[z][0]);
+        dcyy[z] = cx[z][1] - cx[z][0];
+    }
+    const double v = cy[0] + fr[2] * (cy[1] - cy[0]);
+    if (grad) {
+        grad[0] = inside[0] ? (dcyx[0] + fr[2] * (dcyx[1] - dcyx[0])) / (double)g.h : 0.0;
+        grad[1] = inside[1] ? (dcyy[0] + fr[2] * (dcyy[1] - dcyy[0])) / (double)g.h : 0.0;
+        grad[2] = inside[2] ? (cy[1] - cy[0]) / (double)g.h : 0.0;
+    }
+    return v;
+}
+
+/* adds w * d(value)/d(corner values) into gf */
+static void orc_trilinear_scatter(double* gf, orc_grid g, const double X[3], double w)
+{
+    const int32_t n[3] = {g.nx, g.ny, g.nz};
+    int64_t i0[3], i1[3];
+    double fr[3];
+    for (int a = 0; a < 3; ++a) {
+        double c = (X[a] - (double)g.org[a]) / (double)g.h - 0.5;
+        if (c < 0.0) c = 0.0;
+        if (c > (double)(n[a] - 1)) c = (double)(n[a] - 1);
+        int64_t b = (int64_t)floor(c);
+        if (b > n[a] - 2) b = n[a] - 2;
+        if (b < 0) b = 0;
+        i0[a] = b;
+        i1[a] = n[a] > 1 ? b + 1 : b;
+        fr[a] = n[a] > 1 ? c - (double)b : 0.0;
+    }
+    for (int z = 0; z < 2; ++z)
+        for (int y = 0; y < 2; ++y)
+            for (int x = 0; x < 2; ++x) {
+                const double wt = (x ? fr[0] : 1.0 - fr[0]) * (y ? fr[1] : 1.0 - fr[1]) * (z ? fr[2] : 1.0 - fr[2]);
+                gf[(x ? i1[0] : i0[0]) + (int64_t)g.nx * ((y ? i1[1] : i0[1]) + (int64_t)g.ny * (z ? i1[2] : i0[2]))] +=
+                    w * wt;
+            }
+}
+
+/* trilinear value and positional gradient at n points X[3 n] (for tests) */
+void orc_sample(const double* fine, orc_grid g, const double* X, int64_t n, double* val, double* grad)
+{
+    for (int64_t q = 0; q < n; ++q) val[q] = orc_trilinear(fine, g, X + 3 * q, grad ? grad + 3 * q : NULL);
+}
+
+static void orc_pixel_origin(const orc_shadow* s, int32_t a, int32_t b, double P[3])
+{
+    P[0] = (double)s->x0 + ((double)a + 0.5) * (double)s->dx;
+    P[1] = (double)s->y;
+    P[2] = (double)s->z0 + ((double)b + 0.5) * (double)s->dz;
+}
+
+/* one pixel's march; records t_m and s_m (arrays of s->steps) when given.  Returns the
+ * clamped image value; *istar = index of the first step attaining the minimum, or -1 when
+ * the value is the initial 1 or is clamped at 0 (no gradient). */
+static double orc_march(const double* f, orc_grid g, const orc_shadow* s, const double P[3], double* tm,
+                        double* sm, int* istar)
+{
+    double t = (double)s->t0, res = 1.0;
+    int best = -1;
+    for (int m = 0; m < s->steps; ++m) {
+        double X[3];
+        for (int a = 0; a < 3; ++a) X[a] = P[a] + t * (double)s->light[a];
+        const double v = orc_trilinear(f, g, X, NULL);
+        if (tm) tm[m] = t;
+        if (sm) sm[m] = v;
+        const double r = (double)s->k * v / t;
+        if (r < res) {
+            res = r;
+            best = m;
+        }
+        double step = v;
+        if (step < (double)s->smin) step = (double)s->smin;
+        if (step > (double)s->smax) step = (double)s->smax;
+        t += step;
+    }
+    if (res <= 0.0) {
+        *istar = -1;
+        return 0.0;
+    }
+    *istar = best;
+    return res;
+}
+
+void orc_shadow_forward(const double* fine, orc_grid g, const orc_shadow* s, double* img)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t p = 0; p < (int64_t)s->width * s->height; ++p) {
+        double P[3];
+        int istar;
+        orc_pixel_origin(s, (int32_t)(p % s->width), (int32_t)(p / s->width), P);
+        img[p] = orc_march(fine, g, s, P, NULL, NULL, &istar);
+    }
+}
+
+/* grad_fine += (d img / d fine)^T grad_img, by reverse-mode differentiation of the march */
+void orc_shadow_backward(const double* fine, orc_grid g, const orc_shadow* s, const double* grad_img,
+                         double* grad_fine)
+{
+    double* tm = (double*)malloc(sizeof(double) * (size_t)s->steps);
+    double* sm = (double*)malloc(sizeof(double) * (size_t)s->steps);
+    for (int64_t p = 0; p < (int64_t)s->width * s->height; ++p) {
+        if (grad_img[p] == 0.0) continue;
+        double P[3];
+        int istar;
+        orc_pixel_origin(s, (int32_t)(p % s->width), (int32_t)(p / s->width), P);
+        orc_march(fine, g, s, P, tm, sm, &istar);
+        if (istar < 0) continue;
+        const double kk = (double)s->k;
+        double sbar = grad_img[p] * kk / tm[istar];
+        double tbar = -grad_img[p] * kk * sm[istar] / (tm[istar] * tm[istar]);
+        for (int m = istar; m >= 0; --m) {
+            double X[3], gr[3];
+            for (int a = 0; a < 3; ++a) X[a] = P[a] + tm[m] * (double)s->light[a];
+            orc_trilinear(fine, g, X, gr);
+            orc_trilinear_scatter(grad_fine, g, X, sbar);
+            tbar += sbar * ((gr[0] * (double)s->light[0] + gr[1] * (double)s->light[1]) + gr[2] * (double)s->light[2]);
+            if (m == 0) break;
+            /* t_m = t_{m-1} + clamp(s_{m-1}, smin, smax) */
+            const double prev = sm[m - 1];
+            sbar = (prev > (double)s->smin && prev < (double)s->smax) ? tbar : 0.0;
+        }
+    }
+    free(tm);
+    free(sm);
+}
+
+/* ------------------------------------------------------------------------------------
+ * Adjoint of the fine field with respect to vertex positions (running-minimum mode).
+ * Only a masked grid point with at least one hit depends continuously on the vertices:
+ * fine = sign * t - bias, with t the distance along the ray named by its argmin record.
+ * Moving vertex k of the hit triangle by d moves the plane at the hit point by b_k d, so
+ * dt/dv_k = b_k n / (n . w) (n the plane normal, b the barycentrics of the hit), holding
+ * the discrete state (seeds, mask, which ray and triangle give the minimum, the sign) fixed.
+ * grad_verts[3 v + a] += grad_fine[p] * sign * dt/dv; binary64.
+ * ---------------------------------------------------------------------------------- */
+int orc_sdf_backward(const double* grad_fine, const uint32_t* hits, const uint64_t* argmin,
+                     const int32_t* vids, int64_t n, const void* bvh, const float* verts,
+                     const int32_t* tris, orc_grid g, int32_t x, uint64_t seed, uint32_t obj,
+                     double* grad_verts)
+{
+    int bad = 0;
+    for (int64_t q = 0; q < n; ++q) {
+        const int64_t p = vids[q];
+        const uint32_t hc = hits[q];
+        if (hc == 0 || grad_fine[p] == 0.0) continue;
+        const uint32_t code = (uint32_t)(argmin[q] & 0xFFFFFFFFu);
+        const uint32_t frame = code / (uint32_t)x, j = code % (uint32_t)x;
+        float o[3], w[3], t;
+        int32_t tri;
+        int fr;
+        orc_voxel_centre(g, p, o);
+        orc_direction(seed, (uint32_t)p, frame, j, obj, w);
+        if (!orc_bvh_closest(bvh, o, w, &t, &tri, &fr)) {
+            ++bad;
+            continue;
+        }
+        const double sign = (hc >> 16) > (hc & 0xFFFFu) ? -1.0 : 1.0;
+        double V[3][3], O[3], W[3];
+        for (int v = 0; v < 3; ++v)
+            for (int a = 0; a < 3; ++a) V[v][a] = verts[3 * (int64_t)tris[3 * tri + v] + a];
+        for (int a = 0; a < 3; ++a) {
+            O[a] = o[a];
+            W[a] = w[a];
+        }
+        double e1[3], e2[3], nn[3], T[3];
+        for (int a = 0; a < 3; ++a) {
+            e1[a] = V[1][a] - V[0][a];
+            e2[a] = V[2][a] - V[0][a];
+            T[a] = O[a] - V[0][a];
+        }
+        nn[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        nn[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        nn[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        const double nw = nn[0] * W[0] + nn[1] * W[1] + nn[2] * W[2];
+        const double th = -(nn[0] * T[0] + nn[1] * T[1] + nn[2] * T[2]) / nw;  /* exact plane hit */
+        double H[3], r[3];
+        for (int a = 0; a < 3; ++a) H[a] = O[a] + th * W[a];
+        /* barycentrics of H: areas of the sub-triangles against n */
+        double bary[3];
+        const double nn2 = nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2];
+        for (int v = 0; v < 3; ++v) {
+            const double* A = V[(v + 1) % 3];
+            const double* B = V[(v + 2) % 3];
+            double ab[3], ah[3];
+            for (int a = 0; a < 3; ++a) {
+                ab[a] = B[a] - A[a];
+                ah[a] = H[a] - A[a];
+            }
+            r[0] = ab[1] * ah[2] - ab[2] * ah[1];
+            r[1] = ab[2] * ah[0] - ab[0] * ah[2];
+            r[2] = ab[0] * ah[1] - ab[1] * ah[0];
+            bary[v] = (r[0] * nn[0] + r[1] * nn[1] + r[2] * nn[2]) / nn2;
+        }
+        const double scale = grad_fine[p] * sign / nw;
+        for (int v = 0; v < 3; ++v) {
+            const int64_t vi = tris[3 * tri + v];
+            for (int a = 0; a < 3; ++a) grad_verts[3 * vi + a] += scale * bary[v] * nn[a];
+        }
+    }
+    return bad;
+}

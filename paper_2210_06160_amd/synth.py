@@ -248,6 +248,84 @@ def scene_deform(dims=(400, 200, 400), frames=60):
                  name="torus-knot-50k-deforming-%dx%dx%d" % tuple(dims), extra={"frames": fr, "alpha": 0.95})
 
 
+def ellipsoid_sdf(points, semi_axes, centre, iters=64):
+    """Exact signed distance (negative inside) from points [n, 3] to an axis-aligned
+    ellipsoid, by bisection on the monotone root of sum_i (e_i y_i / (t + e_i^2))^2 = 1
+    (Eberly, "Distance from a point to an ellipse, an ellipsoid, or a hyperellipsoid",
+    2013); binary64.  Points exactly on a symmetry plane of the smallest axis are not
+    handled specially (a grid offset by half a voxel never produces them)."""
+    e = np.asarray(semi_axes, np.float64)
+    y = np.abs(np.asarray(points, np.float64) - np.asarray(centre, np.float64))
+    e2 = e * e
+    lo = np.full(len(y), -e2.min() + 1e-300)
+    hi = np.maximum(np.linalg.norm(y, axis=1) * e.max(), 1e-12)
+
+    def G(t):
+        return (((e * y) / (t[:, None] + e2)) ** 2).sum(1)
+
+    while True:
+        bad = G(hi) > 1.0
+        if not bad.any():
+            break
+        hi[bad] *= 2.0
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        g = G(mid)
+        lo = np.where(g > 1.0, mid, lo)
+        hi = np.where(g > 1.0, hi, mid)
+    t = 0.5 * (lo + hi)
+    x = e2 * y / (t[:, None] + e2)
+    d = np.linalg.norm(x - y, axis=1)
+    inside = ((y / e) ** 2).sum(1) < 1.0
+    return np.where(inside, -d, d)
+
+
+_GRID_SDF_CACHE = {}
+
+
+def _grid_ellipsoid_sdf(dims, h, semi_axes, centre):
+    """ellipsoid_sdf at every voxel centre (x fastest), float32.  The distance depends on
+    |p - centre| per axis only, so it is evaluated once per distinct offset triple."""
+    key = (dims, h, tuple(semi_axes), tuple(centre))
+    if key not in _GRID_SDF_CACHE:
+        axes = [np.abs((np.arange(n) + 0.5) * h - c) for n, c in zip(dims, centre)]
+        uniq = [np.unique(a, return_inverse=True) for a in axes]
+        ux, uy, uz = (u[0] for u in uniq)
+        Z, Y, X = np.meshgrid(uz, uy, ux, indexing="ij")
+        pts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+        d = ellipsoid_sdf(pts, semi_axes, (0.0, 0.0, 0.0)).reshape(len(uz), len(uy), len(ux))
+        ix, iy, iz = (u[1] for u in uniq)
+        _GRID_SDF_CACHE[key] = d[iz[:, None, None], iy[None, :, None], ix[None, None, :]].astype(np.float32).ravel()
+    return _GRID_SDF_CACHE[key]
+
+
+def shadow_setup(h, width=512, height=512, plane_y=0.1, light=(0.35, 1.0, 0.25), k=8.0, steps=64,
+                 smax=0.05):
+    """Receiver plane y = plane_y over [0,1]^2 seen by a width x height image, a fixed
+    directional light, penumbra k, a fixed number of sphere-tracing steps, steps clamped
+    to [h/2, smax], start one voxel off the receiver (section 2.4, 2.5.2, 2.5.3)."""
+    l = np.asarray(light, np.float64)
+    l = l / np.linalg.norm(l)
+    return dict(width=width, height=height, x0=0.0, z0=0.0, dx=1.0 / width, dz=1.0 / height, y=plane_y,
+                light=tuple(float(a) for a in l), k=k, steps=steps, smin=h / 2.0, smax=smax, t0=h)
+
+
+def scene_grad(dims=(128, 128, 128), subdiv=5, image=512):
+    """Differentiation workload: icosphere (subdivision 5: 10,242 vertices, 20,480
+    triangles, radius 0.3) centred in the unit cube on a 128^3 grid; offsets 64..1; 2-voxel
+    mask; 16 rays; one frame; running minimum.  Targets: the exact signed distance of the
+    ellipsoid with semi-axes (0.35, 0.3, 0.25) at the voxel centres, and a 512 x 512
+    image uniform in [0, 1) from default_rng(3); the soft shadow of shadow_setup()."""
+    v, t = icosphere(subdiv, 0.3, (0.5, 0.5, 0.5))
+    h = 1.0 / dims[0]
+    target = _grid_ellipsoid_sdf(tuple(dims), h, (0.35, 0.3, 0.25), (0.5, 0.5, 0.5))
+    timg = np.random.default_rng(3).uniform(0.0, 1.0, size=image * image).astype(np.float32)
+    return Scene(v, t, tuple(dims), (0.0, 0.0, 0.0), h, jfa_offsets(dims), 2, 16, 1,
+                 name="icosphere-20480-%dx%dx%d" % tuple(dims),
+                 extra={"target": target, "target_img": timg,
+                        "shadow": shadow_setup(h, width=image, height=image)})
+
+
 def scene_static(dims=(400, 200, 400), nprims=200, seed=0):
     """Paper-shaped static scene over the box [0,2] x [0,1] x [0,2]: a ground quad at
     y = 0.05 (on a voxel face at the full resolution) plus `nprims` boxes, UV spheres and
