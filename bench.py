@@ -29,6 +29,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-deform", action="store_true", help="skip the deforming-mesh (graph) measurement")
+    p.add_argument("--no-grad", action="store_true", help="skip the gradient-workload measurement")
     p.add_argument("--cpu-sample", type=int, default=20000, help="masked voxels ray-sampled by the oracle")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy three times (to scale HBM counters)")
@@ -124,6 +125,50 @@ def deform_bench(torch, rtsdf, synth):
     return {"workload": sc.name, "frames": sc.frames, "triangles": int(len(sc.tris)),
             "ms_per_frame_graph": round(graph * 1e3, 3), "ms_per_frame_eager": round(eager * 1e3, 3),
             "sdf_voxels_per_s_graph": round(N / graph, 1), "masked_voxels_last_frame": int(D.band_count.item())}
+
+
+def grad_bench(torch, rtsdf, synth, reps=20):
+    """Gradient workload (icosphere of 20,480 triangles on 128^3, 16 rays, 512^2 soft shadow):
+    forward = the SDF chain + shadow image + loss, backward = shadow adjoint + SDF term +
+    vertex adjoint.  Medians over `reps` repetitions after 3 warm-ups, HIP events on the
+    launch stream."""
+    import statistics
+    sc = synth.scene_grad()
+    S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
+    sh = rtsdf.make_shadow(**sc.extra["shadow"])
+    tgt = torch.from_numpy(sc.extra["target"].astype("float32")).cuda()
+    timg = torch.from_numpy(sc.extra["target_img"]).cuda().reshape(sh.height, sh.width)
+    img = torch.empty(sh.height, sh.width, dtype=torch.float32, device="cuda")
+    gverts = torch.zeros_like(S.verts)
+    rec = {k: [] for k in ("sdf_fwd", "shadow_fwd", "loss", "shadow_bwd", "vertex_bwd", "fwd", "bwd")}
+    for it in range(reps + 3):
+        T = StageTimer(torch)
+        T.mark("start")
+        fine = S.run()
+        T.mark("sdf_fwd")
+        rtsdf.rtsdf_shadow_forward(fine, S.g, sh, img)
+        T.mark("shadow_fwd")
+        loss = ((fine - tgt) ** 2).sum() + ((img - timg) ** 2).sum()
+        T.mark("loss")
+        gfine = 2.0 * (fine - tgt)
+        rtsdf.rtsdf_shadow_backward(fine, S.g, sh, 2.0 * (img - timg), gfine)
+        T.mark("shadow_bwd")
+        gverts.zero_()
+        S.backward(gfine, gverts)
+        T.mark("vertex_bwd")
+        torch.cuda.synchronize()
+        if it >= 3:
+            d = T.durations()
+            for k in ("sdf_fwd", "shadow_fwd", "loss", "shadow_bwd", "vertex_bwd"):
+                rec[k].append(d[k])
+            rec["fwd"].append(d["sdf_fwd"] + d["shadow_fwd"] + d["loss"])
+            rec["bwd"].append(d["shadow_bwd"] + d["vertex_bwd"])
+    med = {k: statistics.median(v) for k, v in rec.items()}
+    n = int(S.band_count.item())
+    return {"workload": sc.name + "-shadow-%dx%d" % (sh.width, sh.height), "reps": reps,
+            "ms": {k: round(v, 4) for k, v in med.items()}, "bwd_over_fwd": round(med["bwd"] / med["fwd"], 4),
+            "masked_voxels": n, "loss": float(loss.item()),
+            "shadow_samples_per_s_fwd": round(sh.width * sh.height * sh.steps / (med["shadow_fwd"] / 1e3), 1)}
 
 
 def cpu_baseline(sc, sample):
@@ -243,6 +288,8 @@ def main():
     }
     if not args.no_deform:
         out["deform"] = deform_bench(torch, rtsdf, synth)
+    if not args.no_grad:
+        out["grad"] = grad_bench(torch, rtsdf, synth)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample)
     print(json.dumps(out))

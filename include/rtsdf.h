@@ -144,8 +144,8 @@ rtsdf_status rtsdf_reset_accum(float* dmin, uint32_t* hits, uint64_t* argmin, in
  *   band_list/band_count  rtsdf_band output; band_capacity HOST bound on the count
  *   dmin [N] float, hits [N] uint32, argmin [N] uint64 or NULL: accumulated in place
  *   obj  object index (< 2^24) mixed into the counter; 0 for a single scene
- *   work [rtsdf_raysample_work_bytes(band_capacity, rays_per_voxel)]: a work cursor and the
- *        frame's ray directions (12 bytes per ray); nothing is carried between calls
+ *   work [rtsdf_raysample_work_bytes(band_capacity, rays_per_voxel)]: work cursors;
+ *        nothing is carried between calls
  * The listed voxels must be distinct (rtsdf_band lists are).
  * Errors: E_ARG, E_RANGE (rays_per_voxel outside [1, 65535], obj >= 2^24), E_SIZE.
  * ------------------------------------------------------------------------------------- */
@@ -177,6 +177,73 @@ rtsdf_status rtsdf_combine(const int32_t* seeds, float* dmin, uint32_t* hits, rt
                            int32_t band_vox, float beta, float bias, int32_t mode, float alpha,
                            int32_t first_frame, int32_t consume, float* state, float* fine,
                            void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Soft shadows by sphere tracing the fine field (section 2.4; step bounds of section
+ * 2.5.2, start offset of section 2.5.3).  The receiver is the plane y = `y`; pixel (a, b)
+ * (a < width along x, b < height along z; img[b * width + a]) starts at
+ * P = (x0 + (a + 1/2) dx, y, z0 + (b + 1/2) dz) and marches towards the light along the
+ * unit vector `light`: t = t0, res = 1; each of `steps` steps samples s = fine at P + t l
+ * (trilinear over the grid points, the sample position clamped to the grid's box of
+ * centres), sets res = min(res, k s / t) and advances t by s clamped to [smin, smax].
+ * The pixel is clamp(res, 0, 1).  Binary32 arithmetic.
+ * ------------------------------------------------------------------------------------- */
+#define RTSDF_MAX_SHADOW_STEPS 256
+#define RTSDF_MAX_IMAGE 16384
+
+typedef struct rtsdf_shadow {
+    int32_t width, height;  /* pixels, each in [0, 16384] */
+    float x0, z0, dx, dz;   /* pixel lattice on the receiver plane */
+    float y;                /* receiver plane height */
+    float light[3];         /* unit direction towards the light */
+    float k;                /* penumbra sharpness, > 0 */
+    int32_t steps;          /* march steps, [1, 256] */
+    float smin, smax;       /* step clamp, 0 < smin <= smax */
+    float t0;               /* start offset along the light direction, > 0 */
+} rtsdf_shadow;
+
+/* rtsdf_shadow_forward -- the shadow image of the fine field.
+ *   fine [N] float (rtsdf_combine output)     img [height * width] float out
+ * Errors: E_ARG (null pointers, bad grid, non-finite or out-of-range parameters),
+ * E_RANGE (image size, steps). */
+rtsdf_status rtsdf_shadow_forward(const float* fine, rtsdf_grid g, rtsdf_shadow s, float* img,
+                                  void* stream);
+
+/* rtsdf_shadow_backward -- reverse-mode derivative of rtsdf_shadow_forward:
+ * grad_fine += (d img / d fine)^T grad_img.  Per pixel, m* is the first step attaining the
+ * minimum of k s / t; pixels whose value is the initial 1 or is clamped at 0 contribute
+ * nothing.  Otherwise the adjoint of res = k s_m* / t_m* is carried back over m = m*..0
+ * through t_{m+1} = t_m + clamp(s_m) (the clamp passes the derivative only strictly
+ * inside [smin, smax]) and through each trilinear sample to its 8 grid points.
+ *   fine [N] float (the forward's input)   grad_img [height * width] float
+ *   grad_fine [N] float, ACCUMULATED with binary32 atomic adds (summation order varies)
+ * Errors: as rtsdf_shadow_forward. */
+rtsdf_status rtsdf_shadow_backward(const float* fine, rtsdf_grid g, rtsdf_shadow s,
+                                   const float* grad_img, float* grad_fine, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * rtsdf_backward -- derivative of the running-minimum fine field (RTSDF_ACCUM, section
+ * 2.1) with respect to vertex positions, the discrete state held fixed (seeds, mask, the
+ * argmin ray of each grid point, its closest triangle and the sign).  A masked grid point
+ * with hits has fine = sign * t - bias, t the distance along the ray its argmin record
+ * names; that ray is traced again (same direction and hit rule as rtsdf_raysample) to its
+ * closest triangle, and vertex k of that triangle receives
+ *   grad_fine[p] * sign * b_k * n / (n . w)
+ * (n = (v1 - v0) x (v2 - v0), w the ray direction, b the barycentrics of the hit).  Grid
+ * points outside the mask or without hits contribute nothing (the coarse field is
+ * piecewise constant in the vertices).
+ *   grad_fine [N] float; hits [N], argmin [N]: the accumulators after the last frame
+ *   band_list/band_count/band_capacity: the rtsdf_band output used by the forward
+ *   bvh: rtsdf_build_bvh output for these tris; tris [nt*3] int32 (indices < nv)
+ *   rays_per_voxel, rng_key, obj: as passed to rtsdf_raysample
+ *   grad_verts [nv*3] float, ACCUMULATED with binary32 atomic adds
+ * Errors: E_ARG, E_RANGE (rays_per_voxel, obj, nv/nt < 0).
+ * ------------------------------------------------------------------------------------- */
+rtsdf_status rtsdf_backward(const float* grad_fine, const uint32_t* hits, const uint64_t* argmin,
+                            const int32_t* band_list, const int32_t* band_count,
+                            int64_t band_capacity, const void* bvh, const int32_t* tris,
+                            int32_t nv, int32_t nt, rtsdf_grid g, int32_t rays_per_voxel,
+                            uint64_t rng_key, uint32_t obj, float* grad_verts, void* stream);
 
 #ifdef __cplusplus
 }

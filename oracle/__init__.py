@@ -90,6 +90,7 @@ def lib():
         L.orc_sdf_backward.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, Grid, i32, u64, u32, vp]
         L.orc_sdf_backward.restype = ctypes.c_int
         L.orc_sample.argtypes = [vp, Grid, vp, i64, vp, vp]
+        L.orc_shadow_margin.argtypes = [vp, Grid, ctypes.POINTER(Shadow), vp, vp]
         _lib = L
     return _lib
 
@@ -289,6 +290,16 @@ def shadow_backward(fine, g, s, grad_img):
     gf = np.zeros(len(f), np.float64)
     lib().orc_shadow_backward(_p(f), g, ctypes.byref(s), _p(gi), _p(gf))
     return gf
+
+
+def shadow_margin(fine, g, s):
+    """Per-pixel distances of the march's discrete decisions from flipping: (r_margin,
+    s_margin) -- see orc_shadow_margin."""
+    f = np.ascontiguousarray(fine, np.float64)
+    rm = np.empty(s.width * s.height, np.float64)
+    sm = np.empty(s.width * s.height, np.float64)
+    lib().orc_shadow_margin(_p(f), g, ctypes.byref(s), _p(rm), _p(sm))
+    return rm, sm
 
 
 def sdf_backward(grad_fine, hits, argmin, vids, bvh, verts, tris, g, x, seed, obj=0):

@@ -886,6 +886,52 @@ void orc_shadow_backward(const double* fine, orc_grid g, const orc_shadow* s, co
     free(sm);
 }
 
+/* Decision margins of each pixel's march, for comparing implementations that round
+ * differently: r_margin = the least |k s_m / t_m - res| over the steps other than the
+ * minimising one, together with the distances of res from the 0 clamp and from the initial
+ * value 1; s_margin = the least distance of a sample s_m (m before the minimising step)
+ * from the clamp bounds smin and smax.  A pixel whose margins exceed the rounding error
+ * of another implementation takes the same discrete path there. */
+void orc_shadow_margin(const double* fine, orc_grid g, const orc_shadow* s, double* r_margin, double* s_margin)
+{
+#pragma omp parallel
+    {
+        double* tm = (double*)malloc(sizeof(double) * (size_t)s->steps);
+        double* sm = (double*)malloc(sizeof(double) * (size_t)s->steps);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t p = 0; p < (int64_t)s->width * s->height; ++p) {
+            double P[3];
+            int istar;
+            orc_pixel_origin(s, (int32_t)(p % s->width), (int32_t)(p / s->width), P);
+            const double img = orc_march(fine, g, s, P, tm, sm, &istar);
+            /* rmin = least ratio over all steps (not capped by the initial 1) */
+            double rmin = HUGE_VAL, rm = HUGE_VAL, sgap = HUGE_VAL;
+            int mmin = 0;
+            for (int m = 0; m < s->steps; ++m) {
+                const double r = (double)s->k * sm[m] / tm[m];
+                if (r < rmin) {
+                    rmin = r;
+                    mmin = m;
+                }
+            }
+            for (int m = 0; m < s->steps; ++m) {
+                const double r = (double)s->k * sm[m] / tm[m];
+                if (m != mmin) rm = fmin(rm, fabs(r - rmin));
+            }
+            rm = fmin(rm, fabs(rmin));
+            rm = fmin(rm, fabs(1.0 - rmin));
+            const int last = istar < 0 ? s->steps : istar;
+            for (int m = 0; m < last; ++m)
+                sgap = fmin(sgap, fmin(fabs(sm[m] - (double)s->smin), fabs(sm[m] - (double)s->smax)));
+            (void)img;
+            r_margin[p] = rm;
+            s_margin[p] = sgap;
+        }
+        free(tm);
+        free(sm);
+    }
+}
+
 /* ------------------------------------------------------------------------------------
  * Adjoint of the fine field with respect to vertex positions (running-minimum mode).
  * Only a masked grid point with at least one hit depends continuously on the vertices:

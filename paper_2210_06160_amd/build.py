@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librtsdf.so")
-SOURCES = ["capi.cpp", "scan.hip", "voxelize.hip", "jfa.hip", "combine.hip", "lbvh.hip", "raysample.hip"]
+SOURCES = ["capi.cpp", "scan.hip", "voxelize.hip", "jfa.hip", "combine.hip", "lbvh.hip", "raysample.hip",
+           "shadow.hip", "backward.hip"]
 ARCH = os.environ.get("RTSDF_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-ffp-contract=off",

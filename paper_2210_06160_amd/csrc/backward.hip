@@ -1,0 +1,173 @@
+// Derivative of the running-minimum fine field with respect to vertex positions (section
+// 2.1 ray sampling, differentiated with the discrete state held fixed).
+//
+// A masked grid point with hits holds fine = sign * t - bias, where t is the distance along
+// the ray its argmin record names (frame * x + j, with t's bits above).  The ray is rebuilt
+// from that record (same counter-based direction as the forward) and traced again to its
+// closest hit, the least (t, triangle index), which by the exact-culling argument of the
+// traversal helpers is the triangle the forward found.  Moving vertex k of that triangle by
+// d moves the plane at the hit point by b_k d, so dt/dv_k = b_k n / (n . w).
+//
+// One lane per listed grid point (grid-stride); a closest-hit traversal of the 4-wide
+// hierarchy with a per-lane stack in LDS that spills to private memory; the gradient is
+// scattered to the three vertices with binary32 atomic adds.
+#include "traverse.h"
+
+namespace rtsdf {
+
+namespace {
+
+constexpr int kThreads = 128;
+constexpr int kLdsDepth = 8;
+
+__global__ __launch_bounds__(kThreads) void k_sdf_backward(
+    const char* __restrict__ bvh, const rtsdf_grid g, const int32_t* __restrict__ list,
+    const int32_t* __restrict__ count_p, const float* __restrict__ grad_fine,
+    const uint32_t* __restrict__ hits, const uint64_t* __restrict__ argmin,
+    const int32_t* __restrict__ tri_index, int32_t x, uint32_t k0, uint32_t k1, uint32_t obj,
+    float* __restrict__ grad_verts)
+{
+    __shared__ uint64_t s_stk[kLdsDepth][kThreads];  // (t bits << 32) | child code
+    int32_t p_code[kMaxStack - kLdsDepth];
+    float p_t[kMaxStack - kLdsDepth];
+
+    const BvhHeader* H = (const BvhHeader*)bvh;
+    const int32_t nt = H->nt, root = H->root;
+    const float pad = H->pad;
+    if (nt == 0) return;
+    const Bvh4Node* __restrict__ nodes = (const Bvh4Node*)(bvh + 256);
+    const BvhTri* __restrict__ tris =
+        (const BvhTri*)(bvh + 256 + sizeof(Bvh4Node) * (size_t)(nt > 1 ? nt - 1 : 1));
+    const int32_t count = *count_p;
+    const float inf = __int_as_float(0x7f800000);
+    const int tid = threadIdx.x;
+
+    for (int64_t q = (int64_t)blockIdx.x * kThreads + tid; q < count; q += (int64_t)gridDim.x * kThreads) {
+        const int32_t vid = list[q];
+        const uint32_t hc = hits[vid];
+        const float gf = grad_fine[vid];
+        if (hc == 0u || gf == 0.0f) continue;
+        const uint32_t code = (uint32_t)argmin[vid];
+        const uint32_t frame = code / (uint32_t)x, j = code - frame * (uint32_t)x;
+        uint32_t ci, cj, ck;
+        const float3 o = voxel_centre(g, vid, ci, cj, ck);
+        const float3 w = sphere_direction(k0, k1, (uint32_t)vid, frame, j, obj);
+        const float3 inv = make_float3(slab_rcp(w.x), slab_rcp(w.y), slab_rcp(w.z));
+        const float3 oinv = make_float3(o.x * inv.x, o.y * inv.y, o.z * inv.z);
+
+        float tb = inf;
+        int32_t bid = kNone, bpos = -1;
+        int sp = 0;
+        auto push = [&](int32_t c, float t) {
+            if (sp < kLdsDepth) {
+                s_stk[sp][tid] = ((uint64_t)__float_as_uint(t) << 32) | (uint32_t)c;
+            } else {
+                p_code[sp - kLdsDepth] = c;
+                p_t[sp - kLdsDepth] = t;
+            }
+            ++sp;
+        };
+        int32_t cur = root;
+        while (true) {
+            if (cur >= 0) {
+                const Bvh4Node* N = nodes + cur;
+                const float4 lx = N->lox, ly = N->loy, lz = N->loz, hx = N->hix, hy = N->hiy, hz = N->hiz;
+                const int4 ch = N->child;
+                uint32_t s0 = child_key(box_entry(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, inv, oinv, tb), ch.x, 0u);
+                uint32_t s1 = child_key(box_entry(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, inv, oinv, tb), ch.y, 1u);
+                uint32_t s2 = child_key(box_entry(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, inv, oinv, tb), ch.z, 2u);
+                uint32_t s3 = child_key(box_entry(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, inv, oinv, tb), ch.w, 3u);
+                sort4(s0, s1, s2, s3);
+                auto code_of = [&](uint32_t key) {
+                    const uint32_t sl = key & 3u;
+                    return sl == 0u ? ch.x : (sl == 1u ? ch.y : (sl == 2u ? ch.z : ch.w));
+                };
+                auto t_of = [](uint32_t key) { return __uint_as_float(key & ~3u); };
+                if (s3 != kMiss) push(code_of(s3), t_of(s3));
+                if (s2 != kMiss) push(code_of(s2), t_of(s2));
+                if (s1 != kMiss) push(code_of(s1), t_of(s1));
+                if (s0 != kMiss) {
+                    cur = code_of(s0);
+                    continue;
+                }
+            } else {
+                const int32_t first = leaf_first(cur), cnt = leaf_count(cur);
+                for (int32_t i = 0; i < cnt; ++i) {
+                    const float4 a = tris[first + i].v0, b = tris[first + i].v1, c = tris[first + i].v2;
+                    bool fr = false;
+                    const float t = hit_triangle(o, w, make_float3(a.x, a.y, a.z), make_float3(b.x, b.y, b.z),
+                                                 make_float3(c.x, c.y, c.z), pad, fr);
+                    const int32_t id = __float_as_int(a.w);
+                    if (t > 0.0f && (t < tb || (t == tb && id < bid))) {
+                        tb = t;
+                        bid = id;
+                        bpos = first + i;
+                    }
+                }
+            }
+            // next entry whose box may still hold a hit no farther than the best so far
+            cur = kBvhEmptySlot;
+            while (sp > 0) {
+                const int top = --sp;
+                int32_t e;
+                float t;
+                if (top < kLdsDepth) {
+                    const uint64_t v = s_stk[top][tid];
+                    e = (int32_t)(uint32_t)v;
+                    t = __uint_as_float((uint32_t)(v >> 32));
+                } else {
+                    e = p_code[top - kLdsDepth];
+                    t = p_t[top - kLdsDepth];
+                }
+                if (t <= tb) {
+                    cur = e;
+                    break;
+                }
+            }
+            if (cur == kBvhEmptySlot) break;
+        }
+        if (bpos < 0) continue;
+
+        const float4 a = tris[bpos].v0, b = tris[bpos].v1, c = tris[bpos].v2;
+        const float3 v0 = make_float3(a.x, a.y, a.z);
+        const float3 e1 = make_float3(b.x - a.x, b.y - a.y, b.z - a.z);
+        const float3 e2 = make_float3(c.x - a.x, c.y - a.y, c.z - a.z);
+        const float3 n = cross3(e1, e2);
+        const float nw = dot3(n, w);
+        // barycentrics of the hit (Moller-Trumbore u, v)
+        const float3 P = cross3(w, e2);
+        const float inv_det = 1.0f / dot3(e1, P);
+        const float3 T = make_float3(o.x - v0.x, o.y - v0.y, o.z - v0.z);
+        const float u = dot3(T, P) * inv_det;
+        const float v = dot3(w, cross3(T, e1)) * inv_det;
+        const float bary[3] = {(1.0f - u) - v, u, v};
+        const float sign = (hc >> 16) > (hc & 0xFFFFu) ? -1.0f : 1.0f;
+        const float scale = gf * sign / nw;
+        const int32_t* tv = tri_index + 3 * (int64_t)bid;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float* gv = grad_verts + 3 * (int64_t)tv[k];
+            const float s = scale * bary[k];
+            unsafeAtomicAdd(gv + 0, s * n.x);
+            unsafeAtomicAdd(gv + 1, s * n.y);
+            unsafeAtomicAdd(gv + 2, s * n.z);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t sdf_backward(const float* grad_fine, const uint32_t* hits, const uint64_t* argmin,
+                        const int32_t* list, const int32_t* count, int64_t capacity, const void* bvh,
+                        const int32_t* tris, const rtsdf_grid& g, int32_t x, uint64_t key, uint32_t obj,
+                        float* grad_verts, hipStream_t s)
+{
+    if (capacity <= 0) return hipSuccess;
+    const int64_t want = ceil_div(capacity, kThreads);
+    const unsigned groups = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, persistent_groups(kThreads)));
+    hipLaunchKernelGGL(k_sdf_backward, dim3(groups), dim3(kThreads), 0, s, (const char*)bvh, g, list, count,
+                       grad_fine, hits, argmin, tris, x, (uint32_t)key, (uint32_t)(key >> 32), obj, grad_verts);
+    return hipGetLastError();
+}
+
+}  // namespace rtsdf

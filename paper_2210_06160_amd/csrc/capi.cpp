@@ -47,6 +47,20 @@ rtsdf_status check_grid(const rtsdf_grid& g)
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
+rtsdf_status check_shadow(const rtsdf_shadow& s)
+{
+    if (s.width < 0 || s.height < 0 || s.width > RTSDF_MAX_IMAGE || s.height > RTSDF_MAX_IMAGE)
+        return fail(RTSDF_E_RANGE, "image %d x %d outside [0, %d]^2", s.width, s.height, RTSDF_MAX_IMAGE);
+    if (s.steps < 1 || s.steps > RTSDF_MAX_SHADOW_STEPS)
+        return fail(RTSDF_E_RANGE, "steps %d outside [1, %d]", s.steps, RTSDF_MAX_SHADOW_STEPS);
+    const float v[] = {s.x0, s.z0, s.dx, s.dz, s.y, s.light[0], s.light[1], s.light[2], s.k, s.smin, s.smax, s.t0};
+    for (float f : v)
+        if (!std::isfinite(f)) return fail(RTSDF_E_ARG, "shadow parameters must be finite");
+    if (!(s.k > 0.0f) || !(s.t0 > 0.0f) || !(s.smin > 0.0f) || !(s.smax >= s.smin))
+        return fail(RTSDF_E_ARG, "need k > 0, t0 > 0 and 0 < smin <= smax");
+    return RTSDF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -176,6 +190,46 @@ rtsdf_status rtsdf_combine(const int32_t* seeds, float* dmin, uint32_t* hits, rt
     return device(rtsdf::combine(seeds, dmin, hits, g, band_vox, beta, bias, mode, alpha, first_frame, consume,
                                  state, fine, as_stream(stream)),
                   "combine");
+}
+
+rtsdf_status rtsdf_shadow_forward(const float* fine, rtsdf_grid g, rtsdf_shadow s, float* img, void* stream)
+{
+    if (rtsdf_status st = check_grid(g)) return st;
+    if (rtsdf_status st = check_shadow(s)) return st;
+    if (!fine || !img) return fail(RTSDF_E_ARG, "NULL pointer");
+    return device(rtsdf::shadow_forward(fine, g, s, img, as_stream(stream)), "shadow_forward");
+}
+
+rtsdf_status rtsdf_shadow_backward(const float* fine, rtsdf_grid g, rtsdf_shadow s, const float* grad_img,
+                                   float* grad_fine, void* stream)
+{
+    if (rtsdf_status st = check_grid(g)) return st;
+    if (rtsdf_status st = check_shadow(s)) return st;
+    if (!fine || !grad_img || !grad_fine) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (fine == grad_fine) return fail(RTSDF_E_ARG, "fine and grad_fine must not alias");
+    return device(rtsdf::shadow_backward(fine, g, s, grad_img, grad_fine, as_stream(stream)), "shadow_backward");
+}
+
+rtsdf_status rtsdf_backward(const float* grad_fine, const uint32_t* hits, const uint64_t* argmin,
+                            const int32_t* band_list, const int32_t* band_count, int64_t band_capacity,
+                            const void* bvh, const int32_t* tris, int32_t nv, int32_t nt, rtsdf_grid g,
+                            int32_t rays_per_voxel, uint64_t rng_key, uint32_t obj, float* grad_verts,
+                            void* stream)
+{
+    if (rtsdf_status st = check_grid(g)) return st;
+    if (nv < 0 || nt < 0 || nt > (1 << 26)) return fail(RTSDF_E_RANGE, "nv, nt outside [0, 2^26]");
+    if (!grad_fine || !hits || !argmin || !band_list || !band_count || !bvh)
+        return fail(RTSDF_E_ARG, "NULL pointer");
+    if (nt > 0 && (!tris || !grad_verts || nv == 0)) return fail(RTSDF_E_ARG, "tris or grad_verts is NULL");
+    if (rays_per_voxel < 1 || rays_per_voxel > RTSDF_MAX_RAYS)
+        return fail(RTSDF_E_RANGE, "rays_per_voxel %d outside [1, %d]", rays_per_voxel, RTSDF_MAX_RAYS);
+    if (band_capacity < 0 || band_capacity > rtsdf::nvox(g))
+        return fail(RTSDF_E_RANGE, "band_capacity outside [0, N]");
+    if (obj >= (1u << 24)) return fail(RTSDF_E_RANGE, "obj %u >= 2^24", obj);
+    if (nt == 0) return ok();
+    return device(rtsdf::sdf_backward(grad_fine, hits, argmin, band_list, band_count, band_capacity, bvh, tris, g,
+                                      rays_per_voxel, rng_key, obj, grad_verts, as_stream(stream)),
+                  "backward");
 }
 
 }  // extern "C"

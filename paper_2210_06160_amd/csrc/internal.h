@@ -58,6 +58,15 @@ hipError_t combine(const int32_t* seeds, float* dmin, uint32_t* hits, const rtsd
                    int32_t first_frame, int32_t consume, float* state, float* fine,
                    hipStream_t s);
 
+hipError_t shadow_forward(const float* fine, const rtsdf_grid& g, const rtsdf_shadow& s, float* img,
+                          hipStream_t st);
+hipError_t shadow_backward(const float* fine, const rtsdf_grid& g, const rtsdf_shadow& s,
+                           const float* grad_img, float* grad_fine, hipStream_t st);
+hipError_t sdf_backward(const float* grad_fine, const uint32_t* hits, const uint64_t* argmin,
+                        const int32_t* list, const int32_t* count, int64_t capacity, const void* bvh,
+                        const int32_t* tris, const rtsdf_grid& g, int32_t x, uint64_t key, uint32_t obj,
+                        float* grad_verts, hipStream_t s);
+
 // ---- BVH blob layout (lbvh.hip writes it, raysample.hip reads it) ----------------------
 // [header 256 B][4-wide nodes: max(nt-1, 1) x Bvh4Node][triangles: nt x BvhTri]
 // A 4-wide node is stored at the index of the binary radix-tree node it was collapsed

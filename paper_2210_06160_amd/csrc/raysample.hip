@@ -26,7 +26,7 @@
 // every triangle box is widened by 2*pad while a hit's computed point must lie within pad
 // of its triangle's box, so a box holding a hit is never culled and the result equals the
 // brute-force least (t, triangle index).
-#include "sampling.h"
+#include "traverse.h"
 
 namespace rtsdf {
 
@@ -34,38 +34,9 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kLdsDepth = 12;
-constexpr int kMaxStack = 176;  // <= 3 pushes per level + 1; tree depth <= 56
 constexpr int kXcds = 8;
 constexpr int32_t kChunk = 128;  // mask entries a wave takes per cursor atomic
 constexpr int32_t kStartBatch = 12;  // idle lanes restarted together
-constexpr int32_t kNone = 0x7FFFFFFF;
-constexpr uint32_t kMiss = 0xFFFFFFFFu;
-
-__device__ inline float box_entry(float lx, float ly, float lz, float hx, float hy, float hz, float3 inv,
-                                  float3 oinv, float tbest)
-{
-    const float x0 = fmaf(lx, inv.x, -oinv.x), x1 = fmaf(hx, inv.x, -oinv.x);
-    const float y0 = fmaf(ly, inv.y, -oinv.y), y1 = fmaf(hy, inv.y, -oinv.y);
-    const float z0 = fmaf(lz, inv.z, -oinv.z), z1 = fmaf(hz, inv.z, -oinv.z);
-    const float tmin = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
-    const float tmax = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tbest));
-    return tmin <= tmax ? tmin : __int_as_float(0x7f800000);
-}
-
-// sort key of child `slot`: entry distance (>= 0, so its bits are ordered) rounded down to a
-// multiple of 4 ulp, slot in the low two bits; kMiss if the box is missed or the slot empty
-__device__ inline uint32_t child_key(float t, int32_t code, uint32_t slot)
-{
-    return (t == __int_as_float(0x7f800000) || code == kBvhEmptySlot) ? kMiss
-                                                                      : ((__float_as_uint(t) & ~3u) | slot);
-}
-
-// reciprocal for slab tests only (rounding there is harmless; see the file comment)
-__device__ inline float slab_rcp(float a)
-{
-    return __builtin_amdgcn_rcpf(fabsf(a) < 1e-20f ? copysignf(1e-20f, a) : a);
-}
-
 __device__ inline void test_leaf(const BvhTri* __restrict__ tris, int32_t pos, float3 o, float3 w,
                                  float pad, float& tb, int32_t& bid, bool& bfr)
 {
@@ -247,13 +218,7 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
             uint32_t s1 = child_key(box_entry(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, inv, oinv, tb), ch.y, 1u);
             uint32_t s2 = child_key(box_entry(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, inv, oinv, tb), ch.z, 2u);
             uint32_t s3 = child_key(box_entry(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, inv, oinv, tb), ch.w, 3u);
-            // sorting network: s0 <= s1 <= s2 <= s3
-            uint32_t u;
-            u = min(s0, s1); s1 = max(s0, s1); s0 = u;
-            u = min(s2, s3); s3 = max(s2, s3); s2 = u;
-            u = min(s0, s2); s2 = max(s0, s2); s0 = u;
-            u = min(s1, s3); s3 = max(s1, s3); s1 = u;
-            u = min(s1, s2); s2 = max(s1, s2); s1 = u;
+            sort4(s0, s1, s2, s3);
             auto code_of = [&](uint32_t key) {
                 const uint32_t q = key & 3u;
                 return q == 0u ? ch.x : (q == 1u ? ch.y : (q == 2u ? ch.z : ch.w));

@@ -4,7 +4,9 @@ Each `rtsdf_*` function marshals torch CUDA tensors into device pointers and the
 HIP stream and calls the C entry point of the same name; all computation happens in the
 HIP kernels.  There is no fallback: if the library is missing or a call fails, an
 exception is raised.  `StaticSDF` chains the calls into the paper's static pipeline
-(voxelize -> jump flood -> mask -> BVH -> frames of ray sampling -> combine).
+(voxelize -> jump flood -> mask -> BVH -> frames of ray sampling -> combine), `DeformSDF`
+the per-frame chain of a deforming mesh, and `SDF` / `SoftShadow` are autograd Functions
+whose backward passes call the adjoint entry points.
 """
 import ctypes
 import os
@@ -28,6 +30,23 @@ class Grid(ctypes.Structure):
     @property
     def n(self):
         return self.nx * self.ny * self.nz
+
+
+class Shadow(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("x0", ctypes.c_float),
+                ("z0", ctypes.c_float), ("dx", ctypes.c_float), ("dz", ctypes.c_float), ("y", ctypes.c_float),
+                ("light", ctypes.c_float * 3), ("k", ctypes.c_float), ("steps", ctypes.c_int32),
+                ("smin", ctypes.c_float), ("smax", ctypes.c_float), ("t0", ctypes.c_float)]
+
+
+def make_shadow(width, height, x0, z0, dx, dz, y, light, k, steps, smin, smax, t0):
+    s = Shadow()
+    s.width, s.height, s.steps = int(width), int(height), int(steps)
+    s.x0, s.z0, s.dx, s.dz, s.y = float(x0), float(z0), float(dx), float(dz), float(y)
+    for a in range(3):
+        s.light[a] = float(light[a])
+    s.k, s.smin, s.smax, s.t0 = float(k), float(smin), float(smax), float(t0)
+    return s
 
 
 def make_grid(dims, org, h):
@@ -62,6 +81,9 @@ def lib():
             "rtsdf_raysample_work_bytes": ([i64, i32], sz),
             "rtsdf_raysample": ([vp, Grid, vp, vp, i64, i32, u64, u32, u32, vp, vp, vp, vp, sz, vp], i32),
             "rtsdf_combine": ([vp, vp, vp, Grid, i32, f32, f32, i32, f32, i32, i32, vp, vp, vp], i32),
+            "rtsdf_shadow_forward": ([vp, Grid, Shadow, vp, vp], i32),
+            "rtsdf_shadow_backward": ([vp, Grid, Shadow, vp, vp, vp], i32),
+            "rtsdf_backward": ([vp, vp, vp, vp, vp, i64, vp, vp, i32, i32, Grid, i32, u64, u32, vp, vp], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -74,7 +96,7 @@ def lib():
 EXPORTED = ["rtsdf_last_error", "rtsdf_abi_version", "rtsdf_voxelize_work_bytes", "rtsdf_voxelize",
             "rtsdf_jfa", "rtsdf_band_work_bytes", "rtsdf_band", "rtsdf_bvh_bytes", "rtsdf_bvh_work_bytes",
             "rtsdf_build_bvh", "rtsdf_reset_accum", "rtsdf_raysample_work_bytes", "rtsdf_raysample",
-            "rtsdf_combine"]
+            "rtsdf_combine", "rtsdf_shadow_forward", "rtsdf_shadow_backward", "rtsdf_backward"]
 
 
 def _ptr(t, dtype=None):
@@ -185,13 +207,35 @@ def rtsdf_combine(seeds, dmin, hits, grid, band_vox, beta, bias, mode, fine, alp
                                _ptr(fine, torch.float32), _stream(stream)), "rtsdf_combine")
 
 
+def rtsdf_shadow_forward(fine, grid, shadow, img, stream=None):
+    _check(lib().rtsdf_shadow_forward(_ptr(fine, torch.float32), grid, shadow, _ptr(img, torch.float32),
+                                      _stream(stream)), "rtsdf_shadow_forward")
+
+
+def rtsdf_shadow_backward(fine, grid, shadow, grad_img, grad_fine, stream=None):
+    """grad_fine is accumulated into."""
+    _check(lib().rtsdf_shadow_backward(_ptr(fine, torch.float32), grid, shadow, _ptr(grad_img, torch.float32),
+                                       _ptr(grad_fine, torch.float32), _stream(stream)), "rtsdf_shadow_backward")
+
+
+def rtsdf_backward(grad_fine, hits, argmin, band_list, band_count, bvh, tris, nv, grid, rays_per_voxel, rng_key,
+                   grad_verts, obj=0, band_capacity=None, stream=None):
+    """grad_verts [nv, 3] float32 is accumulated into."""
+    cap = band_list.numel() if band_capacity is None else int(band_capacity)
+    _check(lib().rtsdf_backward(_ptr(grad_fine, torch.float32), _ptr(hits, torch.int32),
+                                _ptr(argmin, torch.int64), _ptr(band_list, torch.int32),
+                                _ptr(band_count, torch.int32), cap, _ptr(bvh), _ptr(tris, torch.int32),
+                                int(nv), tris.shape[0], grid, int(rays_per_voxel), int(rng_key) & (2 ** 64 - 1),
+                                int(obj), _ptr(grad_verts, torch.float32), _stream(stream)), "rtsdf_backward")
+
+
 class StaticSDF:
     """Device buffers and the call chain for one static scene (sections 2.1-2.3).
 
     run() = voxelize, jump flood, mask, BVH, `frames` x ray sampling (running minimum),
-    combine.  Buffers are allocated in __init__, except the ray-direction workspace, which
-    mask() sizes from the mask count (one device-to-host read of the count; it grows only
-    when a larger mask appears).
+    combine.  Buffers are allocated in __init__; mask() reads the mask count back to the
+    host once (it bounds the ray-sampling and adjoint launches).  set_verts() replaces the
+    vertex positions in place (same triangle list) for optimisation loops.
     """
 
     def __init__(self, verts, tris, dims, org, h, steps, band, rays, frames, beta=None, bias=0.0,
@@ -219,6 +263,9 @@ class StaticSDF:
         self.band_n = 0
         self.device = device
         self.jfa_out = None
+
+    def set_verts(self, verts):
+        self.verts.copy_(verts.reshape(-1, 3))
 
     def voxelize(self):
         rtsdf_voxelize(self.verts, self.tris, self.g, self.seeds, self.work)
@@ -254,6 +301,55 @@ class StaticSDF:
             self.trace(f)
         self.combine()
         return self.fine
+
+    def backward(self, grad_fine, grad_verts=None):
+        """dL/dverts of the last run() given dL/dfine (running-minimum mode)."""
+        if self.argmin is None:
+            raise RtsdfError("the vertex adjoint needs the argmin records (keep_argmin=True)")
+        if grad_verts is None:
+            grad_verts = torch.zeros_like(self.verts)
+        rtsdf_backward(grad_fine.contiguous(), self.hits, self.argmin, self.band_list, self.band_count, self.bvh,
+                       self.tris, self.verts.shape[0], self.g, self.rays, self.rng_key, grad_verts,
+                       band_capacity=self.band_n)
+        return grad_verts
+
+
+class SDF(torch.autograd.Function):
+    """fine = SDF.apply(verts, S): runs the static pipeline of StaticSDF `S` on `verts`
+    ([nv, 3] float32, on the GPU) and returns a copy of the fine field.  The backward is
+    the vertex adjoint through each grid point's argmin ray (rtsdf_backward)."""
+
+    @staticmethod
+    def forward(ctx, verts, S):
+        S.set_verts(verts.detach())
+        fine = S.run().clone()
+        ctx.S = S
+        return fine
+
+    @staticmethod
+    def backward(ctx, grad_fine):
+        return ctx.S.backward(grad_fine), None
+
+
+class SoftShadow(torch.autograd.Function):
+    """img = SoftShadow.apply(fine, grid, shadow): the soft-shadow image of the fine field
+    (section 2.4), [height, width] float32.  The backward is rtsdf_shadow_backward."""
+
+    @staticmethod
+    def forward(ctx, fine, grid, shadow):
+        fine = fine.detach().contiguous()
+        img = torch.empty(shadow.height, shadow.width, dtype=torch.float32, device=fine.device)
+        rtsdf_shadow_forward(fine, grid, shadow, img)
+        ctx.save_for_backward(fine)
+        ctx.grid, ctx.shadow = grid, shadow
+        return img
+
+    @staticmethod
+    def backward(ctx, grad_img):
+        (fine,) = ctx.saved_tensors
+        grad_fine = torch.zeros_like(fine)
+        rtsdf_shadow_backward(fine, ctx.grid, ctx.shadow, grad_img.contiguous(), grad_fine)
+        return grad_fine, None, None
 
 
 class DeformSDF:

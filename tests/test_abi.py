@@ -91,6 +91,46 @@ def test_host_validation(L):
     assert lib.rtsdf_reset_accum(fake(), fake(), None, -1, None) == E_RANGE
 
 
+def shadow_params(L, **kw):
+    p = dict(width=16, height=16, x0=0.0, z0=0.0, dx=0.05, dz=0.05, y=0.1, light=(0.0, 1.0, 0.0), k=8.0,
+             steps=64, smin=0.05, smax=0.05, t0=0.1)
+    p.update(kw)
+    return L.make_shadow(**p)
+
+
+def test_host_validation_adjoints(L):
+    lib = L.lib()
+    g = L.make_grid((8, 8, 8), (0, 0, 0), 0.1)
+    E_ARG, E_RANGE = -1, -2
+    fwd, bwd = lib.rtsdf_shadow_forward, lib.rtsdf_shadow_backward
+    for kw, code in [(dict(steps=0), E_RANGE), (dict(steps=257), E_RANGE), (dict(width=-1), E_RANGE),
+                     (dict(height=16385), E_RANGE), (dict(k=0.0), E_ARG), (dict(t0=0.0), E_ARG),
+                     (dict(smin=0.0), E_ARG), (dict(smax=0.01), E_ARG), (dict(x0=float("nan")), E_ARG),
+                     (dict(light=(0.0, float("inf"), 0.0)), E_ARG)]:
+        s = shadow_params(L, **kw)
+        assert fwd(fake(), g, s, fake(0x2000), None) == code, kw
+        assert bwd(fake(), g, s, fake(0x2000), fake(0x3000), None) == code, kw
+    s = shadow_params(L)
+    assert fwd(None, g, s, fake(0x2000), None) == E_ARG
+    assert fwd(fake(), L.make_grid((0, 8, 8), (0, 0, 0), 0.1), s, fake(0x2000), None) == E_RANGE
+    assert bwd(fake(), g, s, fake(0x2000), fake(), None) == E_ARG   # grad_fine aliases fine
+    assert bwd(fake(), g, s, None, fake(0x3000), None) == E_ARG
+    # vertex adjoint
+    b = lib.rtsdf_backward
+    args = lambda **kw: [kw.get("gf", fake()), fake(), fake(), fake(), fake(), kw.get("cap", 10), fake(),
+                         kw.get("tris", fake()), kw.get("nv", 3), kw.get("nt", 1), g, kw.get("rays", 4), 0,
+                         kw.get("obj", 0), kw.get("gv", fake()), None]
+    assert b(*args(rays=0)) == E_RANGE
+    assert b(*args(rays=65536)) == E_RANGE
+    assert b(*args(obj=1 << 24)) == E_RANGE
+    assert b(*args(cap=513)) == E_RANGE
+    assert b(*args(nt=-1)) == E_RANGE
+    assert b(*args(gf=None)) == E_ARG
+    assert b(*args(gv=None)) == E_ARG
+    assert b(*args(tris=None)) == E_ARG
+    assert b(*args(nt=0, tris=None, gv=None)) == 0          # no triangles: nothing to do
+
+
 def test_workspace_queries(L):
     lib = L.lib()
     g = L.make_grid((400, 200, 400), (0, 0, 0), 0.005)

@@ -1,0 +1,289 @@
+"""GPU (HIP, gfx950) soft-shadow march and adjoints versus the binary64 oracle, through
+the C ABI, plus the autograd Functions built on them.
+
+Bars (the oracle computes in binary64, the kernels in binary32):
+  * shadow image: |img_gpu - img_oracle| <= 1e-4 per pixel (pixel values lie in [0, 1]; a
+    64-step march accumulates t with 64 binary32 additions and samples the field at points
+    rounded to binary32, about 1e-6 relative each, so 1e-4 leaves a wide margin);
+  * shadow adjoint: the march's discrete choices (minimising step, clamp flags) are only
+    compared where the oracle's decision margins exceed what binary32 rounding can move
+    (r_margin > 1e-4, s_margin > 1e-5; other pixels get zero image gradient), then
+    grad_fine is compared element by element, |diff| <= 1e-3 |g| + 1e-4 max|g|
+    (binary32 atomics sum in a varying order);
+  * vertex adjoint: the integer state is compared bit-exactly first (seeds, mask, hits,
+    argmin), then grad_verts element by element, |diff| <= 1e-3 |g| + 1e-4 max|g| (the
+    1 / (n . w) factor of grazing rays amplifies binary32 rounding).
+Cases: a 48^3 sphere field with 64^2 and ragged 61x37 images, the 128^3 ellipsoid field
+with the 512^2 image of the gradient workload, and the full gradient workload (icosphere of
+20,480 triangles on 128^3, 16 rays, 2-voxel mask).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2210_06160_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2210_06160_amd import rtsdf
+    rtsdf.lib()
+    return rtsdf
+
+
+def centres(dims, h):
+    nx, ny, nz = dims
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return np.stack([(i.ravel() + 0.5) * h, (j.ravel() + 0.5) * h, (k.ravel() + 0.5) * h], 1)
+
+
+def sphere_field(dims, h, C=(0.5, 0.5, 0.5), r=0.15):
+    return (np.linalg.norm(centres(dims, h) - np.asarray(C), axis=1) - r).astype(np.float32)
+
+
+def gpu_img(R, fine, g, s):
+    import torch
+    img = torch.empty(s.height, s.width, dtype=torch.float32, device="cuda")
+    R.rtsdf_shadow_forward(torch.from_numpy(fine).cuda(), g, s, img)
+    torch.cuda.synchronize()
+    return img.cpu().numpy().ravel()
+
+
+def gpu_shadow_bwd(R, fine, g, s, gi):
+    import torch
+    gf = torch.zeros(len(fine), dtype=torch.float32, device="cuda")
+    R.rtsdf_shadow_backward(torch.from_numpy(fine).cuda(), g, s,
+                            torch.from_numpy(gi.astype(np.float32)).cuda(), gf)
+    torch.cuda.synchronize()
+    return gf.cpu().numpy()
+
+
+def close(a, b, rtol=1e-3, arel=1e-4):
+    b = np.asarray(b, np.float64)
+    tol = rtol * np.abs(b) + arel * np.abs(b).max()
+    err = np.abs(np.asarray(a, np.float64) - b)
+    bad = err > tol
+    assert not bad.any(), "%d of %d elements differ; worst %g vs tol %g" % (
+        bad.sum(), bad.size, err[bad].max(), tol[bad][np.argmax(err[bad])])
+
+
+def shadow_cases():
+    return [("sphere48-64x64", (48, 48, 48), 64, 64), ("sphere48-61x37", (48, 48, 48), 61, 37),
+            ("sphere40x24x56-128x96", (40, 24, 56), 128, 96)]
+
+
+@pytest.mark.parametrize("name,dims,w,hgt", shadow_cases())
+def test_shadow_forward_parity(R, orc, name, dims, w, hgt):
+    log("case: shadow forward", name)
+    h = 1.0 / max(dims)
+    g_o, g_r = orc.make_grid(dims, (0, 0, 0), h), R.make_grid(dims, (0, 0, 0), h)
+    p = synth.shadow_setup(h, width=w, height=hgt)
+    f = sphere_field(dims, h, C=(0.5, 0.3, 0.5), r=0.12)
+    ig = gpu_img(R, f, g_r, R.make_shadow(**p))
+    io = orc.shadow_forward(f, g_o, orc.make_shadow(**p))
+    err = np.abs(ig - io)
+    log("  max |diff|", err.max(), "penumbra pixels", ((io > 0) & (io < 1)).sum())
+    assert err.max() <= 1e-4
+    assert ((io > 0) & (io < 1)).sum() > 0 and (io == 0).sum() > 0 and (io == 1).sum() > 0
+
+
+def safe_pixels(orc, f, g, s, img):
+    rm, sm = orc.shadow_margin(f, g, s)
+    return (img > 0) & (img < 1) & (rm > 1e-4) & (sm > 1e-5)
+
+
+@pytest.mark.parametrize("name,dims,w,hgt", shadow_cases())
+def test_shadow_backward_parity(R, orc, name, dims, w, hgt):
+    log("case: shadow backward", name)
+    h = 1.0 / max(dims)
+    g_o, g_r = orc.make_grid(dims, (0, 0, 0), h), R.make_grid(dims, (0, 0, 0), h)
+    p = synth.shadow_setup(h, width=w, height=hgt)
+    s_o = orc.make_shadow(**p)
+    f = sphere_field(dims, h, C=(0.5, 0.3, 0.5), r=0.12)
+    io = orc.shadow_forward(f, g_o, s_o)
+    safe = safe_pixels(orc, f, g_o, s_o, io)
+    gi = np.where(safe, np.random.default_rng(5).normal(size=io.size), 0.0).astype(np.float32)
+    log("  safe penumbra pixels", safe.sum(), "of", ((io > 0) & (io < 1)).sum())
+    assert safe.sum() >= 0.9 * ((io > 0) & (io < 1)).sum()
+    go = orc.shadow_backward(f, g_o, s_o, gi.astype(np.float64))
+    gg = gpu_shadow_bwd(R, f, g_r, R.make_shadow(**p), gi)
+    assert np.abs(go).max() > 0
+    close(gg, go)
+
+
+@pytest.fixture(scope="module")
+def grad_scene():
+    return synth.scene_grad()
+
+
+def test_shadow_parity_grad_workload(R, orc, grad_scene):
+    """The 512^2 image of the 128^3 ellipsoid field: forward on every pixel, adjoint on
+    every pixel with safe margins (the launch configuration the benchmark times)."""
+    sc = grad_scene
+    log("case: shadow 512x512 over the 128^3 ellipsoid field")
+    g_o, g_r = orc.make_grid(sc.dims, sc.org, sc.h), R.make_grid(sc.dims, sc.org, sc.h)
+    p = sc.extra["shadow"]
+    s_o = orc.make_shadow(**p)
+    f = sc.extra["target"].astype(np.float32)
+    io = orc.shadow_forward(f, g_o, s_o)
+    ig = gpu_img(R, f, g_r, R.make_shadow(**p))
+    log("  max |diff|", np.abs(ig - io).max())
+    assert np.abs(ig - io).max() <= 1e-4
+    safe = safe_pixels(orc, f, g_o, s_o, io)
+    gi = np.where(safe, 2.0 * (io - sc.extra["target_img"]), 0.0).astype(np.float32)
+    log("  safe pixels", safe.sum(), "penumbra", ((io > 0) & (io < 1)).sum())
+    go = orc.shadow_backward(f, g_o, s_o, gi.astype(np.float64))
+    gg = gpu_shadow_bwd(R, f, g_r, R.make_shadow(**p), gi)
+    close(gg, go)
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def run_pair(R, orc, sc, key=0):
+    """The forward of both sides; the integer state compared bit-exactly."""
+    import torch
+    S = R.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames, rng_key=key)
+    S.run()
+    torch.cuda.synchronize()
+    g = orc.make_grid(sc.dims, sc.org, sc.h)
+    jfa = orc.jfa(orc.voxelize(sc.verts, sc.tris, g), g, sc.steps)
+    band = orc.band(jfa, g, sc.band)
+    bvh = orc.BVH(sc.verts, sc.tris, orc.hit_pad(g))
+    acc = orc.new_accum(len(band))
+    for f in range(sc.frames):
+        orc.raysample(bvh, g, band, sc.rays, key, f, acc=acc)
+    dmin, hits, argmin = acc
+    N = len(jfa)
+    D = np.full(N, np.inf, np.float32)
+    H = np.zeros(N, np.uint32)
+    D[band], H[band] = dmin, hits
+    fine, _ = orc.combine(jfa, D, H, g, sc.band, sc.h / 2, 0.0, 0)
+    n = int(S.band_count.item())
+    assert np.array_equal(S.jfa_out.cpu().numpy(), jfa)
+    assert np.array_equal(S.band_list[:n].cpu().numpy(), band)
+    assert np.array_equal(u32(S.hits)[band], hits)
+    assert np.array_equal(u64(S.argmin)[band], argmin)
+    np.testing.assert_allclose(S.fine.cpu().numpy(), fine, rtol=1e-5)
+    return S, dict(g=g, band=band, bvh=bvh, hits=hits, argmin=argmin, fine=fine)
+
+
+def test_vertex_adjoint_parity_grad_workload(R, orc, grad_scene):
+    import torch
+    sc = grad_scene
+    log("case: vertex adjoint, icosphere 20480 tris on 128^3, 16 rays")
+    S, O = run_pair(R, orc, sc)
+    gf = (2.0 * (O["fine"].astype(np.float64) - sc.extra["target"])).astype(np.float32)
+    go = orc.sdf_backward(gf.astype(np.float64), O["hits"], O["argmin"], O["band"], O["bvh"], sc.verts, sc.tris,
+                          O["g"], sc.rays, 0)
+    gg = S.backward(torch.from_numpy(gf).cuda())
+    torch.cuda.synchronize()
+    gg = gg.cpu().numpy()
+    log("  max |g|", np.abs(go).max(), "max |diff|", np.abs(gg - go).max())
+    close(gg, go)
+
+
+def test_vertex_adjoint_parity_multi_frame(R, orc):
+    """Two frames and a nonzero key: the argmin record names the frame as well as the ray."""
+    import torch
+    sc = synth.scene_static(dims=(100, 50, 100), nprims=40, seed=1)
+    sc.frames = 2
+    log("case: vertex adjoint, static 100x50x100, 2 frames, key 7")
+    S, O = run_pair(R, orc, sc, key=7)
+    w = np.random.default_rng(6).normal(size=len(O["fine"])).astype(np.float32)
+    go = orc.sdf_backward(w.astype(np.float64), O["hits"], O["argmin"], O["band"], O["bvh"], sc.verts, sc.tris,
+                          O["g"], sc.rays, 7)
+    gg = S.backward(torch.from_numpy(w).cuda()).cpu().numpy()
+    close(gg, go)
+
+
+def test_autograd_chain(R, orc, grad_scene):
+    """L = |fine - target|^2 + |shadow(fine) - target_img|^2 through SDF.apply and
+    SoftShadow.apply equals the adjoint entry points called by hand, and its vertex
+    gradient matches the oracle's chain on pixels with safe margins."""
+    import torch
+    sc = grad_scene
+    log("case: autograd chain on the gradient workload")
+    S = R.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
+    g = S.g
+    sh = R.make_shadow(**sc.extra["shadow"])
+    V = torch.from_numpy(sc.verts).cuda().requires_grad_(True)
+    tgt = torch.from_numpy(sc.extra["target"].astype(np.float32)).cuda()
+    timg = torch.from_numpy(sc.extra["target_img"]).cuda().reshape(sh.height, sh.width)
+    fine = R.SDF.apply(V, S)
+    img = R.SoftShadow.apply(fine, g, sh)
+    loss = ((fine - tgt) ** 2).sum() + ((img - timg) ** 2).sum()
+    (gv,) = torch.autograd.grad(loss, V)
+    # by hand
+    gi = 2.0 * (img.detach() - timg)
+    gfine = 2.0 * (fine.detach() - tgt)
+    R.rtsdf_shadow_backward(fine.detach(), g, sh, gi.contiguous(), gfine)
+    gv2 = S.backward(gfine)
+    torch.cuda.synchronize()
+    close(gv.cpu().numpy(), gv2.cpu().numpy(), rtol=1e-4, arel=1e-5)
+    # against the oracle's chain: the image gradient restricted to pixels with safe margins
+    go_ = orc.make_grid(sc.dims, sc.org, sc.h)
+    so = orc.make_shadow(**sc.extra["shadow"])
+    _, O = run_pair(R, orc, sc)
+    io = orc.shadow_forward(O["fine"], go_, so)
+    safe = safe_pixels(orc, O["fine"].astype(np.float64), go_, so, io)
+    gi_o = np.where(safe, 2.0 * (io - sc.extra["target_img"]), 0.0)
+    gf_o = 2.0 * (O["fine"].astype(np.float64) - sc.extra["target"]) + orc.shadow_backward(O["fine"], go_, so, gi_o)
+    gv_o = orc.sdf_backward(gf_o, O["hits"], O["argmin"], O["band"], O["bvh"], sc.verts, sc.tris, go_, sc.rays, 0)
+    gfine3 = 2.0 * (fine.detach() - tgt)
+    R.rtsdf_shadow_backward(fine.detach(), g, sh, torch.from_numpy(gi_o.astype(np.float32)).cuda(), gfine3)
+    gv3 = S.backward(gfine3).cpu().numpy()
+    log("  vertex grad max", np.abs(gv_o).max(), "max |diff|", np.abs(gv3 - gv_o).max())
+    close(gv3, gv_o)
+
+
+def test_adjoint_edge_cases(R, orc):
+    import torch
+    log("case: adjoint edge cases")
+    # one-point axis (nz = 1) and a single march step; empty image
+    dims, h = (16, 16, 1), 1.0 / 16
+    g_o, g_r = orc.make_grid(dims, (0, 0, 0), h), R.make_grid(dims, (0, 0, 0), h)
+    f = sphere_field(dims, h, C=(0.5, 0.5, 0.0), r=0.2)
+    for steps in (1, 7):
+        p = synth.shadow_setup(h, width=9, height=5, plane_y=0.05, steps=steps)
+        io = orc.shadow_forward(f, g_o, orc.make_shadow(**p))
+        ig = gpu_img(R, f, g_r, R.make_shadow(**p))
+        assert np.abs(ig - io).max() <= 1e-4
+    p = synth.shadow_setup(h, width=0, height=0)
+    img = torch.empty(0, device="cuda")
+    R.rtsdf_shadow_forward(torch.from_numpy(f).cuda(), g_r, R.make_shadow(**p), img)
+    gf = torch.zeros(len(f), device="cuda")
+    R.rtsdf_shadow_backward(torch.from_numpy(f).cuda(), g_r, R.make_shadow(**p), img, gf)
+    torch.cuda.synchronize()
+    assert (gf == 0).all()
+    # zero upstream gradient gives zero vertex gradient; all-lit image gives zero field gradient
+    sc = synth.scene_tiny()
+    S = R.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
+    S.run()
+    gv = S.backward(torch.zeros(S.g.n, device="cuda"))
+    torch.cuda.synchronize()
+    assert (gv == 0).all()
+    p = synth.shadow_setup(sc.h, width=8, height=8)
+    far = torch.full((S.g.n,), 10.0, device="cuda")
+    img = torch.empty(8, 8, device="cuda")
+    R.rtsdf_shadow_forward(far, S.g, R.make_shadow(**p), img)
+    gf = torch.zeros(S.g.n, device="cuda")
+    R.rtsdf_shadow_backward(far, S.g, R.make_shadow(**p), torch.ones(8, 8, device="cuda"), gf)
+    torch.cuda.synchronize()
+    assert (img == 1).all() and (gf == 0).all()
