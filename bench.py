@@ -30,6 +30,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-deform", action="store_true", help="skip the deforming-mesh (graph) measurement")
     p.add_argument("--no-grad", action="store_true", help="skip the gradient-workload measurement")
+    p.add_argument("--no-batch", action="store_true", help="skip the batched-objects measurement")
     p.add_argument("--cpu-sample", type=int, default=20000, help="masked voxels ray-sampled by the oracle")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy three times (to scale HBM counters)")
@@ -171,6 +172,77 @@ def grad_bench(torch, rtsdf, synth, reps=20):
             "shadow_samples_per_s_fwd": round(sh.width * sh.height * sh.steps / (med["shadow_fwd"] / 1e3), 1)}
 
 
+def batch_bench(torch, rtsdf, synth, reps=3):
+    """64 uneven objects (grids 32^3..256^3, 1k..200k triangles): the batched chain (one
+    launch per stage and per JFA pass) against the plain loop of 64 single-object chains on
+    the same stream; then the batched vertex adjoint against 64 looped adjoint calls.  Wall
+    time around each whole chain (host launch cost included), medians over `reps`."""
+    import statistics
+    scenes = synth.scene_batch()
+    B = rtsdf.BatchSDF(scenes, rays=8)
+    singles = [rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, 8, 1, obj=o)
+               for o, sc in enumerate(scenes)]
+    grad = torch.randn(B.fine.numel(), device="cuda")
+    grads = [B.view(grad, o).contiguous() for o in range(len(scenes))]
+    gv = torch.zeros_like(B.verts)
+    gvs = [torch.zeros_like(S.verts) for S in singles]
+
+    def timed(fn):
+        out = []
+        for it in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            if it:
+                out.append(time.perf_counter() - t0)
+        return statistics.median(out)
+
+    def plain():
+        for S in singles:
+            S.run()
+
+    def plain_bwd():
+        for S, gs, gvo in zip(singles, grads, gvs):
+            gvo.zero_()
+            S.backward(gs, gvo)
+
+    def batched_bwd():
+        gv.zero_()
+        B.backward(grad, gv)
+
+    t_batch = timed(B.run)
+    t_plain = timed(plain)
+    tb_bwd = timed(batched_bwd)
+    tp_bwd = timed(plain_bwd)
+    T = StageTimer(torch)
+    T.mark("start")
+    B.voxelize()
+    T.mark("voxelize")
+    B.jfa()
+    T.mark("jfa")
+    B.mask()
+    T.mark("mask")
+    B.build_bvh()
+    T.mark("bvh")
+    rtsdf.rtsdf_reset_accum(B.dmin, B.hits, B.argmin)
+    T.mark("reset")
+    B.trace(0)
+    T.mark("raysample")
+    B.combine()
+    T.mark("combine")
+    torch.cuda.synchronize()
+    masked = int(B.band_count.item())
+    voxels = sum(int(S.g.n) for S in singles)
+    return {"workload": "%d objects, %d triangles, %d grid points" % (len(scenes), int(B.tris.shape[0]), voxels),
+            "ms_batched": round(t_batch * 1e3, 3), "ms_plain_loop": round(t_plain * 1e3, 3),
+            "speedup": round(t_plain / t_batch, 3), "sdf_voxels_per_s_batched": round(voxels / t_batch, 1),
+            "rays_per_s_batched": round(masked * 8 / (T.durations()["raysample"] / 1e3), 1),
+            "stages_ms_batched": {k: round(v, 4) for k, v in T.durations().items()},
+            "bwd_ms_batched": round(tb_bwd * 1e3, 3), "bwd_ms_plain_loop": round(tp_bwd * 1e3, 3),
+            "bwd_speedup": round(tp_bwd / tb_bwd, 3), "masked_voxels": masked}
+
+
 def cpu_baseline(sc, sample):
     """The oracle as it stands, on the host cores, on a bounded sample of the same step:
     voxelize, all jump-flooding passes, mask, hierarchy and combine over the full grid;
@@ -290,6 +362,8 @@ def main():
         out["deform"] = deform_bench(torch, rtsdf, synth)
     if not args.no_grad:
         out["grad"] = grad_bench(torch, rtsdf, synth)
+    if not args.no_batch:
+        out["batch"] = batch_bench(torch, rtsdf, synth)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample)
     print(json.dumps(out))

@@ -245,6 +245,89 @@ rtsdf_status rtsdf_backward(const float* grad_fine, const uint32_t* hits, const 
                             int32_t nv, int32_t nt, rtsdf_grid g, int32_t rays_per_voxel,
                             uint64_t rng_key, uint32_t obj, float* grad_verts, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Batched objects -- many independent scenes, each with its own mesh and grid, run by one
+ * launch per stage (per JFA pass) instead of one call chain per object; the dispatch cost
+ * the paper attributes to its per-pass calls (section 3.1.2) is paid once per batch.  Each
+ * object computes exactly what the single-object calls compute for it (with obj = its
+ * index in the batch), so seeds, masks, hit counts and argmin records are bit-identical.
+ *
+ * Layout of the concatenated arrays (all in object order):
+ *   verts [sum nv][3], tris [sum nt][3] with indices local to the object's vertices;
+ *   per-grid-point arrays (seeds, dmin, hits, argmin, fine, grad_fine): object o's grid
+ *   starts at voxel offset V_o = sum over p < o of roundup(N_p, RTSDF_BATCH_ALIGN); the
+ *   voxels between objects are padding that no call reads or writes;
+ *   mask lists hold indices into these concatenated arrays;
+ *   hierarchies: object o's blob starts at byte offset B_o = sum over p < o of
+ *   roundup(rtsdf_bvh_bytes(nt_p), 256).
+ * A plan (rtsdf_batch_plan) records the layout and the launch tables.  It is caller-owned
+ * memory in two copies of rtsdf_batch_plan_bytes(nobj) bytes, one in host memory (read
+ * by every batched call to size its launches) and one in device memory (read by the
+ * kernels); the host copy remembers the device copy's address.  Both must stay unchanged
+ * while calls that use them are in flight.
+ * ------------------------------------------------------------------------------------- */
+#define RTSDF_BATCH_ALIGN 4096
+#define RTSDF_MAX_OBJECTS 65536
+
+typedef struct rtsdf_object {
+    rtsdf_grid g;          /* the object's grid */
+    int32_t nv, nt;        /* its vertices and triangles */
+    int32_t band_vox;      /* mask width in voxels, [0, 2048] */
+    int32_t extra_passes;  /* trailing JFA passes with offset 1 after 2^(ceil(log2 max dim)-1)..1, [0, 8] */
+    float beta, bias;      /* combine parameters, world units of this object */
+} rtsdf_object;
+
+typedef struct rtsdf_batch_sizes {
+    int64_t voxels;        /* length of the concatenated per-grid-point arrays */
+    int64_t verts, tris;   /* rows of the concatenated verts and tris */
+    size_t bvh_bytes;      /* bytes of the concatenated hierarchies */
+    size_t work_bytes;     /* workspace every batched call accepts */
+    int32_t max_passes;    /* JFA passes of the longest object */
+} rtsdf_batch_sizes;
+
+size_t rtsdf_batch_plan_bytes(int32_t nobj);
+/* Builds the plan from objs (HOST, nobj in [1, 65536]) into plan_host (host work only) and
+ * records plan_device as the address of its device copy.  Errors: E_ARG (null pointers, a
+ * bad grid or parameter), E_RANGE (counts; the batch must stay below 2^31 grid points and
+ * vertices and 2^26 triangles), E_SIZE (plan_bytes too small). */
+rtsdf_status rtsdf_batch_plan(const rtsdf_object* objs, int32_t nobj, void* plan_host, void* plan_device,
+                              size_t plan_bytes, rtsdf_batch_sizes* sizes);
+/* Copies the host plan to its device copy on `stream` and waits for the copy (this call
+ * synchronizes the stream).  Errors: E_ARG (not a plan), E_DEVICE. */
+rtsdf_status rtsdf_batch_upload(const void* plan_host, void* stream);
+/* Layout query: object o's voxel offset V_o and hierarchy byte offset B_o (HOST outs). */
+rtsdf_status rtsdf_batch_offsets(const void* plan_host, int32_t o, int64_t* vox_offset, size_t* bvh_offset);
+
+/* As rtsdf_voxelize per object.  An object with an odd number of JFA passes receives its
+ * seeds in `scratch`, the others in `seeds`, so that rtsdf_jfa_batched leaves every
+ * result in `seeds`.  seeds, scratch [sizes.voxels] int32; work [sizes.work_bytes]. */
+rtsdf_status rtsdf_voxelize_batched(const void* plan_host, const float* verts, const int32_t* tris,
+                                    int32_t* seeds, int32_t* scratch, void* work, size_t work_bytes,
+                                    void* stream);
+/* As rtsdf_jfa per object with its own offsets; one launch per pass over every object
+ * still flooding; the results end in `seeds` (see rtsdf_voxelize_batched). */
+rtsdf_status rtsdf_jfa_batched(const void* plan_host, int32_t* seeds, int32_t* scratch, void* stream);
+/* As rtsdf_band per object with its own mask width; one list over the concatenated grid
+ * points, increasing.  band_list [sizes.voxels] int32, band_count [1] int32 (device). */
+rtsdf_status rtsdf_band_batched(const void* plan_host, const int32_t* seeds, int32_t* band_list,
+                                int32_t* band_count, void* work, size_t work_bytes, void* stream);
+/* As rtsdf_build_bvh per object (grid of the object sets the hit padding). */
+rtsdf_status rtsdf_build_bvh_batched(const void* plan_host, const float* verts, const int32_t* tris, void* bvh,
+                                     size_t bvh_bytes, void* work, size_t work_bytes, void* stream);
+/* As rtsdf_raysample per object with obj = the object's index; one launch for the batch. */
+rtsdf_status rtsdf_raysample_batched(const void* plan_host, const void* bvh, const int32_t* band_list,
+                                     const int32_t* band_count, int64_t band_capacity, int32_t rays_per_voxel,
+                                     uint64_t rng_key, uint32_t frame, float* dmin, uint32_t* hits,
+                                     uint64_t* argmin, void* work, size_t work_bytes, void* stream);
+/* As rtsdf_combine in RTSDF_ACCUM mode per object (its band_vox, beta, bias). */
+rtsdf_status rtsdf_combine_batched(const void* plan_host, const int32_t* seeds, const float* dmin,
+                                   const uint32_t* hits, float* fine, void* stream);
+/* As rtsdf_backward per object; grad_verts [sizes.verts * 3] accumulated. */
+rtsdf_status rtsdf_backward_batched(const void* plan_host, const float* grad_fine, const uint32_t* hits,
+                                    const uint64_t* argmin, const int32_t* band_list, const int32_t* band_count,
+                                    int64_t band_capacity, const void* bvh, const int32_t* tris,
+                                    int32_t rays_per_voxel, uint64_t rng_key, float* grad_verts, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

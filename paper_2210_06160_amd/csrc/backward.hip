@@ -20,24 +20,36 @@ namespace {
 constexpr int kThreads = 128;
 constexpr int kLdsDepth = 8;
 
+// kBatch: list entries index concatenated grids; each voxel's object supplies its grid, its
+// hierarchy, the counter's object word and the base of its vertices and triangles.
+template <bool kBatch>
 __global__ __launch_bounds__(kThreads) void k_sdf_backward(
     const char* __restrict__ bvh, const rtsdf_grid g, const int32_t* __restrict__ list,
     const int32_t* __restrict__ count_p, const float* __restrict__ grad_fine,
     const uint32_t* __restrict__ hits, const uint64_t* __restrict__ argmin,
     const int32_t* __restrict__ tri_index, int32_t x, uint32_t k0, uint32_t k1, uint32_t obj,
-    float* __restrict__ grad_verts)
+    float* __restrict__ grad_verts, const char* plan, int32_t nobj)
 {
     __shared__ uint64_t s_stk[kLdsDepth][kThreads];  // (t bits << 32) | child code
     int32_t p_code[kMaxStack - kLdsDepth];
     float p_t[kMaxStack - kLdsDepth];
 
-    const BvhHeader* H = (const BvhHeader*)bvh;
-    const int32_t nt = H->nt, root = H->root;
-    const float pad = H->pad;
-    if (nt == 0) return;
-    const Bvh4Node* __restrict__ nodes = (const Bvh4Node*)(bvh + 256);
-    const BvhTri* __restrict__ tris =
-        (const BvhTri*)(bvh + 256 + sizeof(Bvh4Node) * (size_t)(nt > 1 ? nt - 1 : 1));
+    int32_t nt = 0, root = 0;
+    float pad = 0.0f;
+    const Bvh4Node* __restrict__ nodes = nullptr;
+    const BvhTri* __restrict__ tris = nullptr;
+    auto use_bvh = [&](const char* b) {
+        const BvhHeader* H = (const BvhHeader*)b;
+        nt = H->nt;
+        root = H->root;
+        pad = H->pad;
+        nodes = (const Bvh4Node*)(b + 256);
+        tris = (const BvhTri*)(b + 256 + sizeof(Bvh4Node) * (size_t)(nt > 1 ? nt - 1 : 1));
+    };
+    if (!kBatch) {
+        use_bvh(bvh);
+        if (nt == 0) return;
+    }
     const int32_t count = *count_p;
     const float inf = __int_as_float(0x7f800000);
     const int tid = threadIdx.x;
@@ -47,11 +59,27 @@ __global__ __launch_bounds__(kThreads) void k_sdf_backward(
         const uint32_t hc = hits[vid];
         const float gf = grad_fine[vid];
         if (hc == 0u || gf == 0.0f) continue;
+        rtsdf_grid lg = g;
+        uint32_t lvid = (uint32_t)vid, lobj = obj;
+        const int32_t* ltri = tri_index;
+        float* lgv = grad_verts;
+        if (kBatch) {
+            const BatchView bv = batch_view(plan, nobj);
+            const int32_t oi = find_object(bv.vox_prefix, nobj, (int64_t)vid);
+            const BatchObject& ob = bv.obj[oi];
+            lvid = (uint32_t)(vid - ob.vox_off);
+            lg = ob.g;
+            lobj = (uint32_t)oi;
+            ltri = tri_index + 3 * (int64_t)ob.tri_off;
+            lgv = grad_verts + 3 * (int64_t)ob.vert_off;
+            use_bvh(bvh + ob.bvh_off);
+            if (nt == 0) continue;
+        }
         const uint32_t code = (uint32_t)argmin[vid];
         const uint32_t frame = code / (uint32_t)x, j = code - frame * (uint32_t)x;
         uint32_t ci, cj, ck;
-        const float3 o = voxel_centre(g, vid, ci, cj, ck);
-        const float3 w = sphere_direction(k0, k1, (uint32_t)vid, frame, j, obj);
+        const float3 o = voxel_centre(lg, lvid, ci, cj, ck);
+        const float3 w = sphere_direction(k0, k1, lvid, frame, j, lobj);
         const float3 inv = make_float3(slab_rcp(w.x), slab_rcp(w.y), slab_rcp(w.z));
         const float3 oinv = make_float3(o.x * inv.x, o.y * inv.y, o.z * inv.z);
 
@@ -143,10 +171,10 @@ __global__ __launch_bounds__(kThreads) void k_sdf_backward(
         const float bary[3] = {(1.0f - u) - v, u, v};
         const float sign = (hc >> 16) > (hc & 0xFFFFu) ? -1.0f : 1.0f;
         const float scale = gf * sign / nw;
-        const int32_t* tv = tri_index + 3 * (int64_t)bid;
+        const int32_t* tv = ltri + 3 * (int64_t)bid;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            float* gv = grad_verts + 3 * (int64_t)tv[k];
+            float* gv = lgv + 3 * (int64_t)tv[k];
             const float s = scale * bary[k];
             unsafeAtomicAdd(gv + 0, s * n.x);
             unsafeAtomicAdd(gv + 1, s * n.y);
@@ -165,8 +193,24 @@ hipError_t sdf_backward(const float* grad_fine, const uint32_t* hits, const uint
     if (capacity <= 0) return hipSuccess;
     const int64_t want = ceil_div(capacity, kThreads);
     const unsigned groups = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, persistent_groups(kThreads)));
-    hipLaunchKernelGGL(k_sdf_backward, dim3(groups), dim3(kThreads), 0, s, (const char*)bvh, g, list, count,
-                       grad_fine, hits, argmin, tris, x, (uint32_t)key, (uint32_t)(key >> 32), obj, grad_verts);
+    hipLaunchKernelGGL(k_sdf_backward<false>, dim3(groups), dim3(kThreads), 0, s, (const char*)bvh, g, list, count,
+                       grad_fine, hits, argmin, tris, x, (uint32_t)key, (uint32_t)(key >> 32), obj, grad_verts,
+                       nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t sdf_backward_batched(const BatchView& hv, const void* dplan, const float* grad_fine,
+                                const uint32_t* hits, const uint64_t* argmin, const int32_t* list,
+                                const int32_t* count, int64_t capacity, const void* bvh, const int32_t* tris,
+                                int32_t x, uint64_t key, float* grad_verts, hipStream_t s)
+{
+    if (capacity <= 0 || hv.h->total_tris == 0) return hipSuccess;
+    const int64_t want = ceil_div(capacity, kThreads);
+    const unsigned groups = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, persistent_groups(kThreads)));
+    const rtsdf_grid g0 = hv.obj[0].g;  // unused in batch mode
+    hipLaunchKernelGGL(k_sdf_backward<true>, dim3(groups), dim3(kThreads), 0, s, (const char*)bvh, g0, list, count,
+                       grad_fine, hits, argmin, tris, x, (uint32_t)key, (uint32_t)(key >> 32), 0u, grad_verts,
+                       (const char*)dplan, hv.h->nobj);
     return hipGetLastError();
 }
 

@@ -4,6 +4,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstring>
+#include <vector>
 
 #include "internal.h"
 
@@ -61,9 +63,249 @@ rtsdf_status check_shadow(const rtsdf_shadow& s)
     return RTSDF_OK;
 }
 
+// ---- batched objects: plan construction ------------------------------------------------
+
+size_t batch_work_bytes(const rtsdf::BatchView& v)
+{
+    size_t w = 256;  // ray-sampling cursors
+    w = std::max(w, rtsdf::voxelize_work_bytes((int32_t)v.h->total_tris));
+    w = std::max(w, rtsdf::band_batched_work_bytes(v.h->total_vox));
+    for (int32_t o = 0; o < v.h->nobj; ++o) w = std::max(w, rtsdf::bvh_work_bytes(v.obj[o].nt));
+    return w;
+}
+
+// validates a host plan; fills the view
+rtsdf_status check_plan(const void* plan, rtsdf::BatchView& v)
+{
+    if (!plan) return fail(RTSDF_E_ARG, "plan is NULL");
+    const rtsdf::BatchHeader* h = (const rtsdf::BatchHeader*)plan;
+    if (h->magic != rtsdf::kBatchMagic || h->nobj < 1 || h->nobj > RTSDF_MAX_OBJECTS || !h->device)
+        return fail(RTSDF_E_ARG, "not a batch plan (use the host copy written by rtsdf_batch_plan)");
+    v = rtsdf::batch_view(plan, h->nobj);
+    return RTSDF_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t rtsdf_batch_plan_bytes(int32_t nobj)
+{
+    return (nobj < 1 || nobj > RTSDF_MAX_OBJECTS) ? 0 : rtsdf::batch_plan_bytes(nobj);
+}
+
+rtsdf_status rtsdf_batch_plan(const rtsdf_object* objs, int32_t nobj, void* plan_host, void* plan_device,
+                              size_t plan_bytes, rtsdf_batch_sizes* sizes)
+{
+    using namespace rtsdf;
+    if (!objs || !plan_host || !plan_device || !sizes) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (nobj < 1 || nobj > RTSDF_MAX_OBJECTS) return fail(RTSDF_E_RANGE, "nobj %d outside [1, %d]", nobj, RTSDF_MAX_OBJECTS);
+    const size_t bytes = batch_plan_bytes(nobj);
+    if (plan_bytes < bytes) return fail(RTSDF_E_SIZE, "plan %zu < %zu bytes", plan_bytes, bytes);
+    std::vector<char> buf(bytes, 0);
+    BatchHeader* h = (BatchHeader*)buf.data();
+    BatchView v = batch_view(buf.data(), nobj);
+    BatchObject* ob = const_cast<BatchObject*>(v.obj);
+    int64_t* vox_prefix = const_cast<int64_t*>(v.vox_prefix);
+    int32_t* tri_prefix = const_cast<int32_t*>(v.tri_prefix);
+    int32_t* pass_prefix = const_cast<int32_t*>(v.pass_prefix);
+    int64_t vox = 0, verts = 0, tris = 0;
+    uint64_t bvh = 0;
+    int32_t max_passes = 0;
+    for (int32_t o = 0; o < nobj; ++o) {
+        const rtsdf_object& in = objs[o];
+        if (rtsdf_status st = check_grid(in.g)) {
+            char msg[sizeof(g_err)];
+            std::snprintf(msg, sizeof(msg), "%s", g_err);
+            return fail(st, "object %d: %s", o, msg);
+        }
+        if (in.nv < 0 || in.nt < 0 || in.nt > (1 << 26))
+            return fail(RTSDF_E_RANGE, "object %d: nv %d / nt %d outside range", o, in.nv, in.nt);
+        if (in.nt > 0 && in.nv == 0) return fail(RTSDF_E_RANGE, "object %d: triangles but no vertices", o);
+        if (in.band_vox < 0 || in.band_vox > 2048) return fail(RTSDF_E_RANGE, "object %d: band_vox outside [0, 2048]", o);
+        if (in.extra_passes < 0 || in.extra_passes > 8) return fail(RTSDF_E_RANGE, "object %d: extra_passes outside [0, 8]", o);
+        if (!std::isfinite(in.beta) || !std::isfinite(in.bias)) return fail(RTSDF_E_ARG, "object %d: beta/bias not finite", o);
+        BatchObject& b = ob[o];
+        b.g = in.g;
+        b.band_vox = in.band_vox;
+        b.vox_off = vox;
+        b.bvh_off = (int64_t)bvh;
+        b.vert_off = (int32_t)verts;
+        b.tri_off = (int32_t)tris;
+        b.nv = in.nv;
+        b.nt = in.nt;
+        const int32_t n = std::max(in.g.nx, std::max(in.g.ny, in.g.nz));
+        int32_t k = 1;
+        while (k < n) k *= 2;
+        b.k0 = std::max(k / 2, 1);
+        b.nhalf = 0;
+        for (int32_t q = b.k0; q >= 1; q /= 2) ++b.nhalf;
+        b.nsteps = b.nhalf + in.extra_passes;
+        b.flip = b.nsteps & 1;
+        b.beta = in.beta;
+        b.bias = in.bias;
+        vox_prefix[o] = vox;
+        tri_prefix[o] = (int32_t)tris;
+        vox += ceil_div(nvox(in.g), kBatchAlign) * kBatchAlign;
+        verts += in.nv;
+        tris += in.nt;
+        bvh += align256(bvh_bytes(in.nt));
+        max_passes = std::max(max_passes, b.nsteps);
+        if (vox >= ((int64_t)1 << 31) || verts >= ((int64_t)1 << 31) || tris > (1 << 26))
+            return fail(RTSDF_E_RANGE, "batch too large: voxels, vertices and triangles must stay below 2^31, 2^31, 2^26");
+    }
+    vox_prefix[nobj] = vox;
+    tri_prefix[nobj] = (int32_t)tris;
+    for (int32_t p = 0; p < max_passes; ++p) {
+        int32_t* pre = pass_prefix + (int64_t)p * (nobj + 1);
+        int64_t acc = 0;
+        for (int32_t o = 0; o < nobj; ++o) {
+            pre[o] = (int32_t)acc;
+            if (p < ob[o].nsteps) acc += jfa_pass_blocks(ob[o].g, jfa_offset(ob[o].k0, ob[o].nhalf, p));
+            if (acc >= ((int64_t)1 << 31)) return fail(RTSDF_E_RANGE, "too many JFA work-groups in pass %d", p);
+        }
+        pre[nobj] = (int32_t)acc;
+        h->pass_blocks[p] = (int32_t)acc;
+    }
+    h->magic = kBatchMagic;
+    h->nobj = nobj;
+    h->max_passes = max_passes;
+    h->total_vox = vox;
+    h->total_verts = verts;
+    h->total_tris = tris;
+    h->bvh_bytes = bvh;
+    h->plan_bytes = bytes;
+    h->device = plan_device;
+    std::memcpy(plan_host, buf.data(), bytes);
+    sizes->voxels = vox;
+    sizes->verts = verts;
+    sizes->tris = tris;
+    sizes->bvh_bytes = bvh;
+    sizes->work_bytes = batch_work_bytes(batch_view(plan_host, nobj));
+    sizes->max_passes = max_passes;
+    return ok();
+}
+
+rtsdf_status rtsdf_batch_upload(const void* plan_host, void* stream)
+{
+    rtsdf::BatchView v;
+    if (rtsdf_status st = check_plan(plan_host, v)) return st;
+    hipError_t e = hipMemcpyAsync(const_cast<void*>(v.h->device), plan_host, v.h->plan_bytes, hipMemcpyHostToDevice,
+                                  as_stream(stream));
+    if (e == hipSuccess) e = hipStreamSynchronize(as_stream(stream));
+    return device(e, "batch plan upload");
+}
+
+rtsdf_status rtsdf_batch_offsets(const void* plan_host, int32_t o, int64_t* vox_offset, size_t* bvh_offset)
+{
+    rtsdf::BatchView v;
+    if (rtsdf_status st = check_plan(plan_host, v)) return st;
+    if (o < 0 || o >= v.h->nobj) return fail(RTSDF_E_RANGE, "object %d outside [0, %d)", o, v.h->nobj);
+    if (vox_offset) *vox_offset = v.obj[o].vox_off;
+    if (bvh_offset) *bvh_offset = (size_t)v.obj[o].bvh_off;
+    return ok();
+}
+
+rtsdf_status rtsdf_voxelize_batched(const void* plan, const float* verts, const int32_t* tris, int32_t* seeds,
+                                    int32_t* scratch, void* work, size_t work_bytes, void* stream)
+{
+    rtsdf::BatchView v;
+    if (rtsdf_status st = check_plan(plan, v)) return st;
+    if (!seeds || !scratch || !work) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (seeds == scratch) return fail(RTSDF_E_ARG, "seeds and scratch must not alias");
+    if (v.h->total_tris > 0 && (!verts || !tris)) return fail(RTSDF_E_ARG, "verts or tris is NULL");
+    if (work_bytes < batch_work_bytes(v)) return fail(RTSDF_E_SIZE, "work %zu < %zu bytes", work_bytes, batch_work_bytes(v));
+    return device(rtsdf::voxelize_batched(v, v.h->device, verts, tris, seeds, scratch, work, as_stream(stream)),
+                  "voxelize_batched");
+}
+
+rtsdf_status rtsdf_jfa_batched(const void* plan, int32_t* seeds, int32_t* scratch, void* stream)
+{
+    rtsdf::BatchView v;
+    if (rtsdf_status st = check_plan(plan, v)) return st;
+    if (!seeds || !scratch) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (seeds == scratch) return fail(RTSDF_E_ARG, "seeds and scratch must not alias");
+    for (int32_t p = 0; p < v.h->max_passes; ++p) {
+        hipError_t e = rtsdf::jfa_batched_pass(v, v.h->device, seeds, scratch, p, as_stream(stream));
+        if (e != hipSuccess) return device(e, "jfa_batched pass");
+    }
+    return ok();
+}
+
+rtsdf_status rtsdf_band_batched(const void* plan, const int32_t* seeds, int32_t* band_list, int32_t* band_count,
+                                void* work, size_t work_bytes, void* stream)
+{
+    rtsdf::BatchView v;
+    if (rtsdf_status st = check_plan(plan, v)) return st;
+    if (!seeds || !band_list || !band_count || !work) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (work_bytes < batch_work_bytes(v)) return fail(RTSDF_E_SIZE, "work %zu < %zu bytes", work_bytes, batch_work_bytes(v));
+    return device(rtsdf::band_batched(v, v.h->device, seeds, band_list, band_count, work, as_stream(stream)),
+                  "band_batched");
+}
+
+rtsdf_status rtsdf_build_bvh_batched(const void* plan, const float* verts, const int32_t* tris, void* bvh,
+                                     size_t bvh_bytes, void* work, size_t work_bytes, void* stream)
+{
+    rtsdf::BatchView v;
+    if (rtsdf_status st = check_plan(plan, v)) return st;
+    if (!bvh || !work) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (v.h->total_tris > 0 && (!verts || !tris)) return fail(RTSDF_E_ARG, "verts or tris is NULL");
+    if (bvh_bytes < v.h->bvh_bytes) return fail(RTSDF_E_SIZE, "bvh %zu < %zu bytes", bvh_bytes, (size_t)v.h->bvh_bytes);
+    if (work_bytes < batch_work_bytes(v)) return fail(RTSDF_E_SIZE, "work %zu < %zu bytes", work_bytes, batch_work_bytes(v));
+    // one build chain per object: the sort and tree passes depend on each object's size
+    for (int32_t o = 0; o < v.h->nobj; ++o) {
+        const rtsdf::BatchObject& b = v.obj[o];
+        hipError_t e = rtsdf::build_bvh(verts + 3 * (int64_t)b.vert_off, tris + 3 * (int64_t)b.tri_off, b.nt, b.g,
+                                        (char*)bvh + b.bvh_off, work, as_stream(stream));
+        if (e != hipSuccess) return device(e, "build_bvh_batched");
+    }
+    return ok();
+}
+
+rtsdf_status rtsdf_raysample_batched(const void* plan, const void* bvh, const int32_t* band_list,
+                                     const int32_t* band_count, int64_t band_capacity, int32_t rays_per_voxel,
+                                     uint64_t rng_key, uint32_t frame, float* dmin, uint32_t* hits, uint64_t* argmin,
+                                     void* work, size_t work_bytes, void* stream)
+{
+    rtsdf::BatchView v;
+    if (rtsdf_status st = check_plan(plan, v)) return st;
+    if (!bvh || !band_list || !band_count || !dmin || !hits || !work) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (rays_per_voxel < 1 || rays_per_voxel > RTSDF_MAX_RAYS)
+        return fail(RTSDF_E_RANGE, "rays_per_voxel %d outside [1, %d]", rays_per_voxel, RTSDF_MAX_RAYS);
+    if (band_capacity < 0 || band_capacity > v.h->total_vox) return fail(RTSDF_E_RANGE, "band_capacity outside [0, voxels]");
+    if (v.h->nobj > (1 << 24)) return fail(RTSDF_E_RANGE, "object index must fit 24 bits");
+    if (work_bytes < batch_work_bytes(v)) return fail(RTSDF_E_SIZE, "work %zu < %zu bytes", work_bytes, batch_work_bytes(v));
+    return device(rtsdf::raysample_batched(v, v.h->device, bvh, band_list, band_count, band_capacity, rays_per_voxel,
+                                           rng_key, frame, dmin, hits, argmin, work, as_stream(stream)),
+                  "raysample_batched");
+}
+
+rtsdf_status rtsdf_combine_batched(const void* plan, const int32_t* seeds, const float* dmin, const uint32_t* hits,
+                                   float* fine, void* stream)
+{
+    rtsdf::BatchView v;
+    if (rtsdf_status st = check_plan(plan, v)) return st;
+    if (!seeds || !dmin || !hits || !fine) return fail(RTSDF_E_ARG, "NULL pointer");
+    return device(rtsdf::combine_batched(v, v.h->device, seeds, dmin, hits, fine, as_stream(stream)), "combine_batched");
+}
+
+rtsdf_status rtsdf_backward_batched(const void* plan, const float* grad_fine, const uint32_t* hits,
+                                    const uint64_t* argmin, const int32_t* band_list, const int32_t* band_count,
+                                    int64_t band_capacity, const void* bvh, const int32_t* tris, int32_t rays_per_voxel,
+                                    uint64_t rng_key, float* grad_verts, void* stream)
+{
+    rtsdf::BatchView v;
+    if (rtsdf_status st = check_plan(plan, v)) return st;
+    if (!grad_fine || !hits || !argmin || !band_list || !band_count || !bvh) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (v.h->total_tris > 0 && (!tris || !grad_verts)) return fail(RTSDF_E_ARG, "tris or grad_verts is NULL");
+    if (rays_per_voxel < 1 || rays_per_voxel > RTSDF_MAX_RAYS)
+        return fail(RTSDF_E_RANGE, "rays_per_voxel %d outside [1, %d]", rays_per_voxel, RTSDF_MAX_RAYS);
+    if (band_capacity < 0 || band_capacity > v.h->total_vox) return fail(RTSDF_E_RANGE, "band_capacity outside [0, voxels]");
+    return device(rtsdf::sdf_backward_batched(v, v.h->device, grad_fine, hits, argmin, band_list, band_count,
+                                              band_capacity, bvh, tris, rays_per_voxel, rng_key, grad_verts,
+                                              as_stream(stream)),
+                  "backward_batched");
+}
 
 const char* rtsdf_last_error(void) { return g_err; }
 

@@ -44,13 +44,36 @@ __device__ uint32_t band_bits(const int32_t* __restrict__ seeds, int64_t N, int3
     return bits;
 }
 
+// The grid a mask work-group scans.  Single object: the arguments.  Batch: the object that
+// owns the work-group's tile (tiles are kBatchAlign = kBandTile voxels and never straddle
+// objects); `base` is added to the listed indices.
+struct BandGrid {
+    const int32_t* seeds;
+    int64_t N, first, base;
+    int32_t nx, ny, b2;
+};
+
+template <bool kBatch>
+__device__ inline BandGrid band_grid(const int32_t* seeds, int64_t N, int32_t nx, int32_t ny, int32_t b2,
+                                     const char* plan, int32_t nobj)
+{
+    const int64_t tile = (int64_t)blockIdx.x * kBandTile;
+    if (!kBatch) return BandGrid{seeds, N, tile + (int64_t)threadIdx.x * kBandItems, 0, nx, ny, b2};
+    const BatchView v = batch_view(plan, nobj);
+    const BatchObject& ob = v.obj[find_object(v.vox_prefix, nobj, tile)];
+    return BandGrid{seeds + ob.vox_off, nvox(ob.g), tile - ob.vox_off + (int64_t)threadIdx.x * kBandItems,
+                    ob.vox_off, ob.g.nx, ob.g.ny, ob.band_vox * ob.band_vox};
+}
+
+template <bool kBatch>
 __global__ __launch_bounds__(kBandThreads) void k_band_count(const int32_t* __restrict__ seeds,
                                                              int64_t N, int32_t nx, int32_t ny,
-                                                             int32_t b2, uint32_t* __restrict__ counts)
+                                                             int32_t b2, uint32_t* __restrict__ counts,
+                                                             const char* plan, int32_t nobj)
 {
     __shared__ uint32_t part[kBandThreads / kWave];
-    const int64_t first = (int64_t)blockIdx.x * kBandTile + (int64_t)threadIdx.x * kBandItems;
-    uint32_t c = __popc(band_bits(seeds, N, nx, ny, b2, first));
+    const BandGrid bg = band_grid<kBatch>(seeds, N, nx, ny, b2, plan, nobj);
+    uint32_t c = __popc(band_bits(bg.seeds, bg.N, bg.nx, bg.ny, bg.b2, bg.first));
     for (int d = kWave / 2; d > 0; d >>= 1) c += __shfl_xor(c, d, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = c;
     __syncthreads();
@@ -61,15 +84,17 @@ __global__ __launch_bounds__(kBandThreads) void k_band_count(const int32_t* __re
     }
 }
 
+template <bool kBatch>
 __global__ __launch_bounds__(kBandThreads) void k_band_write(const int32_t* __restrict__ seeds,
                                                              int64_t N, int32_t nx, int32_t ny,
                                                              int32_t b2,
                                                              const uint32_t* __restrict__ offsets,
-                                                             int32_t* __restrict__ list)
+                                                             int32_t* __restrict__ list, const char* plan,
+                                                             int32_t nobj)
 {
     __shared__ uint32_t part[kBandThreads / kWave];
-    const int64_t first = (int64_t)blockIdx.x * kBandTile + (int64_t)threadIdx.x * kBandItems;
-    const uint32_t bits = band_bits(seeds, N, nx, ny, b2, first);
+    const BandGrid bg = band_grid<kBatch>(seeds, N, nx, ny, b2, plan, nobj);
+    const uint32_t bits = band_bits(bg.seeds, bg.N, bg.nx, bg.ny, bg.b2, bg.first);
     const uint32_t c = __popc(bits);
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     uint32_t inc = c;
@@ -82,7 +107,7 @@ __global__ __launch_bounds__(kBandThreads) void k_band_write(const int32_t* __re
     uint32_t pos = offsets[blockIdx.x] + inc - c;
     for (int w = 0; w < wave; ++w) pos += part[w];
     for (int i = 0; i < kBandItems; ++i)
-        if (bits & (1u << i)) list[pos++] = (int32_t)(first + i);
+        if (bits & (1u << i)) list[pos++] = (int32_t)(bg.base + bg.first + i);
 }
 
 __global__ void k_store_count(const uint32_t* __restrict__ total, int32_t* __restrict__ count)
@@ -160,6 +185,46 @@ __global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ see
     }
 }
 
+// Batch, running minimum only: one kBatchAlign tile per work-group, 16 voxels per thread
+// at a stride of 256 (coalesced), coordinates from the object-local index.
+__global__ __launch_bounds__(256) void k_combine_batched(const char* __restrict__ plan, int32_t nobj,
+                                                         const int32_t* __restrict__ seeds,
+                                                         const float* __restrict__ dmin,
+                                                         const uint32_t* __restrict__ hits, float* __restrict__ fine)
+{
+    const BatchView v = batch_view(plan, nobj);
+    const int64_t tile = (int64_t)blockIdx.x * kBatchAlign;
+    const BatchObject& ob = v.obj[find_object(v.vox_prefix, nobj, tile)];
+    const uint32_t nx = (uint32_t)ob.g.nx, ny = (uint32_t)ob.g.ny;
+    const uint32_t n = (uint32_t)nvox(ob.g);
+    const int32_t b2 = ob.band_vox * ob.band_vox;
+    const float h = ob.g.h, beta = ob.beta, bias = ob.bias;
+    const uint32_t local0 = (uint32_t)(tile - ob.vox_off);
+#pragma unroll 4
+    for (int i = 0; i < (int)(kBatchAlign / 256); ++i) {
+        const uint32_t local = local0 + (uint32_t)(i * 256) + threadIdx.x;
+        if (local >= n) break;
+        const uint32_t row = local / nx;
+        const int32_t x = (int32_t)(local - row * nx), y = (int32_t)(row % ny), z = (int32_t)(row / ny);
+        const int64_t p = ob.vox_off + local;
+        const int32_t sd = seeds[p];
+        float u = __int_as_float(0x7f800000);
+        bool inband = false;
+        if (sd != RTSDF_EMPTY) {
+            const int32_t d2 = seed_d2(sd, x, y, z);
+            u = h * sqrtf((float)d2);
+            inband = d2 <= b2;
+        }
+        const uint32_t hc = hits[p];
+        float val = u - beta;
+        if (inband && hc != 0u) {
+            const float d = dmin[p];
+            val = (hc >> 16) > (hc & 0xFFFFu) ? -d : d;
+        }
+        fine[p] = val - bias;
+    }
+}
+
 }  // namespace
 
 size_t band_work_bytes(const rtsdf_grid& g)
@@ -179,13 +244,49 @@ hipError_t band(const int32_t* seeds, const rtsdf_grid& g, int32_t band_vox, int
     uint32_t* total = (uint32_t*)w;
     w += align256(4);
     const int32_t b2 = band_vox * band_vox;
-    hipLaunchKernelGGL(k_band_count, dim3((unsigned)nb), dim3(kBandThreads), 0, s, seeds, N, g.nx,
-                       g.ny, b2, counts);
+    hipLaunchKernelGGL(k_band_count<false>, dim3((unsigned)nb), dim3(kBandThreads), 0, s, seeds, N, g.nx,
+                       g.ny, b2, counts, nullptr, 0);
     hipError_t e = scan_exclusive_u32(counts, counts, nb, total, w, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_band_write, dim3((unsigned)nb), dim3(kBandThreads), 0, s, seeds, N, g.nx,
-                       g.ny, b2, (const uint32_t*)counts, list);
+    hipLaunchKernelGGL(k_band_write<false>, dim3((unsigned)nb), dim3(kBandThreads), 0, s, seeds, N, g.nx,
+                       g.ny, b2, (const uint32_t*)counts, list, nullptr, 0);
     hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, s, (const uint32_t*)total, count);
+    return hipGetLastError();
+}
+
+size_t band_batched_work_bytes(int64_t total_vox)
+{
+    const int64_t nb = ceil_div(total_vox, kBandTile);
+    return align256((size_t)nb * 4) + align256(4) + scan_work_bytes_u32(nb);
+}
+
+hipError_t band_batched(const BatchView& hv, const void* dplan, const int32_t* seeds, int32_t* list,
+                        int32_t* count, void* work, hipStream_t s)
+{
+    static_assert(kBandTile == kBatchAlign, "a mask tile is one batch alignment unit");
+    const int64_t nb = hv.h->total_vox / kBandTile;
+    const char* plan = (const char*)dplan;
+    const int32_t nobj = hv.h->nobj;
+    char* w = (char*)work;
+    uint32_t* counts = (uint32_t*)w;
+    w += align256((size_t)nb * 4);
+    uint32_t* total = (uint32_t*)w;
+    w += align256(4);
+    hipLaunchKernelGGL(k_band_count<true>, dim3((unsigned)nb), dim3(kBandThreads), 0, s, seeds, (int64_t)0, 0, 0,
+                       0, counts, plan, nobj);
+    hipError_t e = scan_exclusive_u32(counts, counts, nb, total, w, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_band_write<true>, dim3((unsigned)nb), dim3(kBandThreads), 0, s, seeds, (int64_t)0, 0, 0,
+                       0, (const uint32_t*)counts, list, plan, nobj);
+    hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, s, (const uint32_t*)total, count);
+    return hipGetLastError();
+}
+
+hipError_t combine_batched(const BatchView& hv, const void* dplan, const int32_t* seeds, const float* dmin,
+                           const uint32_t* hits, float* fine, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_combine_batched, dim3((unsigned)(hv.h->total_vox / kBatchAlign)), dim3(256), 0, s,
+                       (const char*)dplan, hv.h->nobj, seeds, dmin, hits, fine);
     return hipGetLastError();
 }
 

@@ -57,15 +57,16 @@ __host__ __device__ constexpr int32_t rank_of(int ex, int ey, int ez)
                                                              : 9 * (ez + 1) + 3 * (ey + 1) + (ex + 1);
 }
 
-__global__ __launch_bounds__(kBX * kBY) void k_jfa_stream(const int32_t* __restrict__ in,
-                                                          int32_t* __restrict__ out, int32_t nx,
-                                                          int32_t ny, int32_t nz, int32_t k,
-                                                          int32_t chunks_per_residue)
+// work-group (bx, by, bz) of a pass over one grid: x-columns bx*64.., y-columns by*4..,
+// residue class r and chunk c of that class from bz
+__device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_t* __restrict__ out, int32_t nx,
+                                          int32_t ny, int32_t nz, int32_t k, int32_t chunks_per_residue,
+                                          int32_t bx, int32_t by, int32_t bz)
 {
-    const int32_t x = blockIdx.x * kBX + threadIdx.x;
-    const int32_t y = blockIdx.y * kBY + threadIdx.y;
-    const int32_t r = blockIdx.z / chunks_per_residue;
-    const int32_t c = blockIdx.z - r * chunks_per_residue;
+    const int32_t x = bx * kBX + threadIdx.x;
+    const int32_t y = by * kBY + threadIdx.y;
+    const int32_t r = bz / chunks_per_residue;
+    const int32_t c = bz - r * chunks_per_residue;
     if (x >= nx || y >= ny || r >= nz) return;
     const int32_t mcount = (nz - r + k - 1) / k;  // lattice points z = r + m k < nz
     const int32_t m0 = c * kChunk;
@@ -143,12 +144,62 @@ __global__ __launch_bounds__(kBX * kBY) void k_jfa_stream(const int32_t* __restr
     }
 }
 
+__global__ __launch_bounds__(kBX * kBY) void k_jfa_stream(const int32_t* __restrict__ in,
+                                                          int32_t* __restrict__ out, int32_t nx,
+                                                          int32_t ny, int32_t nz, int32_t k,
+                                                          int32_t chunks_per_residue)
+{
+    jfa_block(in, out, nx, ny, nz, k, chunks_per_residue, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+__host__ __device__ inline int32_t chunks_per_residue(int32_t nz, int32_t k)
+{
+    return (int32_t)ceil_div(ceil_div(nz, k), kChunk);
+}
+
+// One pass over every object still flooding: the flat work-group index picks the object
+// from this pass's prefix table, then the object's own geometry and offset; object o reads
+// the buffer holding its pass-p input (its start buffer alternates with p).
+__global__ __launch_bounds__(kBX * kBY) void k_jfa_batched(const char* __restrict__ plan, int32_t nobj,
+                                                           int32_t pass, int32_t* __restrict__ seeds,
+                                                           int32_t* __restrict__ scratch)
+{
+    const BatchView v = batch_view(plan, nobj);
+    const int32_t* prefix = v.pass_prefix + (int64_t)pass * (nobj + 1);
+    const int32_t b = blockIdx.x;
+    const int32_t o = find_object(prefix, nobj, b);
+    const BatchObject& ob = v.obj[o];
+    const int32_t k = jfa_offset(ob.k0, ob.nhalf, pass);
+    const int32_t nx = ob.g.nx, ny = ob.g.ny, nz = ob.g.nz;
+    const int32_t gx = (nx + kBX - 1) / kBX, gy = (ny + kBY - 1) / kBY;
+    const int32_t l = b - prefix[o];
+    const bool from_scratch = (ob.flip ^ (pass & 1)) != 0;
+    const int32_t* in = (from_scratch ? scratch : seeds) + ob.vox_off;
+    int32_t* out = (from_scratch ? seeds : scratch) + ob.vox_off;
+    jfa_block(in, out, nx, ny, nz, k, chunks_per_residue(nz, k), l % gx, (l / gx) % gy, l / (gx * gy));
+}
+
 }  // namespace
+
+int64_t jfa_pass_blocks(const rtsdf_grid& g, int32_t k)
+{
+    return ceil_div(g.nx, kBX) * ceil_div(g.ny, kBY) * std::min<int64_t>(k, g.nz) * chunks_per_residue(g.nz, k);
+}
+
+hipError_t jfa_batched_pass(const BatchView& hv, const void* dplan, int32_t* seeds, int32_t* scratch, int32_t pass,
+                            hipStream_t s)
+{
+    const int32_t blocks = hv.h->pass_blocks[pass];
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_jfa_batched, dim3((unsigned)blocks), dim3(kBX, kBY), 0, s, (const char*)dplan,
+                       hv.h->nobj, pass, seeds, scratch);
+    return hipGetLastError();
+}
 
 hipError_t jfa_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, hipStream_t s)
 {
     const int64_t residues = std::min<int64_t>(k, g.nz);
-    const int64_t per_res = ceil_div(ceil_div(g.nz, k), kChunk);
+    const int64_t per_res = chunks_per_residue(g.nz, k);
     dim3 grid((unsigned)ceil_div(g.nx, kBX), (unsigned)ceil_div(g.ny, kBY), (unsigned)(residues * per_res));
     hipLaunchKernelGGL(k_jfa_stream, grid, dim3(kBX, kBY), 0, s, in, out, g.nx, g.ny, g.nz, k, (int32_t)per_res);
     return hipGetLastError();

@@ -60,6 +60,9 @@ __global__ void k_cursor_reset(int32_t* cursors)
     if (threadIdx.x < kXcds) cursors[threadIdx.x] = 0;
 }
 
+// kBatch: the mask list indexes concatenated grids; each voxel's object (binary search over
+// the plan's voxel prefix) supplies its grid, its hierarchy and the counter's object word.
+template <bool kBatch>
 __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__ bvh, const rtsdf_grid g,
                                                         const int32_t* __restrict__ list,
                                                         const int32_t* __restrict__ count_p, int32_t x,
@@ -67,30 +70,41 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
                                                         uint32_t obj, float* __restrict__ dmin,
                                                         uint32_t* __restrict__ hits,
                                                         uint64_t* __restrict__ argmin,
-                                                        int32_t* __restrict__ cursors)
+                                                        int32_t* __restrict__ cursors, const char* plan,
+                                                        int32_t nobj)
 {
     __shared__ uint64_t s_stk[kLdsDepth][kThreads];  // (t bits << 32) | child code
     int32_t p_code[kMaxStack - kLdsDepth];
     float p_t[kMaxStack - kLdsDepth];
 
-    const BvhHeader* H = (const BvhHeader*)bvh;
-    const int32_t nt = H->nt, root = H->root;
-    const float pad = H->pad;
-    const Bvh4Node* __restrict__ nodes = (const Bvh4Node*)(bvh + 256);
-    const BvhTri* __restrict__ tris =
-        (const BvhTri*)(bvh + 256 + sizeof(Bvh4Node) * (size_t)(nt > 1 ? nt - 1 : 1));
+    // the hierarchy and grid of the current voxel (fixed for a single object)
+    int32_t nt = 0, root = 0;
+    float pad = 0.0f;
+    const Bvh4Node* __restrict__ nodes = nullptr;
+    const BvhTri* __restrict__ tris = nullptr;
+    auto use_bvh = [&](const char* b) {
+        const BvhHeader* H = (const BvhHeader*)b;
+        nt = H->nt;
+        root = H->root;
+        pad = H->pad;
+        nodes = (const Bvh4Node*)(b + 256);
+        tris = (const BvhTri*)(b + 256 + sizeof(Bvh4Node) * (size_t)(nt > 1 ? nt - 1 : 1));
+    };
+    rtsdf_grid lg = g;
+    uint32_t lobj = obj;
+    if (!kBatch) use_bvh(bvh);
     const int32_t count = *count_p;
     const float inf = __int_as_float(0x7f800000);
     const int tid = threadIdx.x;
     const int lane = __lane_id();
     const uint64_t lt_mask = (1ull << lane) - 1ull;
     const uint32_t code0 = frame * (uint32_t)x;
-    const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny;
     int xcd = (int)(blockIdx.x % kXcds);  // the range this wave takes voxels from
     int tried = 0;                        // ranges found exhausted
     int32_t q_next = 0, q_end = 0;        // the wave's current chunk of the mask list
 
     int32_t vid = -1;
+    uint32_t lvid = 0;  // the voxel's index within its own grid (counter word)
     uint32_t j = 0;
     float acc_d = inf;
     uint32_t acc_h = 0;
@@ -171,11 +185,21 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
                 acc_d = inf;
                 acc_h = 0u;
                 acc_a = ~0ull;
-                const uint32_t uv = (uint32_t)vid;
-                const uint32_t row = uv / nx;
-                const uint32_t i0 = uv - row * nx, i1 = row % ny, i2 = row / ny;
-                o = make_float3(g.org[0] + g.h * ((float)i0 + 0.5f), g.org[1] + g.h * ((float)i1 + 0.5f),
-                                g.org[2] + g.h * ((float)i2 + 0.5f));
+                lvid = (uint32_t)vid;
+                if (kBatch) {
+                    const BatchView bv = batch_view(plan, nobj);
+                    const int32_t oi = find_object(bv.vox_prefix, nobj, (int64_t)vid);
+                    const BatchObject& ob = bv.obj[oi];
+                    lvid = (uint32_t)(vid - ob.vox_off);
+                    lg = ob.g;
+                    lobj = (uint32_t)oi;
+                    use_bvh(bvh + ob.bvh_off);
+                }
+                const uint32_t nx = (uint32_t)lg.nx, ny = (uint32_t)lg.ny;
+                const uint32_t row = lvid / nx;
+                const uint32_t i0 = lvid - row * nx, i1 = row % ny, i2 = row / ny;
+                o = make_float3(lg.org[0] + lg.h * ((float)i0 + 0.5f), lg.org[1] + lg.h * ((float)i1 + 0.5f),
+                                lg.org[2] + lg.h * ((float)i2 + 0.5f));
             }
             q_next += take;
             needers = __ballot(need);
@@ -183,7 +207,7 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
         if (need) alive = false;
         // start the next ray
         if (batch && alive && !active) {
-            w = sphere_direction(k0, k1, (uint32_t)vid, frame, j, obj);
+            w = sphere_direction(k0, k1, lvid, frame, j, lobj);
             inv = make_float3(slab_rcp(w.x), slab_rcp(w.y), slab_rcp(w.z));
             oinv = make_float3(o.x * inv.x, o.y * inv.y, o.z * inv.z);
             tb = inf;
@@ -287,7 +311,7 @@ hipError_t raysample(const void* bvh, const rtsdf_grid& g, const int32_t* list, 
     static int resident = 0;
     if (resident == 0) {
         int per_cu = 0, dev = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_raysample, kThreads, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_raysample<false>, kThreads, 0) != hipSuccess ||
             per_cu <= 0)
             per_cu = 4;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -297,8 +321,35 @@ hipError_t raysample(const void* bvh, const rtsdf_grid& g, const int32_t* list, 
     }
     const int64_t want = ceil_div(capacity, kThreads);
     const unsigned groups = (unsigned)std::max<int64_t>(kXcds, std::min<int64_t>(want, resident));
-    hipLaunchKernelGGL(k_raysample, dim3(groups), dim3(kThreads), 0, s, (const char*)bvh, g, list, count, x,
-                       (uint32_t)key, (uint32_t)(key >> 32), frame, obj, dmin, hits, argmin, cursors);
+    hipLaunchKernelGGL(k_raysample<false>, dim3(groups), dim3(kThreads), 0, s, (const char*)bvh, g, list, count, x,
+                       (uint32_t)key, (uint32_t)(key >> 32), frame, obj, dmin, hits, argmin, cursors, nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t raysample_batched(const BatchView& hv, const void* dplan, const void* bvh, const int32_t* list,
+                             const int32_t* count, int64_t capacity, int32_t x, uint64_t key, uint32_t frame,
+                             float* dmin, uint32_t* hits, uint64_t* argmin, void* work, hipStream_t s)
+{
+    if (capacity <= 0) return hipSuccess;
+    int32_t* cursors = (int32_t*)work;
+    hipLaunchKernelGGL(k_cursor_reset, dim3(1), dim3(64), 0, s, cursors);
+    static int resident = 0;
+    if (resident == 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_raysample<true>, kThreads, 0) != hipSuccess ||
+            per_cu <= 0)
+            per_cu = 4;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        resident = per_cu * cus;
+    }
+    const int64_t want = ceil_div(capacity, kThreads);
+    const unsigned groups = (unsigned)std::max<int64_t>(kXcds, std::min<int64_t>(want, resident));
+    const rtsdf_grid g0 = hv.obj[0].g;  // unused in batch mode
+    hipLaunchKernelGGL(k_raysample<true>, dim3(groups), dim3(kThreads), 0, s, (const char*)bvh, g0, list, count, x,
+                       (uint32_t)key, (uint32_t)(key >> 32), frame, 0u, dmin, hits, argmin, cursors,
+                       (const char*)dplan, hv.h->nobj);
     return hipGetLastError();
 }
 

@@ -54,17 +54,57 @@ __global__ void k_fill(int32_t* __restrict__ p, int64_t n, int32_t v)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
+// Where triangle t's geometry lives and which grid it is voxelized into.  Single object:
+// the arguments themselves.  Batch: t is global; its object (binary search over the
+// triangle prefix) supplies the vertex and triangle bases, the grid, and the output buffer
+// (`scratch` for objects with an odd JFA pass count, see rtsdf_voxelize_batched).
+struct TriSource {
+    const float* verts;
+    const int32_t* tris;
+    int32_t t;
+    rtsdf_grid g;
+    int32_t* out;
+};
+
+template <bool kBatch>
+__device__ inline TriSource tri_source(const float* verts, const int32_t* tris, int32_t t, const rtsdf_grid& g,
+                                       int32_t* seeds, const char* plan, int32_t nobj, int32_t* scratch)
+{
+    if (!kBatch) return TriSource{verts, tris, t, g, seeds};
+    const BatchView v = batch_view(plan, nobj);
+    const BatchObject& ob = v.obj[find_object(v.tri_prefix, nobj, t)];
+    return TriSource{verts + 3 * (int64_t)ob.vert_off, tris + 3 * (int64_t)ob.tri_off, t - ob.tri_off, ob.g,
+                     (ob.flip ? scratch : seeds) + ob.vox_off};
+}
+
+template <bool kBatch>
 __global__ void k_count(const float* __restrict__ verts, const int32_t* __restrict__ tris,
-                        int32_t nt, const rtsdf_grid g, uint64_t* __restrict__ counts)
+                        int32_t nt, const rtsdf_grid g, uint64_t* __restrict__ counts, const char* plan,
+                        int32_t nobj)
 {
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
+    const TriSource src = tri_source<kBatch>(verts, tris, t, g, nullptr, plan, nobj, nullptr);
     Snapped S;
     uint64_t c = 0;
-    if (snap_triangle(verts, tris, t, g, S))
+    if (snap_triangle(src.verts, src.tris, src.t, src.g, S))
         c = (uint64_t)(S.hi[0] - S.lo[0] + 1) * (uint64_t)(S.hi[1] - S.lo[1] + 1) *
             (uint64_t)(S.hi[2] - S.lo[2] + 1);
     counts[t] = c;
+}
+
+// Batch: every grid point of every object <- EMPTY in the buffer its seeds start in.
+// One kBatchAlign tile per work-group; tiles never straddle objects.
+__global__ __launch_bounds__(256) void k_fill_batched(const char* __restrict__ plan, int32_t nobj,
+                                                      int32_t* __restrict__ seeds, int32_t* __restrict__ scratch)
+{
+    const BatchView v = batch_view(plan, nobj);
+    const int64_t first = (int64_t)blockIdx.x * kBatchAlign;
+    const BatchObject& ob = v.obj[find_object(v.vox_prefix, nobj, first)];
+    const int64_t n = (int64_t)ob.g.nx * ob.g.ny * ob.g.nz;
+    int32_t* dst = ob.flip ? scratch : seeds;
+    for (int64_t i = first + threadIdx.x; i < first + kBatchAlign; i += 256)
+        if (i - ob.vox_off < n) dst[i] = RTSDF_EMPTY;
 }
 
 // Projection interval test on one axis: [min p, max p] against [-r, r].
@@ -133,17 +173,20 @@ __device__ bool overlaps(const Snapped& S, int32_t i, int32_t j, int32_t k)
     return true;
 }
 
+template <bool kBatch>
 __global__ __launch_bounds__(256) void k_candidates(const float* __restrict__ verts,
                                                     const int32_t* __restrict__ tris, int32_t nt,
                                                     const rtsdf_grid g,
                                                     const uint64_t* __restrict__ offsets,
                                                     const uint64_t* __restrict__ total_p,
-                                                    int32_t* __restrict__ seeds)
+                                                    int32_t* __restrict__ seeds, const char* plan,
+                                                    int32_t nobj, int32_t* __restrict__ scratch)
 {
     const uint64_t total = *total_p;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     int32_t cur = -1;
     Snapped S;
+    TriSource src;
     int32_t ex = 0, ey = 0;
     for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += stride) {
         // triangle owning candidate c: last t with offsets[t] <= c
@@ -155,7 +198,8 @@ __global__ __launch_bounds__(256) void k_candidates(const float* __restrict__ ve
         }
         if (lo != cur) {
             cur = lo;
-            snap_triangle(verts, tris, cur, g, S);
+            src = tri_source<kBatch>(verts, tris, cur, g, seeds, plan, nobj, scratch);
+            snap_triangle(src.verts, src.tris, src.t, src.g, S);
             ex = S.hi[0] - S.lo[0] + 1;
             ey = S.hi[1] - S.lo[1] + 1;
         }
@@ -165,7 +209,7 @@ __global__ __launch_bounds__(256) void k_candidates(const float* __restrict__ ve
         const int32_t j = S.lo[1] + (int32_t)(rest % (uint64_t)ey);
         const int32_t k = S.lo[2] + (int32_t)(rest / (uint64_t)ey);
         if (overlaps(S, i, j, k))
-            seeds[i + (int64_t)g.nx * (j + (int64_t)g.ny * k)] = i | (j << 10) | (k << 20);
+            src.out[i + (int64_t)src.g.nx * (j + (int64_t)src.g.ny * k)] = i | (j << 10) | (k << 20);
     }
 }
 
@@ -189,12 +233,36 @@ hipError_t voxelize(const float* verts, const int32_t* tris, int32_t nt, const r
     w += align256((size_t)(nt + 1) * 8);
     uint64_t* total = (uint64_t*)w;
     w += align256(8);
-    hipLaunchKernelGGL(k_count, dim3((unsigned)ceil_div(nt, 256)), dim3(256), 0, s, verts, tris, nt,
-                       g, offsets);
+    hipLaunchKernelGGL(k_count<false>, dim3((unsigned)ceil_div(nt, 256)), dim3(256), 0, s, verts, tris, nt,
+                       g, offsets, nullptr, 0);
     hipError_t e = scan_exclusive_u64(offsets, offsets, nt, total, w, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_candidates, dim3((unsigned)persistent_groups(256)), dim3(256), 0, s, verts,
-                       tris, nt, g, offsets, total, seeds);
+    hipLaunchKernelGGL(k_candidates<false>, dim3((unsigned)persistent_groups(256)), dim3(256), 0, s, verts,
+                       tris, nt, g, offsets, total, seeds, nullptr, 0, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t voxelize_batched(const BatchView& hv, const void* dplan, const float* verts, const int32_t* tris,
+                            int32_t* seeds, int32_t* scratch, void* work, hipStream_t s)
+{
+    const int32_t nobj = hv.h->nobj;
+    const char* plan = (const char*)dplan;
+    const int64_t tiles = hv.h->total_vox / kBatchAlign;
+    hipLaunchKernelGGL(k_fill_batched, dim3((unsigned)tiles), dim3(256), 0, s, plan, nobj, seeds, scratch);
+    const int32_t nt = (int32_t)hv.h->total_tris;
+    if (nt == 0) return hipGetLastError();
+    const rtsdf_grid g0 = hv.obj[0].g;  // unused in batch mode
+    char* w = (char*)work;
+    uint64_t* offsets = (uint64_t*)w;
+    w += align256((size_t)(nt + 1) * 8);
+    uint64_t* total = (uint64_t*)w;
+    w += align256(8);
+    hipLaunchKernelGGL(k_count<true>, dim3((unsigned)ceil_div(nt, 256)), dim3(256), 0, s, verts, tris, nt, g0,
+                       offsets, plan, nobj);
+    hipError_t e = scan_exclusive_u64(offsets, offsets, nt, total, w, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_candidates<true>, dim3((unsigned)persistent_groups(256)), dim3(256), 0, s, verts, tris,
+                       nt, g0, offsets, total, seeds, plan, nobj, scratch);
     return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@ whose backward passes call the adjoint entry points.
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librtsdf.so")
@@ -49,6 +50,16 @@ def make_shadow(width, height, x0, z0, dx, dz, y, light, k, steps, smin, smax, t
     return s
 
 
+class Object(ctypes.Structure):
+    _fields_ = [("g", Grid), ("nv", ctypes.c_int32), ("nt", ctypes.c_int32), ("band_vox", ctypes.c_int32),
+                ("extra_passes", ctypes.c_int32), ("beta", ctypes.c_float), ("bias", ctypes.c_float)]
+
+
+class BatchSizes(ctypes.Structure):
+    _fields_ = [("voxels", ctypes.c_int64), ("verts", ctypes.c_int64), ("tris", ctypes.c_int64),
+                ("bvh_bytes", ctypes.c_size_t), ("work_bytes", ctypes.c_size_t), ("max_passes", ctypes.c_int32)]
+
+
 def make_grid(dims, org, h):
     g = Grid()
     g.nx, g.ny, g.nz = (int(d) for d in dims)
@@ -84,6 +95,17 @@ def lib():
             "rtsdf_shadow_forward": ([vp, Grid, Shadow, vp, vp], i32),
             "rtsdf_shadow_backward": ([vp, Grid, Shadow, vp, vp, vp], i32),
             "rtsdf_backward": ([vp, vp, vp, vp, vp, i64, vp, vp, i32, i32, Grid, i32, u64, u32, vp, vp], i32),
+            "rtsdf_batch_plan_bytes": ([i32], sz),
+            "rtsdf_batch_plan": ([vp, i32, vp, vp, sz, vp], i32),
+            "rtsdf_batch_upload": ([vp, vp], i32),
+            "rtsdf_batch_offsets": ([vp, i32, vp, vp], i32),
+            "rtsdf_voxelize_batched": ([vp, vp, vp, vp, vp, vp, sz, vp], i32),
+            "rtsdf_jfa_batched": ([vp, vp, vp, vp], i32),
+            "rtsdf_band_batched": ([vp, vp, vp, vp, vp, sz, vp], i32),
+            "rtsdf_build_bvh_batched": ([vp, vp, vp, vp, sz, vp, sz, vp], i32),
+            "rtsdf_raysample_batched": ([vp, vp, vp, vp, i64, i32, u64, u32, vp, vp, vp, vp, sz, vp], i32),
+            "rtsdf_combine_batched": ([vp, vp, vp, vp, vp, vp], i32),
+            "rtsdf_backward_batched": ([vp, vp, vp, vp, vp, vp, i64, vp, vp, i32, u64, vp, vp], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -96,7 +118,10 @@ def lib():
 EXPORTED = ["rtsdf_last_error", "rtsdf_abi_version", "rtsdf_voxelize_work_bytes", "rtsdf_voxelize",
             "rtsdf_jfa", "rtsdf_band_work_bytes", "rtsdf_band", "rtsdf_bvh_bytes", "rtsdf_bvh_work_bytes",
             "rtsdf_build_bvh", "rtsdf_reset_accum", "rtsdf_raysample_work_bytes", "rtsdf_raysample",
-            "rtsdf_combine", "rtsdf_shadow_forward", "rtsdf_shadow_backward", "rtsdf_backward"]
+            "rtsdf_combine", "rtsdf_shadow_forward", "rtsdf_shadow_backward", "rtsdf_backward",
+            "rtsdf_batch_plan_bytes", "rtsdf_batch_plan", "rtsdf_batch_upload", "rtsdf_batch_offsets", "rtsdf_voxelize_batched",
+            "rtsdf_jfa_batched", "rtsdf_band_batched", "rtsdf_build_bvh_batched", "rtsdf_raysample_batched",
+            "rtsdf_combine_batched", "rtsdf_backward_batched"]
 
 
 def _ptr(t, dtype=None):
@@ -229,17 +254,207 @@ def rtsdf_backward(grad_fine, hits, argmin, band_list, band_count, bvh, tris, nv
                                 int(obj), _ptr(grad_verts, torch.float32), _stream(stream)), "rtsdf_backward")
 
 
+class Plan:
+    """A batch plan: the host copy (ctypes buffer), the device copy (uint8 tensor) and the
+    sizes of the concatenated arrays."""
+
+    def __init__(self, objects, device="cuda", stream=None, upload=True):
+        n = len(objects)
+        arr = (Object * n)(*objects)
+        nbytes = lib().rtsdf_batch_plan_bytes(n)
+        if nbytes == 0:
+            raise RtsdfError("bad object count %d" % n)
+        self.host = ctypes.create_string_buffer(nbytes)
+        self.nbytes = nbytes
+        self.sizes = BatchSizes()
+        if upload:
+            self.device = torch.empty(nbytes, dtype=torch.uint8, device=device)
+            dev_ptr = _ptr(self.device)
+        else:  # host-side inspection only: a placeholder device address, never dereferenced
+            self.device = None
+            dev_ptr = ctypes.c_void_p(0x1000)
+        _check(lib().rtsdf_batch_plan(ctypes.cast(arr, ctypes.c_void_p), n, ctypes.cast(self.host, ctypes.c_void_p),
+                                      dev_ptr, nbytes, ctypes.byref(self.sizes)), "rtsdf_batch_plan")
+        if upload:
+            _check(lib().rtsdf_batch_upload(self.ptr, _stream(stream)), "rtsdf_batch_upload")
+        self.nobj = n
+
+    @property
+    def ptr(self):
+        return ctypes.cast(self.host, ctypes.c_void_p)
+
+    def offsets(self, o):
+        v, b = ctypes.c_int64(0), ctypes.c_size_t(0)
+        _check(lib().rtsdf_batch_offsets(self.ptr, int(o), ctypes.byref(v), ctypes.byref(b)), "rtsdf_batch_offsets")
+        return v.value, b.value
+
+
+def make_object(dims, org, h, nv, nt, band_vox, extra_passes, beta, bias=0.0):
+    o = Object()
+    o.g = make_grid(dims, org, h)
+    o.nv, o.nt, o.band_vox, o.extra_passes = int(nv), int(nt), int(band_vox), int(extra_passes)
+    o.beta, o.bias = float(beta), float(bias)
+    return o
+
+
+def rtsdf_voxelize_batched(plan, verts, tris, seeds, scratch, work, stream=None):
+    _check(lib().rtsdf_voxelize_batched(plan.ptr, _ptr(verts, torch.float32), _ptr(tris, torch.int32),
+                                        _ptr(seeds, torch.int32), _ptr(scratch, torch.int32), _ptr(work), work.numel(),
+                                        _stream(stream)), "rtsdf_voxelize_batched")
+
+
+def rtsdf_jfa_batched(plan, seeds, scratch, stream=None):
+    _check(lib().rtsdf_jfa_batched(plan.ptr, _ptr(seeds, torch.int32), _ptr(scratch, torch.int32), _stream(stream)),
+           "rtsdf_jfa_batched")
+
+
+def rtsdf_band_batched(plan, seeds, band_list, band_count, work, stream=None):
+    _check(lib().rtsdf_band_batched(plan.ptr, _ptr(seeds, torch.int32), _ptr(band_list, torch.int32),
+                                    _ptr(band_count, torch.int32), _ptr(work), work.numel(), _stream(stream)),
+           "rtsdf_band_batched")
+
+
+def rtsdf_build_bvh_batched(plan, verts, tris, bvh, work, stream=None):
+    _check(lib().rtsdf_build_bvh_batched(plan.ptr, _ptr(verts, torch.float32), _ptr(tris, torch.int32), _ptr(bvh),
+                                         bvh.numel(), _ptr(work), work.numel(), _stream(stream)),
+           "rtsdf_build_bvh_batched")
+
+
+def rtsdf_raysample_batched(plan, bvh, band_list, band_count, rays_per_voxel, rng_key, frame, dmin, hits, work,
+                            argmin=None, band_capacity=None, stream=None):
+    cap = band_list.numel() if band_capacity is None else int(band_capacity)
+    _check(lib().rtsdf_raysample_batched(plan.ptr, _ptr(bvh), _ptr(band_list, torch.int32),
+                                         _ptr(band_count, torch.int32), cap, int(rays_per_voxel),
+                                         int(rng_key) & (2 ** 64 - 1), int(frame), _ptr(dmin, torch.float32),
+                                         _ptr(hits, torch.int32), _ptr(argmin, torch.int64) if argmin is not None
+                                         else None, _ptr(work), work.numel(), _stream(stream)),
+           "rtsdf_raysample_batched")
+
+
+def rtsdf_combine_batched(plan, seeds, dmin, hits, fine, stream=None):
+    _check(lib().rtsdf_combine_batched(plan.ptr, _ptr(seeds, torch.int32), _ptr(dmin, torch.float32),
+                                       _ptr(hits, torch.int32), _ptr(fine, torch.float32), _stream(stream)),
+           "rtsdf_combine_batched")
+
+
+def rtsdf_backward_batched(plan, grad_fine, hits, argmin, band_list, band_count, bvh, tris, rays_per_voxel, rng_key,
+                           grad_verts, band_capacity=None, stream=None):
+    cap = band_list.numel() if band_capacity is None else int(band_capacity)
+    _check(lib().rtsdf_backward_batched(plan.ptr, _ptr(grad_fine, torch.float32), _ptr(hits, torch.int32),
+                                        _ptr(argmin, torch.int64), _ptr(band_list, torch.int32),
+                                        _ptr(band_count, torch.int32), cap, _ptr(bvh), _ptr(tris, torch.int32),
+                                        int(rays_per_voxel), int(rng_key) & (2 ** 64 - 1),
+                                        _ptr(grad_verts, torch.float32), _stream(stream)), "rtsdf_backward_batched")
+
+
+class BatchSDF:
+    """Many static objects, each on its own grid, with one launch per stage (per JFA pass):
+    voxelize, jump flood, mask, hierarchies, `frames` x ray sampling, combine (running
+    minimum), and the vertex adjoint.  `objects` are (verts, tris, dims, org, h, steps, band)
+    records such as synth.Scene; each object's JFA offsets must be the standard halving list
+    plus trailing passes of 1.  Object o draws its rays with counter word obj = o, so its
+    results equal StaticSDF(..., obj=o).  No call reads anything back to the host."""
+
+    def __init__(self, objects, rays, frames=1, rng_key=0, beta=None, bias=0.0, device="cuda"):
+        recs = []
+        for sc in objects:
+            std = _halving_offsets(sc.dims)
+            steps = list(sc.steps)
+            extra = len(steps) - len(std)
+            if steps[:len(std)] != std or any(k != 1 for k in steps[len(std):]):
+                raise RtsdfError("batched objects use the halving offsets plus passes of 1, got %s" % steps)
+            b = float(sc.h) / 2 if beta is None else float(beta)
+            recs.append(make_object(sc.dims, sc.org, sc.h, len(sc.verts), len(sc.tris), sc.band, extra, b, bias))
+        self.plan = Plan(recs, device)
+        z = self.plan.sizes
+        self.rays, self.frames, self.rng_key = int(rays), int(frames), int(rng_key)
+        self.verts = torch.from_numpy(np.concatenate([np.asarray(sc.verts, np.float32).reshape(-1, 3)
+                                                      for sc in objects])).to(device)
+        self.tris = torch.from_numpy(np.concatenate([np.asarray(sc.tris, np.int32).reshape(-1, 3)
+                                                     for sc in objects])).to(device)
+        V = z.voxels
+        self.seeds = torch.empty(V, dtype=torch.int32, device=device)
+        self.scratch = torch.empty(V, dtype=torch.int32, device=device)
+        self.band_list = torch.empty(V, dtype=torch.int32, device=device)
+        self.band_count = torch.zeros(1, dtype=torch.int32, device=device)
+        self.dmin = torch.empty(V, dtype=torch.float32, device=device)
+        self.hits = torch.empty(V, dtype=torch.int32, device=device)
+        self.argmin = torch.empty(V, dtype=torch.int64, device=device)
+        self.fine = torch.empty(V, dtype=torch.float32, device=device)
+        self.bvh = torch.empty(max(int(z.bvh_bytes), 1), dtype=torch.uint8, device=device)
+        self.work = workspace(z.work_bytes, device)
+        self.offsets = [self.plan.offsets(o) for o in range(len(objects))]
+        self.dims = [tuple(sc.dims) for sc in objects]
+
+    def voxelize(self):
+        rtsdf_voxelize_batched(self.plan, self.verts, self.tris, self.seeds, self.scratch, self.work)
+
+    def jfa(self):
+        rtsdf_jfa_batched(self.plan, self.seeds, self.scratch)
+
+    def mask(self):
+        rtsdf_band_batched(self.plan, self.seeds, self.band_list, self.band_count, self.work)
+
+    def build_bvh(self):
+        rtsdf_build_bvh_batched(self.plan, self.verts, self.tris, self.bvh, self.work)
+
+    def trace(self, frame):
+        rtsdf_raysample_batched(self.plan, self.bvh, self.band_list, self.band_count, self.rays, self.rng_key, frame,
+                                self.dmin, self.hits, self.work, self.argmin)
+
+    def combine(self):
+        rtsdf_combine_batched(self.plan, self.seeds, self.dmin, self.hits, self.fine)
+
+    def run(self):
+        self.voxelize()
+        self.jfa()
+        self.mask()
+        self.build_bvh()
+        rtsdf_reset_accum(self.dmin, self.hits, self.argmin)
+        for f in range(self.frames):
+            self.trace(f)
+        self.combine()
+        return self.fine
+
+    def backward(self, grad_fine, grad_verts=None):
+        if grad_verts is None:
+            grad_verts = torch.zeros_like(self.verts)
+        rtsdf_backward_batched(self.plan, grad_fine.contiguous(), self.hits, self.argmin, self.band_list,
+                               self.band_count, self.bvh, self.tris, self.rays, self.rng_key, grad_verts)
+        return grad_verts
+
+    def view(self, t, o):
+        """Object o's part of a concatenated per-grid-point tensor."""
+        off = self.offsets[o][0]
+        n = int(np.prod(self.dims[o]))
+        return t[off:off + n]
+
+
+def _halving_offsets(dims):
+    n = max(dims)
+    k = 1
+    while k < n:
+        k *= 2
+    out = []
+    k //= 2
+    while k >= 1:
+        out.append(k)
+        k //= 2
+    return out or [1]
+
+
 class StaticSDF:
     """Device buffers and the call chain for one static scene (sections 2.1-2.3).
 
     run() = voxelize, jump flood, mask, BVH, `frames` x ray sampling (running minimum),
-    combine.  Buffers are allocated in __init__; mask() reads the mask count back to the
-    host once (it bounds the ray-sampling and adjoint launches).  set_verts() replaces the
-    vertex positions in place (same triangle list) for optimisation loops.
+    combine.  Buffers are allocated in __init__ and no call reads anything back to the host
+    (the mask count stays on the device; launches are bounded by the grid size).  `obj` is
+    the object word of the ray counters.  set_verts() replaces the vertex positions in place
+    (same triangle list) for optimisation loops.
     """
 
     def __init__(self, verts, tris, dims, org, h, steps, band, rays, frames, beta=None, bias=0.0,
-                 rng_key=0, keep_argmin=True, device="cuda"):
+                 rng_key=0, keep_argmin=True, obj=0, device="cuda"):
         self.g = make_grid(dims, org, h)
         N = self.g.n
         self.verts = torch.as_tensor(verts, dtype=torch.float32).reshape(-1, 3).contiguous().to(device)
@@ -247,7 +462,7 @@ class StaticSDF:
         nt = self.tris.shape[0]
         self.steps, self.band, self.rays, self.frames = list(steps), int(band), int(rays), int(frames)
         self.beta = float(h) / 2 if beta is None else float(beta)
-        self.bias, self.rng_key = float(bias), int(rng_key)
+        self.bias, self.rng_key, self.obj = float(bias), int(rng_key), int(obj)
         self.seeds = torch.empty(N, dtype=torch.int32, device=device)
         self.scratch = torch.empty(N, dtype=torch.int32, device=device)
         self.band_list = torch.empty(N, dtype=torch.int32, device=device)
@@ -259,8 +474,8 @@ class StaticSDF:
         self.bvh = torch.empty(rtsdf_bvh_bytes(nt), dtype=torch.uint8, device=device)
         wb = max(rtsdf_voxelize_work_bytes(nt), rtsdf_band_work_bytes(self.g), rtsdf_bvh_work_bytes(nt))
         self.work = workspace(wb, device)
-        self.ray_work = workspace(rtsdf_raysample_work_bytes(0, self.rays), device)
-        self.band_n = 0
+        self.ray_work = workspace(rtsdf_raysample_work_bytes(N, self.rays), device)
+        self.band_n = N  # launch bound for the mask list
         self.device = device
         self.jfa_out = None
 
@@ -275,17 +490,13 @@ class StaticSDF:
 
     def mask(self):
         rtsdf_band(self.jfa_out, self.g, self.band, self.band_list, self.band_count, self.work)
-        self.band_n = int(self.band_count.item())
-        need = rtsdf_raysample_work_bytes(self.band_n, self.rays)
-        if self.ray_work.numel() < need:
-            self.ray_work = workspace(need, self.device)
 
     def build_bvh(self):
         rtsdf_build_bvh(self.verts, self.tris, self.g, self.bvh, self.work)
 
     def trace(self, frame):
         rtsdf_raysample(self.bvh, self.g, self.band_list, self.band_count, self.rays, self.rng_key, frame,
-                        self.dmin, self.hits, self.ray_work, self.argmin, band_capacity=self.band_n)
+                        self.dmin, self.hits, self.ray_work, self.argmin, obj=self.obj, band_capacity=self.band_n)
 
     def combine(self):
         rtsdf_combine(self.jfa_out, self.dmin, self.hits, self.g, self.band, self.beta, self.bias, ACCUM,
@@ -309,7 +520,7 @@ class StaticSDF:
         if grad_verts is None:
             grad_verts = torch.zeros_like(self.verts)
         rtsdf_backward(grad_fine.contiguous(), self.hits, self.argmin, self.band_list, self.band_count, self.bvh,
-                       self.tris, self.verts.shape[0], self.g, self.rays, self.rng_key, grad_verts,
+                       self.tris, self.verts.shape[0], self.g, self.rays, self.rng_key, grad_verts, obj=self.obj,
                        band_capacity=self.band_n)
         return grad_verts
 

@@ -326,6 +326,36 @@ def scene_grad(dims=(128, 128, 128), subdiv=5, image=512):
                         "shadow": shadow_setup(h, width=image, height=image)})
 
 
+def scene_batch(nobj=64, seed=2, tri_range=(1e3, 2e5), n_range=(32, 256)):
+    """Many uneven objects, each on its own unit-cube grid: triangle budget T_o log-uniform
+    on tri_range, grid side n_o = round(log-uniform on n_range), h = 1/n_o; each object is the
+    union of 4 UV spheres / tori (random type, rotation and position, inside [0.1, 0.9]^3)
+    tessellated so that the four together have about T_o triangles.  Offsets
+    2^(ceil(log2 n)-1)..1 plus one extra pass of 1, 4-voxel mask, 8 rays, one frame."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for o in range(nobj):
+        T = float(np.exp(rng.uniform(np.log(tri_range[0]), np.log(tri_range[1]))))
+        n = int(round(float(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]))))))
+        meshes = []
+        for _ in range(4):
+            kind = int(rng.integers(0, 2))
+            s = float(rng.uniform(0.08, 0.17))
+            ext = s if kind == 0 else 1.35 * s
+            c = rng.uniform(0.1 + ext, 0.9 - ext, size=3)
+            rot = random_rotation(rng)
+            m = max(3, int(round(np.sqrt(T / 4.0 / 4.0))))  # 4 m^2 triangles per primitive
+            if kind == 0:
+                meshes.append(uv_sphere(s, c, nseg=2 * m, nring=m + 1, rot=rot))
+            else:
+                meshes.append(torus(s, 0.35 * s, c, nmaj=2 * m, nmin=m, rot=rot))
+        v, t = merge(meshes)
+        dims = (n, n, n)
+        out.append(Scene(v, t, dims, (0.0, 0.0, 0.0), 1.0 / n, jfa_offsets(dims, extra=1), 4, 8, 1,
+                         name="object%02d-%d-tris-%d^3" % (o, len(t), n)))
+    return out
+
+
 def scene_static(dims=(400, 200, 400), nprims=200, seed=0):
     """Paper-shaped static scene over the box [0,2] x [0,1] x [0,2]: a ground quad at
     y = 0.05 (on a voxel face at the full resolution) plus `nprims` boxes, UV spheres and
