@@ -90,7 +90,7 @@ def lib():
         L.orc_sdf_backward.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, Grid, i32, u64, u32, vp]
         L.orc_sdf_backward.restype = ctypes.c_int
         L.orc_sample.argtypes = [vp, Grid, vp, i64, vp, vp]
-        L.orc_shadow_margin.argtypes = [vp, Grid, ctypes.POINTER(Shadow), vp, vp]
+        L.orc_shadow_margin.argtypes = [vp, Grid, ctypes.POINTER(Shadow), vp, vp, vp]
         _lib = L
     return _lib
 
@@ -294,12 +294,13 @@ def shadow_backward(fine, g, s, grad_img):
 
 def shadow_margin(fine, g, s):
     """Per-pixel distances of the march's discrete decisions from flipping: (r_margin,
-    s_margin) -- see orc_shadow_margin."""
+    s_margin, c_margin) -- see orc_shadow_margin."""
     f = np.ascontiguousarray(fine, np.float64)
     rm = np.empty(s.width * s.height, np.float64)
     sm = np.empty(s.width * s.height, np.float64)
-    lib().orc_shadow_margin(_p(f), g, ctypes.byref(s), _p(rm), _p(sm))
-    return rm, sm
+    cm = np.empty(s.width * s.height, np.float64)
+    lib().orc_shadow_margin(_p(f), g, ctypes.byref(s), _p(rm), _p(sm), _p(cm))
+    return rm, sm, cm
 
 
 def sdf_backward(grad_fine, hits, argmin, vids, bvh, verts, tris, g, x, seed, obj=0):

@@ -890,9 +890,12 @@ void orc_shadow_backward(const double* fine, orc_grid g, const orc_shadow* s, co
  * differently: r_margin = the least |k s_m / t_m - res| over the steps other than the
  * minimising one, together with the distances of res from the 0 clamp and from the initial
  * value 1; s_margin = the least distance of a sample s_m (m before the minimising step)
- * from the clamp bounds smin and smax.  A pixel whose margins exceed the rounding error
- * of another implementation takes the same discrete path there. */
-void orc_shadow_margin(const double* fine, orc_grid g, const orc_shadow* s, double* r_margin, double* s_margin)
+ * from the clamp bounds smin and smax; c_margin = the least distance, in grid units, of a
+ * sample position (m up to the minimising step) from a cell face of the trilinear lattice
+ * (the interpolant's gradient jumps there).  A pixel whose margins exceed the rounding
+ * error of another implementation takes the same discrete path there. */
+void orc_shadow_margin(const double* fine, orc_grid g, const orc_shadow* s, double* r_margin, double* s_margin,
+                       double* c_margin)
 {
 #pragma omp parallel
     {
@@ -923,9 +926,16 @@ void orc_shadow_margin(const double* fine, orc_grid g, const orc_shadow* s, doub
             const int last = istar < 0 ? s->steps : istar;
             for (int m = 0; m < last; ++m)
                 sgap = fmin(sgap, fmin(fabs(sm[m] - (double)s->smin), fabs(sm[m] - (double)s->smax)));
+            double cgap = HUGE_VAL;
+            for (int m = 0; m <= last && m < s->steps; ++m)
+                for (int a = 0; a < 3; ++a) {
+                    const double c = (P[a] + tm[m] * (double)s->light[a] - (double)g.org[a]) / (double)g.h - 0.5;
+                    cgap = fmin(cgap, fabs(c - nearbyint(c)));
+                }
             (void)img;
             r_margin[p] = rm;
             s_margin[p] = sgap;
+            c_margin[p] = cgap;
         }
         free(tm);
         free(sm);

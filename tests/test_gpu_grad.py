@@ -5,9 +5,12 @@ Bars (the oracle computes in binary64, the kernels in binary32):
   * shadow image: |img_gpu - img_oracle| <= 1e-4 per pixel (pixel values lie in [0, 1]; a
     64-step march accumulates t with 64 binary32 additions and samples the field at points
     rounded to binary32, about 1e-6 relative each, so 1e-4 leaves a wide margin);
-  * shadow adjoint: the march's discrete choices (minimising step, clamp flags) are only
-    compared where the oracle's decision margins exceed what binary32 rounding can move
-    (r_margin > 1e-4, s_margin > 1e-5; other pixels get zero image gradient), then
+  * shadow adjoint: the march's discrete choices (minimising step, clamp flags, and the
+    trilinear cell of every sample up to the minimising step, across whose faces the
+    field's gradient jumps) are only compared where the oracle's decision margins exceed
+    what binary32 rounding can move (r_margin > 1e-4, s_margin > 1e-5, c_margin > 2e-3
+    grid units; a 64-step binary32 march places samples within about 1e-4 grid units;
+    other pixels get zero image gradient), then
     grad_fine is compared element by element, |diff| <= 1e-3 |g| + 1e-4 max|g|
     (binary32 atomics sum in a varying order);
   * vertex adjoint: the integer state is compared bit-exactly first (seeds, mask, hits,
@@ -99,8 +102,8 @@ def test_shadow_forward_parity(R, orc, name, dims, w, hgt):
 
 
 def safe_pixels(orc, f, g, s, img):
-    rm, sm = orc.shadow_margin(f, g, s)
-    return (img > 0) & (img < 1) & (rm > 1e-4) & (sm > 1e-5)
+    rm, sm, cm = orc.shadow_margin(f, g, s)
+    return (img > 0) & (img < 1) & (rm > 1e-4) & (sm > 1e-5) & (cm > 2e-3)
 
 
 @pytest.mark.parametrize("name,dims,w,hgt", shadow_cases())
@@ -115,7 +118,7 @@ def test_shadow_backward_parity(R, orc, name, dims, w, hgt):
     safe = safe_pixels(orc, f, g_o, s_o, io)
     gi = np.where(safe, np.random.default_rng(5).normal(size=io.size), 0.0).astype(np.float32)
     log("  safe penumbra pixels", safe.sum(), "of", ((io > 0) & (io < 1)).sum())
-    assert safe.sum() >= 0.9 * ((io > 0) & (io < 1)).sum()
+    assert safe.sum() >= 0.6 * ((io > 0) & (io < 1)).sum()
     go = orc.shadow_backward(f, g_o, s_o, gi.astype(np.float64))
     gg = gpu_shadow_bwd(R, f, g_r, R.make_shadow(**p), gi)
     assert np.abs(go).max() > 0
@@ -265,11 +268,12 @@ def test_adjoint_edge_cases(R, orc):
         io = orc.shadow_forward(f, g_o, orc.make_shadow(**p))
         ig = gpu_img(R, f, g_r, R.make_shadow(**p))
         assert np.abs(ig - io).max() <= 1e-4
-    p = synth.shadow_setup(h, width=0, height=0)
+    empty = R.make_shadow(**synth.shadow_setup(h, width=8, height=8))
+    empty.width = empty.height = 0
     img = torch.empty(0, device="cuda")
-    R.rtsdf_shadow_forward(torch.from_numpy(f).cuda(), g_r, R.make_shadow(**p), img)
+    R.rtsdf_shadow_forward(torch.from_numpy(f).cuda(), g_r, empty, img)
     gf = torch.zeros(len(f), device="cuda")
-    R.rtsdf_shadow_backward(torch.from_numpy(f).cuda(), g_r, R.make_shadow(**p), img, gf)
+    R.rtsdf_shadow_backward(torch.from_numpy(f).cuda(), g_r, empty, img, gf)
     torch.cuda.synchronize()
     assert (gf == 0).all()
     # zero upstream gradient gives zero vertex gradient; all-lit image gives zero field gradient
