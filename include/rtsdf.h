@@ -203,7 +203,8 @@ typedef struct rtsdf_shadow {
 } rtsdf_shadow;
 
 /* rtsdf_shadow_forward -- the shadow image of the fine field.
- *   fine [N] float (rtsdf_combine output)     img [height * width] float out
+ *   fine [N] float (rtsdf_combine output)     img [height * width] float out (may be NULL
+ *   when the image has no pixels)
  * Errors: E_ARG (null pointers, bad grid, non-finite or out-of-range parameters),
  * E_RANGE (image size, steps). */
 rtsdf_status rtsdf_shadow_forward(const float* fine, rtsdf_grid g, rtsdf_shadow s, float* img,

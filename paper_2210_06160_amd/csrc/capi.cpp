@@ -438,7 +438,8 @@ rtsdf_status rtsdf_shadow_forward(const float* fine, rtsdf_grid g, rtsdf_shadow 
 {
     if (rtsdf_status st = check_grid(g)) return st;
     if (rtsdf_status st = check_shadow(s)) return st;
-    if (!fine || !img) return fail(RTSDF_E_ARG, "NULL pointer");
+    const bool empty = s.width == 0 || s.height == 0;
+    if (!fine || (!img && !empty)) return fail(RTSDF_E_ARG, "NULL pointer");
     return device(rtsdf::shadow_forward(fine, g, s, img, as_stream(stream)), "shadow_forward");
 }
 
@@ -447,7 +448,8 @@ rtsdf_status rtsdf_shadow_backward(const float* fine, rtsdf_grid g, rtsdf_shadow
 {
     if (rtsdf_status st = check_grid(g)) return st;
     if (rtsdf_status st = check_shadow(s)) return st;
-    if (!fine || !grad_img || !grad_fine) return fail(RTSDF_E_ARG, "NULL pointer");
+    const bool empty = s.width == 0 || s.height == 0;
+    if (!fine || !grad_fine || (!grad_img && !empty)) return fail(RTSDF_E_ARG, "NULL pointer");
     if (fine == grad_fine) return fail(RTSDF_E_ARG, "fine and grad_fine must not alias");
     return device(rtsdf::shadow_backward(fine, g, s, grad_img, grad_fine, as_stream(stream)), "shadow_backward");
 }
