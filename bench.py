@@ -135,7 +135,9 @@ def grad_bench(torch, rtsdf, synth, reps=20):
     launch stream."""
     import statistics
     sc = synth.scene_grad()
-    S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
+    # an optimisation loop rebuilds the hierarchy every step: the fast-to-build tree
+    S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames,
+                        bvh_method=rtsdf.BVH_LBVH)
     sh = rtsdf.make_shadow(**sc.extra["shadow"])
     tgt = torch.from_numpy(sc.extra["target"].astype("float32")).cuda()
     timg = torch.from_numpy(sc.extra["target_img"]).cuda().reshape(sh.height, sh.width)

@@ -110,17 +110,26 @@ rtsdf_status rtsdf_band(const int32_t* seeds, rtsdf_grid g, int32_t band_vox, in
 /* ---------------------------------------------------------------------------------------
  * rtsdf_build_bvh -- acceleration structure for the ray sampling of section 2.1 (the
  * paper uses the graphics driver's hierarchy; CDNA has no ray-tracing units, so this is
- * a software linear BVH: 30-bit Morton codes of triangle centroids, stable radix sort,
- * Karras (2012) binary radix tree, bottom-up box refit).  Triangle boxes are widened by
- * 2 * h/256 so that traversal returns exactly the brute-force closest hit of the hit test
- * described at rtsdf_raysample.  The blob is self-contained (it copies the triangles).
+ * a software hierarchy built from 30-bit Morton codes of triangle centroids and a stable
+ * radix sort, then either
+ *   RTSDF_BVH_LBVH: the Karras (2012) binary radix tree with a bottom-up box refit (fast
+ *                   to build; for per-frame rebuilds), or
+ *   RTSDF_BVH_PLOC: parallel locally-ordered clustering (Meister & Bittner 2018: merge
+ *                   mutual nearest neighbours by merged-box area within +-16 clusters
+ *                   in Morton order; about 30 % fewer node visits per ray),
+ * collapsed to a 4-wide hierarchy.  Triangle boxes are widened by 2 * h/256 so that
+ * traversal returns exactly the brute-force closest hit of the hit test described at
+ * rtsdf_raysample, whichever tree is built.  The blob is self-contained (it copies the
+ * triangles).
  *   bvh   [rtsdf_bvh_bytes(nt)] out      work [rtsdf_bvh_work_bytes(nt)]
- * Errors: E_ARG, E_RANGE (nt outside [0, 2^26]), E_SIZE.
+ * Errors: E_ARG, E_RANGE (nt outside [0, 2^26], unknown method), E_SIZE.
  * ------------------------------------------------------------------------------------- */
+#define RTSDF_BVH_LBVH 0
+#define RTSDF_BVH_PLOC 1
 size_t rtsdf_bvh_bytes(int32_t nt);
 size_t rtsdf_bvh_work_bytes(int32_t nt);
 rtsdf_status rtsdf_build_bvh(const float* verts, int32_t nv, const int32_t* tris, int32_t nt,
-                             rtsdf_grid g, void* bvh, size_t bvh_bytes, void* work,
+                             rtsdf_grid g, int32_t method, void* bvh, size_t bvh_bytes, void* work,
                              size_t work_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------
@@ -312,9 +321,12 @@ rtsdf_status rtsdf_jfa_batched(const void* plan_host, int32_t* seeds, int32_t* s
  * points, increasing.  band_list [sizes.voxels] int32, band_count [1] int32 (device). */
 rtsdf_status rtsdf_band_batched(const void* plan_host, const int32_t* seeds, int32_t* band_list,
                                 int32_t* band_count, void* work, size_t work_bytes, void* stream);
-/* As rtsdf_build_bvh per object (grid of the object sets the hit padding). */
-rtsdf_status rtsdf_build_bvh_batched(const void* plan_host, const float* verts, const int32_t* tris, void* bvh,
-                                     size_t bvh_bytes, void* work, size_t work_bytes, void* stream);
+/* As rtsdf_build_bvh per object (the object's grid sets the hit padding); every phase of
+ * the build is one launch for all objects (a segmented sort, then the tree of each object
+ * in its own segment). */
+rtsdf_status rtsdf_build_bvh_batched(const void* plan_host, const float* verts, const int32_t* tris,
+                                     int32_t method, void* bvh, size_t bvh_bytes, void* work, size_t work_bytes,
+                                     void* stream);
 /* As rtsdf_raysample per object with obj = the object's index; one launch for the batch. */
 rtsdf_status rtsdf_raysample_batched(const void* plan_host, const void* bvh, const int32_t* band_list,
                                      const int32_t* band_count, int64_t band_capacity, int32_t rays_per_voxel,

@@ -70,7 +70,7 @@ size_t batch_work_bytes(const rtsdf::BatchView& v)
     size_t w = 256;  // ray-sampling cursors
     w = std::max(w, rtsdf::voxelize_work_bytes((int32_t)v.h->total_tris));
     w = std::max(w, rtsdf::band_batched_work_bytes(v.h->total_vox));
-    for (int32_t o = 0; o < v.h->nobj; ++o) w = std::max(w, rtsdf::bvh_work_bytes(v.obj[o].nt));
+    w = std::max(w, rtsdf::bvh_work_bytes(v.h->total_tris, v.h->total_tiles, v.h->nobj));
     return w;
 }
 
@@ -109,7 +109,7 @@ rtsdf_status rtsdf_batch_plan(const rtsdf_object* objs, int32_t nobj, void* plan
     int64_t* vox_prefix = const_cast<int64_t*>(v.vox_prefix);
     int32_t* tri_prefix = const_cast<int32_t*>(v.tri_prefix);
     int32_t* pass_prefix = const_cast<int32_t*>(v.pass_prefix);
-    int64_t vox = 0, verts = 0, tris = 0;
+    int64_t vox = 0, verts = 0, tris = 0, tiles = 0;
     uint64_t bvh = 0;
     int32_t max_passes = 0;
     for (int32_t o = 0; o < nobj; ++o) {
@@ -144,6 +144,8 @@ rtsdf_status rtsdf_batch_plan(const rtsdf_object* objs, int32_t nobj, void* plan
         b.flip = b.nsteps & 1;
         b.beta = in.beta;
         b.bias = in.bias;
+        b.tile_off = (int32_t)tiles;
+        tiles += ceil_div(in.nt, kBvhSortTile);
         vox_prefix[o] = vox;
         tri_prefix[o] = (int32_t)tris;
         vox += ceil_div(nvox(in.g), kBatchAlign) * kBatchAlign;
@@ -174,6 +176,7 @@ rtsdf_status rtsdf_batch_plan(const rtsdf_object* objs, int32_t nobj, void* plan
     h->total_verts = verts;
     h->total_tris = tris;
     h->bvh_bytes = bvh;
+    h->total_tiles = (int32_t)tiles;
     h->plan_bytes = bytes;
     h->device = plan_device;
     std::memcpy(plan_host, buf.data(), bytes);
@@ -243,23 +246,18 @@ rtsdf_status rtsdf_band_batched(const void* plan, const int32_t* seeds, int32_t*
                   "band_batched");
 }
 
-rtsdf_status rtsdf_build_bvh_batched(const void* plan, const float* verts, const int32_t* tris, void* bvh,
-                                     size_t bvh_bytes, void* work, size_t work_bytes, void* stream)
+rtsdf_status rtsdf_build_bvh_batched(const void* plan, const float* verts, const int32_t* tris, int32_t method,
+                                     void* bvh, size_t bvh_bytes, void* work, size_t work_bytes, void* stream)
 {
     rtsdf::BatchView v;
     if (rtsdf_status st = check_plan(plan, v)) return st;
     if (!bvh || !work) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (method != RTSDF_BVH_LBVH && method != RTSDF_BVH_PLOC) return fail(RTSDF_E_RANGE, "unknown method %d", method);
     if (v.h->total_tris > 0 && (!verts || !tris)) return fail(RTSDF_E_ARG, "verts or tris is NULL");
     if (bvh_bytes < v.h->bvh_bytes) return fail(RTSDF_E_SIZE, "bvh %zu < %zu bytes", bvh_bytes, (size_t)v.h->bvh_bytes);
     if (work_bytes < batch_work_bytes(v)) return fail(RTSDF_E_SIZE, "work %zu < %zu bytes", work_bytes, batch_work_bytes(v));
-    // one build chain per object: the sort and tree passes depend on each object's size
-    for (int32_t o = 0; o < v.h->nobj; ++o) {
-        const rtsdf::BatchObject& b = v.obj[o];
-        hipError_t e = rtsdf::build_bvh(verts + 3 * (int64_t)b.vert_off, tris + 3 * (int64_t)b.tri_off, b.nt, b.g,
-                                        (char*)bvh + b.bvh_off, work, as_stream(stream));
-        if (e != hipSuccess) return device(e, "build_bvh_batched");
-    }
-    return ok();
+    return device(rtsdf::build_bvh_batched(v, v.h->device, verts, tris, bvh, work, method, as_stream(stream)),
+                  "build_bvh_batched");
 }
 
 rtsdf_status rtsdf_raysample_batched(const void* plan, const void* bvh, const int32_t* band_list,
@@ -369,9 +367,10 @@ size_t rtsdf_bvh_bytes(int32_t nt) { return nt < 0 ? 0 : rtsdf::bvh_bytes(nt); }
 size_t rtsdf_bvh_work_bytes(int32_t nt) { return nt < 0 ? 0 : rtsdf::bvh_work_bytes(nt); }
 
 rtsdf_status rtsdf_build_bvh(const float* verts, int32_t nv, const int32_t* tris, int32_t nt,
-                             rtsdf_grid g, void* bvh, size_t bvh_bytes, void* work, size_t work_bytes,
-                             void* stream)
+                             rtsdf_grid g, int32_t method, void* bvh, size_t bvh_bytes, void* work,
+                             size_t work_bytes, void* stream)
 {
+    if (method != RTSDF_BVH_LBVH && method != RTSDF_BVH_PLOC) return fail(RTSDF_E_RANGE, "unknown method %d", method);
     if (rtsdf_status st = check_grid(g)) return st;
     if (nv < 0 || nt < 0 || nt > (1 << 26)) return fail(RTSDF_E_RANGE, "nt %d outside [0, 2^26]", nt);
     if (!bvh) return fail(RTSDF_E_ARG, "bvh is NULL");
@@ -381,7 +380,7 @@ rtsdf_status rtsdf_build_bvh(const float* verts, int32_t nv, const int32_t* tris
         return fail(RTSDF_E_SIZE, "bvh buffer %zu < %zu bytes", bvh_bytes, rtsdf::bvh_bytes(nt));
     if (nt > 0 && work_bytes < rtsdf::bvh_work_bytes(nt))
         return fail(RTSDF_E_SIZE, "bvh work %zu < %zu bytes", work_bytes, rtsdf::bvh_work_bytes(nt));
-    return device(rtsdf::build_bvh(verts, tris, nt, g, bvh, work, as_stream(stream)), "build_bvh");
+    return device(rtsdf::build_bvh(verts, tris, nt, g, bvh, work, method, as_stream(stream)), "build_bvh");
 }
 
 rtsdf_status rtsdf_reset_accum(float* dmin, uint32_t* hits, uint64_t* argmin, int64_t n, void* stream)

@@ -43,9 +43,11 @@ hipError_t band(const int32_t* seeds, const rtsdf_grid& g, int32_t band_vox, int
                 int32_t* count, void* work, hipStream_t s);
 
 size_t bvh_bytes(int32_t nt);
-size_t bvh_work_bytes(int32_t nt);
+constexpr int kBvhSortTile = 1024;  // triangles per sort tile of the hierarchy build
+size_t bvh_work_bytes(int64_t total_tris, int64_t total_tiles, int32_t nobj);
+inline size_t bvh_work_bytes(int32_t nt) { return bvh_work_bytes(nt, ceil_div(nt, kBvhSortTile), 1); }
 hipError_t build_bvh(const float* verts, const int32_t* tris, int32_t nt, const rtsdf_grid& g,
-                     void* bvh, void* work, hipStream_t s);
+                     void* bvh, void* work, int32_t method, hipStream_t s);
 
 hipError_t reset_accum(float* dmin, uint32_t* hits, uint64_t* argmin, int64_t n, hipStream_t s);
 size_t raysample_work_bytes(int64_t capacity, int32_t x);
@@ -87,6 +89,8 @@ struct BatchObject {
     int32_t k0;
     int32_t flip;      // initial seeds go to the second buffer (nsteps odd)
     float beta, bias;
+    int32_t tile_off;  // first hierarchy-build sort tile (tiles of kBvhSortTile triangles)
+    int32_t reserved;
 };
 
 struct BatchHeader {
@@ -94,12 +98,13 @@ struct BatchHeader {
     int32_t nobj;
     int32_t max_passes;
     int32_t reserved0;
-    int64_t total_vox, total_verts, total_tris;
+    int64_t total_vox, total_verts, total_tris;  // total_tris < 2^26
     uint64_t bvh_bytes;
     uint64_t plan_bytes;
     const void* device;   // the device copy of these bytes
     int32_t pass_blocks[kMaxPasses];  // JFA work-groups per pass (host launch sizes)
-    int32_t reserved[256 / 4 - 16 - kMaxPasses];
+    int32_t total_tiles;              // hierarchy-build sort tiles of all objects
+    int32_t reserved[256 / 4 - 17 - kMaxPasses];
 };
 static_assert(sizeof(BatchHeader) == 256, "batch header is 256 bytes");
 constexpr uint32_t kBatchMagic = 0x52534442u;  // "BDSR"
@@ -163,6 +168,8 @@ hipError_t combine_batched(const BatchView& hv, const void* dplan, const int32_t
 hipError_t raysample_batched(const BatchView& hv, const void* dplan, const void* bvh, const int32_t* list,
                              const int32_t* count, int64_t capacity, int32_t x, uint64_t key, uint32_t frame,
                              float* dmin, uint32_t* hits, uint64_t* argmin, void* work, hipStream_t s);
+hipError_t build_bvh_batched(const BatchView& hv, const void* dplan, const float* verts, const int32_t* tris,
+                             void* bvh, void* work, int32_t method, hipStream_t s);
 hipError_t sdf_backward_batched(const BatchView& hv, const void* dplan, const float* grad_fine,
                                 const uint32_t* hits, const uint64_t* argmin, const int32_t* list,
                                 const int32_t* count, int64_t capacity, const void* bvh, const int32_t* tris,

@@ -1,16 +1,27 @@
-// Software linear BVH for the ray sampling of section 2.1 (the paper relies on the
-// graphics driver's hierarchy and RT cores; gfx950 has neither).
+// Software BVH for the ray sampling of section 2.1 (the paper relies on the graphics
+// driver's hierarchy and RT cores; gfx950 has neither), built for one object or for every
+// object of a batch at once.
 //
-//   centroid bounds (atomic min/max on order-preserving float encodings)
+//   centroid bounds per object (atomic min/max on order-preserving float encodings)
 //   -> 30-bit Morton code per triangle centroid
-//   -> stable LSD radix sort of (code, triangle) in four 8-bit passes
-//   -> binary radix tree over the sorted codes (Karras 2012, "Maximizing parallelism in
-//      the construction of BVHs, octrees, and k-d trees"); equal codes are ordered by
-//      position, so every key is unique
-//   -> bottom-up refit: each leaf walks to the root; the second child to arrive at a
-//      node merges both boxes.
-// Each internal node stores both children's boxes so that traversal tests two children
-// with one 64-byte fetch.  Boxes are widened so traversal is exact (see raysample.hip).
+//   -> stable LSD radix sort of (code, triangle) in four 8-bit passes, segmented: every
+//      sort tile belongs to one object and the digit counts are laid out
+//      [object][digit][tile], so one global exclusive scan gives every element a
+//      destination inside its own object's range
+//   -> a binary tree per object, either
+//        LBVH: the binary radix tree over the sorted codes (Karras 2012, "Maximizing
+//              parallelism in the construction of BVHs, octrees, and k-d trees"; equal
+//              codes are ordered by position) and a bottom-up refit, or
+//        PLOC: parallel locally-ordered clustering (Meister & Bittner 2018): the clusters,
+//              in Morton order, repeatedly merge with their mutual nearest neighbour by
+//              merged-box surface area within +-kPlocRadius positions; kPlocWide
+//              iterations run over all objects with one launch per phase, then one
+//              work-group per object finishes its remaining clusters.  The binary nodes
+//              are numbered from the last merge (the root, 0) backwards, and each leaf
+//              walks to the root to find its depth-first position, so that every subtree
+//              covers consecutive triangles.
+//   -> collapse into the 4-wide hierarchy that traversal reads.
+// Boxes are widened so traversal is exact (see traverse.h); the tree only changes speed.
 #include "internal.h"
 
 namespace rtsdf {
@@ -18,8 +29,61 @@ namespace rtsdf {
 namespace {
 
 constexpr int kSortThreads = 256;
-constexpr int kSortRounds = 4;
-constexpr int kSortTile = kSortThreads * kSortRounds;
+constexpr int kSortRounds = kBvhSortTile / kSortThreads;
+constexpr int kPlocRadius = 16;
+constexpr int kPlocThreads = 256;
+constexpr int kPlocWide = 24;
+constexpr int kFinishThreads = 1024;
+
+// ---- objects ------------------------------------------------------------------------------
+// One object: its triangles [tri_off, tri_off + nt) of the concatenated arrays (positions of
+// the sorted arrays, binary nodes and per-triangle state use the same range), its vertex
+// base, its first sort tile, its blob and its hit padding.
+struct Seg {
+    int32_t o, tri_off, nt, vert_off, tile_off;
+    int64_t bvh_off;
+    float pad;
+};
+
+struct Args {       // single object: the fields below; batch: the device plan
+    const char* plan;
+    int32_t nobj;
+    int32_t nt;
+    float pad;
+};
+
+template <bool kBatch>
+__device__ inline Seg seg_of_obj(const Args& a, int32_t o)
+{
+    if (!kBatch) return Seg{0, 0, a.nt, 0, 0, 0, a.pad};
+    const BatchView v = batch_view(a.plan, a.nobj);
+    const BatchObject& b = v.obj[o];
+    return Seg{o, b.tri_off, b.nt, b.vert_off, b.tile_off, b.bvh_off, b.g.h * (1.0f / 256.0f)};
+}
+
+template <bool kBatch>
+__device__ inline Seg seg_of_tri(const Args& a, int32_t t)
+{
+    if (!kBatch) return seg_of_obj<false>(a, 0);
+    const BatchView v = batch_view(a.plan, a.nobj);
+    return seg_of_obj<true>(a, find_object(v.tri_prefix, a.nobj, t));
+}
+
+template <bool kBatch>
+__device__ inline Seg seg_of_tile(const Args& a, int32_t tile)
+{
+    if (!kBatch) return seg_of_obj<false>(a, 0);
+    const BatchView v = batch_view(a.plan, a.nobj);
+    int32_t lo = 0, hi = a.nobj - 1;  // last object whose first tile is <= tile
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (v.obj[mid].tile_off <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return seg_of_obj<true>(a, lo);
+}
+
+__device__ inline int32_t tiles_of(int32_t nt) { return (nt + kBvhSortTile - 1) / kBvhSortTile; }
 
 __device__ inline uint32_t f2o(float f)
 {
@@ -31,46 +95,85 @@ __device__ inline float o2f(uint32_t o)
     return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
 }
 
-__device__ inline float3 tri_centroid(const float* __restrict__ v, const int32_t* __restrict__ t,
-                                      int32_t i)
+__device__ inline float3 tri_centroid(const float* __restrict__ v, const int32_t* __restrict__ t, int32_t i)
 {
     const int64_t a = t[3 * (int64_t)i], b = t[3 * (int64_t)i + 1], c = t[3 * (int64_t)i + 2];
     const float third = 1.0f / 3.0f;
-    return make_float3((v[3 * a] + v[3 * b] + v[3 * c]) * third,
-                       (v[3 * a + 1] + v[3 * b + 1] + v[3 * c + 1]) * third,
+    return make_float3((v[3 * a] + v[3 * b] + v[3 * c]) * third, (v[3 * a + 1] + v[3 * b + 1] + v[3 * c + 1]) * third,
                        (v[3 * a + 2] + v[3 * b + 2] + v[3 * c + 2]) * third);
 }
 
-__global__ void k_init(uint32_t* __restrict__ bounds, uint32_t* __restrict__ flags, int32_t nflags)
+// triangle box widened by 2 pad (culling stays exact, see traverse.h)
+__device__ inline void tri_box(const float* __restrict__ v, const int32_t* __restrict__ t, int32_t i, float pad,
+                               float3& lo, float3& hi)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 3) bounds[i] = 0xFFFFFFFFu;         // running min (encoded)
-    else if (i < 6) bounds[i] = 0u;             // running max (encoded)
-    for (int32_t f = i; f < nflags; f += gridDim.x * blockDim.x) flags[f] = 0u;
+    const int64_t ia = t[3 * (int64_t)i], ib = t[3 * (int64_t)i + 1], ic = t[3 * (int64_t)i + 2];
+    const float pad2 = 2.0f * pad;
+    lo = make_float3(fminf(fminf(v[3 * ia], v[3 * ib]), v[3 * ic]) - pad2,
+                     fminf(fminf(v[3 * ia + 1], v[3 * ib + 1]), v[3 * ic + 1]) - pad2,
+                     fminf(fminf(v[3 * ia + 2], v[3 * ib + 2]), v[3 * ic + 2]) - pad2);
+    hi = make_float3(fmaxf(fmaxf(v[3 * ia], v[3 * ib]), v[3 * ic]) + pad2,
+                     fmaxf(fmaxf(v[3 * ia + 1], v[3 * ib + 1]), v[3 * ic + 1]) + pad2,
+                     fmaxf(fmaxf(v[3 * ia + 2], v[3 * ib + 2]), v[3 * ic + 2]) + pad2);
 }
 
-__global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ v,
-                                                const int32_t* __restrict__ t, int32_t nt,
-                                                uint32_t* __restrict__ bounds)
+// ---- per-object set-up, bounds, Morton codes ------------------------------------------------
+template <bool kBatch>
+__global__ void k_init(Args a, uint32_t* __restrict__ bounds, int32_t* __restrict__ cseg, int32_t* __restrict__ base,
+                       int64_t total)
+{
+    const int32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t nobj = kBatch ? a.nobj : 1;
+    if (o < nobj) {
+        for (int q = 0; q < 3; ++q) {
+            bounds[6 * o + q] = 0xFFFFFFFFu;  // running min (encoded)
+            bounds[6 * o + 3 + q] = 0u;       // running max (encoded)
+        }
+        cseg[o] = seg_of_obj<kBatch>(a, o).tri_off;
+        base[o] = 0;
+    }
+    if (o == 0) cseg[nobj] = (int32_t)total;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <bool kBatch>
+__global__ __launch_bounds__(256) void k_bounds(Args a, const float* __restrict__ v, const int32_t* __restrict__ t,
+                                                int32_t total, uint32_t* __restrict__ bounds)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < total;
+    const Seg s = seg_of_tri<kBatch>(a, valid ? i : total - 1);
     uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0u, 0u, 0u};
-    if (i < nt) {
-        const float3 c = tri_centroid(v, t, i);
+    if (valid) {
+        const float3 c = tri_centroid(v + 3 * (int64_t)s.vert_off, t + 3 * (int64_t)s.tri_off, i - s.tri_off);
         mn[0] = mx[0] = f2o(c.x);
         mn[1] = mx[1] = f2o(c.y);
         mn[2] = mx[2] = f2o(c.z);
     }
-    for (int d = kWave / 2; d > 0; d >>= 1)
-        for (int a = 0; a < 3; ++a) {
-            mn[a] = min(mn[a], (uint32_t)__shfl_xor((int)mn[a], d, kWave));
-            mx[a] = max(mx[a], (uint32_t)__shfl_xor((int)mx[a], d, kWave));
+    // one atomic per wave when the wave lies in one object, else one per lane
+    const int32_t o0 = __shfl(s.o, 0);
+    if (__ballot(s.o != o0) == 0ull) {
+        for (int d = kWave / 2; d > 0; d >>= 1)
+            for (int q = 0; q < 3; ++q) {
+                mn[q] = min(mn[q], (uint32_t)__shfl_xor((int)mn[q], d, kWave));
+                mx[q] = max(mx[q], (uint32_t)__shfl_xor((int)mx[q], d, kWave));
+            }
+        if ((threadIdx.x & (kWave - 1)) == 0)
+            for (int q = 0; q < 3; ++q) {
+                atomicMin(&bounds[6 * o0 + q], mn[q]);
+                atomicMax(&bounds[6 * o0 + 3 + q], mx[q]);
+            }
+    } else if (valid) {
+        for (int q = 0; q < 3; ++q) {
+            atomicMin(&bounds[6 * s.o + q], mn[q]);
+            atomicMax(&bounds[6 * s.o + 3 + q], mx[q]);
         }
-    if ((threadIdx.x & (kWave - 1)) == 0)
-        for (int a = 0; a < 3; ++a) {
-            atomicMin(&bounds[a], mn[a]);
-            atomicMax(&bounds[3 + a], mx[a]);
-        }
+    }
 }
 
 __device__ inline uint32_t spread10(uint32_t x)
@@ -83,63 +186,68 @@ __device__ inline uint32_t spread10(uint32_t x)
     return x;
 }
 
-__global__ __launch_bounds__(256) void k_morton(const float* __restrict__ v,
-                                                const int32_t* __restrict__ t, int32_t nt,
-                                                const uint32_t* __restrict__ bounds,
-                                                uint32_t* __restrict__ keys,
-                                                uint32_t* __restrict__ vals)
+// keys: Morton codes over the object's centroid bounds; vals: global triangle index
+template <bool kBatch>
+__global__ __launch_bounds__(256) void k_morton(Args a, const float* __restrict__ v, const int32_t* __restrict__ t,
+                                                int32_t total, const uint32_t* __restrict__ bounds,
+                                                uint32_t* __restrict__ keys, uint32_t* __restrict__ vals)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nt) return;
-    const float3 c = tri_centroid(v, t, i);
+    if (i >= total) return;
+    const Seg s = seg_of_tri<kBatch>(a, i);
+    const float3 c = tri_centroid(v + 3 * (int64_t)s.vert_off, t + 3 * (int64_t)s.tri_off, i - s.tri_off);
     const float cc[3] = {c.x, c.y, c.z};
     uint32_t q[3];
-    for (int a = 0; a < 3; ++a) {
-        const float lo = o2f(bounds[a]), hi = o2f(bounds[3 + a]);
+    for (int d = 0; d < 3; ++d) {
+        const float lo = o2f(bounds[6 * s.o + d]), hi = o2f(bounds[6 * s.o + 3 + d]);
         const float ext = hi - lo;
-        float f = ext > 0.0f ? (cc[a] - lo) / ext : 0.0f;
+        float f = ext > 0.0f ? (cc[d] - lo) / ext : 0.0f;
         f = fminf(fmaxf(f * 1024.0f, 0.0f), 1023.0f);
-        q[a] = (uint32_t)f;
+        q[d] = (uint32_t)f;
     }
     keys[i] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
     vals[i] = (uint32_t)i;
 }
 
-// ---- stable LSD radix sort, 8-bit digits -----------------------------------------------
-__global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t* __restrict__ keys, int32_t n,
-                                                       int shift, int32_t ntiles,
+// ---- segmented stable LSD radix sort, 8-bit digits ---------------------------------------
+// counts[256 * tile_off + digit * ntiles + local tile] of each object
+template <bool kBatch>
+__global__ __launch_bounds__(kSortThreads) void k_hist(Args a, const uint32_t* __restrict__ keys, int shift,
                                                        uint32_t* __restrict__ counts)
 {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0u;
     __syncthreads();
-    const int32_t base = blockIdx.x * kSortTile;
+    const Seg s = seg_of_tile<kBatch>(a, blockIdx.x);
+    const int32_t lt = blockIdx.x - s.tile_off;
+    const int32_t first = s.tri_off + lt * kBvhSortTile, end = s.tri_off + s.nt;
     for (int r = 0; r < kSortRounds; ++r) {
-        const int32_t i = base + r * kSortThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xFFu], 1u);
+        const int32_t i = first + r * kSortThreads + threadIdx.x;
+        if (i < end) atomicAdd(&h[(keys[i] >> shift) & 0xFFu], 1u);
     }
     __syncthreads();
-    counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+    counts[256 * (int64_t)s.tile_off + (int64_t)threadIdx.x * tiles_of(s.nt) + lt] = h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* __restrict__ kin,
-                                                          const uint32_t* __restrict__ vin,
-                                                          uint32_t* __restrict__ kout,
-                                                          uint32_t* __restrict__ vout, int32_t n,
-                                                          int shift, int32_t ntiles,
+template <bool kBatch>
+__global__ __launch_bounds__(kSortThreads) void k_scatter(Args a, const uint32_t* __restrict__ kin,
+                                                          const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+                                                          uint32_t* __restrict__ vout, int shift,
                                                           const uint32_t* __restrict__ offsets)
 {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcount[kSortThreads / kWave][256];
-    run[threadIdx.x] = offsets[(int64_t)threadIdx.x * ntiles + blockIdx.x];
+    const Seg s = seg_of_tile<kBatch>(a, blockIdx.x);
+    const int32_t lt = blockIdx.x - s.tile_off;
+    run[threadIdx.x] = offsets[256 * (int64_t)s.tile_off + (int64_t)threadIdx.x * tiles_of(s.nt) + lt];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-    const int32_t base = blockIdx.x * kSortTile;
+    const int32_t first = s.tri_off + lt * kBvhSortTile, end = s.tri_off + s.nt;
     for (int r = 0; r < kSortRounds; ++r) {
         for (int w = 0; w < kSortThreads / kWave; ++w) wcount[w][threadIdx.x] = 0u;
         __syncthreads();
-        const int32_t i = base + r * kSortThreads + threadIdx.x;
-        const bool valid = i < n;
+        const int32_t i = first + r * kSortThreads + threadIdx.x;
+        const bool valid = i < end;
         const uint32_t key = valid ? kin[i] : 0u;
         const uint32_t d = (key >> shift) & 0xFFu;
         // lanes of this wave holding the same digit
@@ -165,11 +273,12 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t* __rest
     }
 }
 
-// ---- binary radix tree ------------------------------------------------------------------
-// Binary nodes live in the workspace; each stores both children's boxes, and in the spare
-// lanes its own range of sorted triangles (a_hi.w = first, b_hi.w = count).
+// ---- binary nodes ----------------------------------------------------------------------
+// Each stores both children's boxes, and in the spare lanes its own range of sorted
+// triangles (a_hi.w = first, b_hi.w = count).  Object o's nodes are at [tri_off, tri_off
+// + nt - 1) with local indices; child codes are local (>= 0 node, < 0 leaf ~position).
 struct alignas(16) BinNode {
-    float4 a_lo;  // xyz = child a box min, w = bits of child a (>= 0 node, < 0 leaf ~position)
+    float4 a_lo;  // xyz = child a box min, w = bits of child a
     float4 a_hi;  // xyz = child a box max, w = bits of this node's first triangle
     float4 b_lo;  // child b
     float4 b_hi;  // w = bits of this node's triangle count
@@ -183,43 +292,51 @@ __device__ inline int delta(const uint32_t* __restrict__ k, int32_t n, int32_t i
     return __clz((int)(a ^ b));
 }
 
-__global__ __launch_bounds__(256) void k_tree(const uint32_t* __restrict__ k, int32_t n,
-                                              BinNode* __restrict__ nodes,
-                                              int32_t* __restrict__ parent)
+// LBVH: Karras's radix tree; parent[] of nodes at [tri_off, ...), of leaves at lparent
+template <bool kBatch>
+__global__ __launch_bounds__(256) void k_tree(Args a, const uint32_t* __restrict__ keys, int32_t total,
+                                              BinNode* __restrict__ bin, int32_t* __restrict__ nparent,
+                                              int32_t* __restrict__ lparent)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= total) return;
+    const Seg s = seg_of_tri<kBatch>(a, gi);
+    const int32_t n = s.nt, i = gi - s.tri_off;
     if (i >= n - 1) return;
+    const uint32_t* k = keys + s.tri_off;
     const int d = (delta(k, n, i, i + 1) - delta(k, n, i, i - 1)) >= 0 ? 1 : -1;
     const int dmin = delta(k, n, i, i - d);
     int32_t lmax = 2;
     while (delta(k, n, i, i + lmax * d) > dmin) lmax <<= 1;
     int32_t l = 0;
-    for (int32_t t = lmax >> 1; t >= 1; t >>= 1)
-        if (delta(k, n, i, i + (l + t) * d) > dmin) l += t;
+    for (int32_t tt = lmax >> 1; tt >= 1; tt >>= 1)
+        if (delta(k, n, i, i + (l + tt) * d) > dmin) l += tt;
     const int32_t j = i + l * d;
     const int dnode = delta(k, n, i, j);
-    int32_t s = 0;
+    int32_t sp = 0;
     for (int32_t div = 2;; div <<= 1) {
-        const int32_t t = (l + div - 1) / div;
-        if (delta(k, n, i, i + (s + t) * d) > dnode) s += t;
-        if (t <= 1) break;
+        const int32_t tt = (l + div - 1) / div;
+        if (delta(k, n, i, i + (sp + tt) * d) > dnode) sp += tt;
+        if (tt <= 1) break;
     }
-    const int32_t gamma = i + s * d + min(d, 0);
+    const int32_t gamma = i + sp * d + min(d, 0);
     const int32_t left = (min(i, j) == gamma) ? ~gamma : gamma;
     const int32_t right = (max(i, j) == gamma + 1) ? ~(gamma + 1) : gamma + 1;
     const float inf = __int_as_float(0x7f800000);
-    nodes[i].a_lo = make_float4(inf, inf, inf, __int_as_float(left));
-    nodes[i].a_hi = make_float4(-inf, -inf, -inf, __int_as_float(min(i, j)));
-    nodes[i].b_lo = make_float4(inf, inf, inf, __int_as_float(right));
-    nodes[i].b_hi = make_float4(-inf, -inf, -inf, __int_as_float(max(i, j) - min(i, j) + 1));
-    parent[left >= 0 ? left : (n - 1) + ~left] = i;
-    parent[right >= 0 ? right : (n - 1) + ~right] = i;
+    BinNode* node = bin + s.tri_off + i;
+    node->a_lo = make_float4(inf, inf, inf, __int_as_float(left));
+    node->a_hi = make_float4(-inf, -inf, -inf, __int_as_float(min(i, j)));
+    node->b_lo = make_float4(inf, inf, inf, __int_as_float(right));
+    node->b_hi = make_float4(-inf, -inf, -inf, __int_as_float(max(i, j) - min(i, j) + 1));
+    if (left >= 0) nparent[s.tri_off + left] = i;
+    else lparent[s.tri_off + ~left] = i;
+    if (right >= 0) nparent[s.tri_off + right] = i;
+    else lparent[s.tri_off + ~right] = i;
 }
 
 __device__ inline float ld_coherent(const float* p)
 {
-    return __uint_as_float(__hip_atomic_load((const uint32_t*)p, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT));
+    return __uint_as_float(__hip_atomic_load((const uint32_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
 __device__ inline void st_coherent(float* p, float v)
@@ -227,36 +344,47 @@ __device__ inline void st_coherent(float* p, float v)
     __hip_atomic_store((uint32_t*)p, __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(256) void k_leaves_refit(const float* __restrict__ v,
-                                                      const int32_t* __restrict__ t, int32_t n,
-                                                      const uint32_t* __restrict__ order,
-                                                      float pad, BinNode* nodes,
-                                                      BvhTri* __restrict__ out,
-                                                      const int32_t* __restrict__ parent,
-                                                      uint32_t* flags)
+template <bool kBatch>
+__device__ inline BvhTri* blob_tris(char* bvh, const Seg& s)
 {
-    const int32_t pos = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pos >= n) return;
-    const int32_t id = (int32_t)order[pos];
-    const int64_t ia = t[3 * (int64_t)id], ib = t[3 * (int64_t)id + 1], ic = t[3 * (int64_t)id + 2];
-    const float3 a = make_float3(v[3 * ia], v[3 * ia + 1], v[3 * ia + 2]);
-    const float3 b = make_float3(v[3 * ib], v[3 * ib + 1], v[3 * ib + 2]);
-    const float3 c = make_float3(v[3 * ic], v[3 * ic + 1], v[3 * ic + 2]);
-    const float3 mn = make_float3(fminf(fminf(a.x, b.x), c.x), fminf(fminf(a.y, b.y), c.y),
-                                  fminf(fminf(a.z, b.z), c.z));
-    const float3 mx = make_float3(fmaxf(fmaxf(a.x, b.x), c.x), fmaxf(fmaxf(a.y, b.y), c.y),
-                                  fmaxf(fmaxf(a.z, b.z), c.z));
+    return (BvhTri*)(bvh + s.bvh_off + 256 + sizeof(Bvh4Node) * (size_t)(s.nt > 1 ? s.nt - 1 : 1));
+}
+
+template <bool kBatch>
+__device__ inline BvhTri leaf_record(const float* __restrict__ v, const int32_t* __restrict__ t, const Seg& s,
+                                     int32_t local_id)
+{
+    const float* vb = v + 3 * (int64_t)s.vert_off;
+    const int32_t* tb = t + 3 * (int64_t)s.tri_off;
+    const int64_t ia = tb[3 * (int64_t)local_id], ib = tb[3 * (int64_t)local_id + 1], ic = tb[3 * (int64_t)local_id + 2];
     BvhTri tri;
-    tri.v0 = make_float4(a.x, a.y, a.z, __int_as_float(id));
-    tri.v1 = make_float4(b.x, b.y, b.z, 0.0f);
-    tri.v2 = make_float4(c.x, c.y, c.z, 0.0f);
-    out[pos] = tri;
-    if (n == 1) return;
-    const float pad2 = 2.0f * pad;
-    float3 blo = make_float3(mn.x - pad2, mn.y - pad2, mn.z - pad2);
-    float3 bhi = make_float3(mx.x + pad2, mx.y + pad2, mx.z + pad2);
+    tri.v0 = make_float4(vb[3 * ia], vb[3 * ia + 1], vb[3 * ia + 2], __int_as_float(local_id));
+    tri.v1 = make_float4(vb[3 * ib], vb[3 * ib + 1], vb[3 * ib + 2], 0.0f);
+    tri.v2 = make_float4(vb[3 * ic], vb[3 * ic + 1], vb[3 * ic + 2], 0.0f);
+    return tri;
+}
+
+// LBVH: write the leaf records in sorted order and refit boxes bottom-up (the second child
+// to arrive at a node merges both boxes)
+template <bool kBatch>
+__global__ __launch_bounds__(256) void k_leaves_refit(Args a, const float* __restrict__ v,
+                                                      const int32_t* __restrict__ t, int32_t total,
+                                                      const uint32_t* __restrict__ order, BinNode* bin, char* bvh,
+                                                      const int32_t* __restrict__ nparent,
+                                                      const int32_t* __restrict__ lparent, uint32_t* flags)
+{
+    const int32_t gp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gp >= total) return;
+    const Seg s = seg_of_tri<kBatch>(a, gp);
+    const int32_t pos = gp - s.tri_off;
+    const int32_t id = (int32_t)order[gp] - s.tri_off;
+    blob_tris<kBatch>(bvh, s)[pos] = leaf_record<kBatch>(v, t, s, id);
+    if (s.nt == 1) return;
+    float3 blo, bhi;
+    tri_box(v + 3 * (int64_t)s.vert_off, t + 3 * (int64_t)s.tri_off, id, s.pad, blo, bhi);
     int32_t me = ~pos;
-    int32_t p = parent[(n - 1) + pos];
+    int32_t p = lparent[gp];
+    BinNode* nodes = bin + s.tri_off;
     while (true) {
         BinNode* node = &nodes[p];
         const bool is_a = __float_as_int(node->a_lo.w) == me;
@@ -268,31 +396,329 @@ __global__ __launch_bounds__(256) void k_leaves_refit(const float* __restrict__ 
         st_coherent(shi, bhi.x);
         st_coherent(shi + 1, bhi.y);
         st_coherent(shi + 2, bhi.z);
-        const uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t old = __hip_atomic_fetch_add(&flags[s.tri_off + p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (old == 0u) return;  // the sibling will finish this node
         const float* alo = &node->a_lo.x;
         const float* ahi = &node->a_hi.x;
         const float* bl = &node->b_lo.x;
         const float* bh = &node->b_hi.x;
-        blo = make_float3(fminf(ld_coherent(alo), ld_coherent(bl)),
-                          fminf(ld_coherent(alo + 1), ld_coherent(bl + 1)),
+        blo = make_float3(fminf(ld_coherent(alo), ld_coherent(bl)), fminf(ld_coherent(alo + 1), ld_coherent(bl + 1)),
                           fminf(ld_coherent(alo + 2), ld_coherent(bl + 2)));
-        bhi = make_float3(fmaxf(ld_coherent(ahi), ld_coherent(bh)),
-                          fmaxf(ld_coherent(ahi + 1), ld_coherent(bh + 1)),
+        bhi = make_float3(fmaxf(ld_coherent(ahi), ld_coherent(bh)), fmaxf(ld_coherent(ahi + 1), ld_coherent(bh + 1)),
                           fmaxf(ld_coherent(ahi + 2), ld_coherent(bh + 2)));
         if (p == 0) return;
         me = p;
-        p = parent[p];
+        p = nparent[s.tri_off + p];
     }
+}
+
+// ---- PLOC ------------------------------------------------------------------------------
+// A cluster: lo.xyz / hi.xyz its box, lo.w its code (>= 0 local node, < 0 ~global
+// triangle), hi.w its object.
+struct Cluster {
+    float4 lo, hi;
+};
+
+__device__ inline float union_area(const Cluster& x, const Cluster& y)
+{
+    const float dx = fmaxf(x.hi.x, y.hi.x) - fminf(x.lo.x, y.lo.x);
+    const float dy = fmaxf(x.hi.y, y.hi.y) - fminf(x.lo.y, y.lo.y);
+    const float dz = fmaxf(x.hi.z, y.hi.z) - fminf(x.lo.z, y.lo.z);
+    const float ar = dx * dy + dy * dz + dz * dx;
+    return ar == ar ? ar : __int_as_float(0x7f800000);  // NaN boxes compare as +inf
+}
+
+__device__ inline Cluster merge_cluster(const Cluster& x, const Cluster& y, int32_t code)
+{
+    Cluster c;
+    c.lo = make_float4(fminf(x.lo.x, y.lo.x), fminf(x.lo.y, y.lo.y), fminf(x.lo.z, y.lo.z), __int_as_float(code));
+    c.hi = make_float4(fmaxf(x.hi.x, y.hi.x), fmaxf(x.hi.y, y.hi.y), fmaxf(x.hi.z, y.hi.z), x.hi.w);
+    return c;
+}
+
+__device__ inline int32_t code_of(const Cluster& c) { return __float_as_int(c.lo.w); }
+__device__ inline int32_t obj_of(const Cluster& c) { return __float_as_int(c.hi.w); }
+
+template <bool kBatch>
+__global__ __launch_bounds__(256) void k_ploc_init(Args a, const float* __restrict__ v, const int32_t* __restrict__ t,
+                                                   int32_t total, const uint32_t* __restrict__ order,
+                                                   Cluster* __restrict__ cl)
+{
+    const int32_t gp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gp >= total) return;
+    const Seg s = seg_of_tri<kBatch>(a, gp);
+    const int32_t gt = (int32_t)order[gp];
+    float3 lo, hi;
+    tri_box(v + 3 * (int64_t)s.vert_off, t + 3 * (int64_t)s.tri_off, gt - s.tri_off, s.pad, lo, hi);
+    cl[gp].lo = make_float4(lo.x, lo.y, lo.z, __int_as_float(~gt));
+    cl[gp].hi = make_float4(hi.x, hi.y, hi.z, __int_as_float(s.o));
+}
+
+// nearest neighbour of each cluster among the same object's clusters within +-kPlocRadius
+// positions: least (merged area, position); -1 when the object has no other cluster there
+__device__ inline int32_t nearest(const Cluster* c, int32_t i, int32_t lo, int32_t hi, int32_t base)
+{
+    // c: clusters indexed from `base`; candidates j in [lo, hi] (global positions)
+    const Cluster me = c[i - base];
+    const int32_t mo = obj_of(me);
+    float best = __int_as_float(0x7f800000);
+    int32_t bj = -1;
+    for (int32_t j = lo; j <= hi; ++j) {
+        if (j == i) continue;
+        const Cluster o = c[j - base];
+        if (obj_of(o) != mo) continue;
+        const float ar = union_area(me, o);
+        if (bj < 0 || ar < best) {
+            best = ar;
+            bj = j;
+        }
+    }
+    return bj;
+}
+
+__global__ __launch_bounds__(kPlocThreads) void k_ploc_nn(const Cluster* __restrict__ cl, const int32_t* __restrict__ cseg,
+                                                          int32_t nobj, int32_t* __restrict__ nn)
+{
+    __shared__ Cluster tile[kPlocThreads + 2 * kPlocRadius];
+    const int32_t n = cseg[nobj];
+    const int32_t b0 = blockIdx.x * kPlocThreads;
+    if (b0 >= n) return;
+    const int32_t lo = max(b0 - kPlocRadius, 0), hi = min(b0 + kPlocThreads + kPlocRadius, n);
+    for (int32_t j = lo + (int32_t)threadIdx.x; j < hi; j += kPlocThreads) tile[j - lo] = cl[j];
+    __syncthreads();
+    const int32_t i = b0 + threadIdx.x;
+    if (i >= n) return;
+    nn[i] = nearest(tile, i, max(i - kPlocRadius, 0), min(i + kPlocRadius, n - 1), lo);
+}
+
+// flags[i] = merged << 32 | kept (for the exclusive scan that follows); zero past the end
+__global__ void k_ploc_flags(const int32_t* __restrict__ nn, const int32_t* __restrict__ cseg, int32_t nobj,
+                             int64_t cap, uint64_t* __restrict__ flags)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > cap) return;
+    const int32_t n = cseg[nobj];
+    uint64_t f = 0;
+    if (i < n) {
+        const int32_t j = nn[i];
+        const bool mutual = j >= 0 && nn[j] == (int32_t)i;
+        f = ((uint64_t)(mutual && i < j) << 32) | (uint64_t)(!mutual || i < j);
+    }
+    flags[i] = f;
+}
+
+// per object: its first merge rank this iteration, its merge count so far, its new start
+__global__ void k_ploc_seg(const int32_t* __restrict__ cseg_in, int32_t* __restrict__ cseg_out, int32_t nobj,
+                           const uint64_t* __restrict__ flags, int32_t* __restrict__ base, int32_t* __restrict__ mrank0,
+                           int32_t* __restrict__ mbase)
+{
+    const int32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o > nobj) return;
+    const uint64_t fs = flags[cseg_in[o]];
+    cseg_out[o] = (int32_t)(uint32_t)fs;
+    if (o == nobj) return;
+    const uint64_t fe = flags[cseg_in[o + 1]];
+    const int32_t r0 = (int32_t)(fs >> 32), m = (int32_t)(fe >> 32) - r0;
+    mrank0[o] = r0;
+    mbase[o] = base[o];
+    base[o] += m;
+}
+
+// writes merged node `id` of object `s` from clusters x (left) and y (right)
+template <bool kBatch>
+__device__ inline void write_node(const Seg& s, int32_t id, const Cluster& x, const Cluster& y, BinNode* __restrict__ bin,
+                                  int32_t* __restrict__ ncount, int32_t* __restrict__ nparent,
+                                  int32_t* __restrict__ lparent)
+{
+    const int32_t cx = code_of(x), cy = code_of(y);
+    BinNode nd;
+    nd.a_lo = x.lo;
+    nd.a_hi = make_float4(x.hi.x, x.hi.y, x.hi.z, 0.0f);
+    nd.b_lo = y.lo;
+    nd.b_hi = make_float4(y.hi.x, y.hi.y, y.hi.z, 0.0f);
+    bin[s.tri_off + id] = nd;
+    const int32_t nx = cx >= 0 ? ncount[s.tri_off + cx] : 1, ny = cy >= 0 ? ncount[s.tri_off + cy] : 1;
+    ncount[s.tri_off + id] = nx + ny;
+    if (cx >= 0) nparent[s.tri_off + cx] = id;
+    else lparent[~cx] = id;
+    if (cy >= 0) nparent[s.tri_off + cy] = id;
+    else lparent[~cy] = id;
+}
+
+template <bool kBatch>
+__global__ __launch_bounds__(256) void k_ploc_compact(Args a, const Cluster* __restrict__ cin, Cluster* __restrict__ cout,
+                                                      const int32_t* __restrict__ cseg_in, int32_t nobj,
+                                                      const int32_t* __restrict__ nn, const uint64_t* __restrict__ flags,
+                                                      const int32_t* __restrict__ mrank0, const int32_t* __restrict__ mbase,
+                                                      BinNode* __restrict__ bin, int32_t* __restrict__ ncount,
+                                                      int32_t* __restrict__ nparent, int32_t* __restrict__ lparent)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cseg_in[nobj]) return;
+    const uint64_t f = flags[i], f1 = flags[i + 1];
+    const uint32_t keep = (uint32_t)f1 - (uint32_t)f, merged = (uint32_t)(f1 >> 32) - (uint32_t)(f >> 32);
+    if (!keep) return;
+    const uint32_t pos = (uint32_t)f;
+    const Cluster me = cin[i];
+    if (!merged) {
+        cout[pos] = me;
+        return;
+    }
+    const int32_t j = nn[i];
+    const Cluster other = cin[j];
+    const int32_t o = obj_of(me);
+    const Seg s = seg_of_obj<kBatch>(a, o);
+    const int32_t id = s.nt - 2 - (mbase[o] + ((int32_t)(f >> 32) - mrank0[o]));
+    write_node<kBatch>(s, id, me, other, bin, ncount, nparent, lparent);
+    cout[pos] = merge_cluster(me, other, id);
+}
+
+// One work-group per object finishes its clusters [start, start + n) of buffer A, using
+// the same segment of buffer B as the other half of the ping-pong, `nnw` for the nearest
+// neighbours and LDS scans for the compaction.  Every iteration merges at least one pair
+// (the least (area, position) pair of the object is mutual), so it ends after at most n - 1
+// iterations.
+template <bool kBatch>
+__global__ __launch_bounds__(kFinishThreads) void k_ploc_finish(Args a, Cluster* ca, Cluster* cb,
+                                                                const int32_t* __restrict__ cseg, const int32_t* base_in,
+                                                                int32_t* nnw, BinNode* __restrict__ bin,
+                                                                int32_t* __restrict__ ncount, int32_t* __restrict__ nparent,
+                                                                int32_t* __restrict__ lparent)
+{
+    __shared__ uint32_t s_keep[kFinishThreads / kWave], s_merge[kFinishThreads / kWave];
+    __shared__ uint32_t s_tot[2];
+    const int32_t o = blockIdx.x;
+    const Seg s = seg_of_obj<kBatch>(a, o);
+    const int32_t start = cseg[o];
+    int32_t n = cseg[o + 1] - start;
+    int32_t merges = base_in[o];
+    Cluster* cur = ca;
+    Cluster* nxt = cb;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    for (int32_t guard = 0; n > 1 && guard < s.nt; ++guard) {
+        for (int32_t i = tid; i < n; i += kFinishThreads)
+            nnw[start + i] = nearest(cur + start, i, max(i - kPlocRadius, 0), min(i + kPlocRadius, n - 1), 0);
+        __syncthreads();
+        uint32_t kept_total = 0, merged_total = 0;
+        for (int32_t c0 = 0; c0 < n; c0 += kFinishThreads) {
+            const int32_t i = c0 + tid;
+            uint32_t keep = 0, mrg = 0;
+            int32_t j = -1;
+            if (i < n) {
+                j = nnw[start + i];
+                const bool mutual = j >= 0 && nnw[start + j] == i;
+                keep = (!mutual || i < j) ? 1u : 0u;
+                mrg = (mutual && i < j) ? 1u : 0u;
+            }
+            // exclusive scans of keep and mrg over the work-group
+            uint32_t ik = keep, im = mrg;
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t xk = __shfl_up(ik, d, kWave), xm = __shfl_up(im, d, kWave);
+                if (lane >= d) {
+                    ik += xk;
+                    im += xm;
+                }
+            }
+            if (lane == kWave - 1) {
+                s_keep[wave] = ik;
+                s_merge[wave] = im;
+            }
+            __syncthreads();
+            uint32_t pk = kept_total + ik - keep, pm = merged_total + im - mrg;
+            for (int w = 0; w < wave; ++w) {
+                pk += s_keep[w];
+                pm += s_merge[w];
+            }
+            if (tid == kFinishThreads - 1) {
+                s_tot[0] = pk + keep;
+                s_tot[1] = pm + mrg;
+            }
+            if (keep) {
+                const Cluster me = cur[start + i];
+                if (mrg) {
+                    const Cluster other = cur[start + j];
+                    const int32_t id = s.nt - 2 - (merges + (int32_t)pm);
+                    write_node<kBatch>(s, id, me, other, bin, ncount, nparent, lparent);
+                    nxt[start + pk] = merge_cluster(me, other, id);
+                } else {
+                    nxt[start + pk] = me;
+                }
+            }
+            __syncthreads();
+            kept_total = s_tot[0];
+            merged_total = s_tot[1];
+        }
+        merges += (int32_t)merged_total;
+        n = (int32_t)kept_total;
+        Cluster* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        __syncthreads();
+    }
+}
+
+// PLOC: every leaf walks to the root for its depth-first position; writes its record
+template <bool kBatch>
+__global__ __launch_bounds__(256) void k_ploc_leaves(Args a, const float* __restrict__ v, const int32_t* __restrict__ t,
+                                                     int32_t total, const BinNode* __restrict__ bin,
+                                                     const int32_t* __restrict__ ncount, const int32_t* __restrict__ nparent,
+                                                     const int32_t* __restrict__ lparent, int32_t* __restrict__ posmap,
+                                                     char* bvh)
+{
+    const int32_t gt = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gt >= total) return;
+    const Seg s = seg_of_tri<kBatch>(a, gt);
+    int32_t pos = 0, me = ~gt, p = lparent[gt];
+    for (int32_t guard = 0; p >= 0 && guard < s.nt; ++guard) {
+        const BinNode& nd = bin[s.tri_off + p];
+        if (__float_as_int(nd.b_lo.w) == me) {
+            const int32_t ca = __float_as_int(nd.a_lo.w);
+            pos += ca >= 0 ? ncount[s.tri_off + ca] : 1;
+        }
+        me = p;
+        p = nparent[s.tri_off + p];
+    }
+    posmap[gt] = pos;
+    blob_tris<kBatch>(bvh, s)[pos] = leaf_record<kBatch>(v, t, s, gt - s.tri_off);
+}
+
+// PLOC: node ranges (first by the same walk) and leaf codes as positions
+template <bool kBatch>
+__global__ __launch_bounds__(256) void k_ploc_nodes(Args a, int32_t total, BinNode* __restrict__ bin,
+                                                    const int32_t* __restrict__ ncount,
+                                                    const int32_t* __restrict__ nparent,
+                                                    const int32_t* __restrict__ posmap)
+{
+    const int32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= total) return;
+    const Seg s = seg_of_tri<kBatch>(a, gi);
+    const int32_t id = gi - s.tri_off;
+    if (id >= s.nt - 1) return;
+    int32_t first = 0, me = id, p = nparent[gi];
+    for (int32_t guard = 0; p >= 0 && guard < s.nt; ++guard) {
+        const BinNode& nd = bin[s.tri_off + p];
+        if (__float_as_int(nd.b_lo.w) == me) {
+            const int32_t ca = __float_as_int(nd.a_lo.w);
+            first += ca >= 0 ? ncount[s.tri_off + ca] : 1;
+        }
+        me = p;
+        p = nparent[s.tri_off + p];
+    }
+    BinNode& nd = bin[gi];
+    const int32_t ca = __float_as_int(nd.a_lo.w), cb = __float_as_int(nd.b_lo.w);
+    nd.a_lo.w = __int_as_float(ca >= 0 ? ca : ~posmap[~ca]);
+    nd.b_lo.w = __int_as_float(cb >= 0 ? cb : ~posmap[~cb]);
+    nd.a_hi.w = __int_as_float(first);
+    nd.b_hi.w = __int_as_float(ncount[gi]);
 }
 
 // ---- collapse into a 4-wide hierarchy ---------------------------------------------------
 // For every binary node: start from its two children and repeatedly open the child with
 // the largest surface area that holds more than kLeafMax triangles, until there are 4
 // children or nothing left to open; children with at most kLeafMax triangles become leaf
-// ranges (a radix-tree subtree always covers consecutive sorted triangles).  Each node's
-// result depends only on its own subtree, so all nodes are collapsed in parallel; the ones
-// reachable from the root form the hierarchy.
+// ranges (every subtree covers consecutive triangles).  Each node's result depends only on
+// its own subtree, so all nodes are collapsed in parallel; the ones reachable from the
+// root form the hierarchy.
 struct Slot {
     int32_t code;   // binary code: >= 0 node, < 0 leaf ~position
     int32_t first, count;
@@ -322,11 +748,15 @@ __device__ inline float half_area(const Slot& s)
     return dx * dy + dy * dz + dz * dx;
 }
 
-__global__ __launch_bounds__(256) void k_collapse4(const BinNode* __restrict__ nodes, int32_t n,
-                                                   Bvh4Node* __restrict__ out)
+template <bool kBatch>
+__global__ __launch_bounds__(256) void k_collapse4(Args a, const BinNode* __restrict__ bin, int32_t total, char* bvh)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n - 1) return;
+    const int32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= total) return;
+    const Seg sg = seg_of_tri<kBatch>(a, gi);
+    const int32_t i = gi - sg.tri_off;
+    if (i >= sg.nt - 1) return;
+    const BinNode* nodes = bin + sg.tri_off;
     Slot s[4];
     const BinNode me = nodes[i];
     s[0] = child_slot(nodes, me, true);
@@ -369,50 +799,136 @@ __global__ __launch_bounds__(256) void k_collapse4(const BinNode* __restrict__ n
     o.hiz = make_float4(hz[0], hz[1], hz[2], hz[3]);
     o.child = make_int4(cc[0], cc[1], cc[2], cc[3]);
     o.unused = make_int4(0, 0, 0, 0);
-    out[i] = o;
+    ((Bvh4Node*)(bvh + sg.bvh_off + 256))[i] = o;
 }
 
-__global__ void k_header(BvhHeader* h, int32_t nt, float pad)
+// the header (its reserved words zero) and, when no binary node exists (nt <= 1), the
+// unused node slot, so that every byte of a blob is defined
+template <bool kBatch>
+__global__ void k_header(Args a, char* bvh)
 {
-    h->nt = nt;
-    h->root = nt <= kLeafMax ? (nt > 0 ? leaf_code(0, nt) : kBvhEmptySlot) : 0;
-    h->pad = pad;
+    const int32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= (kBatch ? a.nobj : 1)) return;
+    const Seg s = seg_of_obj<kBatch>(a, o);
+    int4* raw = (int4*)(bvh + s.bvh_off);
+    const int words = (int)(sizeof(BvhHeader) + (s.nt <= 1 ? sizeof(Bvh4Node) : 0)) / 16;
+    for (int q = 0; q < words; ++q) raw[q] = make_int4(0, 0, 0, 0);
+    BvhHeader* h = (BvhHeader*)(bvh + s.bvh_off);
+    h->nt = s.nt;
+    h->root = s.nt <= kLeafMax ? (s.nt > 0 ? leaf_code(0, s.nt) : kBvhEmptySlot) : 0;
+    h->pad = s.pad;
 }
 
-struct SortWork {
-    uint32_t *k0, *v0, *k1, *v1, *counts, *bounds, *flags;
-    int32_t* parent;
+// ---- workspace ----------------------------------------------------------------------------
+struct Work {
+    uint32_t *k0, *v0, *k1, *v1, *counts, *bounds, *flags32;
+    Cluster *ca, *cb;
+    int32_t *nn, *ncount, *nparent, *lparent, *posmap, *cseg0, *cseg1, *base, *mrank0, *mbase;
+    uint64_t* flags;
     BinNode* bin;
     void* scan;
-    int32_t ntiles;
 };
 
-SortWork carve(void* work, int32_t nt)
+Work carve(void* work, int64_t n, int64_t tiles, int32_t nobj)
 {
-    SortWork w;
+    Work w;
     char* p = (char*)work;
-    const size_t a = align256((size_t)nt * 4);
-    w.ntiles = (int32_t)ceil_div(nt, kSortTile);
-    w.k0 = (uint32_t*)p;
-    p += a;
-    w.v0 = (uint32_t*)p;
-    p += a;
-    w.k1 = (uint32_t*)p;
-    p += a;
-    w.v1 = (uint32_t*)p;
-    p += a;
-    w.counts = (uint32_t*)p;
-    p += align256((size_t)w.ntiles * 256 * 4);
-    w.bounds = (uint32_t*)p;
-    p += 256;
-    w.flags = (uint32_t*)p;
-    p += align256((size_t)nt * 4);
-    w.parent = (int32_t*)p;
-    p += align256((size_t)(2 * (int64_t)nt) * 4);
-    w.bin = (BinNode*)p;
-    p += align256(sizeof(BinNode) * (size_t)nt);
+    auto take = [&](size_t bytes) {
+        char* r = p;
+        p += align256(bytes);
+        return (void*)r;
+    };
+    w.k0 = (uint32_t*)take(4 * n);
+    w.v0 = (uint32_t*)take(4 * n);
+    w.k1 = (uint32_t*)take(4 * n);
+    w.v1 = (uint32_t*)take(4 * n);
+    w.counts = (uint32_t*)take(4 * 256 * tiles);
+    w.bounds = (uint32_t*)take(4 * 6 * (size_t)nobj);
+    w.flags32 = (uint32_t*)take(4 * n);
+    w.ca = (Cluster*)take(sizeof(Cluster) * n);
+    w.cb = (Cluster*)take(sizeof(Cluster) * n);
+    w.nn = (int32_t*)take(4 * n);
+    w.ncount = (int32_t*)take(4 * n);
+    w.nparent = (int32_t*)take(4 * n);
+    w.lparent = (int32_t*)take(4 * n);
+    w.posmap = (int32_t*)take(4 * n);
+    w.cseg0 = (int32_t*)take(4 * ((size_t)nobj + 1));
+    w.cseg1 = (int32_t*)take(4 * ((size_t)nobj + 1));
+    w.base = (int32_t*)take(4 * (size_t)nobj);
+    w.mrank0 = (int32_t*)take(4 * (size_t)nobj);
+    w.mbase = (int32_t*)take(4 * (size_t)nobj);
+    w.flags = (uint64_t*)take(8 * (n + 1));
+    w.bin = (BinNode*)take(sizeof(BinNode) * n);
     w.scan = p;
     return w;
+}
+
+size_t carve_bytes(int64_t n, int64_t tiles, int32_t nobj)
+{
+    const size_t head = 4 * align256(4 * n) + align256(4 * 256 * tiles) + align256(4 * 6 * (size_t)nobj) +
+                        align256(4 * n) + 2 * align256(sizeof(Cluster) * n) + 5 * align256(4 * n) +
+                        2 * align256(4 * ((size_t)nobj + 1)) + 3 * align256(4 * (size_t)nobj) + align256(8 * (n + 1)) +
+                        align256(sizeof(BinNode) * n);
+    return head + std::max(scan_work_bytes_u32(256 * tiles), scan_work_bytes_u64(n + 1));
+}
+
+template <bool kBatch>
+hipError_t build(Args a, int32_t nobj, int64_t n, int64_t tiles, const float* verts, const int32_t* tris, char* bvh,
+                 void* work, int32_t method, hipStream_t s)
+{
+    const unsigned ob = (unsigned)ceil_div(nobj + 1, 256);
+    hipLaunchKernelGGL(k_header<kBatch>, dim3(ob), dim3(256), 0, s, a, bvh);
+    if (n == 0) return hipGetLastError();
+    Work w = carve(work, n, tiles, nobj);
+    const unsigned tb = (unsigned)ceil_div(n, 256);
+    const int32_t total = (int32_t)n;
+    hipLaunchKernelGGL(k_init<kBatch>, dim3(ob), dim3(256), 0, s, a, w.bounds, w.cseg0, w.base, n);
+    hipLaunchKernelGGL(k_fill_i32, dim3(std::min<unsigned>(tb, 2048u)), dim3(256), 0, s, w.nparent, n, -1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(std::min<unsigned>(tb, 2048u)), dim3(256), 0, s, w.lparent, n, -1);
+    hipLaunchKernelGGL(k_bounds<kBatch>, dim3(tb), dim3(256), 0, s, a, verts, tris, total, w.bounds);
+    hipLaunchKernelGGL(k_morton<kBatch>, dim3(tb), dim3(256), 0, s, a, verts, tris, total, (const uint32_t*)w.bounds,
+                       w.k0, w.v0);
+    uint32_t *ka = w.k0, *va = w.v0, *kb = w.k1, *vb = w.v1;
+    for (int shift = 0; shift < 32; shift += 8) {
+        hipLaunchKernelGGL(k_hist<kBatch>, dim3((unsigned)tiles), dim3(kSortThreads), 0, s, a, ka, shift, w.counts);
+        hipError_t e = scan_exclusive_u32(w.counts, w.counts, 256 * tiles, nullptr, w.scan, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_scatter<kBatch>, dim3((unsigned)tiles), dim3(kSortThreads), 0, s, a, ka, va, kb, vb, shift,
+                           (const uint32_t*)w.counts);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (method == RTSDF_BVH_LBVH) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(std::min<unsigned>(tb, 2048u)), dim3(256), 0, s, (int32_t*)w.flags32, n, 0);
+        hipLaunchKernelGGL(k_tree<kBatch>, dim3(tb), dim3(256), 0, s, a, ka, total, w.bin, w.nparent, w.lparent);
+        hipLaunchKernelGGL(k_leaves_refit<kBatch>, dim3(tb), dim3(256), 0, s, a, verts, tris, total, va, w.bin, bvh,
+                           w.nparent, w.lparent, w.flags32);
+    } else {
+        hipLaunchKernelGGL(k_ploc_init<kBatch>, dim3(tb), dim3(256), 0, s, a, verts, tris, total, va, w.ca);
+        Cluster *cin = w.ca, *cout = w.cb;
+        int32_t *sin = w.cseg0, *sout = w.cseg1;
+        const unsigned nb = (unsigned)ceil_div(n, kPlocThreads), fb = (unsigned)ceil_div(n + 1, 256);
+        for (int it = 0; it < kPlocWide; ++it) {
+            hipLaunchKernelGGL(k_ploc_nn, dim3(nb), dim3(kPlocThreads), 0, s, cin, sin, nobj, w.nn);
+            hipLaunchKernelGGL(k_ploc_flags, dim3(fb), dim3(256), 0, s, w.nn, sin, nobj, n, w.flags);
+            hipError_t e = scan_exclusive_u64(w.flags, w.flags, n + 1, nullptr, w.scan, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_ploc_seg, dim3(ob), dim3(256), 0, s, sin, sout, nobj, w.flags, w.base, w.mrank0,
+                               w.mbase);
+            hipLaunchKernelGGL(k_ploc_compact<kBatch>, dim3(tb), dim3(256), 0, s, a, cin, cout, sin, nobj, w.nn,
+                               w.flags, w.mrank0, w.mbase, w.bin, w.ncount, w.nparent, w.lparent);
+            std::swap(cin, cout);
+            std::swap(sin, sout);
+        }
+        hipLaunchKernelGGL(k_ploc_finish<kBatch>, dim3((unsigned)nobj), dim3(kFinishThreads), 0, s, a, cin, cout, sin,
+                           w.base, w.nn, w.bin, w.ncount, w.nparent, w.lparent);
+        hipLaunchKernelGGL(k_ploc_leaves<kBatch>, dim3(tb), dim3(256), 0, s, a, verts, tris, total, w.bin, w.ncount,
+                           w.nparent, w.lparent, w.posmap, bvh);
+        hipLaunchKernelGGL(k_ploc_nodes<kBatch>, dim3(tb), dim3(256), 0, s, a, total, w.bin, w.ncount, w.nparent,
+                           w.posmap);
+    }
+    hipLaunchKernelGGL(k_collapse4<kBatch>, dim3(tb), dim3(256), 0, s, a, (const BinNode*)w.bin, total, bvh);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -422,48 +938,23 @@ size_t bvh_bytes(int32_t nt)
     return 256 + sizeof(Bvh4Node) * bvh_node_count(nt) + sizeof(BvhTri) * (size_t)nt;
 }
 
-size_t bvh_work_bytes(int32_t nt)
+size_t bvh_work_bytes(int64_t total_tris, int64_t total_tiles, int32_t nobj)
 {
-    const int64_t ntiles = ceil_div(nt, kSortTile);
-    return 4 * align256((size_t)nt * 4) + align256((size_t)ntiles * 256 * 4) + 256 +
-           align256((size_t)nt * 4) + align256((size_t)(2 * (int64_t)nt) * 4) +
-           align256(sizeof(BinNode) * (size_t)nt) + scan_work_bytes_u32(ntiles * 256);
+    return carve_bytes(std::max<int64_t>(total_tris, 1), std::max<int64_t>(total_tiles, 1), nobj);
 }
 
-hipError_t build_bvh(const float* verts, const int32_t* tris, int32_t nt, const rtsdf_grid& g,
-                     void* bvh, void* work, hipStream_t s)
+hipError_t build_bvh(const float* verts, const int32_t* tris, int32_t nt, const rtsdf_grid& g, void* bvh, void* work,
+                     int32_t method, hipStream_t s)
 {
-    const float pad = g.h * (1.0f / 256.0f);
-    hipLaunchKernelGGL(k_header, dim3(1), dim3(1), 0, s, bvh_header(bvh), nt, pad);
-    if (nt == 0) return hipGetLastError();
-    SortWork w = carve(work, nt);
-    const unsigned tb = (unsigned)ceil_div(nt, 256);
-    hipLaunchKernelGGL(k_init, dim3(std::min<unsigned>(tb, 1024u)), dim3(256), 0, s, w.bounds,
-                       w.flags, nt);
-    hipLaunchKernelGGL(k_bounds, dim3(tb), dim3(256), 0, s, verts, tris, nt, w.bounds);
-    hipLaunchKernelGGL(k_morton, dim3(tb), dim3(256), 0, s, verts, tris, nt, (const uint32_t*)w.bounds,
-                       w.k0, w.v0);
-    uint32_t *ka = w.k0, *va = w.v0, *kb = w.k1, *vb = w.v1;
-    for (int shift = 0; shift < 32; shift += 8) {
-        hipLaunchKernelGGL(k_hist, dim3((unsigned)w.ntiles), dim3(kSortThreads), 0, s, ka, nt, shift,
-                           w.ntiles, w.counts);
-        hipError_t e = scan_exclusive_u32(w.counts, w.counts, (int64_t)w.ntiles * 256, nullptr, w.scan, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_scatter, dim3((unsigned)w.ntiles), dim3(kSortThreads), 0, s, ka, va, kb, vb,
-                           nt, shift, w.ntiles, (const uint32_t*)w.counts);
-        std::swap(ka, kb);
-        std::swap(va, vb);
-    }
-    BvhTri* out = bvh_tris(bvh, nt);
-    if (nt > 1)
-        hipLaunchKernelGGL(k_tree, dim3((unsigned)ceil_div(nt - 1, 256)), dim3(256), 0, s, ka, nt, w.bin,
-                           w.parent);
-    hipLaunchKernelGGL(k_leaves_refit, dim3(tb), dim3(256), 0, s, verts, tris, nt, va, pad, w.bin, out,
-                       w.parent, w.flags);
-    if (nt > 1)
-        hipLaunchKernelGGL(k_collapse4, dim3((unsigned)ceil_div(nt - 1, 256)), dim3(256), 0, s,
-                           (const BinNode*)w.bin, nt, bvh_nodes(bvh));
-    return hipGetLastError();
+    Args a{nullptr, 1, nt, g.h * (1.0f / 256.0f)};
+    return build<false>(a, 1, nt, ceil_div(nt, kBvhSortTile), verts, tris, (char*)bvh, work, method, s);
+}
+
+hipError_t build_bvh_batched(const BatchView& hv, const void* dplan, const float* verts, const int32_t* tris,
+                             void* bvh, void* work, int32_t method, hipStream_t s)
+{
+    Args a{(const char*)dplan, hv.h->nobj, 0, 0.0f};
+    return build<true>(a, hv.h->nobj, hv.h->total_tris, hv.h->total_tiles, verts, tris, (char*)bvh, work, method, s);
 }
 
 }  // namespace rtsdf

@@ -17,6 +17,7 @@ import torch
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librtsdf.so")
 EMPTY = -1
 ACCUM, DECAY = 0, 1
+BVH_LBVH, BVH_PLOC = 0, 1
 _lib = None
 
 
@@ -87,7 +88,7 @@ def lib():
             "rtsdf_band": ([vp, Grid, i32, vp, vp, vp, sz, vp], i32),
             "rtsdf_bvh_bytes": ([i32], sz),
             "rtsdf_bvh_work_bytes": ([i32], sz),
-            "rtsdf_build_bvh": ([vp, i32, vp, i32, Grid, vp, sz, vp, sz, vp], i32),
+            "rtsdf_build_bvh": ([vp, i32, vp, i32, Grid, i32, vp, sz, vp, sz, vp], i32),
             "rtsdf_reset_accum": ([vp, vp, vp, i64, vp], i32),
             "rtsdf_raysample_work_bytes": ([i64, i32], sz),
             "rtsdf_raysample": ([vp, Grid, vp, vp, i64, i32, u64, u32, u32, vp, vp, vp, vp, sz, vp], i32),
@@ -102,7 +103,7 @@ def lib():
             "rtsdf_voxelize_batched": ([vp, vp, vp, vp, vp, vp, sz, vp], i32),
             "rtsdf_jfa_batched": ([vp, vp, vp, vp], i32),
             "rtsdf_band_batched": ([vp, vp, vp, vp, vp, sz, vp], i32),
-            "rtsdf_build_bvh_batched": ([vp, vp, vp, vp, sz, vp, sz, vp], i32),
+            "rtsdf_build_bvh_batched": ([vp, vp, vp, i32, vp, sz, vp, sz, vp], i32),
             "rtsdf_raysample_batched": ([vp, vp, vp, vp, i64, i32, u64, u32, vp, vp, vp, vp, sz, vp], i32),
             "rtsdf_combine_batched": ([vp, vp, vp, vp, vp, vp], i32),
             "rtsdf_backward_batched": ([vp, vp, vp, vp, vp, vp, i64, vp, vp, i32, u64, vp, vp], i32),
@@ -193,9 +194,9 @@ def rtsdf_bvh_work_bytes(nt):
     return lib().rtsdf_bvh_work_bytes(int(nt))
 
 
-def rtsdf_build_bvh(verts, tris, grid, bvh, work, stream=None):
+def rtsdf_build_bvh(verts, tris, grid, bvh, work, method=BVH_PLOC, stream=None):
     _check(lib().rtsdf_build_bvh(_ptr(verts, torch.float32), verts.shape[0], _ptr(tris, torch.int32),
-                                 tris.shape[0], grid, _ptr(bvh), bvh.numel(), _ptr(work), work.numel(),
+                                 tris.shape[0], grid, int(method), _ptr(bvh), bvh.numel(), _ptr(work), work.numel(),
                                  _stream(stream)), "rtsdf_build_bvh")
 
 
@@ -314,9 +315,9 @@ def rtsdf_band_batched(plan, seeds, band_list, band_count, work, stream=None):
            "rtsdf_band_batched")
 
 
-def rtsdf_build_bvh_batched(plan, verts, tris, bvh, work, stream=None):
-    _check(lib().rtsdf_build_bvh_batched(plan.ptr, _ptr(verts, torch.float32), _ptr(tris, torch.int32), _ptr(bvh),
-                                         bvh.numel(), _ptr(work), work.numel(), _stream(stream)),
+def rtsdf_build_bvh_batched(plan, verts, tris, bvh, work, method=BVH_PLOC, stream=None):
+    _check(lib().rtsdf_build_bvh_batched(plan.ptr, _ptr(verts, torch.float32), _ptr(tris, torch.int32), int(method),
+                                         _ptr(bvh), bvh.numel(), _ptr(work), work.numel(), _stream(stream)),
            "rtsdf_build_bvh_batched")
 
 
@@ -355,7 +356,7 @@ class BatchSDF:
     plus trailing passes of 1.  Object o draws its rays with counter word obj = o, so its
     results equal StaticSDF(..., obj=o).  No call reads anything back to the host."""
 
-    def __init__(self, objects, rays, frames=1, rng_key=0, beta=None, bias=0.0, device="cuda"):
+    def __init__(self, objects, rays, frames=1, rng_key=0, beta=None, bias=0.0, bvh_method=BVH_PLOC, device="cuda"):
         recs = []
         for sc in objects:
             std = _halving_offsets(sc.dims)
@@ -368,6 +369,7 @@ class BatchSDF:
         self.plan = Plan(recs, device)
         z = self.plan.sizes
         self.rays, self.frames, self.rng_key = int(rays), int(frames), int(rng_key)
+        self.bvh_method = int(bvh_method)
         self.verts = torch.from_numpy(np.concatenate([np.asarray(sc.verts, np.float32).reshape(-1, 3)
                                                       for sc in objects])).to(device)
         self.tris = torch.from_numpy(np.concatenate([np.asarray(sc.tris, np.int32).reshape(-1, 3)
@@ -396,7 +398,7 @@ class BatchSDF:
         rtsdf_band_batched(self.plan, self.seeds, self.band_list, self.band_count, self.work)
 
     def build_bvh(self):
-        rtsdf_build_bvh_batched(self.plan, self.verts, self.tris, self.bvh, self.work)
+        rtsdf_build_bvh_batched(self.plan, self.verts, self.tris, self.bvh, self.work, self.bvh_method)
 
     def trace(self, frame):
         rtsdf_raysample_batched(self.plan, self.bvh, self.band_list, self.band_count, self.rays, self.rng_key, frame,
@@ -454,7 +456,7 @@ class StaticSDF:
     """
 
     def __init__(self, verts, tris, dims, org, h, steps, band, rays, frames, beta=None, bias=0.0,
-                 rng_key=0, keep_argmin=True, obj=0, device="cuda"):
+                 rng_key=0, keep_argmin=True, obj=0, bvh_method=BVH_PLOC, device="cuda"):
         self.g = make_grid(dims, org, h)
         N = self.g.n
         self.verts = torch.as_tensor(verts, dtype=torch.float32).reshape(-1, 3).contiguous().to(device)
@@ -463,6 +465,7 @@ class StaticSDF:
         self.steps, self.band, self.rays, self.frames = list(steps), int(band), int(rays), int(frames)
         self.beta = float(h) / 2 if beta is None else float(beta)
         self.bias, self.rng_key, self.obj = float(bias), int(rng_key), int(obj)
+        self.bvh_method = int(bvh_method)
         self.seeds = torch.empty(N, dtype=torch.int32, device=device)
         self.scratch = torch.empty(N, dtype=torch.int32, device=device)
         self.band_list = torch.empty(N, dtype=torch.int32, device=device)
@@ -492,7 +495,7 @@ class StaticSDF:
         rtsdf_band(self.jfa_out, self.g, self.band, self.band_list, self.band_count, self.work)
 
     def build_bvh(self):
-        rtsdf_build_bvh(self.verts, self.tris, self.g, self.bvh, self.work)
+        rtsdf_build_bvh(self.verts, self.tris, self.g, self.bvh, self.work, self.bvh_method)
 
     def trace(self, frame):
         rtsdf_raysample(self.bvh, self.g, self.band_list, self.band_count, self.rays, self.rng_key, frame,
@@ -573,7 +576,7 @@ class DeformSDF:
     """
 
     def __init__(self, frame_verts, tris, dims, org, h, steps, band, rays, alpha=0.95, beta=None, bias=0.0,
-                 rng_key=0, device="cuda"):
+                 rng_key=0, bvh_method=BVH_LBVH, device="cuda"):
         self.g = make_grid(dims, org, h)
         N = self.g.n
         self.verts = torch.as_tensor(frame_verts, dtype=torch.float32).contiguous().to(device)
@@ -582,6 +585,7 @@ class DeformSDF:
         nt = self.tris.shape[0]
         self.steps, self.band, self.rays = list(steps), int(band), int(rays)
         self.alpha = float(alpha)
+        self.bvh_method = int(bvh_method)
         self.beta = float(h) / 2 if beta is None else float(beta)
         self.bias, self.rng_key = float(bias), int(rng_key)
         self.seeds = torch.empty(N, dtype=torch.int32, device=device)
@@ -606,7 +610,7 @@ class DeformSDF:
         rtsdf_voxelize(v, self.tris, self.g, self.seeds, self.work)
         self.jfa_out = rtsdf_jfa(self.seeds, self.scratch, self.g, self.steps)
         rtsdf_band(self.jfa_out, self.g, self.band, self.band_list, self.band_count, self.work)
-        rtsdf_build_bvh(v, self.tris, self.g, self.bvh, self.work)
+        rtsdf_build_bvh(v, self.tris, self.g, self.bvh, self.work, self.bvh_method)
         rtsdf_raysample(self.bvh, self.g, self.band_list, self.band_count, self.rays, self.rng_key, f, self.dmin,
                         self.hits, self.ray_work)
         rtsdf_combine(self.jfa_out, self.dmin, self.hits, self.g, self.band, self.beta, self.bias, DECAY,

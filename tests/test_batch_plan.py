@@ -14,11 +14,12 @@ from paper_2210_06160_amd import synth
 MAX_PASSES = 19
 HEADER = np.dtype([("magic", "<u4"), ("nobj", "<i4"), ("max_passes", "<i4"), ("r0", "<i4"), ("total_vox", "<i8"),
                    ("total_verts", "<i8"), ("total_tris", "<i8"), ("bvh_bytes", "<u8"), ("plan_bytes", "<u8"),
-                   ("device", "<u8"), ("pass_blocks", "<i4", (MAX_PASSES,)), ("rest", "V%d" % (256 - 64 - 4 * MAX_PASSES))])
+                   ("device", "<u8"), ("pass_blocks", "<i4", (MAX_PASSES,)), ("total_tiles", "<i4"),
+                   ("rest", "V%d" % (256 - 68 - 4 * MAX_PASSES))])
 OBJECT = np.dtype([("n", "<i4", (3,)), ("org", "<f4", (3,)), ("h", "<f4"), ("band_vox", "<i4"), ("vox_off", "<i8"),
                    ("bvh_off", "<i8"), ("vert_off", "<i4"), ("tri_off", "<i4"), ("nv", "<i4"), ("nt", "<i4"),
                    ("nsteps", "<i4"), ("nhalf", "<i4"), ("k0", "<i4"), ("flip", "<i4"), ("beta", "<f4"),
-                   ("bias", "<f4")])
+                   ("bias", "<f4"), ("tile_off", "<i4"), ("r1", "<i4")])
 
 
 @pytest.fixture(scope="module")
@@ -98,6 +99,8 @@ def test_plan_tables(R, which):
         assert objs[o]["bvh_off"] == b and b % 256 == 0 and plan.offsets(o)[1] == b
         b += -(-R.rtsdf_bvh_bytes(len(sc.tris)) // 256) * 256
     assert b == h["bvh_bytes"] == plan.sizes.bvh_bytes
+    tiles = np.cumsum([0] + [-(-len(s.tris) // 1024) for s in scenes])
+    assert list(objs["tile_off"]) == list(tiles[:-1]) and h["total_tiles"] == tiles[-1]
     # JFA offsets and start-buffer parity
     for o, sc in enumerate(scenes):
         ob = objs[o]
@@ -134,6 +137,7 @@ def test_plan_tables(R, which):
         assert vox_prefix[o] <= t < vox_prefix[o + 1]
     # workspace covers every stage
     need = max(R.rtsdf_voxelize_work_bytes(int(h["total_tris"])), max(R.rtsdf_bvh_work_bytes(len(s.tris)) for s in scenes))
+    assert OBJECT.itemsize == 96
     assert plan.sizes.work_bytes >= need
 
 

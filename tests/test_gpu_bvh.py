@@ -1,0 +1,119 @@
+"""The hierarchy builders on the GPU: every blob decoded and validated on the host (leaf
+ranges partition the triangles, child boxes contain their triangles, records match the
+mesh), ray sampling bit-identical whichever tree is built (culling is exact), and the
+batched build equal byte for byte to the single-object build of every object.
+Cases: 1, 2, 3, 4 and 5 triangles, triangles sharing one centroid, the 32^3 icosphere, a
+reduced static scene, a mixed batch, and the full static scene (PLOC)."""
+import sys
+
+import numpy as np
+import pytest
+
+from bvh_check import check
+from paper_2210_06160_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2210_06160_amd import rtsdf
+    rtsdf.lib()
+    return rtsdf
+
+
+def build(R, verts, tris, dims, h, method):
+    import torch
+    g = R.make_grid(dims, (0, 0, 0), h)
+    V = torch.from_numpy(np.ascontiguousarray(verts, np.float32)).cuda()
+    T = torch.from_numpy(np.ascontiguousarray(tris, np.int32).reshape(-1, 3)).cuda()
+    bvh = torch.empty(R.rtsdf_bvh_bytes(len(tris)), dtype=torch.uint8, device="cuda")
+    work = R.workspace(R.rtsdf_bvh_work_bytes(len(tris)))
+    R.rtsdf_build_bvh(V, T, g, bvh, work, method)
+    torch.cuda.synchronize()
+    return bvh.cpu().numpy()
+
+
+def small_meshes():
+    rng = np.random.default_rng(3)
+    out = []
+    for n in (1, 2, 3, 4, 5, 17):
+        v = rng.uniform(0.2, 0.8, size=(3 * n, 3)).astype(np.float32)
+        out.append(("random%d" % n, v, np.arange(3 * n, dtype=np.int32).reshape(n, 3)))
+    # eight triangles rotated about one point: identical centroids (equal Morton codes)
+    base = np.array([[0.1, 0, 0], [-0.05, 0.08, 0], [-0.05, -0.08, 0]], np.float32)
+    tris_v = []
+    for k in range(8):
+        a = k * np.pi / 8
+        rot = np.array([[np.cos(a), 0, np.sin(a)], [0, 1, 0], [-np.sin(a), 0, np.cos(a)]], np.float32)
+        tris_v.append(base @ rot.T + 0.5)
+    out.append(("same-centroid", np.concatenate(tris_v).astype(np.float32), np.arange(24, dtype=np.int32).reshape(8, 3)))
+    v, t = synth.icosphere(1, 0.3, (0.5, 0.5, 0.5))
+    out.append(("icosphere80", v, t))
+    sc = synth.scene_static(dims=(100, 50, 100), nprims=40, seed=1)
+    out.append(("static-reduced", sc.verts, sc.tris))
+    return out
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_blob_valid(R, method):
+    for name, v, t in small_meshes():
+        log("case: %s, %d triangles, method %d" % (name, len(t), method))
+        blob = build(R, v, t, (32, 32, 32), 1.0 / 32, method)
+        check(blob, v, t, np.float32(1.0 / 32) * np.float32(1.0 / 256))
+
+
+def test_raysample_independent_of_tree(R):
+    import torch
+    sc = synth.scene_static(dims=(100, 50, 100), nprims=40, seed=1)
+    sc.frames = 2
+    log("case: static 100x50x100, LBVH vs PLOC")
+    out = []
+    for method in (0, 1):
+        S = R.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames,
+                        bvh_method=method)
+        S.run()
+        torch.cuda.synchronize()
+        out.append((S.dmin.clone(), S.hits.clone(), S.argmin.clone(), S.fine.clone()))
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a.view(torch.int32) if a.dtype == torch.float32 else a,
+                           b.view(torch.int32) if b.dtype == torch.float32 else b)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_batched_build_equals_single(R, method):
+    import torch
+    objs = synth.scene_batch(nobj=6, seed=5, tri_range=(80, 5000), n_range=(12, 70))
+    v, t = synth.icosphere(1, 0.3, (0.5, 0.5, 0.5))
+    empty = synth.Scene(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32), (5, 7, 3), (0, 0, 0), 0.2,
+                        synth.jfa_offsets((5, 7, 3)), 2, 8, 1)
+    one = synth.Scene(v[:3], np.array([[0, 1, 2]], np.int32), (9, 9, 9), (0, 0, 0), 1 / 9, synth.jfa_offsets((9, 9, 9)),
+                      2, 8, 1)
+    objs = objs[:2] + [empty] + objs[2:4] + [one] + objs[4:]
+    log("case: batched build of %d objects, method %d" % (len(objs), method))
+    B = R.BatchSDF(objs, rays=8, bvh_method=method)
+    B.build_bvh()
+    torch.cuda.synchronize()
+    blob = B.bvh.cpu().numpy()
+    for o, sc in enumerate(objs):
+        off = B.offsets[o][1]
+        nbytes = R.rtsdf_bvh_bytes(len(sc.tris))
+        single = build(R, sc.verts, sc.tris, sc.dims, sc.h, method)
+        assert np.array_equal(blob[off:off + nbytes], single[:nbytes]), "object %d" % o
+        check(single, sc.verts, sc.tris, np.float32(sc.h) * np.float32(1.0 / 256))
+
+
+def test_full_static_ploc_blob(R):
+    sc = synth.scene_static()
+    log("case: static 400x200x400 scene, PLOC blob")
+    blob = build(R, sc.verts, sc.tris, sc.dims, sc.h, 1)
+    nodes = check(blob, sc.verts, sc.tris, np.float32(sc.h) * np.float32(1.0 / 256))
+    log("  reachable 4-wide nodes", nodes)
