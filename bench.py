@@ -31,6 +31,8 @@ def parse():
     p.add_argument("--no-deform", action="store_true", help="skip the deforming-mesh (graph) measurement")
     p.add_argument("--no-grad", action="store_true", help="skip the gradient-workload measurement")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-objects measurement")
+    p.add_argument("--only", choices=["static", "deform", "grad", "batch"],
+                   help="run one workload alone and print its record (for profiling)")
     p.add_argument("--cpu-sample", type=int, default=20000, help="masked voxels ray-sampled by the oracle")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy three times (to scale HBM counters)")
@@ -38,7 +40,7 @@ def parse():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "raysample_static_400x200x400_counters.md")
-TRAFFIC_SOURCES = ["raysample.hip", "sampling.h", "lbvh.hip", "internal.h"]
+TRAFFIC_SOURCES = ["raysample.hip", "traverse.h", "sampling.h", "lbvh.hip", "internal.h"]
 
 
 def recorded_traffic():
@@ -308,6 +310,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n, "copy_calibration_bytes_written": n, "dispatches": 3}))
         return
+    if args.only in ("deform", "grad", "batch"):
+        fn = {"deform": deform_bench, "grad": grad_bench, "batch": batch_bench}[args.only]
+        print(json.dumps({args.only: fn(torch, rtsdf, synth)}))
+        return
+    if args.only == "static":
+        args.no_deform = args.no_grad = args.no_batch = True
     sc = synth.scene_static()
     S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
     N = S.g.n
@@ -330,9 +338,11 @@ def main():
     rays_per_s = rays / (stages["raysample"] / 1e3)
     dominant = max(stages, key=stages.get)
     launch_ms = stages["raysample"] / sc.frames
-    # ray sampling: bound by plain ALU work and cache latency (no dense contraction, no
-    # streaming); algorithmic ops per ray are the estimate stated in the design doc
-    ops_per_ray = 2500.0
+    # ray sampling: bound by plain ALU issue (no dense contraction, no streaming).  Algorithmic
+    # lane-ops per ray on this scene's PLOC hierarchy: Philox + Marsaglia (~100) + 20.1
+    # four-wide node visits x 64 (4 slab tests) + 9.4 triangle tests x 45, the visit and test
+    # counts measured with an instrumented copy of the kernel
+    ops_per_ray = 100.0 + 20.12 * 64.0 + 9.40 * 45.0
     achieved = band * sc.rays * ops_per_ray / (launch_ms / 1e3) / 1e12
     traffic = recorded_traffic()
     roof = {"kernel": "raysample", "bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
