@@ -1,16 +1,19 @@
-// Ray sampling of the masked grid points (section 2.1) against the software LBVH.
+// Ray sampling of the masked grid points (section 2.1) against the software BVH.
 //
-// A persistent grid; each lane owns one masked voxel at a time and traces its rays
-// j = 0..x-1 one after the other, keeping the minimum distance, hit counts and argmin
-// record in registers, and folds them into the voxel's accumulators once at the end
-// (min / add are order-free, so the result does not depend on scheduling).  A lane whose
-// ray ends starts its next ray at once, and a lane whose voxel is done takes the next
-// voxel from its wave's chunk of the mask list (one cursor atomic per kChunk voxels: device-
-// scope atomics on one address serialise across the chip), so divergent ray lengths
-// neither idle lanes nor leave a tail of busy waves.  The mask list is split into one contiguous
-// range per XCD (work-groups are dealt to the 8 XCDs round-robin); a wave takes voxels
-// from its own XCD's range first, so list reads and the hierarchy working set stay in
-// that XCD's L2, and steals from the other ranges when its own is exhausted.
+// A persistent grid; each lane owns one work unit at a time -- a masked voxel and a group of
+// its rays j (all x of them unless the mask is small, see below) -- and traces those rays
+// one after the other, keeping the minimum distance, hit counts and argmin record in
+// registers, and folds them into the voxel's accumulators once at the end (min / add are
+// order-free, so the result does not depend on scheduling).  A lane whose ray ends starts
+// its next ray at once, and a lane whose unit is done takes the next unit from its wave's
+// chunk of the unit range (one cursor atomic per kChunk units: device-scope atomics on one
+// address serialise across the chip), so divergent ray lengths neither idle lanes nor
+// leave a tail of busy waves.  A mask with fewer than about two voxels per lane of the grid
+// is split into groups of consecutive rays so that every lane has work.  The unit range is
+// split into one contiguous range per XCD (work-groups are dealt to the 8 XCDs
+// round-robin); a wave takes units from its own XCD's range first, so list reads and the
+// hierarchy working set stay in that XCD's L2, and steals from the other ranges when its
+// own is exhausted.
 // The loop touches no cold memory: directions are drawn in registers and accumulators are
 // updated with fire-and-forget atomics, because on CDNA loads retire in order and one
 // HBM-latency load would stall every later node fetch of the wave.
@@ -35,8 +38,9 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kLdsDepth = 12;
 constexpr int kXcds = 8;
-constexpr int32_t kChunk = 128;  // mask entries a wave takes per cursor atomic
+constexpr int32_t kChunk = 128;  // work units a wave takes per cursor atomic
 constexpr int32_t kStartBatch = 12;  // idle lanes restarted together
+constexpr int kMinWaves = 6;         // waves per SIMD the register budget must allow
 __device__ inline void test_leaf(const BvhTri* __restrict__ tris, int32_t pos, float3 o, float3 w,
                                  float pad, float& tb, int32_t& bid, bool& bfr)
 {
@@ -54,7 +58,7 @@ __device__ inline void test_leaf(const BvhTri* __restrict__ tris, int32_t pos, f
     }
 }
 
-// cursors[x] walks XCD x's range [x*count/8, (x+1)*count/8) of the mask list
+// cursors[x] walks XCD x's range [x*units/8, (x+1)*units/8) of the work units
 __global__ void k_cursor_reset(int32_t* cursors)
 {
     if (threadIdx.x < kXcds) cursors[threadIdx.x] = 0;
@@ -63,7 +67,7 @@ __global__ void k_cursor_reset(int32_t* cursors)
 // kBatch: the mask list indexes concatenated grids; each voxel's object (binary search over
 // the plan's voxel prefix) supplies its grid, its hierarchy and the counter's object word.
 template <bool kBatch>
-__global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__ bvh, const rtsdf_grid g,
+__global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* __restrict__ bvh, const rtsdf_grid g,
                                                         const int32_t* __restrict__ list,
                                                         const int32_t* __restrict__ count_p, int32_t x,
                                                         uint32_t k0, uint32_t k1, uint32_t frame,
@@ -94,6 +98,14 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
     uint32_t lobj = obj;
     if (!kBatch) use_bvh(bvh);
     const int32_t count = *count_p;
+    // Work units: (listed voxel, group of consecutive rays).  A mask smaller than about two
+    // units per lane of the grid is split into ray groups so that every lane has work;
+    // otherwise a unit is a whole voxel.  units <= max(count, 2 * lanes) < 2^31.
+    const int64_t lanes = (int64_t)gridDim.x * kThreads;
+    int32_t ngroups = (int32_t)min((int64_t)x, max((int64_t)1, (2 * lanes) / max((int64_t)count, (int64_t)1)));
+    const uint32_t gsize = (uint32_t)((x + ngroups - 1) / ngroups);
+    ngroups = (int32_t)((x + (int32_t)gsize - 1) / (int32_t)gsize);
+    const int32_t units = count * ngroups;
     const float inf = __int_as_float(0x7f800000);
     const int tid = threadIdx.x;
     const int lane = __lane_id();
@@ -101,11 +113,11 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
     const uint32_t code0 = frame * (uint32_t)x;
     int xcd = (int)(blockIdx.x % kXcds);  // the range this wave takes voxels from
     int tried = 0;                        // ranges found exhausted
-    int32_t q_next = 0, q_end = 0;        // the wave's current chunk of the mask list
+    int32_t q_next = 0, q_end = 0;        // the wave's current chunk of the unit range
 
     int32_t vid = -1;
     uint32_t lvid = 0;  // the voxel's index within its own grid (counter word)
-    uint32_t j = 0;
+    uint32_t j = 0, jend = 0;  // the unit's current and end ray
     float acc_d = inf;
     uint32_t acc_h = 0;
     uint64_t acc_a = ~0ull;
@@ -145,7 +157,7 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
                     const uint64_t rec = ((uint64_t)__float_as_uint(tb) << 32) | (uint64_t)(code0 + j);
                     acc_a = rec < acc_a ? rec : acc_a;
                 }
-                if (++j == (uint32_t)x) {
+                if (++j == jend) {
                     if (acc_h != 0u) {
                         atomicMin((uint32_t*)&dmin[vid], __float_as_uint(acc_d));
                         atomicAdd(&hits[vid], acc_h);
@@ -156,14 +168,14 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
             }
             need = vid < 0;
         }
-        // wave-cooperative refill: lanes take voxels from the wave's current chunk of the mask
-        // list; an empty chunk is replaced by one atomic on this XCD's cursor, and an
+        // wave-cooperative refill: lanes take units from the wave's current chunk; an empty
+        // chunk is replaced by one atomic on this XCD's cursor, and an
         // exhausted range moves the wave on to the next XCD's range
         uint64_t needers = __ballot(need);
         while (needers && tried < kXcds) {
             if (q_next >= q_end) {
-                const int32_t lo = (int32_t)(((int64_t)count * xcd) / kXcds);
-                const int32_t hi = (int32_t)(((int64_t)count * (xcd + 1)) / kXcds);
+                const int32_t lo = (int32_t)(((int64_t)units * xcd) / kXcds);
+                const int32_t hi = (int32_t)(((int64_t)units * (xcd + 1)) / kXcds);
                 int32_t base = 0;
                 if (lane == 0) base = atomicAdd(&cursors[xcd], kChunk);
                 base = __shfl(base, 0) + lo;
@@ -178,10 +190,12 @@ __global__ __launch_bounds__(kThreads) void k_raysample(const char* __restrict__
             const int32_t rank = (int32_t)__popcll(needers & lt_mask);
             const int32_t take = min((int32_t)__popcll(needers), q_end - q_next);
             if (need && rank < take) {
-                const int32_t idx = q_next + rank;
-                vid = list[idx];
+                const int32_t u = q_next + rank;
+                const int32_t q = u / ngroups;
+                vid = list[q];
                 need = false;
-                j = 0;
+                j = (uint32_t)(u - q * ngroups) * gsize;
+                jend = min(j + gsize, (uint32_t)x);
                 acc_d = inf;
                 acc_h = 0u;
                 acc_a = ~0ull;
