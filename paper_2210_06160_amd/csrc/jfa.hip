@@ -13,7 +13,8 @@
 //     key = (w - 2 pz sz) * 32 + rank = (d2 - pz^2) * 32 + rank,
 // an order-preserving image of (d2, rank) (one v_mad_i32_i24 and one v_lshl_add_u32),
 // reduced with v_min3_i32.  The winner's id is reloaded from its (recently cached)
-// position.  EMPTY (-1) unpacks to (1023, 1023, 4095), which makes w - 2 pz sz >= 8.39e6
+// position (the offset of each rank for the pass's k comes from a small LDS table, and the
+// nine gathers of a plane are buffer loads off a scalar plane base).  EMPTY (-1) unpacks to (1023, 1023, 4095), which makes w - 2 pz sz >= 8.39e6
 // > any real d2 (<= 3 * 1023^2), so it never wins against a seed; out-of-grid queries load
 // EMPTY.  Keys stay within +-2^30.
 #include "internal.h"
@@ -57,11 +58,31 @@ __host__ __device__ constexpr int32_t rank_of(int ex, int ey, int ez)
                                                              : 9 * (ez + 1) + 3 * (ey + 1) + (ex + 1);
 }
 
+// element offset, relative to the output point, of the query that rank rk names, for
+// offset k (the winner's id is reloaded from there); built once per work-group in LDS
+__device__ inline void rank_table(int32_t* tab, int32_t nx, int32_t ny, int32_t k)
+{
+    const int t = threadIdx.x + threadIdx.y * kBX;
+    if (t < 27) {
+        const int32_t L = t == 0 ? 13 : (t <= 13 ? t - 1 : t);
+        const int32_t ez = L / 9 - 1, ey = (L / 3) % 3 - 1, ex = L % 3 - 1;
+        tab[t] = ex * k + ey * k * nx + ez * k * (nx * ny);
+    }
+}
+
+// One plane of the input as a buffer resource: a scalar base and 32-bit byte offsets, so
+// the nine gathers of a plane need no per-lane address arithmetic.
+__device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const int32_t* in, uint32_t plane, int32_t z)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(in + (size_t)plane * (uint32_t)z), (short)0, 0x7FFFFFFF,
+                                            0x00020000);
+}
+
 // work-group (bx, by, bz) of a pass over one grid: x-columns bx*64.., y-columns by*4..,
-// residue class r and chunk c of that class from bz
+// residue class r and chunk c of that class from bz; tab = rank_table(nx, ny, k)
 __device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_t* __restrict__ out, int32_t nx,
                                           int32_t ny, int32_t nz, int32_t k, int32_t chunks_per_residue,
-                                          int32_t bx, int32_t by, int32_t bz)
+                                          int32_t bx, int32_t by, int32_t bz, const int32_t* tab)
 {
     const int32_t x = bx * kBX + threadIdx.x;
     const int32_t y = by * kBY + threadIdx.y;
@@ -88,20 +109,18 @@ __device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_
         }
 
     const short2_t pxy = __builtin_bit_cast(short2_t, (uint32_t)x | ((uint32_t)y << 16));
+    // planes outside the grid (m < 0 or z >= nz, uniform) load a valid plane and read EMPTY
     auto load_plane = [&](int32_t m, Cand* dst) {
         const int32_t z = r + m * k;
-        if (m >= 0 && z < nz) {  // wave-uniform
-            const char* pb = (const char*)(in + plane * (uint32_t)z);
+        const bool pv = m >= 0 && z < nz;
+        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(in, plane, pv ? z : r);
 #pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                const int32_t v = *(const int32_t*)(pb + off[q]);
-                dst[q] = prep(ok[q] ? v : RTSDF_EMPTY, pxy);
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < 9; ++q) dst[q] = prep(RTSDF_EMPTY, pxy);
+        for (int q = 0; q < 9; ++q) {
+            const int32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off[q], 0, 0);
+            dst[q] = prep(ok[q] && pv ? v : RTSDF_EMPTY, pxy);
         }
     };
+    const uint32_t pxy_idx = (uint32_t)x + (uint32_t)nx * (uint32_t)y;
     // output for lattice point m from planes m-1 (lo), m (mid), m+1 (hi)
     auto emit = [&](int32_t m, const Cand* lo, const Cand* mid, const Cand* hi) {
         const int32_t pz = r + m * k;
@@ -118,14 +137,10 @@ __device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_
                 const int32_t d = cand_key(P[ez + 1][q + 2], m2pz, rank_of(1, ey, ez));
                 best = min(best, min(min(a, b), d));
             }
+        const uint32_t p = pxy_idx + plane * (uint32_t)pz;
         int32_t id = RTSDF_EMPTY;
-        if ((best >> 5) < kEmptyV) {
-            const int32_t rk = best & 31;
-            const int32_t L = rk == 0 ? 13 : (rk <= 13 ? rk - 1 : rk);
-            const int32_t ez = L / 9 - 1, ey = (L / 3) % 3 - 1, ex = L % 3 - 1;
-            id = in[(uint32_t)(x + ex * k) + (uint32_t)nx * (uint32_t)(y + ey * k) + plane * (uint32_t)(pz + ez * k)];
-        }
-        out[(uint32_t)x + (uint32_t)nx * (uint32_t)y + plane * (uint32_t)pz] = id;
+        if ((best >> 5) < kEmptyV) id = in[(uint32_t)((int32_t)p + tab[best & 31])];
+        out[p] = id;
     };
 
     Cand A[9], B[9], C[9];
@@ -149,7 +164,10 @@ __global__ __launch_bounds__(kBX * kBY) void k_jfa_stream(const int32_t* __restr
                                                           int32_t ny, int32_t nz, int32_t k,
                                                           int32_t chunks_per_residue)
 {
-    jfa_block(in, out, nx, ny, nz, k, chunks_per_residue, blockIdx.x, blockIdx.y, blockIdx.z);
+    __shared__ int32_t tab[32];
+    rank_table(tab, nx, ny, k);
+    __syncthreads();
+    jfa_block(in, out, nx, ny, nz, k, chunks_per_residue, blockIdx.x, blockIdx.y, blockIdx.z, tab);
 }
 
 __host__ __device__ inline int32_t chunks_per_residue(int32_t nz, int32_t k)
@@ -176,7 +194,10 @@ __global__ __launch_bounds__(kBX * kBY) void k_jfa_batched(const char* __restric
     const bool from_scratch = (ob.flip ^ (pass & 1)) != 0;
     const int32_t* in = (from_scratch ? scratch : seeds) + ob.vox_off;
     int32_t* out = (from_scratch ? seeds : scratch) + ob.vox_off;
-    jfa_block(in, out, nx, ny, nz, k, chunks_per_residue(nz, k), l % gx, (l / gx) % gy, l / (gx * gy));
+    __shared__ int32_t tab[32];
+    rank_table(tab, nx, ny, k);
+    __syncthreads();
+    jfa_block(in, out, nx, ny, nz, k, chunks_per_residue(nz, k), l % gx, (l / gx) % gy, l / (gx * gy), tab);
 }
 
 }  // namespace
