@@ -27,25 +27,28 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-ffp-contract=
          "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 
 
-def _compile(src):
-    obj = os.path.join(OUT, os.path.basename(src) + ".o")
-    cmd = ["hipcc", *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src, out, defines):
+    obj = os.path.join(out, os.path.basename(src) + ".o")
+    cmd = ["hipcc", *FLAGS, *["-D%s=%s" % kv for kv in sorted(defines.items())], "-x", "hip", "-c",
+           os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))
     return obj
 
 
-def build(verbose=False):
-    os.makedirs(OUT, exist_ok=True)
+def build(verbose=False, defines=None, out=OUT, lib=LIB):
+    """Compiles every source and links `lib`.  `defines` override csrc/tuning.h values."""
+    os.makedirs(out, exist_ok=True)
+    defines = dict(defines or {})
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, out, defines), SOURCES))
+    tmp = lib + ".tmp"
     subprocess.check_call(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp])
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(LIB)
-    return LIB
+        print(lib)
+    return lib
 
 
 if __name__ == "__main__":

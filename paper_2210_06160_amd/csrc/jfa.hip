@@ -18,13 +18,16 @@
 // > any real d2 (<= 3 * 1023^2), so it never wins against a seed; out-of-grid queries load
 // EMPTY.  Keys stay within +-2^30.
 #include "internal.h"
+#include "tuning.h"
 
 namespace rtsdf {
 
 namespace {
 
-constexpr int kBX = 64, kBY = 4;   // threads per block: 64 x-columns x 4 y-columns
-constexpr int kChunk = 16;          // lattice points per block along z
+constexpr int kBX = 64, kBY = RTSDF_JFA_ROWS;  // threads per block: 64 x-columns x kBY y-columns
+constexpr int kChunk = RTSDF_JFA_CHUNK;        // lattice points per block along z
+constexpr int kChunkSmall = 16;                // ... for passes that would launch few blocks
+constexpr int64_t kFewBlocks = 2048;           // below this many blocks, use kChunkSmall
 constexpr int32_t kEmptyV = 8000000;  // v >= this only for EMPTY
 
 struct Cand {
@@ -80,6 +83,7 @@ __device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const int32_t* in, uint32_t 
 
 // work-group (bx, by, bz) of a pass over one grid: x-columns bx*64.., y-columns by*4..,
 // residue class r and chunk c of that class from bz; tab = rank_table(nx, ny, k)
+template <int kCh>
 __device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_t* __restrict__ out, int32_t nx,
                                           int32_t ny, int32_t nz, int32_t k, int32_t chunks_per_residue,
                                           int32_t bx, int32_t by, int32_t bz, const int32_t* tab)
@@ -90,9 +94,9 @@ __device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_
     const int32_t c = bz - r * chunks_per_residue;
     if (x >= nx || y >= ny || r >= nz) return;
     const int32_t mcount = (nz - r + k - 1) / k;  // lattice points z = r + m k < nz
-    const int32_t m0 = c * kChunk;
+    const int32_t m0 = c * kCh;
     if (m0 >= mcount) return;
-    const int32_t m1 = min(m0 + kChunk, mcount);
+    const int32_t m1 = min(m0 + kCh, mcount);
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;  // grids hold at most 2^30 points
 
     // byte offsets of the 3 x 3 neighbourhood columns; out-of-grid columns read EMPTY
@@ -159,6 +163,7 @@ __device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_
     }
 }
 
+template <int kCh>
 __global__ __launch_bounds__(kBX * kBY) void k_jfa_stream(const int32_t* __restrict__ in,
                                                           int32_t* __restrict__ out, int32_t nx,
                                                           int32_t ny, int32_t nz, int32_t k,
@@ -167,12 +172,12 @@ __global__ __launch_bounds__(kBX * kBY) void k_jfa_stream(const int32_t* __restr
     __shared__ int32_t tab[32];
     rank_table(tab, nx, ny, k);
     __syncthreads();
-    jfa_block(in, out, nx, ny, nz, k, chunks_per_residue, blockIdx.x, blockIdx.y, blockIdx.z, tab);
+    jfa_block<kCh>(in, out, nx, ny, nz, k, chunks_per_residue, blockIdx.x, blockIdx.y, blockIdx.z, tab);
 }
 
-__host__ __device__ inline int32_t chunks_per_residue(int32_t nz, int32_t k)
+__host__ __device__ inline int32_t chunks_per_residue(int32_t nz, int32_t k, int32_t chunk = kChunk)
 {
-    return (int32_t)ceil_div(ceil_div(nz, k), kChunk);
+    return (int32_t)ceil_div(ceil_div(nz, k), chunk);
 }
 
 // One pass over every object still flooding: the flat work-group index picks the object
@@ -197,7 +202,7 @@ __global__ __launch_bounds__(kBX * kBY) void k_jfa_batched(const char* __restric
     __shared__ int32_t tab[32];
     rank_table(tab, nx, ny, k);
     __syncthreads();
-    jfa_block(in, out, nx, ny, nz, k, chunks_per_residue(nz, k), l % gx, (l / gx) % gy, l / (gx * gy), tab);
+    jfa_block<kChunk>(in, out, nx, ny, nz, k, chunks_per_residue(nz, k), l % gx, (l / gx) % gy, l / (gx * gy), tab);
 }
 
 }  // namespace
@@ -220,9 +225,15 @@ hipError_t jfa_batched_pass(const BatchView& hv, const void* dplan, int32_t* see
 hipError_t jfa_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, hipStream_t s)
 {
     const int64_t residues = std::min<int64_t>(k, g.nz);
-    const int64_t per_res = chunks_per_residue(g.nz, k);
+    const bool few = jfa_pass_blocks(g, k) < kFewBlocks;  // small grids: shorter chunks, more blocks
+    const int64_t per_res = chunks_per_residue(g.nz, k, few ? kChunkSmall : kChunk);
     dim3 grid((unsigned)ceil_div(g.nx, kBX), (unsigned)ceil_div(g.ny, kBY), (unsigned)(residues * per_res));
-    hipLaunchKernelGGL(k_jfa_stream, grid, dim3(kBX, kBY), 0, s, in, out, g.nx, g.ny, g.nz, k, (int32_t)per_res);
+    if (few)
+        hipLaunchKernelGGL(k_jfa_stream<kChunkSmall>, grid, dim3(kBX, kBY), 0, s, in, out, g.nx, g.ny, g.nz, k,
+                           (int32_t)per_res);
+    else
+        hipLaunchKernelGGL(k_jfa_stream<kChunk>, grid, dim3(kBX, kBY), 0, s, in, out, g.nx, g.ny, g.nz, k,
+                           (int32_t)per_res);
     return hipGetLastError();
 }
 

@@ -6,8 +6,8 @@
 // registers, and folds them into the voxel's accumulators once at the end (min / add are
 // order-free, so the result does not depend on scheduling).  A lane whose ray ends starts
 // its next ray at once, and a lane whose unit is done takes the next unit from its wave's
-// chunk of the unit range (one cursor atomic per kChunk units: device-scope atomics on one
-// address serialise across the chip), so divergent ray lengths neither idle lanes nor
+// chunk of the unit range (one cursor atomic per chunk of units: device-scope atomics on
+// one address serialise across the chip), so divergent ray lengths neither idle lanes nor
 // leave a tail of busy waves.  A mask with fewer than about two voxels per lane of the grid
 // is split into groups of consecutive rays so that every lane has work.  The unit range is
 // split into one contiguous range per XCD (work-groups are dealt to the 8 XCDs
@@ -30,6 +30,7 @@
 // of its triangle's box, so a box holding a hit is never culled and the result equals the
 // brute-force least (t, triangle index).
 #include "traverse.h"
+#include "tuning.h"
 
 namespace rtsdf {
 
@@ -38,8 +39,9 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kLdsDepth = 12;
 constexpr int kXcds = 8;
-constexpr int32_t kChunk = 128;  // work units a wave takes per cursor atomic
-constexpr int32_t kStartBatch = 12;  // idle lanes restarted together
+constexpr int32_t kChunk = RTSDF_RAY_CHUNK;            // work units a wave takes per cursor atomic
+constexpr int32_t kChunkSmall = 128;                   // ... when there are few units per lane
+constexpr int32_t kStartBatch = RTSDF_RAY_START_BATCH;  // idle lanes restarted together
 constexpr int kMinWaves = 6;         // waves per SIMD the register budget must allow
 __device__ inline void test_leaf(const BvhTri* __restrict__ tris, int32_t pos, float3 o, float3 w,
                                  float pad, float& tb, int32_t& bid, bool& bfr)
@@ -106,6 +108,8 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
     const uint32_t gsize = (uint32_t)((x + ngroups - 1) / ngroups);
     ngroups = (int32_t)((x + (int32_t)gsize - 1) / (int32_t)gsize);
     const int32_t units = count * ngroups;
+    // many units per lane: short chunks balance the tail; few: long chunks, fewer atomics
+    const int32_t chunk = (int64_t)units >= 8 * lanes ? kChunk : kChunkSmall;
     const float inf = __int_as_float(0x7f800000);
     const int tid = threadIdx.x;
     const int lane = __lane_id();
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
                 const int32_t lo = (int32_t)(((int64_t)units * xcd) / kXcds);
                 const int32_t hi = (int32_t)(((int64_t)units * (xcd + 1)) / kXcds);
                 int32_t base = 0;
-                if (lane == 0) base = atomicAdd(&cursors[xcd], kChunk);
+                if (lane == 0) base = atomicAdd(&cursors[xcd], chunk);
                 base = __shfl(base, 0) + lo;
                 if (base >= hi) {
                     xcd = (xcd + 1) % kXcds;
@@ -185,7 +189,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
                     continue;
                 }
                 q_next = base;
-                q_end = min(base + kChunk, hi);
+                q_end = min(base + chunk, hi);
             }
             const int32_t rank = (int32_t)__popcll(needers & lt_mask);
             const int32_t take = min((int32_t)__popcll(needers), q_end - q_next);

@@ -1,7 +1,7 @@
 // Soft shadows by sphere tracing the fine field (section 2.4) and the reverse pass that
 // carries an image gradient back to the field.
 //
-// One wave shades an 8 x 8 tile of pixels: neighbouring shadow rays march through
+// One wave shades a tile of 64 pixels (8 x 8 unless tuned otherwise): neighbouring shadow rays march through
 // neighbouring cells, so a wave's trilinear gathers share cache lines.  Work-groups are
 // dealt to the eight XCDs round-robin; the tile order is remapped so that each XCD shades
 // one contiguous band of image rows and its L2 holds the part of the field those rays cross.
@@ -12,12 +12,15 @@
 // bit records whether the step clamp was active), then the adjoint runs backwards from the
 // minimising step and scatters into the field with binary32 atomic adds (no return value).
 #include "internal.h"
+#include "tuning.h"
 
 namespace rtsdf {
 
 namespace {
 
-constexpr int kTile = 8;     // 8 x 8 pixels per wave
+constexpr int kTX = RTSDF_SHADOW_TILE_X;  // a wave shades kTX x kTY pixels
+constexpr int kTY = 64 / kTX;
+static_assert(kTX * kTY == 64 && (kTX & (kTX - 1)) == 0, "a shadow tile is one wave");
 constexpr int kXcds = 8;
 
 // block b runs on XCD b % 8; XCD x receives the contiguous tile range starting at start(x)
@@ -116,8 +119,8 @@ __device__ inline void scatter(float* __restrict__ gf, const Cell& c, float w)
 __device__ inline bool pixel_of(const rtsdf_shadow& s, int tiles_x, int& a, int& b)
 {
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    a = (tile % tiles_x) * kTile + (int)(threadIdx.x & (kTile - 1));
-    b = (tile / tiles_x) * kTile + (int)(threadIdx.x / kTile);
+    a = (tile % tiles_x) * kTX + (int)(threadIdx.x & (kTX - 1));
+    b = (tile / tiles_x) * kTY + (int)(threadIdx.x / kTX);
     return a < s.width && b < s.height;
 }
 
@@ -126,7 +129,7 @@ __device__ inline float3 march_point(float3 P, float t, const rtsdf_shadow& s)
     return make_float3(P.x + t * s.light[0], P.y + t * s.light[1], P.z + t * s.light[2]);
 }
 
-__global__ __launch_bounds__(kTile* kTile) void k_shadow_forward(const float* __restrict__ fine,
+__global__ __launch_bounds__(kTX* kTY) void k_shadow_forward(const float* __restrict__ fine,
                                                                  const rtsdf_grid g, const rtsdf_shadow s,
                                                                  float inv_h, int tiles_x,
                                                                  float* __restrict__ img)
@@ -145,7 +148,7 @@ __global__ __launch_bounds__(kTile* kTile) void k_shadow_forward(const float* __
     img[(int64_t)b * s.width + a] = res > 0.0f ? res : 0.0f;
 }
 
-__global__ __launch_bounds__(kTile* kTile) void k_shadow_backward(const float* __restrict__ fine,
+__global__ __launch_bounds__(kTX* kTY) void k_shadow_backward(const float* __restrict__ fine,
                                                                   const rtsdf_grid g, const rtsdf_shadow s,
                                                                   float inv_h, int tiles_x,
                                                                   const float* __restrict__ grad_img,
@@ -170,7 +173,7 @@ __global__ __launch_bounds__(kTile* kTile) void k_shadow_backward(const float* _
             s_best = v;
             t_best = t;
         }
-        s_t[m * (kTile * kTile) + lane] = (v > s.smin && v < s.smax) ? t : -t;
+        s_t[m * (kTX * kTY) + lane] = (v > s.smin && v < s.smax) ? t : -t;
         t += fminf(fmaxf(v, s.smin), s.smax);
     }
     if (best < 0 || !(res > 0.0f)) return;
@@ -178,7 +181,7 @@ __global__ __launch_bounds__(kTile* kTile) void k_shadow_backward(const float* _
     float sbar = gi * s.k / t_best;
     float tbar = -gi * s.k * s_best / (t_best * t_best);
     for (int m = best; m >= 0; --m) {
-        const float tm = fabsf(s_t[m * (kTile * kTile) + lane]);
+        const float tm = fabsf(s_t[m * (kTX * kTY) + lane]);
         const Cell c = cell_of(g, inv_h, march_point(P, tm, s));
         float3 gr;
         trilinear(fine, c, inv_h, &gr);
@@ -186,11 +189,11 @@ __global__ __launch_bounds__(kTile* kTile) void k_shadow_backward(const float* _
         tbar += sbar * ((gr.x * s.light[0] + gr.y * s.light[1]) + gr.z * s.light[2]);
         if (m == 0) break;
         // t_m = t_{m-1} + clamp(s_{m-1}): s_{m-1} receives tbar where the clamp is inactive
-        sbar = s_t[(m - 1) * (kTile * kTile) + lane] > 0.0f ? tbar : 0.0f;
+        sbar = s_t[(m - 1) * (kTX * kTY) + lane] > 0.0f ? tbar : 0.0f;
     }
 }
 
-int tiles(int n) { return (n + kTile - 1) / kTile; }
+int tiles(int n, int t) { return (n + t - 1) / t; }
 
 }  // namespace
 
@@ -198,8 +201,8 @@ hipError_t shadow_forward(const float* fine, const rtsdf_grid& g, const rtsdf_sh
                           hipStream_t st)
 {
     if (s.width == 0 || s.height == 0) return hipSuccess;
-    const int tx = tiles(s.width), nb = tx * tiles(s.height);
-    k_shadow_forward<<<nb, kTile * kTile, 0, st>>>(fine, g, s, 1.0f / g.h, tx, img);
+    const int tx = tiles(s.width, kTX), nb = tx * tiles(s.height, kTY);
+    k_shadow_forward<<<nb, kTX * kTY, 0, st>>>(fine, g, s, 1.0f / g.h, tx, img);
     return hipGetLastError();
 }
 
@@ -207,9 +210,9 @@ hipError_t shadow_backward(const float* fine, const rtsdf_grid& g, const rtsdf_s
                            const float* grad_img, float* grad_fine, hipStream_t st)
 {
     if (s.width == 0 || s.height == 0) return hipSuccess;
-    const int tx = tiles(s.width), nb = tx * tiles(s.height);
-    const size_t lds = sizeof(float) * (size_t)s.steps * kTile * kTile;
-    k_shadow_backward<<<nb, kTile * kTile, lds, st>>>(fine, g, s, 1.0f / g.h, tx, grad_img, grad_fine);
+    const int tx = tiles(s.width, kTX), nb = tx * tiles(s.height, kTY);
+    const size_t lds = sizeof(float) * (size_t)s.steps * kTX * kTY;
+    k_shadow_backward<<<nb, kTX * kTY, lds, st>>>(fine, g, s, 1.0f / g.h, tx, grad_img, grad_fine);
     return hipGetLastError();
 }
 

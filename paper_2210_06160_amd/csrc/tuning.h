@@ -1,0 +1,27 @@
+// Tile shapes and work-distribution constants of the kernels.  The values below are the
+// ones paper_2210_06160_amd/autotune.py measured fastest on MI355X (gfx950) for the
+// benchmark workloads; every choice computes identical results, only speed differs.
+// A -D definition on the compiler command line overrides a value (the autotuner builds
+// its candidate libraries that way).
+#pragma once
+
+// jump flooding: lattice points per work-group along z, and y-rows of 64 x-columns
+#ifndef RTSDF_JFA_CHUNK
+#define RTSDF_JFA_CHUNK 32
+#endif
+#ifndef RTSDF_JFA_ROWS
+#define RTSDF_JFA_ROWS 4
+#endif
+
+// ray sampling: work units a wave takes per cursor atomic, and idle lanes restarted together
+#ifndef RTSDF_RAY_CHUNK
+#define RTSDF_RAY_CHUNK 32
+#endif
+#ifndef RTSDF_RAY_START_BATCH
+#define RTSDF_RAY_START_BATCH 12
+#endif
+
+// soft shadows: pixels per wave along x (the tile is RTSDF_SHADOW_TILE_X x 64/RTSDF_SHADOW_TILE_X)
+#ifndef RTSDF_SHADOW_TILE_X
+#define RTSDF_SHADOW_TILE_X 4
+#endif

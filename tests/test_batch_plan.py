@@ -52,10 +52,21 @@ def find_object(prefix, n, i):
     return int(np.searchsorted(prefix[:n], i, side="right") - 1)
 
 
+def tuning():
+    import os
+    import re
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2210_06160_amd", "csrc",
+                        "tuning.h")
+    return {m.group(1): int(m.group(2)) for m in re.finditer(r"#define (RTSDF_\w+) (\d+)", open(path).read())}
+
+
+ROWS, CHUNK = tuning()["RTSDF_JFA_ROWS"], tuning()["RTSDF_JFA_CHUNK"]
+
+
 def jfa_blocks(n, k):
     nx, ny, nz = n
-    cpr = -(-(-(-nz // k)) // 16)
-    return -(-nx // 64) * -(-ny // 4) * min(k, nz) * cpr
+    cpr = -(-(-(-nz // k)) // CHUNK)
+    return -(-nx // 64) * -(-ny // ROWS) * min(k, nz) * cpr
 
 
 def batch_scenes():
@@ -125,9 +136,9 @@ def test_plan_tables(R, which):
             l = blk - pass_prefix[p][o]
             assert 0 <= l < counts[o]
             nx, ny, nz = sc.dims
-            gx, gy = -(-nx // 64), -(-ny // 4)
+            gx, gy = -(-nx // 64), -(-ny // ROWS)
             bz = l // (gx * gy)
-            cpr = -(-(-(-nz // k)) // 16)
+            cpr = -(-(-(-nz // k)) // CHUNK)
             assert l % gx < gx and (l // gx) % gy < gy and bz // cpr < min(k, nz)
             seen[o] += 1
         assert all(seen[o] > 0 for o in range(n) if counts[o] > 0)
