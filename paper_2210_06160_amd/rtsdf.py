@@ -418,6 +418,16 @@ class BatchSDF:
         self.combine()
         return self.fine
 
+    def capture(self):
+        """Records the whole chain (run()) into one HIP graph; replay() runs it.  Nothing in
+        the chain reads back to the host or allocates, so the graph replays it exactly."""
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.run()
+
+    def replay(self):
+        self.graph.replay()
+
     def backward(self, grad_fine, grad_verts=None):
         if grad_verts is None:
             grad_verts = torch.zeros_like(self.verts)
