@@ -66,7 +66,7 @@ def lib():
         L.orc_jfa_pass.argtypes = [vp, vp, Grid, i32]
         L.orc_jfa.argtypes = [vp, vp, Grid, vp, i32]
         L.orc_seed_d2.argtypes = [vp, Grid, vp]
-        L.orc_band.argtypes = [vp, Grid, i32, vp]
+        L.orc_band.argtypes = [vp, Grid, i32, i32, vp]
         L.orc_band.restype = i64
         L.orc_philox4x32_10.argtypes = [vp, vp, vp]
         L.orc_direction.argtypes = [u64, u32, u32, u32, u32, vp]
@@ -82,7 +82,7 @@ def lib():
         L.orc_bvh_closest.restype = ctypes.c_int
         L.orc_voxel_centre.argtypes = [Grid, i64, vp]
         L.orc_raysample.argtypes = [vp, Grid, vp, i64, i32, u64, u32, u32, vp, vp, vp]
-        L.orc_combine.argtypes = [vp, vp, vp, Grid, vp, i64, i32, f32, f32, i32, f32, i32, vp, vp]
+        L.orc_combine.argtypes = [vp, vp, vp, Grid, i32, vp, i64, i32, f32, f32, i32, f32, i32, vp, vp]
         L.orc_pack_id.argtypes = [i32, i32, i32]
         L.orc_pack_id.restype = i32
         L.orc_shadow_forward.argtypes = [vp, Grid, ctypes.POINTER(Shadow), vp]
@@ -97,6 +97,11 @@ def lib():
 
 def nvox(g):
     return g.nx * g.ny * g.nz
+
+
+def refine_grid(g, ratio):
+    """The grid with `ratio` times the points per axis over the same box."""
+    return make_grid((g.nx * ratio, g.ny * ratio, g.nz * ratio), tuple(g.org), np.float32(g.h) / np.float32(ratio))
 
 
 def pack_id(i, j, k):
@@ -159,12 +164,13 @@ def seed_d2(seeds, g):
     return d2
 
 
-def band(seeds, g, band_vox):
-    """Section 2.3 ray mask as an increasing list of voxel ids."""
+def band(seeds, g, band_vox, ratio=1):
+    """Section 2.3 ray mask as an increasing list of voxel ids; with ratio > 1 the ids of the
+    grid refined `ratio` times per axis whose coarse point is in the mask."""
     seeds = np.ascontiguousarray(seeds, np.int32)
-    n = lib().orc_band(_p(seeds), g, int(band_vox), None)
+    n = lib().orc_band(_p(seeds), g, int(ratio), int(band_vox), None)
     out = np.empty(n, np.int32)
-    lib().orc_band(_p(seeds), g, int(band_vox), _p(out))
+    lib().orc_band(_p(seeds), g, int(ratio), int(band_vox), _p(out))
     return out
 
 
@@ -248,18 +254,20 @@ def raysample(bvh, g, vids, x, seed, frame, obj=0, acc=None):
 
 
 def combine(seeds, dmin, hits, g, band_vox, beta, bias, mode, alpha=0.95, reset=True,
-            state=None, vids=None):
-    """Coarse/fine combination: mode 0 running minimum (section 2.1), mode 1 decay (Eq. 1)."""
+            state=None, vids=None, ratio=1):
+    """Coarse/fine combination: mode 0 running minimum (section 2.1), mode 1 decay (Eq. 1).
+    With ratio > 1, g is the jump-flooded (coarse) grid and dmin/hits/state/the result live
+    on the grid refined `ratio` times per axis."""
     seeds = np.ascontiguousarray(seeds, np.int32)
     dmin = np.ascontiguousarray(dmin, np.float32)
     hits = np.ascontiguousarray(hits, np.uint32)
-    n = len(vids) if vids is not None else nvox(g)
+    n = len(vids) if vids is not None else nvox(g) * int(ratio) ** 3
     if vids is not None:
         vids = np.ascontiguousarray(vids, np.int32)
     if state is None:
         state = np.zeros(n, np.float32)
     fine = np.empty(n, np.float32)
-    lib().orc_combine(_p(seeds), _p(dmin), _p(hits), g, _p(vids), n, int(band_vox),
+    lib().orc_combine(_p(seeds), _p(dmin), _p(hits), g, int(ratio), _p(vids), n, int(band_vox),
                       float(beta), float(bias), int(mode), float(alpha), int(bool(reset)),
                       _p(state), _p(fine))
     return fine, state

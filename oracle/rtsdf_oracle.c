@@ -238,18 +238,24 @@ void orc_seed_d2(const int32_t* seeds, orc_grid g, int32_t* d2)
  * Ray mask (section 2.3).  A grid point is ray traced iff the jump-flooded distance is
  * within the mask width; the width is given in voxels, so the test is the exact integer
  * comparison d2 <= band^2 on the stored seed.  The list is in increasing voxel order.
+ * Two levels (section 2.3: the coarse field is the mask of a finer traced field; section
+ * 2.5.1: coarse 128^3, fine 256^3): with a refinement ratio r the traced grid has r times
+ * the points per axis over the same box, fine point (i, j, k) lies in coarse point
+ * (i/r, j/r, k/r) (integer division) and is traced iff that coarse point is in the mask;
+ * list entries are fine linear indices.  r = 1 is the single-level mask.
  * ---------------------------------------------------------------------------------- */
-int64_t orc_band(const int32_t* seeds, orc_grid g, int32_t band, int32_t* list)
+int64_t orc_band(const int32_t* seeds, orc_grid g, int32_t r, int32_t band, int32_t* list)
 {
     int64_t n = 0;
     const int32_t b2 = band * band;
-    for (int32_t z = 0; z < g.nz; ++z)
-        for (int32_t y = 0; y < g.ny; ++y)
-            for (int32_t x = 0; x < g.nx; ++x) {
-                int64_t p = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
-                int32_t s = seeds[p];
-                if (s != ORC_EMPTY && orc_d2(s, x, y, z) <= b2) {
-                    if (list) list[n] = (int32_t)p;
+    const int32_t fx = g.nx * r, fy = g.ny * r, fz = g.nz * r;
+    for (int32_t z = 0; z < fz; ++z)
+        for (int32_t y = 0; y < fy; ++y)
+            for (int32_t x = 0; x < fx; ++x) {
+                const int32_t cx = x / r, cy = y / r, cz = z / r;
+                int32_t s = seeds[cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz)];
+                if (s != ORC_EMPTY && orc_d2(s, cx, cy, cz) <= b2) {
+                    if (list) list[n] = (int32_t)(x + (int64_t)fx * (y + (int64_t)fy * z));
                     ++n;
                 }
             }
@@ -646,17 +652,20 @@ void orc_raysample(const void* bvh, orc_grid g, const int32_t* vids, int64_t n, 
  * The voxels combined are vids[0..n) (all voxels if vids is NULL); the outputs dmin,
  * hits, state and fine are indexed like vids.
  * ---------------------------------------------------------------------------------- */
-void orc_combine(const int32_t* seeds, const float* dmin, const uint32_t* hits, orc_grid g,
+void orc_combine(const int32_t* seeds, const float* dmin, const uint32_t* hits, orc_grid g, int32_t r,
                  const int32_t* vids, int64_t n, int32_t band, float beta, float bias, int32_t mode,
                  float alpha, int32_t reset, float* state, float* fine)
 {
+    /* g is the jump-flooded grid; the combined field has r times its points per axis and
+     * each of its points takes the coarse distance of the coarse point it lies in */
     const float oma = 1.0f - alpha;
-    if (!vids) n = orc_nvox(g);
+    const int64_t fx = (int64_t)g.nx * r, fy = (int64_t)g.ny * r;
+    if (!vids) n = orc_nvox(g) * r * r * r;
     for (int64_t q = 0; q < n; ++q) {
         int64_t p = vids ? vids[q] : q;
-        int32_t x = (int32_t)(p % g.nx), y = (int32_t)((p / g.nx) % g.ny),
-                z = (int32_t)(p / ((int64_t)g.nx * g.ny));
-        int32_t s = seeds[p];
+        int32_t x = (int32_t)((p % fx) / r), y = (int32_t)(((p / fx) % fy) / r),
+                z = (int32_t)((p / (fx * fy)) / r);
+        int32_t s = seeds[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)];
         float u;
         int inband;
         if (s == ORC_EMPTY) {
