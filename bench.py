@@ -31,7 +31,8 @@ def parse():
     p.add_argument("--no-deform", action="store_true", help="skip the deforming-mesh (graph) measurement")
     p.add_argument("--no-grad", action="store_true", help="skip the gradient-workload measurement")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-objects measurement")
-    p.add_argument("--only", choices=["static", "deform", "grad", "batch"],
+    p.add_argument("--no-two-level", action="store_true", help="skip the two-level (coarse/fine) measurement")
+    p.add_argument("--only", choices=["static", "deform", "grad", "batch", "two_level"],
                    help="run one workload alone and print its record (for profiling)")
     p.add_argument("--cpu-sample", type=int, default=4000000,
                    help="masked voxels ray-sampled by the oracle (about 6 s on 16 host cores)")
@@ -131,6 +132,56 @@ def deform_bench(torch, rtsdf, synth):
             "sdf_voxels_per_s_graph": round(N / graph, 1), "masked_voxels_last_frame": int(D.band_count.item())}
 
 
+def two_level_bench(torch, rtsdf, synth, steps=3):
+    """Two-level field (sections 2.3, 2.5.1): the static scene flooded at 200 x 100 x 200 and
+    traced at 400 x 200 x 400 (ratio 2, 2-coarse-voxel mask, 8 rays x 16 frames), and the
+    deforming knot the same way (60 frames, Eq. 1 decay, every frame a replayed HIP graph).
+    Voxel rates count points of the traced 400 x 200 x 400 field."""
+    sc = synth.scene_static(dims=(200, 100, 200))
+    sc.band = 2
+    S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames, ratio=2)
+    gpu_step(S, rtsdf, StageTimer(torch))
+    torch.cuda.synchronize()
+    timers = [StageTimer(torch) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        gpu_step(S, rtsdf, timers[k])
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    stages = {}
+    for tm in timers:
+        for k, v in tm.durations().items():
+            stages[k] = stages.get(k, 0.0) + v / steps
+    band = int(S.band_count.item())
+    Nf = S.gf.n
+    out = {"static": {"workload": sc.name + "-ratio-2", "traced_grid": [S.gf.nx, S.gf.ny, S.gf.nz],
+                      "ms_per_step": round(ms, 3), "sdf_voxels_per_s": round(Nf / (ms / 1e3), 1),
+                      "masked_fine_voxels": band,
+                      "rays_per_s": round(band * sc.rays * sc.frames / (stages["raysample"] / 1e3), 1),
+                      "stages_ms": {k: round(v, 4) for k, v in stages.items()}}}
+    del S
+    sd = synth.scene_deform(dims=(200, 100, 200))
+    sd.band = 2
+    D = rtsdf.DeformSDF(sd.extra["frames"], sd.tris, sd.dims, sd.org, sd.h, sd.steps, sd.band, sd.rays,
+                        sd.extra["alpha"], ratio=2)
+    for f in range(sd.frames):
+        D.frame(f)
+    D.capture()
+    for f in range(sd.frames):
+        D.replay(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in range(sd.frames):
+        D.replay(f)
+    torch.cuda.synchronize()
+    graph = (time.perf_counter() - t0) / sd.frames
+    out["deform"] = {"workload": sd.name + "-ratio-2", "frames": sd.frames,
+                     "ms_per_frame_graph": round(graph * 1e3, 3),
+                     "sdf_voxels_per_s_graph": round(D.gf.n / graph, 1),
+                     "masked_fine_voxels_last_frame": int(D.band_count.item())}
+    return out
+
+
 def grad_bench(torch, rtsdf, synth, reps=20):
     """Gradient workload (icosphere of 20,480 triangles on 128^3, 16 rays, 512^2 soft shadow):
     forward = the SDF chain + shadow image + loss, backward = shadow adjoint + SDF term +
@@ -152,12 +203,12 @@ def grad_bench(torch, rtsdf, synth, reps=20):
         T.mark("start")
         fine = S.run()
         T.mark("sdf_fwd")
-        rtsdf.rtsdf_shadow_forward(fine, S.g, sh, img)
+        rtsdf.rtsdf_shadow_forward(fine, S.gf, sh, img)
         T.mark("shadow_fwd")
         loss = ((fine - tgt) ** 2).sum() + ((img - timg) ** 2).sum()
         T.mark("loss")
         gfine = 2.0 * (fine - tgt)
-        rtsdf.rtsdf_shadow_backward(fine, S.g, sh, 2.0 * (img - timg), gfine)
+        rtsdf.rtsdf_shadow_backward(fine, S.gf, sh, 2.0 * (img - timg), gfine)
         T.mark("shadow_bwd")
         gverts.zero_()
         S.backward(gfine, gverts)
@@ -311,12 +362,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n, "copy_calibration_bytes_written": n, "dispatches": 3}))
         return
-    if args.only in ("deform", "grad", "batch"):
-        fn = {"deform": deform_bench, "grad": grad_bench, "batch": batch_bench}[args.only]
+    if args.only in ("deform", "grad", "batch", "two_level"):
+        fn = {"deform": deform_bench, "grad": grad_bench, "batch": batch_bench, "two_level": two_level_bench}[args.only]
         print(json.dumps({args.only: fn(torch, rtsdf, synth)}))
         return
     if args.only == "static":
-        args.no_deform = args.no_grad = args.no_batch = True
+        args.no_deform = args.no_grad = args.no_batch = args.no_two_level = True
     sc = synth.scene_static()
     S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
     N = S.g.n
@@ -377,6 +428,8 @@ def main():
         out["grad"] = grad_bench(torch, rtsdf, synth)
     if not args.no_batch:
         out["batch"] = batch_bench(torch, rtsdf, synth)
+    if not args.no_two_level:
+        out["two_level"] = two_level_bench(torch, rtsdf, synth)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample)
     print(json.dumps(out))

@@ -58,12 +58,12 @@ typedef int32_t rtsdf_status;
 
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* rtsdf_last_error(void);
-/* ABI version of this header: 1. */
+/* ABI version of this header: 2. */
 int32_t rtsdf_abi_version(void);
 
 /* ---------------------------------------------------------------------------------------
- * rtsdf_voxelize -- section 2.2 "voxelize the scene with voxel resolution equal to our
- * final distance field": every grid point whose closed voxel cube meets a closed triangle
+ * rtsdf_voxelize -- section 2.2 seeding, at the resolution of the distance field itself:
+ * every grid point whose closed voxel cube meets a closed triangle
  * becomes a seed holding its own id; every other grid point is set to RTSDF_EMPTY.
  * Vertices are snapped to 1/256 voxel, X = rint(((v - org) / h) * 256) in binary32, and the
  * overlap is decided exactly in integers (separating axes of a box and a triangle).
@@ -186,6 +186,36 @@ rtsdf_status rtsdf_combine(const int32_t* seeds, float* dmin, uint32_t* hits, rt
                            int32_t band_vox, float beta, float bias, int32_t mode, float alpha,
                            int32_t first_frame, int32_t consume, float* state, float* fine,
                            void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Two-level field -- jump flooding on a coarse grid, rays and the combined field on a grid
+ * refined by an integer ratio r over the same box (section 2.3 masks a traced field finer
+ * than the flooded one; section 2.5.1 floods 128^3 beside a 256^3 traced field).
+ * rtsdf_refine_grid (host only): fine = (r nx, r ny, r nz) points, same origin,
+ *   h_fine = h / r in binary32.  Fine point (x, y, z) lies in coarse point
+ *   (x / r, y / r, z / r) (integer division) and takes that point's coarse distance u,
+ *   outside value c and band test.  Errors: E_ARG (NULL fine), E_RANGE (r < 1 or a fine
+ *   dimension above RTSDF_MAX_DIM; the coarse grid as rtsdf_grid).
+ * rtsdf_band_refined: the mask of rtsdf_band on the fine grid -- the fine points whose
+ *   coarse parent is in band -- listed by fine linear index in increasing order.
+ *   seeds [N_coarse] int32; band_list [N_fine] out; band_count [1] out (device);
+ *   work [rtsdf_band_refined_work_bytes(coarse, r)].  Errors as rtsdf_band, plus r.
+ * rtsdf_combine_refined: rtsdf_combine on the fine grid.  seeds [N_coarse]; dmin, hits,
+ *   state and fine are [N_fine] (the fine grid's ray-sampling accumulators); u is computed
+ *   with the coarse h.  Errors as rtsdf_combine, plus r.
+ * Ray sampling and the vertex adjoint run unchanged on the fine grid and its mask
+ * (rtsdf_raysample / rtsdf_backward with g = the refined grid); ratio 1 is the
+ * single-level chain.
+ * ------------------------------------------------------------------------------------- */
+rtsdf_status rtsdf_refine_grid(rtsdf_grid coarse, int32_t ratio, rtsdf_grid* fine);
+size_t rtsdf_band_refined_work_bytes(rtsdf_grid coarse, int32_t ratio);
+rtsdf_status rtsdf_band_refined(const int32_t* seeds, rtsdf_grid coarse, int32_t ratio, int32_t band_vox,
+                                int32_t* band_list, int32_t* band_count, void* work, size_t work_bytes,
+                                void* stream);
+rtsdf_status rtsdf_combine_refined(const int32_t* seeds, float* dmin, uint32_t* hits, rtsdf_grid coarse,
+                                   int32_t ratio, int32_t band_vox, float beta, float bias, int32_t mode,
+                                   float alpha, int32_t first_frame, int32_t consume, float* state,
+                                   float* fine, void* stream);
 
 /* ---------------------------------------------------------------------------------------
  * Soft shadows by sphere tracing the fine field (section 2.4; step bounds of section

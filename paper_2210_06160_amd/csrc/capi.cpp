@@ -307,7 +307,7 @@ rtsdf_status rtsdf_backward_batched(const void* plan, const float* grad_fine, co
 
 const char* rtsdf_last_error(void) { return g_err; }
 
-int32_t rtsdf_abi_version(void) { return 1; }
+int32_t rtsdf_abi_version(void) { return 2; }
 
 size_t rtsdf_voxelize_work_bytes(int32_t nt) { return nt < 0 ? 0 : rtsdf::voxelize_work_bytes(nt); }
 
@@ -431,6 +431,65 @@ rtsdf_status rtsdf_combine(const int32_t* seeds, float* dmin, uint32_t* hits, rt
     return device(rtsdf::combine(seeds, dmin, hits, g, band_vox, beta, bias, mode, alpha, first_frame, consume,
                                  state, fine, as_stream(stream)),
                   "combine");
+}
+
+rtsdf_status rtsdf_refine_grid(rtsdf_grid coarse, int32_t ratio, rtsdf_grid* fine)
+{
+    if (rtsdf_status st = check_grid(coarse)) return st;
+    if (!fine) return fail(RTSDF_E_ARG, "fine is NULL");
+    if (ratio < 1 || ratio > RTSDF_MAX_DIM) return fail(RTSDF_E_RANGE, "ratio %d outside [1, %d]", ratio, RTSDF_MAX_DIM);
+    const int64_t fx = (int64_t)coarse.nx * ratio, fy = (int64_t)coarse.ny * ratio, fz = (int64_t)coarse.nz * ratio;
+    if (fx > RTSDF_MAX_DIM || fy > RTSDF_MAX_DIM || fz > RTSDF_MAX_DIM)
+        return fail(RTSDF_E_RANGE, "refined grid %lld x %lld x %lld exceeds %d per axis", (long long)fx,
+                    (long long)fy, (long long)fz, RTSDF_MAX_DIM);
+    rtsdf_grid f = coarse;
+    f.nx = (int32_t)fx;
+    f.ny = (int32_t)fy;
+    f.nz = (int32_t)fz;
+    f.h = coarse.h / (float)ratio;
+    *fine = f;
+    return ok();
+}
+
+size_t rtsdf_band_refined_work_bytes(rtsdf_grid coarse, int32_t ratio)
+{
+    rtsdf_grid f;
+    if (rtsdf_refine_grid(coarse, ratio, &f) != RTSDF_OK) return 0;
+    return rtsdf::band_refined_work_bytes(coarse, ratio);
+}
+
+rtsdf_status rtsdf_band_refined(const int32_t* seeds, rtsdf_grid coarse, int32_t ratio, int32_t band_vox,
+                                int32_t* band_list, int32_t* band_count, void* work, size_t work_bytes,
+                                void* stream)
+{
+    rtsdf_grid f;
+    if (rtsdf_status st = rtsdf_refine_grid(coarse, ratio, &f)) return st;
+    if (!seeds || !band_list || !band_count || !work) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (band_vox < 0 || band_vox > 2048) return fail(RTSDF_E_RANGE, "band_vox %d outside [0, 2048]", band_vox);
+    const size_t need = rtsdf::band_refined_work_bytes(coarse, ratio);
+    if (work_bytes < need) return fail(RTSDF_E_SIZE, "band work %zu < %zu bytes", work_bytes, need);
+    return device(rtsdf::band_refined(seeds, coarse, ratio, band_vox, band_list, band_count, work, as_stream(stream)),
+                  "band_refined");
+}
+
+rtsdf_status rtsdf_combine_refined(const int32_t* seeds, float* dmin, uint32_t* hits, rtsdf_grid coarse,
+                                   int32_t ratio, int32_t band_vox, float beta, float bias, int32_t mode,
+                                   float alpha, int32_t first_frame, int32_t consume, float* state,
+                                   float* fine, void* stream)
+{
+    rtsdf_grid f;
+    if (rtsdf_status st = rtsdf_refine_grid(coarse, ratio, &f)) return st;
+    if (!seeds || !dmin || !hits || !fine) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (band_vox < 0 || band_vox > 2048) return fail(RTSDF_E_RANGE, "band_vox %d outside [0, 2048]", band_vox);
+    if (mode != RTSDF_ACCUM && mode != RTSDF_DECAY) return fail(RTSDF_E_RANGE, "unknown mode %d", mode);
+    if (!std::isfinite(beta) || !std::isfinite(bias)) return fail(RTSDF_E_ARG, "beta and bias must be finite");
+    if (mode == RTSDF_DECAY) {
+        if (!(alpha >= 0.0f && alpha <= 1.0f)) return fail(RTSDF_E_ARG, "alpha outside [0, 1]");
+        if (!state) return fail(RTSDF_E_ARG, "DECAY needs a state buffer");
+    }
+    return device(rtsdf::combine_refined(seeds, dmin, hits, coarse, ratio, band_vox, beta, bias, mode, alpha,
+                                         first_frame, consume, state, fine, as_stream(stream)),
+                  "combine_refined");
 }
 
 rtsdf_status rtsdf_shadow_forward(const float* fine, rtsdf_grid g, rtsdf_shadow s, float* img, void* stream)

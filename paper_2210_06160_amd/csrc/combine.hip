@@ -16,64 +16,95 @@ __device__ inline int32_t seed_d2(int32_t s, int32_t x, int32_t y, int32_t z)
     return dx * dx + dy * dy + dz * dz;
 }
 
-// Flags of the kBandItems voxels of this thread, as a bit mask.
+// Flags of the kBandItems grid points of this thread, as a bit mask.  (nx, ny) are the
+// dimensions of the masked grid.  With kRef it is refined by `r` over a coarse grid of
+// (cnx, cny) columns and rows: point (x, y, z) takes the flag of its parent
+// (x / r, y / r, z / r); without it r = 1 and the parent is the point itself.
+template <bool kRef>
 __device__ uint32_t band_bits(const int32_t* __restrict__ seeds, int64_t N, int32_t nx, int32_t ny,
-                              int32_t b2, int64_t first)
+                              int32_t b2, int64_t first, int32_t r, int32_t cnx, int32_t cny)
 {
     uint32_t bits = 0;
     if (first >= N) return 0;
-    int64_t row = first / nx;
+    const int64_t row = first / nx;
     int32_t x = (int32_t)(first - row * nx);
     int32_t y = (int32_t)(row % ny);
     int32_t z = (int32_t)(row / ny);
+    int32_t cx = x, cy = y, cz = z, rx = 0;
+    if (kRef) {
+        cx = x / r;
+        rx = x - cx * r;
+        cy = y / r;
+        cz = z / r;
+    } else {
+        cnx = nx;
+        cny = ny;
+    }
+    const int32_t* line = seeds + (int64_t)cnx * (cy + (int64_t)cny * cz);
 #pragma unroll
     for (int i = 0; i < kBandItems; ++i) {
-        const int64_t p = first + i;
-        if (p < N) {
-            const int32_t s = seeds[p];
-            if (s != RTSDF_EMPTY && seed_d2(s, x, y, z) <= b2) bits |= 1u << i;
+        if (first + i < N) {
+            const int32_t s = line[cx];
+            if (s != RTSDF_EMPTY && seed_d2(s, cx, cy, cz) <= b2) bits |= 1u << i;
         }
-        if (++x == nx) {
-            x = 0;
+        ++x;
+        if (kRef) {
+            if (++rx == r) {
+                rx = 0;
+                ++cx;
+            }
+        } else {
+            cx = x;
+        }
+        if (x == nx) {
+            x = cx = rx = 0;
             if (++y == ny) {
                 y = 0;
                 ++z;
             }
+            cy = kRef ? y / r : y;
+            cz = kRef ? z / r : z;
+            line = seeds + (int64_t)cnx * (cy + (int64_t)cny * cz);
         }
     }
     return bits;
 }
 
-// The grid a mask work-group scans.  Single object: the arguments.  Batch: the object that
-// owns the work-group's tile (tiles are kBatchAlign = kBandTile voxels and never straddle
-// objects); `base` is added to the listed indices.
+// The grid a mask work-group scans.  Single object: the arguments (a refined grid also
+// names its coarse dimensions and ratio).  Batch: the object that owns the work-group's
+// tile (tiles are kBatchAlign = kBandTile voxels and never straddle objects); `base` is
+// added to the listed indices.
 struct BandGrid {
     const int32_t* seeds;
     int64_t N, first, base;
     int32_t nx, ny, b2;
 };
 
+struct BandArgs {
+    const int32_t* seeds;
+    int64_t N;               // points of the masked grid
+    int32_t nx, ny, b2;      // masked grid
+    int32_t r, cnx, cny;     // refinement ratio and coarse dimensions (refined mask only)
+};
+
 template <bool kBatch>
-__device__ inline BandGrid band_grid(const int32_t* seeds, int64_t N, int32_t nx, int32_t ny, int32_t b2,
-                                     const char* plan, int32_t nobj)
+__device__ inline BandGrid band_grid(const BandArgs& a, const char* plan, int32_t nobj)
 {
     const int64_t tile = (int64_t)blockIdx.x * kBandTile;
-    if (!kBatch) return BandGrid{seeds, N, tile + (int64_t)threadIdx.x * kBandItems, 0, nx, ny, b2};
+    if (!kBatch) return BandGrid{a.seeds, a.N, tile + (int64_t)threadIdx.x * kBandItems, 0, a.nx, a.ny, a.b2};
     const BatchView v = batch_view(plan, nobj);
     const BatchObject& ob = v.obj[find_object(v.vox_prefix, nobj, tile)];
-    return BandGrid{seeds + ob.vox_off, nvox(ob.g), tile - ob.vox_off + (int64_t)threadIdx.x * kBandItems,
+    return BandGrid{a.seeds + ob.vox_off, nvox(ob.g), tile - ob.vox_off + (int64_t)threadIdx.x * kBandItems,
                     ob.vox_off, ob.g.nx, ob.g.ny, ob.band_vox * ob.band_vox};
 }
 
-template <bool kBatch>
-__global__ __launch_bounds__(kBandThreads) void k_band_count(const int32_t* __restrict__ seeds,
-                                                             int64_t N, int32_t nx, int32_t ny,
-                                                             int32_t b2, uint32_t* __restrict__ counts,
+template <bool kBatch, bool kRef>
+__global__ __launch_bounds__(kBandThreads) void k_band_count(const BandArgs a, uint32_t* __restrict__ counts,
                                                              const char* plan, int32_t nobj)
 {
     __shared__ uint32_t part[kBandThreads / kWave];
-    const BandGrid bg = band_grid<kBatch>(seeds, N, nx, ny, b2, plan, nobj);
-    uint32_t c = __popc(band_bits(bg.seeds, bg.N, bg.nx, bg.ny, bg.b2, bg.first));
+    const BandGrid bg = band_grid<kBatch>(a, plan, nobj);
+    uint32_t c = __popc(band_bits<kRef>(bg.seeds, bg.N, bg.nx, bg.ny, bg.b2, bg.first, a.r, a.cnx, a.cny));
     for (int d = kWave / 2; d > 0; d >>= 1) c += __shfl_xor(c, d, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = c;
     __syncthreads();
@@ -84,17 +115,15 @@ __global__ __launch_bounds__(kBandThreads) void k_band_count(const int32_t* __re
     }
 }
 
-template <bool kBatch>
-__global__ __launch_bounds__(kBandThreads) void k_band_write(const int32_t* __restrict__ seeds,
-                                                             int64_t N, int32_t nx, int32_t ny,
-                                                             int32_t b2,
+template <bool kBatch, bool kRef>
+__global__ __launch_bounds__(kBandThreads) void k_band_write(const BandArgs a,
                                                              const uint32_t* __restrict__ offsets,
                                                              int32_t* __restrict__ list, const char* plan,
                                                              int32_t nobj)
 {
     __shared__ uint32_t part[kBandThreads / kWave];
-    const BandGrid bg = band_grid<kBatch>(seeds, N, nx, ny, b2, plan, nobj);
-    const uint32_t bits = band_bits(bg.seeds, bg.N, bg.nx, bg.ny, bg.b2, bg.first);
+    const BandGrid bg = band_grid<kBatch>(a, plan, nobj);
+    const uint32_t bits = band_bits<kRef>(bg.seeds, bg.N, bg.nx, bg.ny, bg.b2, bg.first, a.r, a.cnx, a.cny);
     const uint32_t c = __popc(bits);
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     uint32_t inc = c;
@@ -126,25 +155,30 @@ __global__ void k_reset(float* __restrict__ dmin, uint32_t* __restrict__ hits,
     }
 }
 
-template <int MODE>
+// One thread per point of the combined grid.  g is the jump-flooded grid; the combined
+// grid has r times its points per axis (kRef) or is g itself (r = 1), and each of its
+// points takes the coarse distance, inside flag and band test of the coarse point it lies in.
+template <int MODE, bool kRef>
 __global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ seeds,
                                                  float* __restrict__ dmin,
-                                                 uint32_t* __restrict__ hits, const rtsdf_grid g,
+                                                 uint32_t* __restrict__ hits, const rtsdf_grid g, int32_t r,
                                                  int32_t b2, float beta, float bias, float alpha,
                                                  float one_minus_alpha, int32_t first_frame,
                                                  int32_t consume, float* __restrict__ state,
                                                  float* __restrict__ fine)
 {
+    const int32_t fnx = kRef ? g.nx * r : g.nx, fny = kRef ? g.ny * r : g.ny;
     const int32_t x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int32_t y = blockIdx.y * 4 + (threadIdx.x >> 6);
     const int32_t z = blockIdx.z;
-    if (x >= g.nx || y >= g.ny) return;
-    const int64_t p = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
-    const int32_t s = seeds[p];
+    if (x >= fnx || y >= fny) return;
+    const int64_t p = x + (int64_t)fnx * (y + (int64_t)fny * z);
+    const int32_t cx = kRef ? x / r : x, cy = kRef ? y / r : y, cz = kRef ? z / r : z;
+    const int32_t s = seeds[cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz)];
     float u = __int_as_float(0x7f800000);
     bool inband = false;
     if (s != RTSDF_EMPTY) {
-        const int32_t d2 = seed_d2(s, x, y, z);
+        const int32_t d2 = seed_d2(s, cx, cy, cz);
         u = g.h * sqrtf((float)d2);
         inband = d2 <= b2;
     }
@@ -227,59 +261,68 @@ __global__ __launch_bounds__(256) void k_combine_batched(const char* __restrict_
 
 }  // namespace
 
-size_t band_work_bytes(const rtsdf_grid& g)
+namespace {
+
+size_t band_work_points(int64_t N)
 {
-    const int64_t nb = ceil_div(nvox(g), kBandTile);
+    const int64_t nb = ceil_div(N, kBandTile);
     return align256((size_t)nb * 4) + align256(4) + scan_work_bytes_u32(nb);
+}
+
+// count, scan, write: the mask list of the grid `a` describes (or of a batch when `plan`)
+template <bool kBatch, bool kRef>
+hipError_t band_launch(const BandArgs& a, int64_t nb, const char* plan, int32_t nobj, int32_t* list,
+                       int32_t* count, void* work, hipStream_t s)
+{
+    char* w = (char*)work;
+    uint32_t* counts = (uint32_t*)w;
+    w += align256((size_t)nb * 4);
+    uint32_t* total = (uint32_t*)w;
+    w += align256(4);
+    hipLaunchKernelGGL((k_band_count<kBatch, kRef>), dim3((unsigned)nb), dim3(kBandThreads), 0, s, a, counts, plan,
+                       nobj);
+    hipError_t e = scan_exclusive_u32(counts, counts, nb, total, w, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_band_write<kBatch, kRef>), dim3((unsigned)nb), dim3(kBandThreads), 0, s, a,
+                       (const uint32_t*)counts, list, plan, nobj);
+    hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, s, (const uint32_t*)total, count);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t band_work_bytes(const rtsdf_grid& g) { return band_work_points(nvox(g)); }
+
+size_t band_refined_work_bytes(const rtsdf_grid& coarse, int32_t r)
+{
+    return band_work_points(nvox(coarse) * r * r * r);
 }
 
 hipError_t band(const int32_t* seeds, const rtsdf_grid& g, int32_t band_vox, int32_t* list,
                 int32_t* count, void* work, hipStream_t s)
 {
-    const int64_t N = nvox(g);
-    const int64_t nb = ceil_div(N, kBandTile);
-    char* w = (char*)work;
-    uint32_t* counts = (uint32_t*)w;
-    w += align256((size_t)nb * 4);
-    uint32_t* total = (uint32_t*)w;
-    w += align256(4);
-    const int32_t b2 = band_vox * band_vox;
-    hipLaunchKernelGGL(k_band_count<false>, dim3((unsigned)nb), dim3(kBandThreads), 0, s, seeds, N, g.nx,
-                       g.ny, b2, counts, nullptr, 0);
-    hipError_t e = scan_exclusive_u32(counts, counts, nb, total, w, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_band_write<false>, dim3((unsigned)nb), dim3(kBandThreads), 0, s, seeds, N, g.nx,
-                       g.ny, b2, (const uint32_t*)counts, list, nullptr, 0);
-    hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, s, (const uint32_t*)total, count);
-    return hipGetLastError();
+    const BandArgs a{seeds, nvox(g), g.nx, g.ny, band_vox * band_vox, 1, g.nx, g.ny};
+    return band_launch<false, false>(a, ceil_div(a.N, kBandTile), nullptr, 0, list, count, work, s);
 }
 
-size_t band_batched_work_bytes(int64_t total_vox)
+hipError_t band_refined(const int32_t* seeds, const rtsdf_grid& coarse, int32_t r, int32_t band_vox,
+                        int32_t* list, int32_t* count, void* work, hipStream_t s)
 {
-    const int64_t nb = ceil_div(total_vox, kBandTile);
-    return align256((size_t)nb * 4) + align256(4) + scan_work_bytes_u32(nb);
+    if (r == 1) return band(seeds, coarse, band_vox, list, count, work, s);
+    const BandArgs a{seeds, nvox(coarse) * r * r * r, coarse.nx * r, coarse.ny * r, band_vox * band_vox,
+                     r, coarse.nx, coarse.ny};
+    return band_launch<false, true>(a, ceil_div(a.N, kBandTile), nullptr, 0, list, count, work, s);
 }
+
+size_t band_batched_work_bytes(int64_t total_vox) { return band_work_points(total_vox); }
 
 hipError_t band_batched(const BatchView& hv, const void* dplan, const int32_t* seeds, int32_t* list,
                         int32_t* count, void* work, hipStream_t s)
 {
     static_assert(kBandTile == kBatchAlign, "a mask tile is one batch alignment unit");
-    const int64_t nb = hv.h->total_vox / kBandTile;
-    const char* plan = (const char*)dplan;
-    const int32_t nobj = hv.h->nobj;
-    char* w = (char*)work;
-    uint32_t* counts = (uint32_t*)w;
-    w += align256((size_t)nb * 4);
-    uint32_t* total = (uint32_t*)w;
-    w += align256(4);
-    hipLaunchKernelGGL(k_band_count<true>, dim3((unsigned)nb), dim3(kBandThreads), 0, s, seeds, (int64_t)0, 0, 0,
-                       0, counts, plan, nobj);
-    hipError_t e = scan_exclusive_u32(counts, counts, nb, total, w, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_band_write<true>, dim3((unsigned)nb), dim3(kBandThreads), 0, s, seeds, (int64_t)0, 0, 0,
-                       0, (const uint32_t*)counts, list, plan, nobj);
-    hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, s, (const uint32_t*)total, count);
-    return hipGetLastError();
+    const BandArgs a{seeds, 0, 0, 0, 0, 1, 0, 0};
+    return band_launch<true, false>(a, hv.h->total_vox / kBandTile, (const char*)dplan, hv.h->nobj, list, count,
+                                    work, s);
 }
 
 hipError_t combine_batched(const BatchView& hv, const void* dplan, const int32_t* seeds, const float* dmin,
@@ -298,20 +341,45 @@ hipError_t reset_accum(float* dmin, uint32_t* hits, uint64_t* argmin, int64_t n,
     return hipGetLastError();
 }
 
+namespace {
+
+template <int MODE, bool kRef>
+hipError_t combine_launch(const int32_t* seeds, float* dmin, uint32_t* hits, const rtsdf_grid& g, int32_t r,
+                          int32_t band_vox, float beta, float bias, float alpha, int32_t first_frame,
+                          int32_t consume, float* state, float* fine, hipStream_t s)
+{
+    dim3 grid((unsigned)ceil_div(g.nx * r, 64), (unsigned)ceil_div(g.ny * r, 4), (unsigned)(g.nz * r));
+    hipLaunchKernelGGL((k_combine<MODE, kRef>), grid, dim3(256), 0, s, seeds, dmin, hits, g, r,
+                       band_vox * band_vox, beta, bias, alpha, 1.0f - alpha, first_frame, consume, state, fine);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t combine_refined(const int32_t* seeds, float* dmin, uint32_t* hits, const rtsdf_grid& coarse, int32_t r,
+                           int32_t band_vox, float beta, float bias, int32_t mode, float alpha,
+                           int32_t first_frame, int32_t consume, float* state, float* fine, hipStream_t s)
+{
+    if (r == 1) {
+        if (mode == RTSDF_ACCUM)
+            return combine_launch<RTSDF_ACCUM, false>(seeds, dmin, hits, coarse, 1, band_vox, beta, bias, alpha,
+                                                      first_frame, consume, state, fine, s);
+        return combine_launch<RTSDF_DECAY, false>(seeds, dmin, hits, coarse, 1, band_vox, beta, bias, alpha,
+                                                  first_frame, consume, state, fine, s);
+    }
+    if (mode == RTSDF_ACCUM)
+        return combine_launch<RTSDF_ACCUM, true>(seeds, dmin, hits, coarse, r, band_vox, beta, bias, alpha,
+                                                 first_frame, consume, state, fine, s);
+    return combine_launch<RTSDF_DECAY, true>(seeds, dmin, hits, coarse, r, band_vox, beta, bias, alpha,
+                                             first_frame, consume, state, fine, s);
+}
+
 hipError_t combine(const int32_t* seeds, float* dmin, uint32_t* hits, const rtsdf_grid& g,
                    int32_t band_vox, float beta, float bias, int32_t mode, float alpha,
                    int32_t first_frame, int32_t consume, float* state, float* fine, hipStream_t s)
 {
-    dim3 grid((unsigned)ceil_div(g.nx, 64), (unsigned)ceil_div(g.ny, 4), (unsigned)g.nz);
-    const float oma = 1.0f - alpha;
-    const int32_t b2 = band_vox * band_vox;
-    if (mode == RTSDF_ACCUM)
-        hipLaunchKernelGGL(k_combine<RTSDF_ACCUM>, grid, dim3(256), 0, s, seeds, dmin, hits, g, b2,
-                           beta, bias, alpha, oma, first_frame, consume, state, fine);
-    else
-        hipLaunchKernelGGL(k_combine<RTSDF_DECAY>, grid, dim3(256), 0, s, seeds, dmin, hits, g, b2,
-                           beta, bias, alpha, oma, first_frame, consume, state, fine);
-    return hipGetLastError();
+    return combine_refined(seeds, dmin, hits, g, 1, band_vox, beta, bias, mode, alpha, first_frame, consume,
+                           state, fine, s);
 }
 
 }  // namespace rtsdf

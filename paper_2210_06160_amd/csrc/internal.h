@@ -41,6 +41,10 @@ int64_t jfa_pass_blocks(const rtsdf_grid& g, int32_t k);  // work-groups of one 
 size_t band_work_bytes(const rtsdf_grid& g);
 hipError_t band(const int32_t* seeds, const rtsdf_grid& g, int32_t band_vox, int32_t* list,
                 int32_t* count, void* work, hipStream_t s);
+// mask of the grid refined by r over `coarse` (section 2.3 on a finer traced grid)
+size_t band_refined_work_bytes(const rtsdf_grid& coarse, int32_t r);
+hipError_t band_refined(const int32_t* seeds, const rtsdf_grid& coarse, int32_t r, int32_t band_vox,
+                        int32_t* list, int32_t* count, void* work, hipStream_t s);
 
 size_t bvh_bytes(int32_t nt);
 constexpr int kBvhSortTile = 1024;  // triangles per sort tile of the hierarchy build
@@ -60,6 +64,9 @@ hipError_t combine(const int32_t* seeds, float* dmin, uint32_t* hits, const rtsd
                    int32_t band_vox, float beta, float bias, int32_t mode, float alpha,
                    int32_t first_frame, int32_t consume, float* state, float* fine,
                    hipStream_t s);
+hipError_t combine_refined(const int32_t* seeds, float* dmin, uint32_t* hits, const rtsdf_grid& coarse, int32_t r,
+                           int32_t band_vox, float beta, float bias, int32_t mode, float alpha,
+                           int32_t first_frame, int32_t consume, float* state, float* fine, hipStream_t s);
 
 hipError_t shadow_forward(const float* fine, const rtsdf_grid& g, const rtsdf_shadow& s, float* img,
                           hipStream_t st);

@@ -93,6 +93,10 @@ def lib():
             "rtsdf_raysample_work_bytes": ([i64, i32], sz),
             "rtsdf_raysample": ([vp, Grid, vp, vp, i64, i32, u64, u32, u32, vp, vp, vp, vp, sz, vp], i32),
             "rtsdf_combine": ([vp, vp, vp, Grid, i32, f32, f32, i32, f32, i32, i32, vp, vp, vp], i32),
+            "rtsdf_refine_grid": ([Grid, i32, ctypes.POINTER(Grid)], i32),
+            "rtsdf_band_refined_work_bytes": ([Grid, i32], sz),
+            "rtsdf_band_refined": ([vp, Grid, i32, i32, vp, vp, vp, sz, vp], i32),
+            "rtsdf_combine_refined": ([vp, vp, vp, Grid, i32, i32, f32, f32, i32, f32, i32, i32, vp, vp, vp], i32),
             "rtsdf_shadow_forward": ([vp, Grid, Shadow, vp, vp], i32),
             "rtsdf_shadow_backward": ([vp, Grid, Shadow, vp, vp, vp], i32),
             "rtsdf_backward": ([vp, vp, vp, vp, vp, i64, vp, vp, i32, i32, Grid, i32, u64, u32, vp, vp], i32),
@@ -119,7 +123,8 @@ def lib():
 EXPORTED = ["rtsdf_last_error", "rtsdf_abi_version", "rtsdf_voxelize_work_bytes", "rtsdf_voxelize",
             "rtsdf_jfa", "rtsdf_band_work_bytes", "rtsdf_band", "rtsdf_bvh_bytes", "rtsdf_bvh_work_bytes",
             "rtsdf_build_bvh", "rtsdf_reset_accum", "rtsdf_raysample_work_bytes", "rtsdf_raysample",
-            "rtsdf_combine", "rtsdf_shadow_forward", "rtsdf_shadow_backward", "rtsdf_backward",
+            "rtsdf_combine", "rtsdf_refine_grid", "rtsdf_band_refined_work_bytes", "rtsdf_band_refined",
+            "rtsdf_combine_refined", "rtsdf_shadow_forward", "rtsdf_shadow_backward", "rtsdf_backward",
             "rtsdf_batch_plan_bytes", "rtsdf_batch_plan", "rtsdf_batch_upload", "rtsdf_batch_offsets", "rtsdf_voxelize_batched",
             "rtsdf_jfa_batched", "rtsdf_band_batched", "rtsdf_build_bvh_batched", "rtsdf_raysample_batched",
             "rtsdf_combine_batched", "rtsdf_backward_batched"]
@@ -231,6 +236,34 @@ def rtsdf_combine(seeds, dmin, hits, grid, band_vox, beta, bias, mode, fine, alp
                                int(bool(first_frame)), int(bool(consume)),
                                _ptr(state, torch.float32) if state is not None else None,
                                _ptr(fine, torch.float32), _stream(stream)), "rtsdf_combine")
+
+
+def rtsdf_refine_grid(grid, ratio):
+    fine = Grid()
+    _check(lib().rtsdf_refine_grid(grid, int(ratio), ctypes.byref(fine)), "rtsdf_refine_grid")
+    return fine
+
+
+def rtsdf_band_refined_work_bytes(grid, ratio):
+    return lib().rtsdf_band_refined_work_bytes(grid, int(ratio))
+
+
+def rtsdf_band_refined(seeds, grid, ratio, band_vox, band_list, band_count, work, stream=None):
+    """Mask of the grid refined by `ratio` over the coarse grid `grid`; lists fine indices."""
+    _check(lib().rtsdf_band_refined(_ptr(seeds, torch.int32), grid, int(ratio), int(band_vox),
+                                    _ptr(band_list, torch.int32), _ptr(band_count, torch.int32), _ptr(work),
+                                    work.numel(), _stream(stream)), "rtsdf_band_refined")
+
+
+def rtsdf_combine_refined(seeds, dmin, hits, grid, ratio, band_vox, beta, bias, mode, fine, alpha=0.95,
+                          first_frame=True, consume=False, state=None, stream=None):
+    """rtsdf_combine on the grid refined by `ratio` over the coarse grid `grid` (seeds are
+    coarse; dmin, hits, state and fine are fine)."""
+    _check(lib().rtsdf_combine_refined(_ptr(seeds, torch.int32), _ptr(dmin, torch.float32), _ptr(hits, torch.int32),
+                                       grid, int(ratio), int(band_vox), float(beta), float(bias), int(mode),
+                                       float(alpha), int(bool(first_frame)), int(bool(consume)),
+                                       _ptr(state, torch.float32) if state is not None else None,
+                                       _ptr(fine, torch.float32), _stream(stream)), "rtsdf_combine_refined")
 
 
 def rtsdf_shadow_forward(fine, grid, shadow, img, stream=None):
@@ -463,12 +496,20 @@ class StaticSDF:
     (the mask count stays on the device; launches are bounded by the grid size).  `obj` is
     the object word of the ray counters.  set_verts() replaces the vertex positions in place
     (same triangle list) for optimisation loops.
+
+    Two-level field (sections 2.3 and 2.5.1): with ratio r > 1, `dims` and `h` describe the
+    coarse grid that is voxelized and jump-flooded (`g`); rays, the mask list, the
+    accumulators and the field live on the grid refined by r over the same box (`gf`),
+    each fine point taking its coarse parent's distance and band test.  With r = 1 both
+    are the same grid and the single-level calls run.
     """
 
     def __init__(self, verts, tris, dims, org, h, steps, band, rays, frames, beta=None, bias=0.0,
-                 rng_key=0, keep_argmin=True, obj=0, bvh_method=BVH_PLOC, device="cuda"):
+                 rng_key=0, keep_argmin=True, obj=0, bvh_method=BVH_PLOC, ratio=1, device="cuda"):
         self.g = make_grid(dims, org, h)
-        N = self.g.n
+        self.ratio = int(ratio)
+        self.gf = rtsdf_refine_grid(self.g, self.ratio) if self.ratio != 1 else self.g
+        N, Nf = self.g.n, self.gf.n
         self.verts = torch.as_tensor(verts, dtype=torch.float32).reshape(-1, 3).contiguous().to(device)
         self.tris = torch.as_tensor(tris, dtype=torch.int32).reshape(-1, 3).contiguous().to(device)
         nt = self.tris.shape[0]
@@ -478,17 +519,18 @@ class StaticSDF:
         self.bvh_method = int(bvh_method)
         self.seeds = torch.empty(N, dtype=torch.int32, device=device)
         self.scratch = torch.empty(N, dtype=torch.int32, device=device)
-        self.band_list = torch.empty(N, dtype=torch.int32, device=device)
+        self.band_list = torch.empty(Nf, dtype=torch.int32, device=device)
         self.band_count = torch.zeros(1, dtype=torch.int32, device=device)
-        self.dmin = torch.empty(N, dtype=torch.float32, device=device)
-        self.hits = torch.empty(N, dtype=torch.int32, device=device)
-        self.argmin = torch.empty(N, dtype=torch.int64, device=device) if keep_argmin else None
-        self.fine = torch.empty(N, dtype=torch.float32, device=device)
+        self.dmin = torch.empty(Nf, dtype=torch.float32, device=device)
+        self.hits = torch.empty(Nf, dtype=torch.int32, device=device)
+        self.argmin = torch.empty(Nf, dtype=torch.int64, device=device) if keep_argmin else None
+        self.fine = torch.empty(Nf, dtype=torch.float32, device=device)
         self.bvh = torch.empty(rtsdf_bvh_bytes(nt), dtype=torch.uint8, device=device)
-        wb = max(rtsdf_voxelize_work_bytes(nt), rtsdf_band_work_bytes(self.g), rtsdf_bvh_work_bytes(nt))
+        wb = max(rtsdf_voxelize_work_bytes(nt), rtsdf_band_refined_work_bytes(self.g, self.ratio),
+                 rtsdf_bvh_work_bytes(nt))
         self.work = workspace(wb, device)
-        self.ray_work = workspace(rtsdf_raysample_work_bytes(N, self.rays), device)
-        self.band_n = N  # launch bound for the mask list
+        self.ray_work = workspace(rtsdf_raysample_work_bytes(Nf, self.rays), device)
+        self.band_n = Nf  # launch bound for the mask list
         self.device = device
         self.jfa_out = None
 
@@ -502,18 +544,26 @@ class StaticSDF:
         self.jfa_out = rtsdf_jfa(self.seeds, self.scratch, self.g, self.steps)
 
     def mask(self):
-        rtsdf_band(self.jfa_out, self.g, self.band, self.band_list, self.band_count, self.work)
+        if self.ratio == 1:
+            rtsdf_band(self.jfa_out, self.g, self.band, self.band_list, self.band_count, self.work)
+        else:
+            rtsdf_band_refined(self.jfa_out, self.g, self.ratio, self.band, self.band_list, self.band_count,
+                               self.work)
 
     def build_bvh(self):
-        rtsdf_build_bvh(self.verts, self.tris, self.g, self.bvh, self.work, self.bvh_method)
+        rtsdf_build_bvh(self.verts, self.tris, self.gf, self.bvh, self.work, self.bvh_method)
 
     def trace(self, frame):
-        rtsdf_raysample(self.bvh, self.g, self.band_list, self.band_count, self.rays, self.rng_key, frame,
+        rtsdf_raysample(self.bvh, self.gf, self.band_list, self.band_count, self.rays, self.rng_key, frame,
                         self.dmin, self.hits, self.ray_work, self.argmin, obj=self.obj, band_capacity=self.band_n)
 
     def combine(self):
-        rtsdf_combine(self.jfa_out, self.dmin, self.hits, self.g, self.band, self.beta, self.bias, ACCUM,
-                      self.fine)
+        if self.ratio == 1:
+            rtsdf_combine(self.jfa_out, self.dmin, self.hits, self.g, self.band, self.beta, self.bias, ACCUM,
+                          self.fine)
+        else:
+            rtsdf_combine_refined(self.jfa_out, self.dmin, self.hits, self.g, self.ratio, self.band, self.beta,
+                                  self.bias, ACCUM, self.fine)
 
     def run(self):
         self.voxelize()
@@ -533,7 +583,7 @@ class StaticSDF:
         if grad_verts is None:
             grad_verts = torch.zeros_like(self.verts)
         rtsdf_backward(grad_fine.contiguous(), self.hits, self.argmin, self.band_list, self.band_count, self.bvh,
-                       self.tris, self.verts.shape[0], self.g, self.rays, self.rng_key, grad_verts, obj=self.obj,
+                       self.tris, self.verts.shape[0], self.gf, self.rays, self.rng_key, grad_verts, obj=self.obj,
                        band_capacity=self.band_n)
         return grad_verts
 
@@ -583,12 +633,16 @@ class DeformSDF:
     ray accumulators).  All frames' vertices are resident on the device.  frame(f) only
     enqueues kernels and never synchronizes, so capture() can record each frame's chain
     into a HIP graph once and replay() runs it; frame 0 also clears the accumulators.
+    ratio r > 1 is the paper's two-level configuration: `dims`/`h` are the coarse flooded
+    grid `g`, rays and the field run on the grid `gf` refined by r (see StaticSDF).
     """
 
     def __init__(self, frame_verts, tris, dims, org, h, steps, band, rays, alpha=0.95, beta=None, bias=0.0,
-                 rng_key=0, bvh_method=BVH_LBVH, device="cuda"):
+                 rng_key=0, bvh_method=BVH_LBVH, ratio=1, device="cuda"):
         self.g = make_grid(dims, org, h)
-        N = self.g.n
+        self.ratio = int(ratio)
+        self.gf = rtsdf_refine_grid(self.g, self.ratio) if self.ratio != 1 else self.g
+        N, Nf = self.g.n, self.gf.n
         self.verts = torch.as_tensor(frame_verts, dtype=torch.float32).contiguous().to(device)
         self.nframes = self.verts.shape[0]
         self.tris = torch.as_tensor(tris, dtype=torch.int32).reshape(-1, 3).contiguous().to(device)
@@ -600,16 +654,17 @@ class DeformSDF:
         self.bias, self.rng_key = float(bias), int(rng_key)
         self.seeds = torch.empty(N, dtype=torch.int32, device=device)
         self.scratch = torch.empty(N, dtype=torch.int32, device=device)
-        self.band_list = torch.empty(N, dtype=torch.int32, device=device)
+        self.band_list = torch.empty(Nf, dtype=torch.int32, device=device)
         self.band_count = torch.zeros(1, dtype=torch.int32, device=device)
-        self.dmin = torch.empty(N, dtype=torch.float32, device=device)
-        self.hits = torch.empty(N, dtype=torch.int32, device=device)
-        self.state = torch.zeros(N, dtype=torch.float32, device=device)
-        self.fine = torch.empty(N, dtype=torch.float32, device=device)
+        self.dmin = torch.empty(Nf, dtype=torch.float32, device=device)
+        self.hits = torch.empty(Nf, dtype=torch.int32, device=device)
+        self.state = torch.zeros(Nf, dtype=torch.float32, device=device)
+        self.fine = torch.empty(Nf, dtype=torch.float32, device=device)
         self.bvh = torch.empty(rtsdf_bvh_bytes(nt), dtype=torch.uint8, device=device)
-        wb = max(rtsdf_voxelize_work_bytes(nt), rtsdf_band_work_bytes(self.g), rtsdf_bvh_work_bytes(nt))
+        wb = max(rtsdf_voxelize_work_bytes(nt), rtsdf_band_refined_work_bytes(self.g, self.ratio),
+                 rtsdf_bvh_work_bytes(nt))
         self.work = workspace(wb, device)
-        self.ray_work = workspace(rtsdf_raysample_work_bytes(N, self.rays), device)
+        self.ray_work = workspace(rtsdf_raysample_work_bytes(Nf, self.rays), device)
         self.graphs = {}
         self.jfa_out = None
 
@@ -619,12 +674,21 @@ class DeformSDF:
             rtsdf_reset_accum(self.dmin, self.hits)
         rtsdf_voxelize(v, self.tris, self.g, self.seeds, self.work)
         self.jfa_out = rtsdf_jfa(self.seeds, self.scratch, self.g, self.steps)
-        rtsdf_band(self.jfa_out, self.g, self.band, self.band_list, self.band_count, self.work)
-        rtsdf_build_bvh(v, self.tris, self.g, self.bvh, self.work, self.bvh_method)
-        rtsdf_raysample(self.bvh, self.g, self.band_list, self.band_count, self.rays, self.rng_key, f, self.dmin,
+        if self.ratio == 1:
+            rtsdf_band(self.jfa_out, self.g, self.band, self.band_list, self.band_count, self.work)
+        else:
+            rtsdf_band_refined(self.jfa_out, self.g, self.ratio, self.band, self.band_list, self.band_count,
+                               self.work)
+        rtsdf_build_bvh(v, self.tris, self.gf, self.bvh, self.work, self.bvh_method)
+        rtsdf_raysample(self.bvh, self.gf, self.band_list, self.band_count, self.rays, self.rng_key, f, self.dmin,
                         self.hits, self.ray_work)
-        rtsdf_combine(self.jfa_out, self.dmin, self.hits, self.g, self.band, self.beta, self.bias, DECAY,
-                      self.fine, alpha=self.alpha, first_frame=(f == 0), consume=True, state=self.state)
+        if self.ratio == 1:
+            rtsdf_combine(self.jfa_out, self.dmin, self.hits, self.g, self.band, self.beta, self.bias, DECAY,
+                          self.fine, alpha=self.alpha, first_frame=(f == 0), consume=True, state=self.state)
+        else:
+            rtsdf_combine_refined(self.jfa_out, self.dmin, self.hits, self.g, self.ratio, self.band, self.beta,
+                                  self.bias, DECAY, self.fine, alpha=self.alpha, first_frame=(f == 0), consume=True,
+                                  state=self.state)
 
     def capture(self, frames=None):
         for f in (range(self.nframes) if frames is None else frames):

@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(L):
     for n in names:
         assert hasattr(raw, n), n
     assert set(names) == set(L.EXPORTED)
-    assert L.rtsdf_abi_version() == 1
+    assert L.rtsdf_abi_version() == 2
 
 
 def fake(v=0x1000):
@@ -141,3 +141,36 @@ def test_workspace_queries(L):
     assert lib.rtsdf_bvh_work_bytes(103000) >= 16 * 103000
     assert lib.rtsdf_voxelize_work_bytes(-1) == 0
     assert lib.rtsdf_raysample_work_bytes(1000, 8) >= 32
+
+
+def test_refined_grid_and_validation(L, orc):
+    """rtsdf_refine_grid (host only) against the oracle's refinement, and host validation of
+    the two-level entries."""
+    lib = L.lib()
+    E_ARG, E_RANGE, E_SIZE = -1, -2, -3
+    for dims, org, h, r in [((200, 100, 200), (-1.0, 0.0, -1.0), 0.01, 2), ((16, 16, 16), (0, 0, 0), 1 / 16, 3),
+                            ((7, 1, 5), (0.25, 0.5, 0.125), 0.3, 1), ((128, 128, 128), (0, 0, 0), 1 / 128, 8)]:
+        g = L.make_grid(dims, org, h)
+        f = L.rtsdf_refine_grid(g, r)
+        o = orc.refine_grid(orc.make_grid(dims, org, h), r)
+        assert (f.nx, f.ny, f.nz) == (o.nx, o.ny, o.nz)
+        assert list(f.org) == list(o.org)
+        assert ctypes.c_float(f.h).value == ctypes.c_float(o.h).value
+        assert lib.rtsdf_band_refined_work_bytes(g, r) >= lib.rtsdf_band_work_bytes(f)
+    g = L.make_grid((300, 8, 8), (0, 0, 0), 0.1)
+    out = L.Grid()
+    assert lib.rtsdf_refine_grid(g, 4, ctypes.byref(out)) == E_RANGE      # 1200 > 1024
+    assert lib.rtsdf_refine_grid(g, 0, ctypes.byref(out)) == E_RANGE
+    assert lib.rtsdf_refine_grid(g, 2, None) == E_ARG
+    assert lib.rtsdf_band_refined_work_bytes(g, 4) == 0
+    g = L.make_grid((8, 8, 8), (0, 0, 0), 0.1)
+    need = lib.rtsdf_band_refined_work_bytes(g, 2)
+    assert lib.rtsdf_band_refined(fake(), g, 2, 2, fake(), fake(), fake(), need - 1, None) == E_SIZE
+    assert lib.rtsdf_band_refined(fake(), g, 2, -1, fake(), fake(), fake(), need, None) == E_RANGE
+    assert lib.rtsdf_band_refined(fake(), g, 0, 2, fake(), fake(), fake(), need, None) == E_RANGE
+    assert lib.rtsdf_band_refined(None, g, 2, 2, fake(), fake(), fake(), need, None) == E_ARG
+    c = lib.rtsdf_combine_refined
+    assert c(fake(), fake(), fake(), g, 2, 2, 0.0, 0.0, 7, 0.9, 1, 0, fake(), fake(), None) == E_RANGE
+    assert c(fake(), fake(), fake(), g, 2, 2, 0.0, 0.0, 1, 0.9, 1, 0, None, fake(), None) == E_ARG
+    assert c(fake(), fake(), fake(), g, 200, 2, 0.0, 0.0, 0, 0.9, 1, 0, None, fake(), None) == E_RANGE
+    assert c(fake(), fake(), fake(), g, 2, 2, float("nan"), 0.0, 0, 0.9, 1, 0, None, fake(), None) == E_ARG
