@@ -12,6 +12,7 @@ the CPU oracle baseline are reported beside it.
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -32,7 +33,7 @@ def parse():
     p.add_argument("--no-grad", action="store_true", help="skip the gradient-workload measurement")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-objects measurement")
     p.add_argument("--no-two-level", action="store_true", help="skip the two-level (coarse/fine) measurement")
-    p.add_argument("--only", choices=["static", "deform", "grad", "batch", "two_level"],
+    p.add_argument("--only", choices=["static", "deform", "grad", "batch", "two_level", "tables"],
                    help="run one workload alone and print its record (for profiling)")
     p.add_argument("--cpu-sample", type=int, default=4000000,
                    help="masked voxels ray-sampled by the oracle (about 6 s on 16 host cores)")
@@ -179,6 +180,97 @@ def two_level_bench(torch, rtsdf, synth, steps=3):
                      "ms_per_frame_graph": round(graph * 1e3, 3),
                      "sdf_voxels_per_s_graph": round(D.gf.n / graph, 1),
                      "masked_fine_voxels_last_frame": int(D.band_count.item())}
+    return out
+
+
+# GPU timings (ms) the paper reports on its own scene and GPU (RTX 2080 Ti): Table 3
+# (V, JF, RT per size and rays per texel x, mask distance d = 0.1) and Table 4 (RT of size M
+# per x and d).  Context beside the re-run, not a target.
+PAPER_TABLE3 = {"S": {"V": 0.49, "JF": 0.28, "RT": {0: 0.14, 1: 0.16, 5: 0.71, 10: 1.41}},
+                "M": {"V": 0.49, "JF": 2.37, "RT": {0: 0.55, 1: 1.41, 5: 4.51, 10: 8.36}},
+                "L": {"V": 1.12, "JF": 21.89, "RT": {0: 3.98, 1: 9.12, 5: 26.56, 10: 48.32}}}
+PAPER_TABLE4 = {1: {0.01: 0.8, 0.05: 1.28, 0.1: 1.63, 0.5: 3.12, "inf": 4.08},
+                5: {0.01: 1.43, 0.05: 3.17, 0.1: 4.82, 0.5: 11.71, "inf": 16.15},
+                10: {0.01: 2.18, 0.05: 5.41, 0.1: 8.36, 0.5: 22.25, "inf": 30.69},
+                15: {0.01: 3.17, 0.05: 7.7, 0.1: 12.42, 0.5: 32.7, "inf": 46.0}}
+TABLE_SIZES = {"S": 64, "M": 128, "L": 256}  # coarse side; the fine side is twice it
+
+
+def mask_vox(d, h):
+    """Mask width in whole coarse voxels for a world distance d (infinity: every point)."""
+    return 2048 if d == "inf" else int(round(d / h))
+
+
+def table_frame(D, rtsdf, timer, f, x, band):
+    """One frame of the two-level dynamic chain of a static mesh (hierarchy built once):
+    V = voxelize, JF = all jump-flooding passes, RT = mask + x rays per masked fine point +
+    Eq. 1 combine (x = 0: mask and combine only)."""
+    v = D.verts[0]
+    timer.mark("start")
+    rtsdf.rtsdf_voxelize(v, D.tris, D.g, D.seeds, D.work)
+    timer.mark("V")
+    out = rtsdf.rtsdf_jfa(D.seeds, D.scratch, D.g, D.steps)
+    timer.mark("JF")
+    rtsdf.rtsdf_band_refined(out, D.g, D.ratio, band, D.band_list, D.band_count, D.work)
+    timer.mark("mask")
+    if x > 0:
+        rtsdf.rtsdf_raysample(D.bvh, D.gf, D.band_list, D.band_count, x, D.rng_key, f, D.dmin, D.hits, D.ray_work)
+        timer.mark("rays")
+    rtsdf.rtsdf_combine_refined(out, D.dmin, D.hits, D.g, D.ratio, band, D.beta, D.bias, rtsdf.DECAY, D.fine,
+                                alpha=D.alpha, first_frame=(f == 0), consume=True, state=D.state)
+    timer.mark("combine")
+
+
+def tables_bench(torch, rtsdf, synth, reps=7):
+    """Tables 3 and 4 re-run on this GPU with the static scene generator over the cube
+    [0,2]^3 (ground plane + 200 primitives): sizes S/M/L flood 64^3/128^3/256^3 and trace
+    twice the resolution; Table 3 at d = 0.1 for x in {0, 1, 5, 10}, Table 4 at size M for
+    x in {1, 5, 10, 15} and d in {0.01, 0.05, 0.1, 0.5, inf}.  Medians over `reps` frames after
+    one warm-up frame (sustained load can slow single frames for a while)."""
+    def run(D, x, band):
+        table_frame(D, rtsdf, StageTimer(torch), 0, x, band)
+        timers = [StageTimer(torch) for _ in range(reps)]
+        for k in range(reps):
+            table_frame(D, rtsdf, timers[k], k + 1, x, band)
+        torch.cuda.synchronize()
+        per = {}
+        for tm in timers:
+            for k, v in tm.durations().items():
+                per.setdefault(k, []).append(v)
+        st = {k: statistics.median(v) for k, v in per.items()}
+        rt = st["mask"] + st.get("rays", 0.0) + st["combine"]
+        return {"V": round(st["V"], 4), "JF": round(st["JF"], 4), "RT": round(rt, 4),
+                "mask_ms": round(st["mask"], 4), "rays_ms": round(st.get("rays", 0.0), 4),
+                "combine_ms": round(st["combine"], 4), "masked_fine_points": int(D.band_count.item())}
+
+    out = {"table3": {}, "table4": {}}
+    for size, n in TABLE_SIZES.items():
+        sc = synth.scene_static(dims=(n, n, n))
+        band = mask_vox(0.1, sc.h)
+        D = rtsdf.DeformSDF(sc.verts[None], sc.tris, sc.dims, sc.org, sc.h, sc.steps, band, 15, ratio=2,
+                            bvh_method=rtsdf.BVH_PLOC)
+        t0 = StageTimer(torch)
+        t0.mark("start")
+        rtsdf.rtsdf_build_bvh(D.verts[0], D.tris, D.gf, D.bvh, D.work, D.bvh_method)
+        t0.mark("bvh")
+        torch.cuda.synchronize()
+        rows = {"coarse": n, "fine": 2 * n, "band_vox": band, "triangles": int(len(sc.tris)),
+                "bvh_ms_once": round(t0.durations()["bvh"], 4), "x": {}}
+        for x in (0, 1, 5, 10):
+            rows["x"][x] = run(D, x, band)
+            rows["x"][x]["paper_RT"] = PAPER_TABLE3[size]["RT"][x]
+        rows["paper_V"], rows["paper_JF"] = PAPER_TABLE3[size]["V"], PAPER_TABLE3[size]["JF"]
+        out["table3"][size] = rows
+        if size == "M":
+            for x in (1, 5, 10, 15):
+                out["table4"][x] = {}
+                for d in (0.01, 0.05, 0.1, 0.5, "inf"):
+                    r = run(D, x, mask_vox(d, sc.h))
+                    out["table4"][x][str(d)] = {"RT": r["RT"], "rays_ms": r["rays_ms"], "band_vox": mask_vox(d, sc.h),
+                                                "masked_fine_points": r["masked_fine_points"],
+                                                "paper_RT": PAPER_TABLE4[x][d]}
+        del D
+        torch.cuda.empty_cache()
     return out
 
 
@@ -362,8 +454,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n, "copy_calibration_bytes_written": n, "dispatches": 3}))
         return
-    if args.only in ("deform", "grad", "batch", "two_level"):
-        fn = {"deform": deform_bench, "grad": grad_bench, "batch": batch_bench, "two_level": two_level_bench}[args.only]
+    if args.only in ("deform", "grad", "batch", "two_level", "tables"):
+        fn = {"deform": deform_bench, "grad": grad_bench, "batch": batch_bench, "two_level": two_level_bench,
+              "tables": tables_bench}[args.only]
         print(json.dumps({args.only: fn(torch, rtsdf, synth)}))
         return
     if args.only == "static":

@@ -41,6 +41,7 @@ constexpr int kLdsDepth = 12;
 constexpr int kXcds = 8;
 constexpr int32_t kChunk = RTSDF_RAY_CHUNK;            // work units a wave takes per cursor atomic
 constexpr int32_t kChunkSmall = 128;                   // ... when there are few units per lane
+constexpr int32_t kChunkRays = RTSDF_RAY_CHUNK_RAYS;   // ... and at least this many rays
 constexpr int32_t kStartBatch = RTSDF_RAY_START_BATCH;  // idle lanes restarted together
 constexpr int kMinWaves = 6;         // waves per SIMD the register budget must allow
 __device__ inline void test_leaf(const BvhTri* __restrict__ tris, int32_t pos, float3 o, float3 w,
@@ -108,8 +109,11 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
     const uint32_t gsize = (uint32_t)((x + ngroups - 1) / ngroups);
     ngroups = (int32_t)((x + (int32_t)gsize - 1) / (int32_t)gsize);
     const int32_t units = count * ngroups;
-    // many units per lane: short chunks balance the tail; few: long chunks, fewer atomics
-    const int32_t chunk = (int64_t)units >= 8 * lanes ? kChunk : kChunkSmall;
+    // many units per lane: short chunks balance the tail; few: long chunks, fewer atomics;
+    // and never fewer than kChunkRays rays per atomic (with one ray per unit the cursor
+    // atomics, serialised per XCD, would otherwise bound the launch)
+    const int32_t chunk = max((int64_t)units >= 8 * lanes ? kChunk : kChunkSmall,
+                              (int32_t)((kChunkRays + gsize - 1) / gsize));
     const float inf = __int_as_float(0x7f800000);
     const int tid = threadIdx.x;
     const int lane = __lane_id();

@@ -13,9 +13,13 @@
 #define RTSDF_JFA_ROWS 4
 #endif
 
-// ray sampling: work units a wave takes per cursor atomic, and idle lanes restarted together
+// ray sampling: work units a wave takes per cursor atomic (raised so that one atomic
+// covers at least RTSDF_RAY_CHUNK_RAYS rays), and idle lanes restarted together
 #ifndef RTSDF_RAY_CHUNK
 #define RTSDF_RAY_CHUNK 32
+#endif
+#ifndef RTSDF_RAY_CHUNK_RAYS
+#define RTSDF_RAY_CHUNK_RAYS 128
 #endif
 #ifndef RTSDF_RAY_START_BATCH
 #define RTSDF_RAY_START_BATCH 12
