@@ -28,6 +28,8 @@ GROUPS = {
     "jfa": {"RTSDF_JFA_CHUNK": [16, 32, 64], "RTSDF_JFA_ROWS": [2, 4, 8]},
     "ray": {"RTSDF_RAY_CHUNK": [32, 64, 128], "RTSDF_RAY_START_BATCH": [10, 12, 14]},
     "shadow": {"RTSDF_SHADOW_TILE_X": [1, 2, 4, 8]},
+    "ray_small": {"RTSDF_RAY_RANGES": [8, 32, 64], "RTSDF_RAY_CHUNK_SMALL": [16, 32, 128],
+                  "RTSDF_RAY_CHUNK_RAYS": [32, 64, 128]},
 }
 
 
@@ -55,7 +57,7 @@ def lib_path(group, defines):
 
 def cmd_build(args):
     from paper_2210_06160_amd import build as B
-    for group in GROUPS:
+    for group in (args.groups.split(",") if args.groups else GROUPS):
         for d in candidates(group):
             path = lib_path(group, d)
             B.build(defines=d, out=os.path.dirname(path), lib=path)
@@ -96,6 +98,8 @@ def time_candidate(group, path, reps):
         S.build_bvh()
         rtsdf.rtsdf_reset_accum(S.dmin, S.hits, S.argmin)
         return events(lambda: S.trace(0))
+    if group == "ray_small":
+        return sum(events(fn) for fn in small_ray_launches(rtsdf, synth))
     sc = synth.scene_grad()
     g = rtsdf.make_grid(sc.dims, sc.org, sc.h)
     sh = rtsdf.make_shadow(**sc.extra["shadow"])
@@ -107,9 +111,34 @@ def time_candidate(group, path, reps):
                            rtsdf.rtsdf_shadow_backward(fine, g, sh, gi, gf)))
 
 
+def small_ray_launches(rtsdf, synth):
+    """Ray-sampling launches far from the static workload's shape, where the work
+    distribution constants matter: the gradient workload (92 k masked points x 16 rays), the
+    deforming knot's first frame (4 rays), every fine point of a 128^3 -> 256^3 two-level
+    field with one ray, and a 64^3 -> 128^3 two-level field (mask d = 0.1) with 10 rays."""
+    out = []
+    sg = synth.scene_grad()
+    G = rtsdf.StaticSDF(sg.verts, sg.tris, sg.dims, sg.org, sg.h, sg.steps, sg.band, sg.rays, 1,
+                        bvh_method=rtsdf.BVH_LBVH)
+    G.run()
+    out.append(lambda: G.trace(0))
+    sd = synth.scene_deform(frames=1)
+    D = rtsdf.StaticSDF(sd.verts, sd.tris, sd.dims, sd.org, sd.h, sd.steps, sd.band, sd.rays, 1)
+    D.run()
+    out.append(lambda: D.trace(0))
+    for n, band, x in ((128, 2048, 1), (64, None, 10)):
+        sc = synth.scene_static(dims=(n, n, n))
+        band = int(round(0.1 / sc.h)) if band is None else band
+        T = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, band, x, 1, ratio=2,
+                            keep_argmin=False)
+        T.run()
+        out.append(lambda T=T: T.trace(0))
+    return out
+
+
 def cmd_run(args):
     results = {}
-    for group in GROUPS:
+    for group in (args.groups.split(",") if args.groups else GROUPS):
         results[group] = []
         for d in candidates(group):
             path = lib_path(group, d)
@@ -146,10 +175,12 @@ def cmd_apply(args):
 def main():
     p = argparse.ArgumentParser()
     sub = p.add_subparsers(dest="cmd", required=True)
-    sub.add_parser("build")
+    b = sub.add_parser("build")
+    b.add_argument("--groups", help="comma-separated groups (default: all)")
     r = sub.add_parser("run")
     r.add_argument("--json", required=True)
     r.add_argument("--reps", type=int, default=5)
+    r.add_argument("--groups", help="comma-separated groups (default: all)")
     t = sub.add_parser("time")
     t.add_argument("--group", required=True)
     t.add_argument("--lib", required=True)

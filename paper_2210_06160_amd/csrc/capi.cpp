@@ -67,7 +67,7 @@ rtsdf_status check_shadow(const rtsdf_shadow& s)
 
 size_t batch_work_bytes(const rtsdf::BatchView& v)
 {
-    size_t w = 256;  // ray-sampling cursors
+    size_t w = rtsdf::raysample_work_bytes(0, 1);  // ray-sampling cursors
     w = std::max(w, rtsdf::voxelize_work_bytes((int32_t)v.h->total_tris));
     w = std::max(w, rtsdf::band_batched_work_bytes(v.h->total_vox));
     w = std::max(w, rtsdf::bvh_work_bytes(v.h->total_tris, v.h->total_tiles, v.h->nobj));

@@ -10,10 +10,11 @@
 // one address serialise across the chip), so divergent ray lengths neither idle lanes nor
 // leave a tail of busy waves.  A mask with fewer than about two voxels per lane of the grid
 // is split into groups of consecutive rays so that every lane has work.  The unit range is
-// split into one contiguous range per XCD (work-groups are dealt to the 8 XCDs
-// round-robin); a wave takes units from its own XCD's range first, so list reads and the
-// hierarchy working set stay in that XCD's L2, and steals from the other ranges when its
-// own is exhausted.
+// split into contiguous ranges, RTSDF_RAY_RANGES / 8 per XCD (work-groups are dealt to
+// the 8 XCDs round-robin), each with its own cursor on its own cache line (device-scope
+// atomics on one line serialise); a wave takes units from a range of its own XCD, so list
+// reads and the hierarchy working set stay in that XCD's L2, and moves on to the next
+// range -- its own XCD's first -- when that one is exhausted.
 // The loop touches no cold memory: directions are drawn in registers and accumulators are
 // updated with fire-and-forget atomics, because on CDNA loads retire in order and one
 // HBM-latency load would stall every later node fetch of the wave.
@@ -40,10 +41,14 @@ constexpr int kThreads = 256;
 constexpr int kLdsDepth = 12;
 constexpr int kXcds = 8;
 constexpr int32_t kChunk = RTSDF_RAY_CHUNK;            // work units a wave takes per cursor atomic
-constexpr int32_t kChunkSmall = 128;                   // ... when there are few units per lane
+constexpr int32_t kChunkSmall = RTSDF_RAY_CHUNK_SMALL;  // ... when there are few units per lane
 constexpr int32_t kChunkRays = RTSDF_RAY_CHUNK_RAYS;   // ... and at least this many rays
 constexpr int32_t kStartBatch = RTSDF_RAY_START_BATCH;  // idle lanes restarted together
 constexpr int kMinWaves = 6;         // waves per SIMD the register budget must allow
+constexpr int kRanges = RTSDF_RAY_RANGES;  // unit ranges, each with its own cursor
+constexpr int kSub = kRanges / kXcds;      // ranges per XCD
+constexpr int kCursorStride = 32;          // cursors are 128 bytes apart
+static_assert(kSub * kXcds == kRanges, "ranges split evenly over the XCDs");
 __device__ inline void test_leaf(const BvhTri* __restrict__ tris, int32_t pos, float3 o, float3 w,
                                  float pad, float& tb, int32_t& bid, bool& bfr)
 {
@@ -61,10 +66,11 @@ __device__ inline void test_leaf(const BvhTri* __restrict__ tris, int32_t pos, f
     }
 }
 
-// cursors[x] walks XCD x's range [x*units/8, (x+1)*units/8) of the work units
+// cursors[r * kCursorStride] walks range r = [r*units/kRanges, (r+1)*units/kRanges) of the
+// work units; ranges x*kSub ... x*kSub + kSub - 1 belong to XCD x
 __global__ void k_cursor_reset(int32_t* cursors)
 {
-    if (threadIdx.x < kXcds) cursors[threadIdx.x] = 0;
+    if (threadIdx.x < kRanges) cursors[threadIdx.x * kCursorStride] = 0;
 }
 
 // kBatch: the mask list indexes concatenated grids; each voxel's object (binary search over
@@ -119,7 +125,8 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
     const int lane = __lane_id();
     const uint64_t lt_mask = (1ull << lane) - 1ull;
     const uint32_t code0 = frame * (uint32_t)x;
-    int xcd = (int)(blockIdx.x % kXcds);  // the range this wave takes voxels from
+    // the range this wave takes units from: one of its own XCD's
+    int rng = (int)(blockIdx.x % kXcds) * kSub + (int)((blockIdx.x / kXcds) % kSub);
     int tried = 0;                        // ranges found exhausted
     int32_t q_next = 0, q_end = 0;        // the wave's current chunk of the unit range
 
@@ -180,15 +187,15 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
         // chunk is replaced by one atomic on this XCD's cursor, and an
         // exhausted range moves the wave on to the next XCD's range
         uint64_t needers = __ballot(need);
-        while (needers && tried < kXcds) {
+        while (needers && tried < kRanges) {
             if (q_next >= q_end) {
-                const int32_t lo = (int32_t)(((int64_t)units * xcd) / kXcds);
-                const int32_t hi = (int32_t)(((int64_t)units * (xcd + 1)) / kXcds);
+                const int32_t lo = (int32_t)(((int64_t)units * rng) / kRanges);
+                const int32_t hi = (int32_t)(((int64_t)units * (rng + 1)) / kRanges);
                 int32_t base = 0;
-                if (lane == 0) base = atomicAdd(&cursors[xcd], chunk);
+                if (lane == 0) base = atomicAdd(&cursors[rng * kCursorStride], chunk);
                 base = __shfl(base, 0) + lo;
                 if (base >= hi) {
-                    xcd = (xcd + 1) % kXcds;
+                    rng = (rng + 1) % kRanges;  // the next range: the same XCD's first
                     ++tried;
                     continue;
                 }
@@ -320,7 +327,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
 
 }  // namespace
 
-size_t raysample_work_bytes(int64_t, int32_t) { return 256; }
+size_t raysample_work_bytes(int64_t, int32_t) { return sizeof(int32_t) * kRanges * kCursorStride; }
 
 hipError_t raysample(const void* bvh, const rtsdf_grid& g, const int32_t* list, const int32_t* count,
                      int64_t capacity, int32_t x, uint64_t key, uint32_t frame, uint32_t obj,
@@ -328,7 +335,7 @@ hipError_t raysample(const void* bvh, const rtsdf_grid& g, const int32_t* list, 
 {
     if (capacity <= 0) return hipSuccess;
     int32_t* cursors = (int32_t*)work;
-    hipLaunchKernelGGL(k_cursor_reset, dim3(1), dim3(64), 0, s, cursors);
+    hipLaunchKernelGGL(k_cursor_reset, dim3(1), dim3(kRanges), 0, s, cursors);
     // exactly the resident grid: more groups would only start after others finish
     static int resident = 0;
     if (resident == 0) {
@@ -354,7 +361,7 @@ hipError_t raysample_batched(const BatchView& hv, const void* dplan, const void*
 {
     if (capacity <= 0) return hipSuccess;
     int32_t* cursors = (int32_t*)work;
-    hipLaunchKernelGGL(k_cursor_reset, dim3(1), dim3(64), 0, s, cursors);
+    hipLaunchKernelGGL(k_cursor_reset, dim3(1), dim3(kRanges), 0, s, cursors);
     static int resident = 0;
     if (resident == 0) {
         int per_cu = 0, dev = 0, cus = 0;

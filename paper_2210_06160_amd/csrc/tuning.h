@@ -19,7 +19,15 @@
 #define RTSDF_RAY_CHUNK 32
 #endif
 #ifndef RTSDF_RAY_CHUNK_RAYS
-#define RTSDF_RAY_CHUNK_RAYS 128
+#define RTSDF_RAY_CHUNK_RAYS 64
+#endif
+// ... units per cursor atomic when there are fewer than 8 units per lane, and the number of
+// unit ranges (each with its own cursor; a multiple of the 8 XCDs)
+#ifndef RTSDF_RAY_CHUNK_SMALL
+#define RTSDF_RAY_CHUNK_SMALL 16
+#endif
+#ifndef RTSDF_RAY_RANGES
+#define RTSDF_RAY_RANGES 8
 #endif
 #ifndef RTSDF_RAY_START_BATCH
 #define RTSDF_RAY_START_BATCH 12
