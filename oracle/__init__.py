@@ -41,6 +41,28 @@ def make_shadow(width, height, x0, z0, dx, dz, y, light, k, steps, smin, smax, t
     return s
 
 
+MAX_LIGHTS = 8
+
+
+class ShadowEx(ctypes.Structure):
+    """The shadow pass with several lights, a jittered start and optional triangulation;
+    base.light is not used."""
+    _fields_ = [("base", Shadow), ("nlights", ctypes.c_int32), ("lights", (ctypes.c_float * 3) * MAX_LIGHTS),
+                ("triangulate", ctypes.c_int32), ("jitter", ctypes.c_float), ("frame", ctypes.c_uint32),
+                ("key", ctypes.c_uint64)]
+
+
+def make_shadow_ex(base, lights, triangulate=False, jitter=0.0, frame=0, key=0):
+    s = ShadowEx()
+    s.base = base
+    s.nlights = len(lights)
+    for i, l in enumerate(lights):
+        for a in range(3):
+            s.lights[i][a] = float(l[a])
+    s.triangulate, s.jitter, s.frame, s.key = int(bool(triangulate)), float(jitter), int(frame), int(key)
+    return s
+
+
 def make_grid(dims, org, h):
     g = Grid()
     g.nx, g.ny, g.nz = (int(d) for d in dims)
@@ -91,6 +113,11 @@ def lib():
         L.orc_sdf_backward.restype = ctypes.c_int
         L.orc_sample.argtypes = [vp, Grid, vp, i64, vp, vp]
         L.orc_shadow_margin.argtypes = [vp, Grid, ctypes.POINTER(Shadow), vp, vp, vp]
+        L.orc_shadow_forward_ex.argtypes = [vp, Grid, ctypes.POINTER(ShadowEx), vp]
+        L.orc_shadow_backward_ex.argtypes = [vp, Grid, ctypes.POINTER(ShadowEx), vp, vp]
+        L.orc_shadow_margin_ex.argtypes = [vp, Grid, ctypes.POINTER(ShadowEx), vp, vp, vp]
+        L.orc_shadow_triangulate.argtypes = [ctypes.c_double] * 5 + [vp]
+        L.orc_shadow_triangulate.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -308,6 +335,40 @@ def shadow_margin(fine, g, s):
     sm = np.empty(s.width * s.height, np.float64)
     cm = np.empty(s.width * s.height, np.float64)
     lib().orc_shadow_margin(_p(f), g, ctypes.byref(s), _p(rm), _p(sm), _p(cm))
+    return rm, sm, cm
+
+
+def shadow_triangulate(r1, r2, delta, t, k):
+    """Two-sample estimate of the closest approach: (estimate, triangulated?)."""
+    v = ctypes.c_int(0)
+    e = lib().orc_shadow_triangulate(float(r1), float(r2), float(delta), float(t), float(k), ctypes.byref(v))
+    return e, bool(v.value)
+
+
+def shadow_forward_ex(fine, g, s):
+    """Shadow images [nlights][height][width] (several lights, jitter, triangulation; binary64)."""
+    f = np.ascontiguousarray(fine, np.float64)
+    img = np.empty(s.nlights * s.base.width * s.base.height, np.float64)
+    lib().orc_shadow_forward_ex(_p(f), g, ctypes.byref(s), _p(img))
+    return img
+
+
+def shadow_backward_ex(fine, g, s, grad_img):
+    """(d img / d fine)^T grad_img for shadow_forward_ex (binary64)."""
+    f = np.ascontiguousarray(fine, np.float64)
+    gi = np.ascontiguousarray(grad_img, np.float64)
+    gf = np.zeros(len(f), np.float64)
+    lib().orc_shadow_backward_ex(_p(f), g, ctypes.byref(s), _p(gi), _p(gf))
+    return gf
+
+
+def shadow_margin_ex(fine, g, s):
+    """Decision margins of shadow_forward_ex per pixel and light (r, s, c) -- see
+    orc_shadow_margin_ex."""
+    f = np.ascontiguousarray(fine, np.float64)
+    n = s.nlights * s.base.width * s.base.height
+    rm, sm, cm = np.empty(n), np.empty(n), np.empty(n)
+    lib().orc_shadow_margin_ex(_p(f), g, ctypes.byref(s), _p(rm), _p(sm), _p(cm))
     return rm, sm, cm
 
 

@@ -820,29 +820,68 @@ static void orc_pixel_origin(const orc_shadow* s, int32_t a, int32_t b, double P
     P[2] = (double)s->z0 + ((double)b + 0.5) * (double)s->dz;
 }
 
-/* one pixel's march; records t_m and s_m (arrays of s->steps) when given.  Returns the
- * clamped image value; *istar = index of the first step attaining the minimum, or -1 when
- * the value is the initial 1 or is clamped at 0 (no gradient). */
-static double orc_march(const double* f, orc_grid g, const orc_shadow* s, const double P[3], double* tm,
-                        double* sm, int* istar)
+/* ------------------------------------------------------------------------------------
+ * Two-sample triangulation of the closest approach (section 2.5.2, after Aaltonen 2018).
+ * The paper prints no formula; the reading used: consecutive samples s_{m-1} = r1 at
+ * P + t_{m-1} l and s_m = r2 at P + t_m l each bound an empty sphere; the step between
+ * them is delta = clamp(r1, smin, smax).  The two sphere surfaces meet on a circle in the
+ * plane perpendicular to the ray at distance y = (r2^2 - r1^2 + delta^2) / (2 delta)
+ * behind the later sample, with radius d = sqrt(r2^2 - y^2): the nearest point to the ray
+ * that both samples allow.  The estimate at step m is k d / (t_m - y) when r1 > 0, r2 > 0,
+ * d^2 > 0 and t_m - y > 0, else the one-sample k r2 / t_m.  (For a point occluder both
+ * spheres pass through the point, so d is exactly its distance from the ray.)  Binary64.
+ * Returns the estimate; *valid says which form was used.
+ * ---------------------------------------------------------------------------------- */
+double orc_shadow_triangulate(double r1, double r2, double delta, double t, double k, int* valid)
 {
-    double t = (double)s->t0, res = 1.0;
+    if (r1 > 0.0 && r2 > 0.0 && delta > 0.0) {
+        const double y = (r2 * r2 - r1 * r1 + delta * delta) / (2.0 * delta);
+        const double d2 = r2 * r2 - y * y;
+        if (d2 > 0.0 && t - y > 0.0) {
+            if (valid) *valid = 1;
+            return k * sqrt(d2) / (t - y);
+        }
+    }
+    if (valid) *valid = 0;
+    return k * r2 / t;
+}
+
+static double orc_clamp_step(const orc_shadow* s, double v)
+{
+    if (v < (double)s->smin) v = (double)s->smin;
+    if (v > (double)s->smax) v = (double)s->smax;
+    return v;
+}
+
+/* the estimate of step m from the recorded samples (plain, or triangulated when tri) */
+static double orc_estimate(const orc_shadow* s, int tri, const double* tm, const double* sm, int m, int* valid)
+{
+    if (valid) *valid = 0;
+    if (!tri || m == 0) return (double)s->k * sm[m] / tm[m];
+    return orc_shadow_triangulate(sm[m - 1], sm[m], orc_clamp_step(s, sm[m - 1]), tm[m], (double)s->k, valid);
+}
+
+/* one pixel's march towards the unit direction l from t = t_start; records t_m and s_m
+ * (arrays of s->steps, always given).  Returns the clamped image value; *istar = index of
+ * the first step attaining the minimum, or -1 when the value is the initial 1 or is
+ * clamped at 0 (no gradient). */
+static double orc_march_ex(const double* f, orc_grid g, const orc_shadow* s, const double l[3], double t_start,
+                           int tri, const double P[3], double* tm, double* sm, int* istar)
+{
+    double t = t_start, res = 1.0;
     int best = -1;
     for (int m = 0; m < s->steps; ++m) {
         double X[3];
-        for (int a = 0; a < 3; ++a) X[a] = P[a] + t * (double)s->light[a];
+        for (int a = 0; a < 3; ++a) X[a] = P[a] + t * l[a];
         const double v = orc_trilinear(f, g, X, NULL);
-        if (tm) tm[m] = t;
-        if (sm) sm[m] = v;
-        const double r = (double)s->k * v / t;
+        tm[m] = t;
+        sm[m] = v;
+        const double r = orc_estimate(s, tri, tm, sm, m, NULL);
         if (r < res) {
             res = r;
             best = m;
         }
-        double step = v;
-        if (step < (double)s->smin) step = (double)s->smin;
-        if (step > (double)s->smax) step = (double)s->smax;
-        t += step;
+        t += orc_clamp_step(s, v);
     }
     if (res <= 0.0) {
         *istar = -1;
@@ -852,14 +891,28 @@ static double orc_march(const double* f, orc_grid g, const orc_shadow* s, const 
     return res;
 }
 
+static double orc_march(const double* f, orc_grid g, const orc_shadow* s, const double P[3], double* tm,
+                        double* sm, int* istar)
+{
+    const double l[3] = {(double)s->light[0], (double)s->light[1], (double)s->light[2]};
+    return orc_march_ex(f, g, s, l, (double)s->t0, 0, P, tm, sm, istar);
+}
+
 void orc_shadow_forward(const double* fine, orc_grid g, const orc_shadow* s, double* img)
 {
-#pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t p = 0; p < (int64_t)s->width * s->height; ++p) {
-        double P[3];
-        int istar;
-        orc_pixel_origin(s, (int32_t)(p % s->width), (int32_t)(p / s->width), P);
-        img[p] = orc_march(fine, g, s, P, NULL, NULL, &istar);
+#pragma omp parallel
+    {
+        double* tm = (double*)malloc(sizeof(double) * (size_t)s->steps);
+        double* sm = (double*)malloc(sizeof(double) * (size_t)s->steps);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t p = 0; p < (int64_t)s->width * s->height; ++p) {
+            double P[3];
+            int istar;
+            orc_pixel_origin(s, (int32_t)(p % s->width), (int32_t)(p / s->width), P);
+            img[p] = orc_march(fine, g, s, P, tm, sm, &istar);
+        }
+        free(tm);
+        free(sm);
     }
 }
 
@@ -948,6 +1001,183 @@ void orc_shadow_margin(const double* fine, orc_grid g, const orc_shadow* s, doub
         }
         free(tm);
         free(sm);
+    }
+}
+
+/* ------------------------------------------------------------------------------------
+ * The shadow pass with several lights, a jittered start and optional triangulation
+ * (sections 2.5.2 and 3.2: three lights; a 0.05 step cap with about 128 samples; the start
+ * offset jittered along the light to break up the fixed-step pattern).  Image l (of
+ * nlights, each height x width, img[(l * height + b) * width + a]) marches towards
+ * lights[l] from t = t0 + jitter * u, with u = (w0 >> 8) 2^-24 and w0 the first word of
+ * Philox4x32-10 with counter (b * width + a, frame, l, 0xFFFFFFFF) and key (key_lo,
+ * key_hi): one draw per pixel, light and frame.  The start offset is computed in binary32
+ * (t0 + jitter * u, no contraction), the march in binary64.
+ * ---------------------------------------------------------------------------------- */
+#define ORC_MAX_LIGHTS 8
+typedef struct {
+    orc_shadow base;                   /* base.light is not used */
+    int32_t nlights;
+    float lights[ORC_MAX_LIGHTS][3];
+    int32_t triangulate;
+    float jitter;
+    uint32_t frame;
+    uint64_t key;
+} orc_shadow_ex;
+
+static double orc_shadow_start(const orc_shadow_ex* s, int64_t pixel, int32_t l)
+{
+    if (s->jitter == 0.0f) return (double)s->base.t0;
+    const uint32_t ctr[4] = {(uint32_t)pixel, s->frame, (uint32_t)l, 0xFFFFFFFFu};
+    const uint32_t key[2] = {(uint32_t)s->key, (uint32_t)(s->key >> 32)};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    const float u = (float)(w[0] >> 8) * (1.0f / 16777216.0f);
+    volatile float ju = s->jitter * u; /* binary32 product, then a binary32 sum */
+    return (double)(float)(s->base.t0 + ju);
+}
+
+void orc_shadow_forward_ex(const double* fine, orc_grid g, const orc_shadow_ex* s, double* img)
+{
+    const orc_shadow* b = &s->base;
+    const int64_t npix = (int64_t)b->width * b->height;
+#pragma omp parallel
+    {
+        double* tm = (double*)malloc(sizeof(double) * (size_t)b->steps);
+        double* sm = (double*)malloc(sizeof(double) * (size_t)b->steps);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t q = 0; q < npix * s->nlights; ++q) {
+            const int32_t l = (int32_t)(q / npix);
+            const int64_t p = q % npix;
+            const double L[3] = {(double)s->lights[l][0], (double)s->lights[l][1], (double)s->lights[l][2]};
+            double P[3];
+            int istar;
+            orc_pixel_origin(b, (int32_t)(p % b->width), (int32_t)(p / b->width), P);
+            img[q] = orc_march_ex(fine, g, b, L, orc_shadow_start(s, p, l), s->triangulate, P, tm, sm, &istar);
+        }
+        free(tm);
+        free(sm);
+    }
+}
+
+/* grad_fine += (d img / d fine)^T grad_img.  Reverse mode of the march: at the minimising
+ * step m* the estimate E depends on s_{m*} and t_{m*} (and, triangulated, on s_{m*-1}
+ * directly and through delta = clamp(s_{m*-1})); then for m = m* ... 0 each s_m's adjoint is
+ * scattered to its 8 grid points, t_m's adjoint gains s_m's adjoint times grad s . l, and
+ * t_m = t_{m-1} + clamp(s_{m-1}) hands t_m's adjoint to s_{m-1} strictly inside
+ * [smin, smax] (and to t_{m-1} always). */
+void orc_shadow_backward_ex(const double* fine, orc_grid g, const orc_shadow_ex* s, const double* grad_img,
+                            double* grad_fine)
+{
+    const orc_shadow* b = &s->base;
+    const int64_t npix = (int64_t)b->width * b->height;
+    double* tm = (double*)malloc(sizeof(double) * (size_t)b->steps);
+    double* sm = (double*)malloc(sizeof(double) * (size_t)b->steps);
+    const double smin = (double)b->smin, smax = (double)b->smax, kk = (double)b->k;
+    for (int64_t q = 0; q < npix * s->nlights; ++q) {
+        if (grad_img[q] == 0.0) continue;
+        const int32_t l = (int32_t)(q / npix);
+        const int64_t p = q % npix;
+        const double L[3] = {(double)s->lights[l][0], (double)s->lights[l][1], (double)s->lights[l][2]};
+        double P[3];
+        int istar;
+        orc_pixel_origin(b, (int32_t)(p % b->width), (int32_t)(p / b->width), P);
+        orc_march_ex(fine, g, b, L, orc_shadow_start(s, p, l), s->triangulate, P, tm, sm, &istar);
+        if (istar < 0) continue;
+        const double gi = grad_img[q];
+        double sbar, tbar, extra = 0.0; /* extra: direct adjoint of s_{m*-1} */
+        int valid = 0;
+        const double E = orc_estimate(b, s->triangulate, tm, sm, istar, &valid);
+        if (valid) {
+            const double r1 = sm[istar - 1], r2 = sm[istar], T = tm[istar];
+            const double delta = orc_clamp_step(b, r1);
+            const double y = (r2 * r2 - r1 * r1 + delta * delta) / (2.0 * delta);
+            const double D = sqrt(r2 * r2 - y * y);
+            const double dy_r2 = r2 / delta, dy_r1 = -r1 / delta, dy_dl = 1.0 - y / delta;
+            const double dD_r2 = (r2 - y * dy_r2) / D, dD_r1 = -y * dy_r1 / D, dD_dl = -y * dy_dl / D;
+            const double a = kk / (T - y), c = E / (T - y);
+            sbar = gi * (a * dD_r2 + c * dy_r2);
+            tbar = -gi * c;
+            extra = gi * (a * dD_r1 + c * dy_r1);
+            if (r1 > smin && r1 < smax) extra += gi * (a * dD_dl + c * dy_dl);
+        } else {
+            sbar = gi * kk / tm[istar];
+            tbar = -gi * kk * sm[istar] / (tm[istar] * tm[istar]);
+        }
+        for (int m = istar; m >= 0; --m) {
+            double X[3], gr[3];
+            for (int a = 0; a < 3; ++a) X[a] = P[a] + tm[m] * L[a];
+            orc_trilinear(fine, g, X, gr);
+            orc_trilinear_scatter(grad_fine, g, X, sbar);
+            tbar += sbar * ((gr[0] * L[0] + gr[1] * L[1]) + gr[2] * L[2]);
+            if (m == 0) break;
+            const double prev = sm[m - 1];
+            sbar = (prev > smin && prev < smax) ? tbar : 0.0;
+            if (m == istar) sbar += extra;
+        }
+    }
+    free(tm);
+    free(sm);
+}
+
+/* Decision margins of the pass (as orc_shadow_margin, per pixel and light): r_margin also
+ * covers the triangulation's validity tests (r1, r2, d^2 relative to r2^2, t - y relative
+ * to t, each at every step up to the minimising one). */
+void orc_shadow_margin_ex(const double* fine, orc_grid g, const orc_shadow_ex* s, double* r_margin,
+                          double* s_margin, double* c_margin)
+{
+    const orc_shadow* b = &s->base;
+    const int64_t npix = (int64_t)b->width * b->height;
+#pragma omp parallel
+    {
+        double* tm = (double*)malloc(sizeof(double) * (size_t)b->steps);
+        double* sm = (double*)malloc(sizeof(double) * (size_t)b->steps);
+        double* em = (double*)malloc(sizeof(double) * (size_t)b->steps);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t q = 0; q < npix * s->nlights; ++q) {
+            const int32_t l = (int32_t)(q / npix);
+            const int64_t p = q % npix;
+            const double L[3] = {(double)s->lights[l][0], (double)s->lights[l][1], (double)s->lights[l][2]};
+            double P[3];
+            int istar;
+            orc_pixel_origin(b, (int32_t)(p % b->width), (int32_t)(p / b->width), P);
+            orc_march_ex(fine, g, b, L, orc_shadow_start(s, p, l), s->triangulate, P, tm, sm, &istar);
+            double rmin = HUGE_VAL, rm = HUGE_VAL, sgap = HUGE_VAL, cgap = HUGE_VAL;
+            int mmin = 0;
+            for (int m = 0; m < b->steps; ++m) {
+                em[m] = orc_estimate(b, s->triangulate, tm, sm, m, NULL);
+                if (em[m] < rmin) {
+                    rmin = em[m];
+                    mmin = m;
+                }
+            }
+            for (int m = 0; m < b->steps; ++m)
+                if (m != mmin) rm = fmin(rm, fabs(em[m] - rmin));
+            rm = fmin(rm, fabs(rmin));
+            rm = fmin(rm, fabs(1.0 - rmin));
+            const int last = istar < 0 ? b->steps : istar;
+            if (s->triangulate)
+                for (int m = 1; m < b->steps; ++m) {
+                    const double r1 = sm[m - 1], r2 = sm[m], delta = orc_clamp_step(b, r1);
+                    rm = fmin(rm, fmin(fabs(r1), fabs(r2)));
+                    const double y = (r2 * r2 - r1 * r1 + delta * delta) / (2.0 * delta);
+                    if (r2 != 0.0) rm = fmin(rm, fabs(r2 * r2 - y * y) / (r2 * r2));
+                    rm = fmin(rm, fabs(tm[m] - y) / tm[m]);
+                }
+            for (int m = 0; m < last; ++m)
+                sgap = fmin(sgap, fmin(fabs(sm[m] - (double)b->smin), fabs(sm[m] - (double)b->smax)));
+            for (int m = 0; m <= last && m < b->steps; ++m)
+                for (int a = 0; a < 3; ++a) {
+                    const double c = (P[a] + tm[m] * L[a] - (double)g.org[a]) / (double)g.h - 0.5;
+                    cgap = fmin(cgap, fabs(c - nearbyint(c)));
+                }
+            r_margin[q] = rm;
+            s_margin[q] = sgap;
+            c_margin[q] = cgap;
+        }
+        free(tm);
+        free(sm);
+        free(em);
     }
 }
 
