@@ -33,7 +33,8 @@ def parse():
     p.add_argument("--no-grad", action="store_true", help="skip the gradient-workload measurement")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-objects measurement")
     p.add_argument("--no-two-level", action="store_true", help="skip the two-level (coarse/fine) measurement")
-    p.add_argument("--only", choices=["static", "deform", "grad", "batch", "two_level", "tables"],
+    p.add_argument("--no-dl", action="store_true", help="skip the full shadow pass measurement")
+    p.add_argument("--only", choices=["static", "deform", "grad", "batch", "two_level", "tables", "dl"],
                    help="run one workload alone and print its record (for profiling)")
     p.add_argument("--cpu-sample", type=int, default=4000000,
                    help="masked voxels ray-sampled by the oracle (about 6 s on 16 host cores)")
@@ -274,6 +275,42 @@ def tables_bench(torch, rtsdf, synth, reps=7):
     return out
 
 
+def dl_bench(torch, rtsdf, synth, reps=20):
+    """The full shadow pass (sections 2.5.2, 3.2) over the 128^3 ellipsoid field: three
+    lights, 128 steps capped at 0.05, two-sample triangulation, jittered start; 512^2 forward
+    and adjoint, and a 1920 x 1080 forward.  Medians of `reps` launches (HIP events)."""
+    sc = synth.scene_grad()
+    g = rtsdf.make_grid(sc.dims, sc.org, sc.h)
+    fine = torch.from_numpy(sc.extra["target"].astype("float32")).cuda()
+    out = {"field": "ellipsoid SDF on 128^3", "lights": 3, "steps": 128, "triangulate": True}
+
+    def med(fn):
+        ts = []
+        for it in range(reps + 2):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            if it >= 2:
+                ts.append(a.elapsed_time(b))
+        return statistics.median(ts)
+
+    for w, hgt, bwd in ((512, 512, True), (1920, 1080, False)):
+        p, lights, kw = synth.dl_setup(sc.h, width=w, height=hgt)
+        s = rtsdf.make_shadow_ex(rtsdf.make_shadow(**p), lights, **kw)
+        img = torch.empty(len(lights), hgt, w, device="cuda")
+        fwd_ms = med(lambda: rtsdf.rtsdf_shadow_forward_ex(fine, g, s, img))
+        # pixel-light marches per second (a bounded march may end before its 128 steps)
+        rec = {"fwd_ms": round(fwd_ms, 4), "marches_per_s_fwd": round(len(lights) * w * hgt / (fwd_ms / 1e3), 1)}
+        if bwd:
+            gi = torch.ones_like(img)
+            gf = torch.zeros_like(fine)
+            rec["bwd_ms"] = round(med(lambda: rtsdf.rtsdf_shadow_backward_ex(fine, g, s, gi, gf)), 4)
+        out["%dx%d" % (w, hgt)] = rec
+    return out
+
+
 def grad_bench(torch, rtsdf, synth, reps=20):
     """Gradient workload (icosphere of 20,480 triangles on 128^3, 16 rays, 512^2 soft shadow):
     forward = the SDF chain + shadow image + loss, backward = shadow adjoint + SDF term +
@@ -454,13 +491,13 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n, "copy_calibration_bytes_written": n, "dispatches": 3}))
         return
-    if args.only in ("deform", "grad", "batch", "two_level", "tables"):
+    if args.only in ("deform", "grad", "batch", "two_level", "tables", "dl"):
         fn = {"deform": deform_bench, "grad": grad_bench, "batch": batch_bench, "two_level": two_level_bench,
-              "tables": tables_bench}[args.only]
+              "tables": tables_bench, "dl": dl_bench}[args.only]
         print(json.dumps({args.only: fn(torch, rtsdf, synth)}))
         return
     if args.only == "static":
-        args.no_deform = args.no_grad = args.no_batch = args.no_two_level = True
+        args.no_deform = args.no_grad = args.no_batch = args.no_two_level = args.no_dl = True
     sc = synth.scene_static()
     S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
     N = S.g.n
@@ -523,6 +560,8 @@ def main():
         out["batch"] = batch_bench(torch, rtsdf, synth)
     if not args.no_two_level:
         out["two_level"] = two_level_bench(torch, rtsdf, synth)
+    if not args.no_dl:
+        out["dl"] = dl_bench(torch, rtsdf, synth)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample)
     print(json.dumps(out))

@@ -262,6 +262,49 @@ rtsdf_status rtsdf_shadow_backward(const float* fine, rtsdf_grid g, rtsdf_shadow
                                    const float* grad_img, float* grad_fine, void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * The full shadow pass (sections 2.5.2 and 3.2): several lights in one launch, the start
+ * offset jittered along the light, and optionally the two-sample triangulation of the
+ * closest approach (after Aaltonen 2018).  Image l marches towards lights[l] exactly as
+ * rtsdf_shadow_forward, except:
+ *  - start: t = t0 + jitter * u in binary32, u = (w0 >> 8) * 2^-24 with w0 the first word
+ *    of Philox4x32-10 for counter (b * width + a, frame, l, 0xFFFFFFFF) and key; jitter 0
+ *    starts at t0;
+ *  - triangulate != 0: from the second step on, the estimate k s / t is replaced by the
+ *    closest approach both samples allow: r1 = s_{m-1}, r2 = s_m bound empty spheres one
+ *    step delta = clamp(r1, smin, smax) apart; their intersection circle lies
+ *    y = (r2^2 - r1^2 + delta^2) / (2 delta) behind the later sample with radius
+ *    d = sqrt(r2^2 - y^2), and the estimate is k d / (t_m - y) when r1 > 0, r2 > 0,
+ *    d^2 > 0 and t_m - y > 0, else k r2 / t_m.
+ *  - bounded != 0: the march ends before the first sample point outside the grid's box
+ *    [org, org + n h] (per axis, closed), so that a long march does not keep sampling the
+ *    clamped border of the field (section 2.4 stops beyond the scene bounds).
+ * The adjoint is the reverse march of rtsdf_shadow_backward; triangulated, the minimising
+ * estimate also depends on s_{m*-1} directly and through delta.
+ *   base: receiver lattice, k, steps, step bounds and t0 as rtsdf_shadow (base.light is
+ *         ignored but must be finite); lights: nlights unit directions, 1 <= nlights <= 8;
+ *   jitter >= 0 (world units); img / grad_img [nlights][height][width] float.
+ * s is a HOST pointer.  Errors: as rtsdf_shadow_forward, plus E_RANGE (nlights) and E_ARG
+ * (non-finite light or jitter < 0).
+ * ------------------------------------------------------------------------------------- */
+#define RTSDF_MAX_LIGHTS 8
+
+typedef struct rtsdf_shadow_ex {
+    rtsdf_shadow base;
+    int32_t nlights;
+    float lights[RTSDF_MAX_LIGHTS][3];
+    int32_t triangulate;
+    int32_t bounded;
+    float jitter;
+    uint32_t frame;
+    uint64_t key;
+} rtsdf_shadow_ex;
+
+rtsdf_status rtsdf_shadow_forward_ex(const float* fine, rtsdf_grid g, const rtsdf_shadow_ex* s, float* img,
+                                     void* stream);
+rtsdf_status rtsdf_shadow_backward_ex(const float* fine, rtsdf_grid g, const rtsdf_shadow_ex* s,
+                                      const float* grad_img, float* grad_fine, void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * rtsdf_backward -- derivative of the running-minimum fine field (RTSDF_ACCUM, section
  * 2.1) with respect to vertex positions, the discrete state held fixed (seeds, mask, the
  * argmin ray of each grid point, its closest triangle and the sign).  A masked grid point

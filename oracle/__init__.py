@@ -48,11 +48,11 @@ class ShadowEx(ctypes.Structure):
     """The shadow pass with several lights, a jittered start and optional triangulation;
     base.light is not used."""
     _fields_ = [("base", Shadow), ("nlights", ctypes.c_int32), ("lights", (ctypes.c_float * 3) * MAX_LIGHTS),
-                ("triangulate", ctypes.c_int32), ("jitter", ctypes.c_float), ("frame", ctypes.c_uint32),
-                ("key", ctypes.c_uint64)]
+                ("triangulate", ctypes.c_int32), ("bounded", ctypes.c_int32), ("jitter", ctypes.c_float),
+                ("frame", ctypes.c_uint32), ("key", ctypes.c_uint64)]
 
 
-def make_shadow_ex(base, lights, triangulate=False, jitter=0.0, frame=0, key=0):
+def make_shadow_ex(base, lights, triangulate=False, jitter=0.0, frame=0, key=0, bounded=False):
     s = ShadowEx()
     s.base = base
     s.nlights = len(lights)
@@ -60,6 +60,7 @@ def make_shadow_ex(base, lights, triangulate=False, jitter=0.0, frame=0, key=0):
         for a in range(3):
             s.lights[i][a] = float(l[a])
     s.triangulate, s.jitter, s.frame, s.key = int(bool(triangulate)), float(jitter), int(frame), int(key)
+    s.bounded = int(bool(bounded))
     return s
 
 
@@ -115,7 +116,7 @@ def lib():
         L.orc_shadow_margin.argtypes = [vp, Grid, ctypes.POINTER(Shadow), vp, vp, vp]
         L.orc_shadow_forward_ex.argtypes = [vp, Grid, ctypes.POINTER(ShadowEx), vp]
         L.orc_shadow_backward_ex.argtypes = [vp, Grid, ctypes.POINTER(ShadowEx), vp, vp]
-        L.orc_shadow_margin_ex.argtypes = [vp, Grid, ctypes.POINTER(ShadowEx), vp, vp, vp]
+        L.orc_shadow_margin_ex.argtypes = [vp, Grid, ctypes.POINTER(ShadowEx), vp, vp, vp, vp]
         L.orc_shadow_triangulate.argtypes = [ctypes.c_double] * 5 + [vp]
         L.orc_shadow_triangulate.restype = ctypes.c_double
         _lib = L
@@ -363,13 +364,13 @@ def shadow_backward_ex(fine, g, s, grad_img):
 
 
 def shadow_margin_ex(fine, g, s):
-    """Decision margins of shadow_forward_ex per pixel and light (r, s, c) -- see
+    """Decision margins of shadow_forward_ex per pixel and light (r, s, c, v) -- see
     orc_shadow_margin_ex."""
     f = np.ascontiguousarray(fine, np.float64)
     n = s.nlights * s.base.width * s.base.height
-    rm, sm, cm = np.empty(n), np.empty(n), np.empty(n)
-    lib().orc_shadow_margin_ex(_p(f), g, ctypes.byref(s), _p(rm), _p(sm), _p(cm))
-    return rm, sm, cm
+    rm, sm, cm, vm = np.empty(n), np.empty(n), np.empty(n), np.empty(n)
+    lib().orc_shadow_margin_ex(_p(f), g, ctypes.byref(s), _p(rm), _p(sm), _p(cm), _p(vm))
+    return rm, sm, cm, vm
 
 
 def sdf_backward(grad_fine, hits, argmin, vids, bvh, verts, tris, g, x, seed, obj=0):

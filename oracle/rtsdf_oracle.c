@@ -861,18 +861,37 @@ static double orc_estimate(const orc_shadow* s, int tri, const double* tm, const
     return orc_shadow_triangulate(sm[m - 1], sm[m], orc_clamp_step(s, sm[m - 1]), tm[m], (double)s->k, valid);
 }
 
+/* Whether X lies in the grid's box [org, org + n h] (closed), and its least distance to
+ * the box faces in grid units (positive inside). */
+static int orc_in_box(orc_grid g, const double X[3], double* gap)
+{
+    const int32_t n[3] = {g.nx, g.ny, g.nz};
+    double least = HUGE_VAL;
+    int in = 1;
+    for (int a = 0; a < 3; ++a) {
+        const double c = (X[a] - (double)g.org[a]) / (double)g.h;
+        if (c < 0.0 || c > (double)n[a]) in = 0;
+        least = fmin(least, fmin(fabs(c), fabs((double)n[a] - c)));
+    }
+    if (gap) *gap = least;
+    return in;
+}
+
 /* one pixel's march towards the unit direction l from t = t_start; records t_m and s_m
- * (arrays of s->steps, always given).  Returns the clamped image value; *istar = index of
- * the first step attaining the minimum, or -1 when the value is the initial 1 or is
- * clamped at 0 (no gradient). */
+ * (arrays of s->steps, always given).  bounded: the march ends before the first sample
+ * that lies outside the grid's box (section 2.4: stop beyond the scene bounds); *taken =
+ * the number of samples taken.  Returns the clamped image value; *istar = index of the
+ * first step attaining the minimum, or -1 when the value is the initial 1 or is clamped at
+ * 0 (no gradient). */
 static double orc_march_ex(const double* f, orc_grid g, const orc_shadow* s, const double l[3], double t_start,
-                           int tri, const double P[3], double* tm, double* sm, int* istar)
+                           int tri, int bounded, const double P[3], double* tm, double* sm, int* istar, int* taken)
 {
     double t = t_start, res = 1.0;
-    int best = -1;
-    for (int m = 0; m < s->steps; ++m) {
+    int best = -1, m = 0;
+    for (; m < s->steps; ++m) {
         double X[3];
         for (int a = 0; a < 3; ++a) X[a] = P[a] + t * l[a];
+        if (bounded && !orc_in_box(g, X, NULL)) break;
         const double v = orc_trilinear(f, g, X, NULL);
         tm[m] = t;
         sm[m] = v;
@@ -883,6 +902,7 @@ static double orc_march_ex(const double* f, orc_grid g, const orc_shadow* s, con
         }
         t += orc_clamp_step(s, v);
     }
+    if (taken) *taken = m;
     if (res <= 0.0) {
         *istar = -1;
         return 0.0;
@@ -895,7 +915,7 @@ static double orc_march(const double* f, orc_grid g, const orc_shadow* s, const 
                         double* sm, int* istar)
 {
     const double l[3] = {(double)s->light[0], (double)s->light[1], (double)s->light[2]};
-    return orc_march_ex(f, g, s, l, (double)s->t0, 0, P, tm, sm, istar);
+    return orc_march_ex(f, g, s, l, (double)s->t0, 0, 0, P, tm, sm, istar, NULL);
 }
 
 void orc_shadow_forward(const double* fine, orc_grid g, const orc_shadow* s, double* img)
@@ -1020,6 +1040,7 @@ typedef struct {
     int32_t nlights;
     float lights[ORC_MAX_LIGHTS][3];
     int32_t triangulate;
+    int32_t bounded;                   /* end the march where it leaves the grid's box */
     float jitter;
     uint32_t frame;
     uint64_t key;
@@ -1051,9 +1072,10 @@ void orc_shadow_forward_ex(const double* fine, orc_grid g, const orc_shadow_ex* 
             const int64_t p = q % npix;
             const double L[3] = {(double)s->lights[l][0], (double)s->lights[l][1], (double)s->lights[l][2]};
             double P[3];
-            int istar;
+            int istar, taken;
             orc_pixel_origin(b, (int32_t)(p % b->width), (int32_t)(p / b->width), P);
-            img[q] = orc_march_ex(fine, g, b, L, orc_shadow_start(s, p, l), s->triangulate, P, tm, sm, &istar);
+            img[q] = orc_march_ex(fine, g, b, L, orc_shadow_start(s, p, l), s->triangulate, s->bounded, P, tm, sm,
+                                  &istar, &taken);
         }
         free(tm);
         free(sm);
@@ -1080,9 +1102,10 @@ void orc_shadow_backward_ex(const double* fine, orc_grid g, const orc_shadow_ex*
         const int64_t p = q % npix;
         const double L[3] = {(double)s->lights[l][0], (double)s->lights[l][1], (double)s->lights[l][2]};
         double P[3];
-        int istar;
+        int istar, taken;
         orc_pixel_origin(b, (int32_t)(p % b->width), (int32_t)(p / b->width), P);
-        orc_march_ex(fine, g, b, L, orc_shadow_start(s, p, l), s->triangulate, P, tm, sm, &istar);
+        orc_march_ex(fine, g, b, L, orc_shadow_start(s, p, l), s->triangulate, s->bounded, P, tm, sm, &istar,
+                     &taken);
         if (istar < 0) continue;
         const double gi = grad_img[q];
         double sbar, tbar, extra = 0.0; /* extra: direct adjoint of s_{m*-1} */
@@ -1120,11 +1143,14 @@ void orc_shadow_backward_ex(const double* fine, orc_grid g, const orc_shadow_ex*
     free(sm);
 }
 
-/* Decision margins of the pass (as orc_shadow_margin, per pixel and light): r_margin also
- * covers the triangulation's validity tests (r1, r2, d^2 relative to r2^2, t - y relative
- * to t, each at every step up to the minimising one). */
+/* Decision margins of the pass (as orc_shadow_margin, per pixel and light), plus
+ * v_margin: the least distance of the triangulation's validity tests from flipping at any
+ * step (r1 and r2 from 0 in grid units, d^2 relative to r2^2, t - y relative to t) and, for
+ * a bounded march, of each sample taken and the first sample outside from the grid box's
+ * faces (grid units); +inf when neither applies.  A flipped validity test switches the estimate's formula, so it matters
+ * for the image itself; the other margins only for the adjoint. */
 void orc_shadow_margin_ex(const double* fine, orc_grid g, const orc_shadow_ex* s, double* r_margin,
-                          double* s_margin, double* c_margin)
+                          double* s_margin, double* c_margin, double* v_margin)
 {
     const orc_shadow* b = &s->base;
     const int64_t npix = (int64_t)b->width * b->height;
@@ -1139,34 +1165,47 @@ void orc_shadow_margin_ex(const double* fine, orc_grid g, const orc_shadow_ex* s
             const int64_t p = q % npix;
             const double L[3] = {(double)s->lights[l][0], (double)s->lights[l][1], (double)s->lights[l][2]};
             double P[3];
-            int istar;
+            int istar, taken;
             orc_pixel_origin(b, (int32_t)(p % b->width), (int32_t)(p / b->width), P);
-            orc_march_ex(fine, g, b, L, orc_shadow_start(s, p, l), s->triangulate, P, tm, sm, &istar);
-            double rmin = HUGE_VAL, rm = HUGE_VAL, sgap = HUGE_VAL, cgap = HUGE_VAL;
+            const double t_start = orc_shadow_start(s, p, l);
+            orc_march_ex(fine, g, b, L, t_start, s->triangulate, s->bounded, P, tm, sm, &istar, &taken);
+            double rmin = HUGE_VAL, rm = HUGE_VAL, sgap = HUGE_VAL, cgap = HUGE_VAL, vm = HUGE_VAL;
             int mmin = 0;
-            for (int m = 0; m < b->steps; ++m) {
+            for (int m = 0; m < taken; ++m) {
                 em[m] = orc_estimate(b, s->triangulate, tm, sm, m, NULL);
                 if (em[m] < rmin) {
                     rmin = em[m];
                     mmin = m;
                 }
             }
-            for (int m = 0; m < b->steps; ++m)
+            for (int m = 0; m < taken; ++m)
                 if (m != mmin) rm = fmin(rm, fabs(em[m] - rmin));
             rm = fmin(rm, fabs(rmin));
             rm = fmin(rm, fabs(1.0 - rmin));
-            const int last = istar < 0 ? b->steps : istar;
+            const int last = istar < 0 ? taken : istar;
             if (s->triangulate)
-                for (int m = 1; m < b->steps; ++m) {
+                for (int m = 1; m < taken; ++m) {
                     const double r1 = sm[m - 1], r2 = sm[m], delta = orc_clamp_step(b, r1);
-                    rm = fmin(rm, fmin(fabs(r1), fabs(r2)));
+                    vm = fmin(vm, fmin(fabs(r1), fabs(r2)) / (double)g.h);
                     const double y = (r2 * r2 - r1 * r1 + delta * delta) / (2.0 * delta);
-                    if (r2 != 0.0) rm = fmin(rm, fabs(r2 * r2 - y * y) / (r2 * r2));
-                    rm = fmin(rm, fabs(tm[m] - y) / tm[m]);
+                    if (r2 != 0.0) vm = fmin(vm, fabs(r2 * r2 - y * y) / (r2 * r2));
+                    vm = fmin(vm, fabs(tm[m] - y) / tm[m]);
                 }
+            if (s->bounded) {
+                /* every sample position taken, and the first one outside (if any), from the box faces */
+                double t = t_start;
+                for (int m = 0; m <= taken && m < b->steps; ++m) {
+                    if (m < taken) t = tm[m];
+                    else if (m > 0) t = tm[m - 1] + orc_clamp_step(b, sm[m - 1]);
+                    double X[3], gap;
+                    for (int a = 0; a < 3; ++a) X[a] = P[a] + t * L[a];
+                    orc_in_box(g, X, &gap);
+                    vm = fmin(vm, gap);
+                }
+            }
             for (int m = 0; m < last; ++m)
                 sgap = fmin(sgap, fmin(fabs(sm[m] - (double)b->smin), fabs(sm[m] - (double)b->smax)));
-            for (int m = 0; m <= last && m < b->steps; ++m)
+            for (int m = 0; m <= last && m < taken; ++m)
                 for (int a = 0; a < 3; ++a) {
                     const double c = (P[a] + tm[m] * L[a] - (double)g.org[a]) / (double)g.h - 0.5;
                     cgap = fmin(cgap, fabs(c - nearbyint(c)));
@@ -1174,6 +1213,7 @@ void orc_shadow_margin_ex(const double* fine, orc_grid g, const orc_shadow_ex* s
             r_margin[q] = rm;
             s_margin[q] = sgap;
             c_margin[q] = cgap;
+            v_margin[q] = vm;
         }
         free(tm);
         free(sm);

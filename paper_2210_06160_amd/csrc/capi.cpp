@@ -512,6 +512,45 @@ rtsdf_status rtsdf_shadow_backward(const float* fine, rtsdf_grid g, rtsdf_shadow
     return device(rtsdf::shadow_backward(fine, g, s, grad_img, grad_fine, as_stream(stream)), "shadow_backward");
 }
 
+namespace {
+
+rtsdf_status check_shadow_ex(const rtsdf_shadow_ex* s)
+{
+    if (!s) return fail(RTSDF_E_ARG, "shadow parameters are NULL");
+    if (rtsdf_status st = check_shadow(s->base)) return st;
+    if (s->nlights < 1 || s->nlights > RTSDF_MAX_LIGHTS)
+        return fail(RTSDF_E_RANGE, "nlights %d outside [1, %d]", s->nlights, RTSDF_MAX_LIGHTS);
+    for (int l = 0; l < s->nlights; ++l)
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(s->lights[l][a])) return fail(RTSDF_E_ARG, "light %d is not finite", l);
+    if (!std::isfinite(s->jitter) || s->jitter < 0.0f) return fail(RTSDF_E_ARG, "jitter must be finite and >= 0");
+    return RTSDF_OK;
+}
+
+}  // namespace
+
+rtsdf_status rtsdf_shadow_forward_ex(const float* fine, rtsdf_grid g, const rtsdf_shadow_ex* s, float* img,
+                                     void* stream)
+{
+    if (rtsdf_status st = check_grid(g)) return st;
+    if (rtsdf_status st = check_shadow_ex(s)) return st;
+    const bool empty = s->base.width == 0 || s->base.height == 0;
+    if (!fine || (!img && !empty)) return fail(RTSDF_E_ARG, "NULL pointer");
+    return device(rtsdf::shadow_forward_ex(fine, g, *s, img, as_stream(stream)), "shadow_forward_ex");
+}
+
+rtsdf_status rtsdf_shadow_backward_ex(const float* fine, rtsdf_grid g, const rtsdf_shadow_ex* s,
+                                      const float* grad_img, float* grad_fine, void* stream)
+{
+    if (rtsdf_status st = check_grid(g)) return st;
+    if (rtsdf_status st = check_shadow_ex(s)) return st;
+    const bool empty = s->base.width == 0 || s->base.height == 0;
+    if (!fine || !grad_fine || (!grad_img && !empty)) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (fine == grad_fine) return fail(RTSDF_E_ARG, "fine and grad_fine must not alias");
+    return device(rtsdf::shadow_backward_ex(fine, g, *s, grad_img, grad_fine, as_stream(stream)),
+                  "shadow_backward_ex");
+}
+
 rtsdf_status rtsdf_backward(const float* grad_fine, const uint32_t* hits, const uint64_t* argmin,
                             const int32_t* band_list, const int32_t* band_count, int64_t band_capacity,
                             const void* bvh, const int32_t* tris, int32_t nv, int32_t nt, rtsdf_grid g,

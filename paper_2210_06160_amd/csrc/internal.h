@@ -72,6 +72,10 @@ hipError_t shadow_forward(const float* fine, const rtsdf_grid& g, const rtsdf_sh
                           hipStream_t st);
 hipError_t shadow_backward(const float* fine, const rtsdf_grid& g, const rtsdf_shadow& s,
                            const float* grad_img, float* grad_fine, hipStream_t st);
+hipError_t shadow_forward_ex(const float* fine, const rtsdf_grid& g, const rtsdf_shadow_ex& s, float* img,
+                             hipStream_t st);
+hipError_t shadow_backward_ex(const float* fine, const rtsdf_grid& g, const rtsdf_shadow_ex& s,
+                              const float* grad_img, float* grad_fine, hipStream_t st);
 hipError_t sdf_backward(const float* grad_fine, const uint32_t* hits, const uint64_t* argmin,
                         const int32_t* list, const int32_t* count, int64_t capacity, const void* bvh,
                         const int32_t* tris, const rtsdf_grid& g, int32_t x, uint64_t key, uint32_t obj,

@@ -1,5 +1,8 @@
 // Soft shadows by sphere tracing the fine field (section 2.4) and the reverse pass that
-// carries an image gradient back to the field.
+// carries an image gradient back to the field.  One launch shades every light's image
+// (blockIdx.y is the light); the start offset may be jittered along the light per pixel,
+// light and frame, and the closest-approach estimate may be triangulated from two
+// consecutive samples (section 2.5.2).
 //
 // One wave shades a tile of 64 pixels (8 x 8 unless tuned otherwise): neighbouring shadow rays march through
 // neighbouring cells, so a wave's trilinear gathers share cache lines.  Work-groups are
@@ -12,6 +15,7 @@
 // bit records whether the step clamp was active), then the adjoint runs backwards from the
 // minimising step and scatters into the field with binary32 atomic adds (no return value).
 #include "internal.h"
+#include "sampling.h"
 #include "tuning.h"
 
 namespace rtsdf {
@@ -116,6 +120,45 @@ __device__ inline void scatter(float* __restrict__ gf, const Cell& c, float w)
     unsafeAtomicAdd(p + c.sz + c.sy + c.sx, w * (fx * fy * fz));
 }
 
+// Everything a launch needs besides the field: the receiver lattice and march constants,
+// the lights, and the jitter draw.
+struct March {
+    rtsdf_shadow s;                     // s.light is not used
+    float light[RTSDF_MAX_LIGHTS][3];
+    float jitter;                       // start offset t0 + jitter * u
+    uint32_t frame, k0, k1;             // counter word and key of the jitter draw
+    int32_t bounded;                    // end the march where it leaves the grid's box
+};
+
+// whether X lies in the grid's box [org, org + n h] (closed)
+__device__ inline bool in_box(const rtsdf_grid& g, float inv_h, float3 X)
+{
+    const float cx = (X.x - g.org[0]) * inv_h, cy = (X.y - g.org[1]) * inv_h, cz = (X.z - g.org[2]) * inv_h;
+    return cx >= 0.0f && cx <= (float)g.nx && cy >= 0.0f && cy <= (float)g.ny && cz >= 0.0f && cz <= (float)g.nz;
+}
+
+__device__ inline float clamp_step(const rtsdf_shadow& s, float v) { return fminf(fmaxf(v, s.smin), s.smax); }
+
+// Two-sample estimate of the closest approach: samples r1 and r2 one clamped step delta
+// apart bound empty spheres; their intersection circle lies y behind the later sample with
+// radius d, giving k d / (t - y); without a circle (or behind the start) the one-sample
+// k r2 / t.  Returns the estimate and whether the circle was used.
+__device__ inline float triangulate(float r1, float r2, float delta, float t, float k, bool& valid)
+{
+    const float y = (r2 * r2 - r1 * r1 + delta * delta) / (2.0f * delta);
+    const float d2 = r2 * r2 - y * y;
+    valid = r1 > 0.0f && r2 > 0.0f && d2 > 0.0f && t - y > 0.0f;
+    return valid ? k * sqrtf(d2) / (t - y) : k * r2 / t;
+}
+
+__device__ inline float start_offset(const March& M, int64_t pixel, int light)
+{
+    if (M.jitter == 0.0f) return M.s.t0;
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)pixel, M.frame, (uint32_t)light, 0xFFFFFFFFu), M.k0, M.k1);
+    const float u = (float)(w.x >> 8) * (1.0f / 16777216.0f);
+    return M.s.t0 + M.jitter * u;
+}
+
 __device__ inline bool pixel_of(const rtsdf_shadow& s, int tiles_x, int& a, int& b)
 {
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
@@ -129,91 +172,188 @@ __device__ inline float3 march_point(float3 P, float t, const rtsdf_shadow& s)
     return make_float3(P.x + t * s.light[0], P.y + t * s.light[1], P.z + t * s.light[2]);
 }
 
+template <bool kTri>
 __global__ __launch_bounds__(kTX* kTY) void k_shadow_forward(const float* __restrict__ fine,
-                                                                 const rtsdf_grid g, const rtsdf_shadow s,
+                                                                 const rtsdf_grid g, const March M,
                                                                  float inv_h, int tiles_x,
                                                                  float* __restrict__ img)
 {
+    const rtsdf_shadow& s = M.s;
     int a, b;
     if (!pixel_of(s, tiles_x, a, b)) return;
+    const int l = (int)blockIdx.y;
+    const float3 L = make_float3(M.light[l][0], M.light[l][1], M.light[l][2]);
+    const int64_t pix = (int64_t)b * s.width + a;
     const float3 P = make_float3(s.x0 + ((float)a + 0.5f) * s.dx, s.y, s.z0 + ((float)b + 0.5f) * s.dz);
-    float t = s.t0, res = 1.0f;
+    float t = start_offset(M, pix, l), res = 1.0f, prev = 0.0f;
     for (int m = 0; m < s.steps; ++m) {
-        const Cell c = cell_of(g, inv_h, march_point(P, t, s));
+        const float3 X = make_float3(P.x + t * L.x, P.y + t * L.y, P.z + t * L.z);
+        if (M.bounded && !in_box(g, inv_h, X)) break;
+        const Cell c = cell_of(g, inv_h, X);
         const float v = trilinear(fine, c, inv_h, nullptr);
-        const float r = s.k * v / t;
+        float r;
+        if (kTri && m > 0) {
+            bool valid;
+            r = triangulate(prev, v, clamp_step(s, prev), t, s.k, valid);
+        } else {
+            r = s.k * v / t;
+        }
         res = r < res ? r : res;
-        t += fminf(fmaxf(v, s.smin), s.smax);
+        prev = v;
+        t += clamp_step(s, v);
     }
-    img[(int64_t)b * s.width + a] = res > 0.0f ? res : 0.0f;
+    img[(int64_t)l * s.width * s.height + pix] = res > 0.0f ? res : 0.0f;
 }
 
+template <bool kTri>
 __global__ __launch_bounds__(kTX* kTY) void k_shadow_backward(const float* __restrict__ fine,
-                                                                  const rtsdf_grid g, const rtsdf_shadow s,
+                                                                  const rtsdf_grid g, const March M,
                                                                   float inv_h, int tiles_x,
                                                                   const float* __restrict__ grad_img,
                                                                   float* __restrict__ grad_fine)
 {
     extern __shared__ float s_t[];  // [steps][64]: t_m, negative when clamp(s_m) was active
+    const rtsdf_shadow& s = M.s;
     int a, b;
     if (!pixel_of(s, tiles_x, a, b)) return;
-    const float gi = grad_img[(int64_t)b * s.width + a];
+    const int l = (int)blockIdx.y;
+    const int64_t pix = (int64_t)b * s.width + a;
+    const float gi = grad_img[(int64_t)l * s.width * s.height + pix];
     if (gi == 0.0f) return;
+    const float3 L = make_float3(M.light[l][0], M.light[l][1], M.light[l][2]);
     const int lane = (int)threadIdx.x;
     const float3 P = make_float3(s.x0 + ((float)a + 0.5f) * s.dx, s.y, s.z0 + ((float)b + 0.5f) * s.dz);
-    float t = s.t0, res = 1.0f, s_best = 0.0f, t_best = 1.0f;
+    float t = start_offset(M, pix, l), res = 1.0f, prev = 0.0f;
+    float s_best = 0.0f, s_prev_best = 0.0f, t_best = 1.0f;
+    bool tri_best = false;
     int best = -1;
     for (int m = 0; m < s.steps; ++m) {
-        const Cell c = cell_of(g, inv_h, march_point(P, t, s));
+        const float3 X = make_float3(P.x + t * L.x, P.y + t * L.y, P.z + t * L.z);
+        if (M.bounded && !in_box(g, inv_h, X)) break;
+        const Cell c = cell_of(g, inv_h, X);
         const float v = trilinear(fine, c, inv_h, nullptr);
-        const float r = s.k * v / t;
+        float r;
+        bool valid = false;
+        if (kTri && m > 0)
+            r = triangulate(prev, v, clamp_step(s, prev), t, s.k, valid);
+        else
+            r = s.k * v / t;
         if (r < res) {
             res = r;
             best = m;
             s_best = v;
+            s_prev_best = prev;
             t_best = t;
+            tri_best = valid;
         }
         s_t[m * (kTX * kTY) + lane] = (v > s.smin && v < s.smax) ? t : -t;
-        t += fminf(fmaxf(v, s.smin), s.smax);
+        prev = v;
+        t += clamp_step(s, v);
     }
     if (best < 0 || !(res > 0.0f)) return;
-    // res = k s / t at the minimising step
-    float sbar = gi * s.k / t_best;
-    float tbar = -gi * s.k * s_best / (t_best * t_best);
+    float sbar, tbar, extra = 0.0f;  // extra: direct adjoint of s_{best-1}
+    if (kTri && tri_best) {
+        // res = k D / (T - y), D = sqrt(r2^2 - y^2), y = (r2^2 - r1^2 + delta^2) / (2 delta)
+        const float r1 = s_prev_best, r2 = s_best, T = t_best, delta = clamp_step(s, r1);
+        const float y = (r2 * r2 - r1 * r1 + delta * delta) / (2.0f * delta);
+        const float D = sqrtf(r2 * r2 - y * y);
+        const float dy_r2 = r2 / delta, dy_r1 = -r1 / delta, dy_dl = 1.0f - y / delta;
+        const float dD_r2 = (r2 - y * dy_r2) / D, dD_r1 = -y * dy_r1 / D, dD_dl = -y * dy_dl / D;
+        const float ka = s.k / (T - y), kc = res / (T - y);
+        sbar = gi * (ka * dD_r2 + kc * dy_r2);
+        tbar = -gi * kc;
+        extra = gi * (ka * dD_r1 + kc * dy_r1);
+        if (r1 > s.smin && r1 < s.smax) extra += gi * (ka * dD_dl + kc * dy_dl);
+    } else {
+        sbar = gi * s.k / t_best;
+        tbar = -gi * s.k * s_best / (t_best * t_best);
+    }
     for (int m = best; m >= 0; --m) {
         const float tm = fabsf(s_t[m * (kTX * kTY) + lane]);
-        const Cell c = cell_of(g, inv_h, march_point(P, tm, s));
+        const Cell c = cell_of(g, inv_h, make_float3(P.x + tm * L.x, P.y + tm * L.y, P.z + tm * L.z));
         float3 gr;
         trilinear(fine, c, inv_h, &gr);
         scatter(grad_fine, c, sbar);
-        tbar += sbar * ((gr.x * s.light[0] + gr.y * s.light[1]) + gr.z * s.light[2]);
+        tbar += sbar * ((gr.x * L.x + gr.y * L.y) + gr.z * L.z);
         if (m == 0) break;
         // t_m = t_{m-1} + clamp(s_{m-1}): s_{m-1} receives tbar where the clamp is inactive
         sbar = s_t[(m - 1) * (kTX * kTY) + lane] > 0.0f ? tbar : 0.0f;
+        if (kTri && m == best) sbar += extra;
     }
 }
 
 int tiles(int n, int t) { return (n + t - 1) / t; }
+
+March make_march(const rtsdf_shadow& s, const float (*lights)[3], int32_t nlights, float jitter, uint32_t frame,
+                 uint64_t key, int32_t bounded)
+{
+    March M;
+    M.bounded = bounded;
+    M.s = s;
+    for (int l = 0; l < RTSDF_MAX_LIGHTS; ++l)
+        for (int a = 0; a < 3; ++a) M.light[l][a] = l < nlights ? lights[l][a] : 0.0f;
+    M.jitter = jitter;
+    M.frame = frame;
+    M.k0 = (uint32_t)key;
+    M.k1 = (uint32_t)(key >> 32);
+    return M;
+}
+
+hipError_t forward(const float* fine, const rtsdf_grid& g, const March& M, int32_t nlights, bool tri, float* img,
+                   hipStream_t st)
+{
+    const rtsdf_shadow& s = M.s;
+    if (s.width == 0 || s.height == 0) return hipSuccess;
+    const int tx = tiles(s.width, kTX);
+    const dim3 grid((unsigned)(tx * tiles(s.height, kTY)), (unsigned)nlights);
+    if (tri)
+        k_shadow_forward<true><<<grid, kTX * kTY, 0, st>>>(fine, g, M, 1.0f / g.h, tx, img);
+    else
+        k_shadow_forward<false><<<grid, kTX * kTY, 0, st>>>(fine, g, M, 1.0f / g.h, tx, img);
+    return hipGetLastError();
+}
+
+hipError_t backward(const float* fine, const rtsdf_grid& g, const March& M, int32_t nlights, bool tri,
+                    const float* grad_img, float* grad_fine, hipStream_t st)
+{
+    const rtsdf_shadow& s = M.s;
+    if (s.width == 0 || s.height == 0) return hipSuccess;
+    const int tx = tiles(s.width, kTX);
+    const dim3 grid((unsigned)(tx * tiles(s.height, kTY)), (unsigned)nlights);
+    const size_t lds = sizeof(float) * (size_t)s.steps * kTX * kTY;
+    if (tri)
+        k_shadow_backward<true><<<grid, kTX * kTY, lds, st>>>(fine, g, M, 1.0f / g.h, tx, grad_img, grad_fine);
+    else
+        k_shadow_backward<false><<<grid, kTX * kTY, lds, st>>>(fine, g, M, 1.0f / g.h, tx, grad_img, grad_fine);
+    return hipGetLastError();
+}
 
 }  // namespace
 
 hipError_t shadow_forward(const float* fine, const rtsdf_grid& g, const rtsdf_shadow& s, float* img,
                           hipStream_t st)
 {
-    if (s.width == 0 || s.height == 0) return hipSuccess;
-    const int tx = tiles(s.width, kTX), nb = tx * tiles(s.height, kTY);
-    k_shadow_forward<<<nb, kTX * kTY, 0, st>>>(fine, g, s, 1.0f / g.h, tx, img);
-    return hipGetLastError();
+    return forward(fine, g, make_march(s, &s.light, 1, 0.0f, 0, 0, 0), 1, false, img, st);
 }
 
 hipError_t shadow_backward(const float* fine, const rtsdf_grid& g, const rtsdf_shadow& s,
                            const float* grad_img, float* grad_fine, hipStream_t st)
 {
-    if (s.width == 0 || s.height == 0) return hipSuccess;
-    const int tx = tiles(s.width, kTX), nb = tx * tiles(s.height, kTY);
-    const size_t lds = sizeof(float) * (size_t)s.steps * kTX * kTY;
-    k_shadow_backward<<<nb, kTX * kTY, lds, st>>>(fine, g, s, 1.0f / g.h, tx, grad_img, grad_fine);
-    return hipGetLastError();
+    return backward(fine, g, make_march(s, &s.light, 1, 0.0f, 0, 0, 0), 1, false, grad_img, grad_fine, st);
+}
+
+hipError_t shadow_forward_ex(const float* fine, const rtsdf_grid& g, const rtsdf_shadow_ex& s, float* img,
+                             hipStream_t st)
+{
+    return forward(fine, g, make_march(s.base, s.lights, s.nlights, s.jitter, s.frame, s.key, s.bounded != 0), s.nlights,
+                   s.triangulate != 0, img, st);
+}
+
+hipError_t shadow_backward_ex(const float* fine, const rtsdf_grid& g, const rtsdf_shadow_ex& s,
+                              const float* grad_img, float* grad_fine, hipStream_t st)
+{
+    return backward(fine, g, make_march(s.base, s.lights, s.nlights, s.jitter, s.frame, s.key, s.bounded != 0), s.nlights,
+                    s.triangulate != 0, grad_img, grad_fine, st);
 }
 
 }  // namespace rtsdf

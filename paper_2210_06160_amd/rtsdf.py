@@ -51,6 +51,32 @@ def make_shadow(width, height, x0, z0, dx, dz, y, light, k, steps, smin, smax, t
     return s
 
 
+MAX_LIGHTS = 8
+
+
+class ShadowEx(ctypes.Structure):
+    _fields_ = [("base", Shadow), ("nlights", ctypes.c_int32), ("lights", (ctypes.c_float * 3) * MAX_LIGHTS),
+                ("triangulate", ctypes.c_int32), ("bounded", ctypes.c_int32), ("jitter", ctypes.c_float),
+                ("frame", ctypes.c_uint32), ("key", ctypes.c_uint64)]
+
+
+def make_shadow_ex(base, lights, triangulate=False, jitter=0.0, frame=0, key=0, bounded=False):
+    """The full shadow pass: `base` (a Shadow; its light is ignored) marched towards each of
+    `lights` (unit directions), with a jittered start, optional triangulation, and
+    (bounded) an end where the march leaves the grid's box."""
+    if not 1 <= len(lights) <= MAX_LIGHTS:
+        raise RtsdfError("1 to %d lights" % MAX_LIGHTS)
+    s = ShadowEx()
+    s.base = base
+    s.nlights = len(lights)
+    for i, l in enumerate(lights):
+        for a in range(3):
+            s.lights[i][a] = float(l[a])
+    s.triangulate, s.jitter, s.frame, s.key = int(bool(triangulate)), float(jitter), int(frame), int(key)
+    s.bounded = int(bool(bounded))
+    return s
+
+
 class Object(ctypes.Structure):
     _fields_ = [("g", Grid), ("nv", ctypes.c_int32), ("nt", ctypes.c_int32), ("band_vox", ctypes.c_int32),
                 ("extra_passes", ctypes.c_int32), ("beta", ctypes.c_float), ("bias", ctypes.c_float)]
@@ -99,6 +125,8 @@ def lib():
             "rtsdf_combine_refined": ([vp, vp, vp, Grid, i32, i32, f32, f32, i32, f32, i32, i32, vp, vp, vp], i32),
             "rtsdf_shadow_forward": ([vp, Grid, Shadow, vp, vp], i32),
             "rtsdf_shadow_backward": ([vp, Grid, Shadow, vp, vp, vp], i32),
+            "rtsdf_shadow_forward_ex": ([vp, Grid, ctypes.POINTER(ShadowEx), vp, vp], i32),
+            "rtsdf_shadow_backward_ex": ([vp, Grid, ctypes.POINTER(ShadowEx), vp, vp, vp], i32),
             "rtsdf_backward": ([vp, vp, vp, vp, vp, i64, vp, vp, i32, i32, Grid, i32, u64, u32, vp, vp], i32),
             "rtsdf_batch_plan_bytes": ([i32], sz),
             "rtsdf_batch_plan": ([vp, i32, vp, vp, sz, vp], i32),
@@ -124,7 +152,8 @@ EXPORTED = ["rtsdf_last_error", "rtsdf_abi_version", "rtsdf_voxelize_work_bytes"
             "rtsdf_jfa", "rtsdf_band_work_bytes", "rtsdf_band", "rtsdf_bvh_bytes", "rtsdf_bvh_work_bytes",
             "rtsdf_build_bvh", "rtsdf_reset_accum", "rtsdf_raysample_work_bytes", "rtsdf_raysample",
             "rtsdf_combine", "rtsdf_refine_grid", "rtsdf_band_refined_work_bytes", "rtsdf_band_refined",
-            "rtsdf_combine_refined", "rtsdf_shadow_forward", "rtsdf_shadow_backward", "rtsdf_backward",
+            "rtsdf_combine_refined", "rtsdf_shadow_forward", "rtsdf_shadow_backward", "rtsdf_shadow_forward_ex",
+            "rtsdf_shadow_backward_ex", "rtsdf_backward",
             "rtsdf_batch_plan_bytes", "rtsdf_batch_plan", "rtsdf_batch_upload", "rtsdf_batch_offsets", "rtsdf_voxelize_batched",
             "rtsdf_jfa_batched", "rtsdf_band_batched", "rtsdf_build_bvh_batched", "rtsdf_raysample_batched",
             "rtsdf_combine_batched", "rtsdf_backward_batched"]
@@ -275,6 +304,19 @@ def rtsdf_shadow_backward(fine, grid, shadow, grad_img, grad_fine, stream=None):
     """grad_fine is accumulated into."""
     _check(lib().rtsdf_shadow_backward(_ptr(fine, torch.float32), grid, shadow, _ptr(grad_img, torch.float32),
                                        _ptr(grad_fine, torch.float32), _stream(stream)), "rtsdf_shadow_backward")
+
+
+def rtsdf_shadow_forward_ex(fine, grid, shadow, img, stream=None):
+    """img [nlights, height, width] float32."""
+    _check(lib().rtsdf_shadow_forward_ex(_ptr(fine, torch.float32), grid, ctypes.byref(shadow),
+                                         _ptr(img, torch.float32), _stream(stream)), "rtsdf_shadow_forward_ex")
+
+
+def rtsdf_shadow_backward_ex(fine, grid, shadow, grad_img, grad_fine, stream=None):
+    """grad_fine is accumulated into."""
+    _check(lib().rtsdf_shadow_backward_ex(_ptr(fine, torch.float32), grid, ctypes.byref(shadow),
+                                          _ptr(grad_img, torch.float32), _ptr(grad_fine, torch.float32),
+                                          _stream(stream)), "rtsdf_shadow_backward_ex")
 
 
 def rtsdf_backward(grad_fine, hits, argmin, band_list, band_count, bvh, tris, nv, grid, rays_per_voxel, rng_key,
@@ -607,13 +649,19 @@ class SDF(torch.autograd.Function):
 
 class SoftShadow(torch.autograd.Function):
     """img = SoftShadow.apply(fine, grid, shadow): the soft-shadow image of the fine field
-    (section 2.4), [height, width] float32.  The backward is rtsdf_shadow_backward."""
+    (section 2.4), [height, width] float32 for a Shadow, [nlights, height, width] for a
+    ShadowEx (the full pass).  The backward is rtsdf_shadow_backward(_ex)."""
 
     @staticmethod
     def forward(ctx, fine, grid, shadow):
         fine = fine.detach().contiguous()
-        img = torch.empty(shadow.height, shadow.width, dtype=torch.float32, device=fine.device)
-        rtsdf_shadow_forward(fine, grid, shadow, img)
+        if isinstance(shadow, ShadowEx):
+            img = torch.empty(shadow.nlights, shadow.base.height, shadow.base.width, dtype=torch.float32,
+                              device=fine.device)
+            rtsdf_shadow_forward_ex(fine, grid, shadow, img)
+        else:
+            img = torch.empty(shadow.height, shadow.width, dtype=torch.float32, device=fine.device)
+            rtsdf_shadow_forward(fine, grid, shadow, img)
         ctx.save_for_backward(fine)
         ctx.grid, ctx.shadow = grid, shadow
         return img
@@ -622,7 +670,10 @@ class SoftShadow(torch.autograd.Function):
     def backward(ctx, grad_img):
         (fine,) = ctx.saved_tensors
         grad_fine = torch.zeros_like(fine)
-        rtsdf_shadow_backward(fine, ctx.grid, ctx.shadow, grad_img.contiguous(), grad_fine)
+        if isinstance(ctx.shadow, ShadowEx):
+            rtsdf_shadow_backward_ex(fine, ctx.grid, ctx.shadow, grad_img.contiguous(), grad_fine)
+        else:
+            rtsdf_shadow_backward(fine, ctx.grid, ctx.shadow, grad_img.contiguous(), grad_fine)
         return grad_fine, None, None
 
 

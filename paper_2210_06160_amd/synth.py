@@ -310,6 +310,20 @@ def shadow_setup(h, width=512, height=512, plane_y=0.1, light=(0.35, 1.0, 0.25),
                 light=tuple(float(a) for a in l), k=k, steps=steps, smin=h / 2.0, smax=smax, t0=h)
 
 
+DL_LIGHTS = ((0.35, 1.0, 0.25), (-0.5, 1.0, 0.2), (0.15, 1.0, -0.45))
+
+
+def dl_setup(h, width=512, height=512, steps=128, smax=0.05, frame=0, key=0x5EED5EED):
+    """The full shadow pass (sections 2.5.2, 3.2): the receiver of shadow_setup, three
+    fixed directional lights, 128 steps capped at 0.05, the two-sample triangulation, the
+    start jittered by up to one maximal step, and the march ended where it leaves the field's
+    box.  Returns (base parameters, unit light
+    directions, the pass options)."""
+    p = shadow_setup(h, width=width, height=height, steps=steps, smax=smax)
+    lights = [tuple(float(a) for a in np.asarray(v) / np.linalg.norm(v)) for v in DL_LIGHTS]
+    return p, lights, dict(triangulate=True, jitter=smax, frame=frame, key=key, bounded=True)
+
+
 def scene_grad(dims=(128, 128, 128), subdiv=5, image=512):
     """Differentiation workload: icosphere (subdivision 5: 10,242 vertices, 20,480
     triangles, radius 0.3) centred in the unit cube on a 128^3 grid; offsets 64..1; 2-voxel

@@ -9,8 +9,11 @@ offset jittered along the light, and the two-sample triangulation of the closest
   * the jittered start equals t0 + jitter * u with u from Philox4x32-10 (itself pinned
     against rocRAND), recovered from one-step images of a constant field;
   * several lights equal the single-light calls image by image, forward and adjoint;
-  * the adjoint (triangulated, two lights, jittered) agrees with binary64 central
-    differences pixel by pixel.
+  * a bounded march stops at the grid's box: a constant field's image is the closed form
+    over the samples inside the box (the exit computed from plain ray/box geometry), and a
+    receiver outside the box stays lit;
+  * the adjoint (triangulated, two lights, jittered, bounded or not) agrees with binary64
+    central differences pixel by pixel.
 """
 import numpy as np
 import pytest
@@ -110,6 +113,33 @@ def test_jittered_start(orc):
     assert (starts >= b.t0).all() and (starts < b.t0 + jit + 1e-7).all()
 
 
+def test_bounded_march_constant_field(orc):
+    dims, h = (20, 10, 16), 0.05            # box [0, 1] x [0, 0.5] x [0, 0.8]
+    g = orc.make_grid(dims, (0, 0, 0), h)
+    c, k = 0.3, 0.05
+    b = base(orc, h, 7, 6, steps=200, k=k, y=0.1)
+    L = unit((0.35, 1.0, 0.25))
+    s = orc.make_shadow_ex(b, [L], bounded=True)
+    img = orc.shadow_forward_ex(np.full(np.prod(dims), c), g, s).reshape(6, 7)
+    smax = float(b.smax)
+    hi = np.array(dims) * h
+    for bb in range(6):
+        for a in range(7):
+            P = np.array([(a + 0.5) * float(b.dx), float(b.y), (bb + 0.5) * float(b.dz)])
+            t = float(b.t0) + smax * np.arange(200)            # every step is capped (c > smax)
+            X = P[None, :] + t[:, None] * L[None, :]
+            inside = ((X >= 0) & (X <= hi)).all(1)
+            n = int(np.argmin(inside)) if not inside.all() else 200
+            want = min(1.0, (float(b.k) * c / t[:n]).min()) if n else 1.0
+            assert img[bb, a] == pytest.approx(want, rel=1e-12), (a, bb, n)
+    # unbounded, the same march keeps sampling the clamped border and darkens
+    u = orc.shadow_forward_ex(np.full(np.prod(dims), c), g, orc.make_shadow_ex(b, [L]))
+    assert u.max() < img.min()
+    # a receiver outside the box: no sample is taken, the pixel stays lit
+    out = base(orc, h, 3, 3, steps=50, y=0.9)
+    assert (orc.shadow_forward_ex(np.full(np.prod(dims), 0.001), g, orc.make_shadow_ex(out, [L], bounded=True)) == 1).all()
+
+
 def sphere_field(dims, h, C, R):
     nx, ny, nz = dims
     k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
@@ -141,13 +171,14 @@ def test_lights_equal_single_light_calls(orc, tri):
     assert 0.0 < img.mean() < 1.0
 
 
-def test_adjoint_matches_central_differences(orc):
+@pytest.mark.parametrize("bounded", [False, True])
+def test_adjoint_matches_central_differences(orc, bounded):
     dims, h = (36, 36, 36), 1.0 / 36
     g = orc.make_grid(dims, (0, 0, 0), h)
     f = sphere_field(dims, h, (0.5, 0.45, 0.52), 0.17)
     b = base(orc, h, 40, 40, steps=96)
     s = orc.make_shadow_ex(b, [unit((0.35, 1.0, 0.25)), unit((-0.3, 1.0, 0.2))], triangulate=True,
-                           jitter=0.02, frame=3, key=77)
+                           jitter=0.02, frame=3, key=77, bounded=bounded)
     rng = np.random.default_rng(5)
     delta = rng.normal(size=f.size)
     img = orc.shadow_forward_ex(f, g, s)
