@@ -44,7 +44,7 @@ def parse():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "raysample_static_400x200x400_counters.md")
-TRAFFIC_SOURCES = ["raysample.hip", "traverse.h", "sampling.h", "lbvh.hip", "internal.h"]
+TRAFFIC_SOURCES = ["raysample.hip", "traverse.h", "sampling.h", "lbvh.hip", "layout.h", "tuning.h"]
 
 
 def recorded_traffic():
