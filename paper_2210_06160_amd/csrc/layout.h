@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include "../../include/rtsdf.h"
+#include "tuning.h"
 
 namespace rtsdf {
 
@@ -110,7 +111,7 @@ __host__ __device__ inline int32_t jfa_offset(int32_t k0, int32_t nhalf, int32_t
 // kBvhEmptySlot an unused slot, any other c < 0 a leaf range ~c = first | (count-1) << 26
 // of `count` (1..kLeafMax) consecutive triangles in sorted order.
 constexpr int32_t kBvhEmptySlot = (int32_t)0x80000000;
-constexpr int kLeafMax = 3;
+constexpr int kLeafMax = RTSDF_LEAF_MAX;
 
 struct BvhHeader {
     int32_t nt;

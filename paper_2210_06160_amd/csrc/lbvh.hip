@@ -30,7 +30,7 @@ namespace {
 
 constexpr int kSortThreads = 256;
 constexpr int kSortRounds = kBvhSortTile / kSortThreads;
-constexpr int kPlocRadius = 16;
+constexpr int kPlocRadius = RTSDF_PLOC_RADIUS;
 constexpr int kPlocThreads = 256;
 constexpr int kPlocWide = 24;
 constexpr int kFinishThreads = 1024;

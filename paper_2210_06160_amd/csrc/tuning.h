@@ -37,3 +37,12 @@
 #ifndef RTSDF_SHADOW_TILE_X
 #define RTSDF_SHADOW_TILE_X 4
 #endif
+
+// hierarchy shape: most triangles in a leaf of the 4-wide tree, and the PLOC neighbourhood
+// radius (positions searched on each side for a cluster's nearest neighbour)
+#ifndef RTSDF_LEAF_MAX
+#define RTSDF_LEAF_MAX 3
+#endif
+#ifndef RTSDF_PLOC_RADIUS
+#define RTSDF_PLOC_RADIUS 16
+#endif

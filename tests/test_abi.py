@@ -174,3 +174,35 @@ def test_refined_grid_and_validation(L, orc):
     assert c(fake(), fake(), fake(), g, 2, 2, 0.0, 0.0, 1, 0.9, 1, 0, None, fake(), None) == E_ARG
     assert c(fake(), fake(), fake(), g, 200, 2, 0.0, 0.0, 0, 0.9, 1, 0, None, fake(), None) == E_RANGE
     assert c(fake(), fake(), fake(), g, 2, 2, float("nan"), 0.0, 0, 0.9, 1, 0, None, fake(), None) == E_ARG
+
+
+def test_host_validation_shadow_ex(L):
+    """The full shadow pass rejects bad parameters on the host."""
+    import ctypes as C
+    lib = L.lib()
+    g = L.make_grid((8, 8, 8), (0, 0, 0), 0.1)
+    E_ARG, E_RANGE = -1, -2
+    base = shadow_params(L)
+    light = (0.0, 1.0, 0.0)
+
+    def run(s, img=fake(0x2000)):
+        return lib.rtsdf_shadow_forward_ex(fake(), g, C.byref(s), img, None)
+
+    assert lib.rtsdf_shadow_forward_ex(fake(), g, None, fake(0x2000), None) == E_ARG
+    s = L.make_shadow_ex(base, [light])
+    s.nlights = 0
+    assert run(s) == E_RANGE
+    s.nlights = L.MAX_LIGHTS + 1
+    assert run(s) == E_RANGE
+    s = L.make_shadow_ex(base, [light, (float("nan"), 1.0, 0.0)])
+    assert run(s) == E_ARG
+    s = L.make_shadow_ex(base, [light], jitter=-0.1)
+    assert run(s) == E_ARG
+    s = L.make_shadow_ex(shadow_params(L, steps=0), [light])
+    assert run(s) == E_RANGE
+    s = L.make_shadow_ex(base, [light])
+    assert lib.rtsdf_shadow_forward_ex(None, g, C.byref(s), fake(0x2000), None) == E_ARG
+    assert lib.rtsdf_shadow_backward_ex(fake(), g, C.byref(s), fake(0x2000), fake(), None) == E_ARG  # aliases fine
+    assert lib.rtsdf_shadow_backward_ex(fake(), g, C.byref(s), None, fake(0x3000), None) == E_ARG
+    with pytest.raises(L.RtsdfError):
+        L.make_shadow_ex(base, [])
