@@ -1,18 +1,22 @@
 // One jump-flooding pass (section 2.2) over packed int32 seed ids.
 //
-// Query order: the stored seed first (rank 0), then the 26 offsets e in {-1,0,1}^3 \ {0}
-// in the order ez, ey, ex ascending (ranks 1..26).  A later query replaces the incumbent
-// only when strictly closer, which is the same as taking the minimum of (d2, rank).
+// Query order: the stored seed first, then the 26 offsets e in {-1,0,1}^3 \ {0} in the
+// order ez, ey, ex ascending.  A later query replaces the incumbent only when strictly
+// closer, which is the same as taking the minimum of (d2, rank) for any rank that is
+// increasing in that order: here rank 0 for the stored seed and 1 + L for the others,
+// L = 9 (ez+1) + 3 (ey+1) + (ex+1) (so 1..13 and 15..27).
 //
 // Kernel: each thread owns one (x, y) column and walks the z positions of one residue
 // class z = r + m*k (the only planes a pass with offset k couples), holding the 3 x 3
 // neighbourhoods of planes m-1, m, m+1 in registers, so each output loads one new plane
-// (9 values) instead of 27.  For every loaded seed s the thread precomputes
-//     w = (sx - px)^2 + (sy - py)^2 + sz^2,
-// and for output z = pz a candidate's key is the signed 32-bit value
-//     key = (w - 2 pz sz) * 32 + rank = (d2 - pz^2) * 32 + rank,
-// an order-preserving image of (d2, rank) (one v_mad_i32_i24 and one v_lshl_add_u32),
-// reduced with v_min3_i32.  The winner's id is reloaded from its (recently cached)
+// (9 values) instead of 27.  For every loaded seed s at column slot q = 3 (ey+1) + (ex+1)
+// the thread precomputes
+//     W = ((sx - px)^2 + (sy - py)^2 + sz^2) * 32 + 1 + q,
+// and for output z = pz a candidate from plane ez has the signed 32-bit key
+//     W + sz * (-64 pz) + 9 (ez+1) = (d2 - pz^2) * 32 + rank,
+// an order-preserving image of (d2, rank): one v_mad_i32_i24 per candidate, each plane's
+// nine keys reduced with v_min3_i32 before its rank offset 9 (ez+1) is added once (the
+// stored seed takes its mid-plane key minus 1 + 4, i.e. rank 0).  The winner's id is reloaded from its (recently cached)
 // position (the offset of each rank for the pass's k comes from a small LDS table, and the
 // nine gathers of a plane are buffer loads off a scalar plane base).  EMPTY (-1) unpacks to (1023, 1023, 4095), which makes w - 2 pz sz >= 8.39e6
 // > any real d2 (<= 3 * 1023^2), so it never wins against a seed; out-of-grid queries load
@@ -31,7 +35,7 @@ constexpr int64_t kFewBlocks = 2048;           // below this many blocks, use kC
 constexpr int32_t kEmptyV = 8000000;  // v >= this only for EMPTY
 
 struct Cand {
-    int32_t w;   // (sx-px)^2 + (sy-py)^2 + sz^2
+    int32_t W;   // ((sx-px)^2 + (sy-py)^2 + sz^2) * 32 + 1 + q
     int32_t sz;
 };
 
@@ -39,35 +43,30 @@ typedef short short2_t __attribute__((ext_vector_type(2)));
 
 // (dx, dy) as packed int16 (|d| <= 1023) so that dx^2 + dy^2 + sz^2 is one v_dot2c_i32_i16
 // on top of sz^2; all other factors are below 2^23, so the 24-bit multiplier is exact.
-__device__ inline Cand prep(int32_t s, short2_t pxy)
+__device__ inline Cand prep(int32_t s, short2_t pxy, int32_t q)
 {
     const uint32_t u = (uint32_t)s;
     const int32_t sz = (int32_t)(u >> 20);
     const short2_t sxy = __builtin_bit_cast(short2_t, (u & 1023u) | (((u >> 10) & 1023u) << 16));
     const short2_t d = sxy - pxy;
-    return Cand{__builtin_amdgcn_sdot2(d, d, __mul24(sz, sz), false), sz};
+    return Cand{__builtin_amdgcn_sdot2(d, d, __mul24(sz, sz), false) * 32 + (1 + q), sz};
 }
 
-__device__ inline int32_t cand_key(Cand c, int32_t m2pz, int32_t rank)
-{
-    return (c.w + __mul24(c.sz, m2pz)) * 32 + rank;
-}
+__device__ inline int32_t cand_key(Cand c, int32_t m64pz) { return c.W + __mul24(c.sz, m64pz); }
 
-// query rank of offset (ex, ey, ez): self 0, others their position in (ez, ey, ex) order
-__host__ __device__ constexpr int32_t rank_of(int ex, int ey, int ez)
+__device__ inline int32_t min9(const int32_t* k)
 {
-    return (ex == 0 && ey == 0 && ez == 0) ? 0
-           : (9 * (ez + 1) + 3 * (ey + 1) + (ex + 1)) < 13 ? 9 * (ez + 1) + 3 * (ey + 1) + (ex + 1) + 1
-                                                             : 9 * (ez + 1) + 3 * (ey + 1) + (ex + 1);
+    return min(min(min(k[0], k[1]), k[2]), min(min(min(k[3], k[4]), k[5]), min(min(k[6], k[7]), k[8])));
 }
 
 // element offset, relative to the output point, of the query that rank rk names, for
-// offset k (the winner's id is reloaded from there); built once per work-group in LDS
+// offset k (the winner's id is reloaded from there); built once per work-group in LDS:
+// rank 0 is the point itself, rank 1 + L the query L = 9 (ez+1) + 3 (ey+1) + (ex+1)
 __device__ inline void rank_table(int32_t* tab, int32_t nx, int32_t ny, int32_t k)
 {
     const int t = threadIdx.x + threadIdx.y * kBX;
-    if (t < 27) {
-        const int32_t L = t == 0 ? 13 : (t <= 13 ? t - 1 : t);
+    if (t < 28) {
+        const int32_t L = t == 0 ? 13 : t - 1;
         const int32_t ez = L / 9 - 1, ey = (L / 3) % 3 - 1, ex = L % 3 - 1;
         tab[t] = ex * k + ey * k * nx + ez * k * (nx * ny);
     }
@@ -121,26 +120,24 @@ __device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             const int32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off[q], 0, 0);
-            dst[q] = prep(ok[q] && pv ? v : RTSDF_EMPTY, pxy);
+            dst[q] = prep(ok[q] && pv ? v : RTSDF_EMPTY, pxy, q);
         }
     };
     const uint32_t pxy_idx = (uint32_t)x + (uint32_t)nx * (uint32_t)y;
     // output for lattice point m from planes m-1 (lo), m (mid), m+1 (hi)
     auto emit = [&](int32_t m, const Cand* lo, const Cand* mid, const Cand* hi) {
         const int32_t pz = r + m * k;
-        const int32_t m2pz = -2 * pz;
-        const Cand* P[3] = {lo, mid, hi};
-        int32_t best = 0x7FFFFFFF;
+        const int32_t m64pz = -64 * pz;
+        int32_t a[9], b[9], c[9];
 #pragma unroll
-        for (int ez = -1; ez <= 1; ++ez)
-#pragma unroll
-            for (int ey = -1; ey <= 1; ++ey) {
-                const int q = 3 * (ey + 1);
-                const int32_t a = cand_key(P[ez + 1][q], m2pz, rank_of(-1, ey, ez));
-                const int32_t b = cand_key(P[ez + 1][q + 1], m2pz, rank_of(0, ey, ez));
-                const int32_t d = cand_key(P[ez + 1][q + 2], m2pz, rank_of(1, ey, ez));
-                best = min(best, min(min(a, b), d));
-            }
+        for (int q = 0; q < 9; ++q) {
+            a[q] = cand_key(lo[q], m64pz);
+            b[q] = cand_key(mid[q], m64pz);
+            c[q] = cand_key(hi[q], m64pz);
+        }
+        const int32_t self = b[4] - 5;  // the stored seed: rank 0 instead of 1 + 4
+        const int32_t mid8 = min(min(min(b[0], b[1]), b[2]), min(min(b[3], b[5]), min(min(b[6], b[7]), b[8])));
+        const int32_t best = min(min(min9(a), mid8 + 9), min(min9(c) + 18, self));
         const uint32_t p = pxy_idx + plane * (uint32_t)pz;
         int32_t id = RTSDF_EMPTY;
         if ((best >> 5) < kEmptyV) id = in[(uint32_t)((int32_t)p + tab[best & 31])];
