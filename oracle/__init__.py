@@ -117,6 +117,10 @@ def lib():
         L.orc_shadow_forward_ex.argtypes = [vp, Grid, ctypes.POINTER(ShadowEx), vp]
         L.orc_shadow_backward_ex.argtypes = [vp, Grid, ctypes.POINTER(ShadowEx), vp, vp]
         L.orc_shadow_margin_ex.argtypes = [vp, Grid, ctypes.POINTER(ShadowEx), vp, vp, vp, vp]
+        L.orc_clipmap_sample.argtypes = [vp, vp, vp, i32, vp, i64, vp, vp]
+        L.orc_shadow_forward_clip.argtypes = [vp, vp, vp, i32, ctypes.POINTER(ShadowEx), vp]
+        L.orc_shadow_backward_clip.argtypes = [vp, vp, vp, i32, ctypes.POINTER(ShadowEx), vp, vp]
+        L.orc_shadow_margin_clip.argtypes = [vp, vp, vp, i32, ctypes.POINTER(ShadowEx), vp, vp, vp, vp]
         L.orc_shadow_triangulate.argtypes = [ctypes.c_double] * 5 + [vp]
         L.orc_shadow_triangulate.restype = ctypes.c_double
         _lib = L
@@ -337,6 +341,72 @@ def shadow_margin(fine, g, s):
     cm = np.empty(s.width * s.height, np.float64)
     lib().orc_shadow_margin(_p(f), g, ctypes.byref(s), _p(rm), _p(sm), _p(cm))
     return rm, sm, cm
+
+
+def clipmap_levels(camera, h0, n, levels):
+    """Grids of a clip map around `camera`: level l has n^3 points of size h0 * 2^l, its
+    origin the camera's voxel of that level minus n/2 voxels on every axis (binary32:
+    (floor(c / h) - n/2) * h), so that each level is fixed while the camera stays in one
+    of its voxels, and each level's box lies inside the next one's (n >= 4, even)."""
+    out = []
+    for l in range(levels):
+        h = np.float32(h0) * np.float32(2.0 ** l)
+        org = [np.float32((np.floor(np.float32(c) / h) - np.float32(n // 2)) * h) for c in camera]
+        out.append(make_grid((n, n, n), org, h))
+    return out
+
+
+def _levels(grids, fields):
+    off = np.zeros(len(grids), np.int64)
+    total = 0
+    for l, g in enumerate(grids):
+        off[l] = total
+        total += nvox(g)
+    f = np.ascontiguousarray(np.concatenate([np.asarray(x, np.float64).ravel() for x in fields]), np.float64)
+    assert len(f) == total
+    G = (Grid * len(grids))(*grids)
+    return f, off, G
+
+
+def clipmap_sample(grids, fields, X):
+    """Values of a clip map (levels finest first, fields[l] on grids[l]) at points X [n, 3]:
+    each point reads the finest level whose box of grid-point centres holds it, else the
+    coarsest; returns (values, level of each point)."""
+    f, off, G = _levels(grids, fields)
+    X = np.ascontiguousarray(X, np.float64).reshape(-1, 3)
+    val = np.empty(len(X))
+    lev = np.empty(len(X), np.int32)
+    lib().orc_clipmap_sample(_p(f), _p(off), ctypes.cast(G, ctypes.c_void_p), len(grids), _p(X), len(X), _p(val),
+                             _p(lev))
+    return val, lev
+
+
+def shadow_forward_clip(grids, fields, s):
+    """shadow_forward_ex over a clip map (a bounded march ends at the coarsest level's box)."""
+    f, off, G = _levels(grids, fields)
+    img = np.empty(s.nlights * s.base.width * s.base.height)
+    lib().orc_shadow_forward_clip(_p(f), _p(off), ctypes.cast(G, ctypes.c_void_p), len(grids), ctypes.byref(s),
+                                  _p(img))
+    return img
+
+
+def shadow_backward_clip(grids, fields, s, grad_img):
+    """(d img / d fields)^T grad_img over a clip map: the concatenated fields' gradient."""
+    f, off, G = _levels(grids, fields)
+    gi = np.ascontiguousarray(grad_img, np.float64)
+    gf = np.zeros(len(f))
+    lib().orc_shadow_backward_clip(_p(f), _p(off), ctypes.cast(G, ctypes.c_void_p), len(grids), ctypes.byref(s),
+                                   _p(gi), _p(gf))
+    return gf
+
+
+def shadow_margin_clip(grids, fields, s):
+    f, off, G = _levels(grids, fields)
+    n = s.nlights * s.base.width * s.base.height
+    rm, sm, cm, vm = np.empty(n), np.empty(n), np.empty(n), np.empty(n)
+    lib().orc_shadow_margin_clip(_p(f), _p(off), ctypes.cast(G, ctypes.c_void_p), len(grids), ctypes.byref(s),
+                                 _p(rm), _p(sm), _p(cm), _p(vm))
+    return rm, sm, cm, vm
 
 
 def shadow_triangulate(r1, r2, delta, t, k):

@@ -877,22 +877,80 @@ static int orc_in_box(orc_grid g, const double X[3], double* gap)
     return in;
 }
 
+/* ------------------------------------------------------------------------------------
+ * The field a march samples: one grid (L = 1), or the levels of a clip map, finest first
+ * (level l's values start at f + off[l]).  A clip map is the multi-resolution field around
+ * a camera that the paper proposes for large scenes: the reading used is that a point reads
+ * the finest level whose box of grid-point centres holds it (grid coordinate
+ * (X - org)/h - 1/2 in [0, n-1] on every axis), and the coarsest level (clamped) when none
+ * does.  *gap (when given) is the least distance, in the grid units of each level tested
+ * before the choice, of X from the box faces that decided it (+inf with one level).
+ * ---------------------------------------------------------------------------------- */
+typedef struct {
+    const double* f;
+    const int64_t* off;
+    const orc_grid* g;
+    int L;
+} orc_field;
+
+static int orc_field_level(const orc_field* F, const double X[3], double* gap)
+{
+    double least = HUGE_VAL;
+    int l = 0;
+    for (; l < F->L - 1; ++l) {
+        const orc_grid* g = &F->g[l];
+        const int32_t n[3] = {g->nx, g->ny, g->nz};
+        int in = 1;
+        for (int a = 0; a < 3; ++a) {
+            const double c = (X[a] - (double)g->org[a]) / (double)g->h - 0.5;
+            if (c < 0.0 || c > (double)(n[a] - 1)) in = 0;
+            least = fmin(least, fmin(fabs(c), fabs((double)(n[a] - 1) - c)));
+        }
+        if (in) break;
+    }
+    if (gap) *gap = least;
+    return l;
+}
+
+static double orc_field_sample(const orc_field* F, const double X[3], double grad[3])
+{
+    const int l = orc_field_level(F, X, NULL);
+    return orc_trilinear(F->f + F->off[l], F->g[l], X, grad);
+}
+
+static void orc_field_scatter(double* gf, const orc_field* F, const double X[3], double w)
+{
+    const int l = orc_field_level(F, X, NULL);
+    orc_trilinear_scatter(gf + F->off[l], F->g[l], X, w);
+}
+
+/* values of a clip map (or one grid) at n points X[3 n]; level[q] = the level read */
+void orc_clipmap_sample(const double* f, const int64_t* off, const orc_grid* g, int32_t L, const double* X, int64_t n,
+                        double* val, int32_t* level)
+{
+    const orc_field F = {f, off, g, L};
+    for (int64_t q = 0; q < n; ++q) {
+        if (level) level[q] = orc_field_level(&F, X + 3 * q, NULL);
+        val[q] = orc_field_sample(&F, X + 3 * q, NULL);
+    }
+}
+
 /* one pixel's march towards the unit direction l from t = t_start; records t_m and s_m
  * (arrays of s->steps, always given).  bounded: the march ends before the first sample
  * that lies outside the grid's box (section 2.4: stop beyond the scene bounds); *taken =
  * the number of samples taken.  Returns the clamped image value; *istar = index of the
  * first step attaining the minimum, or -1 when the value is the initial 1 or is clamped at
  * 0 (no gradient). */
-static double orc_march_ex(const double* f, orc_grid g, const orc_shadow* s, const double l[3], double t_start,
-                           int tri, int bounded, const double P[3], double* tm, double* sm, int* istar, int* taken)
+static double orc_march_ex(const orc_field* F, const orc_shadow* s, const double l[3], double t_start, int tri,
+                           int bounded, const double P[3], double* tm, double* sm, int* istar, int* taken)
 {
     double t = t_start, res = 1.0;
     int best = -1, m = 0;
     for (; m < s->steps; ++m) {
         double X[3];
         for (int a = 0; a < 3; ++a) X[a] = P[a] + t * l[a];
-        if (bounded && !orc_in_box(g, X, NULL)) break;
-        const double v = orc_trilinear(f, g, X, NULL);
+        if (bounded && !orc_in_box(F->g[F->L - 1], X, NULL)) break;
+        const double v = orc_field_sample(F, X, NULL);
         tm[m] = t;
         sm[m] = v;
         const double r = orc_estimate(s, tri, tm, sm, m, NULL);
@@ -915,7 +973,9 @@ static double orc_march(const double* f, orc_grid g, const orc_shadow* s, const 
                         double* sm, int* istar)
 {
     const double l[3] = {(double)s->light[0], (double)s->light[1], (double)s->light[2]};
-    return orc_march_ex(f, g, s, l, (double)s->t0, 0, 0, P, tm, sm, istar, NULL);
+    const int64_t zero = 0;
+    const orc_field F = {f, &zero, &g, 1};
+    return orc_march_ex(&F, s, l, (double)s->t0, 0, 0, P, tm, sm, istar, NULL);
 }
 
 void orc_shadow_forward(const double* fine, orc_grid g, const orc_shadow* s, double* img)
@@ -1058,7 +1118,7 @@ static double orc_shadow_start(const orc_shadow_ex* s, int64_t pixel, int32_t l)
     return (double)(float)(s->base.t0 + ju);
 }
 
-void orc_shadow_forward_ex(const double* fine, orc_grid g, const orc_shadow_ex* s, double* img)
+static void orc_shadow_forward_field(const orc_field* F, const orc_shadow_ex* s, double* img)
 {
     const orc_shadow* b = &s->base;
     const int64_t npix = (int64_t)b->width * b->height;
@@ -1074,8 +1134,8 @@ void orc_shadow_forward_ex(const double* fine, orc_grid g, const orc_shadow_ex* 
             double P[3];
             int istar, taken;
             orc_pixel_origin(b, (int32_t)(p % b->width), (int32_t)(p / b->width), P);
-            img[q] = orc_march_ex(fine, g, b, L, orc_shadow_start(s, p, l), s->triangulate, s->bounded, P, tm, sm,
-                                  &istar, &taken);
+            img[q] = orc_march_ex(F, b, L, orc_shadow_start(s, p, l), s->triangulate, s->bounded, P, tm, sm, &istar,
+                                  &taken);
         }
         free(tm);
         free(sm);
@@ -1088,8 +1148,8 @@ void orc_shadow_forward_ex(const double* fine, orc_grid g, const orc_shadow_ex* 
  * scattered to its 8 grid points, t_m's adjoint gains s_m's adjoint times grad s . l, and
  * t_m = t_{m-1} + clamp(s_{m-1}) hands t_m's adjoint to s_{m-1} strictly inside
  * [smin, smax] (and to t_{m-1} always). */
-void orc_shadow_backward_ex(const double* fine, orc_grid g, const orc_shadow_ex* s, const double* grad_img,
-                            double* grad_fine)
+static void orc_shadow_backward_field(const orc_field* F, const orc_shadow_ex* s, const double* grad_img,
+                                      double* grad_fine)
 {
     const orc_shadow* b = &s->base;
     const int64_t npix = (int64_t)b->width * b->height;
@@ -1104,8 +1164,7 @@ void orc_shadow_backward_ex(const double* fine, orc_grid g, const orc_shadow_ex*
         double P[3];
         int istar, taken;
         orc_pixel_origin(b, (int32_t)(p % b->width), (int32_t)(p / b->width), P);
-        orc_march_ex(fine, g, b, L, orc_shadow_start(s, p, l), s->triangulate, s->bounded, P, tm, sm, &istar,
-                     &taken);
+        orc_march_ex(F, b, L, orc_shadow_start(s, p, l), s->triangulate, s->bounded, P, tm, sm, &istar, &taken);
         if (istar < 0) continue;
         const double gi = grad_img[q];
         double sbar, tbar, extra = 0.0; /* extra: direct adjoint of s_{m*-1} */
@@ -1130,8 +1189,8 @@ void orc_shadow_backward_ex(const double* fine, orc_grid g, const orc_shadow_ex*
         for (int m = istar; m >= 0; --m) {
             double X[3], gr[3];
             for (int a = 0; a < 3; ++a) X[a] = P[a] + tm[m] * L[a];
-            orc_trilinear(fine, g, X, gr);
-            orc_trilinear_scatter(grad_fine, g, X, sbar);
+            orc_field_sample(F, X, gr);
+            orc_field_scatter(grad_fine, F, X, sbar);
             tbar += sbar * ((gr[0] * L[0] + gr[1] * L[1]) + gr[2] * L[2]);
             if (m == 0) break;
             const double prev = sm[m - 1];
@@ -1145,12 +1204,14 @@ void orc_shadow_backward_ex(const double* fine, orc_grid g, const orc_shadow_ex*
 
 /* Decision margins of the pass (as orc_shadow_margin, per pixel and light), plus
  * v_margin: the least distance of the triangulation's validity tests from flipping at any
- * step (r1 and r2 from 0 in grid units, d^2 relative to r2^2, t - y relative to t) and, for
- * a bounded march, of each sample taken and the first sample outside from the grid box's
- * faces (grid units); +inf when neither applies.  A flipped validity test switches the estimate's formula, so it matters
- * for the image itself; the other margins only for the adjoint. */
-void orc_shadow_margin_ex(const double* fine, orc_grid g, const orc_shadow_ex* s, double* r_margin,
-                          double* s_margin, double* c_margin, double* v_margin)
+ * step (r1 and r2 from 0 in grid units of the coarsest level, d^2 relative to r2^2, t - y
+ * relative to t), for a bounded march of each sample taken and the first sample outside
+ * from the box faces, and with several levels of each sample from the level boxes that
+ * chose its level (grid units); +inf when none applies.  A flipped validity test, exit or
+ * level choice changes the image discontinuously, so v_margin matters for the image
+ * itself; the other margins only for the adjoint. */
+static void orc_shadow_margin_field(const orc_field* F, const orc_shadow_ex* s, double* r_margin, double* s_margin,
+                                    double* c_margin, double* v_margin)
 {
     const orc_shadow* b = &s->base;
     const int64_t npix = (int64_t)b->width * b->height;
@@ -1168,7 +1229,7 @@ void orc_shadow_margin_ex(const double* fine, orc_grid g, const orc_shadow_ex* s
             int istar, taken;
             orc_pixel_origin(b, (int32_t)(p % b->width), (int32_t)(p / b->width), P);
             const double t_start = orc_shadow_start(s, p, l);
-            orc_march_ex(fine, g, b, L, t_start, s->triangulate, s->bounded, P, tm, sm, &istar, &taken);
+            orc_march_ex(F, b, L, t_start, s->triangulate, s->bounded, P, tm, sm, &istar, &taken);
             double rmin = HUGE_VAL, rm = HUGE_VAL, sgap = HUGE_VAL, cgap = HUGE_VAL, vm = HUGE_VAL;
             int mmin = 0;
             for (int m = 0; m < taken; ++m) {
@@ -1186,7 +1247,7 @@ void orc_shadow_margin_ex(const double* fine, orc_grid g, const orc_shadow_ex* s
             if (s->triangulate)
                 for (int m = 1; m < taken; ++m) {
                     const double r1 = sm[m - 1], r2 = sm[m], delta = orc_clamp_step(b, r1);
-                    vm = fmin(vm, fmin(fabs(r1), fabs(r2)) / (double)g.h);
+                    vm = fmin(vm, fmin(fabs(r1), fabs(r2)) / (double)F->g[F->L - 1].h);
                     const double y = (r2 * r2 - r1 * r1 + delta * delta) / (2.0 * delta);
                     if (r2 != 0.0) vm = fmin(vm, fabs(r2 * r2 - y * y) / (r2 * r2));
                     vm = fmin(vm, fabs(tm[m] - y) / tm[m]);
@@ -1199,17 +1260,23 @@ void orc_shadow_margin_ex(const double* fine, orc_grid g, const orc_shadow_ex* s
                     else if (m > 0) t = tm[m - 1] + orc_clamp_step(b, sm[m - 1]);
                     double X[3], gap;
                     for (int a = 0; a < 3; ++a) X[a] = P[a] + t * L[a];
-                    orc_in_box(g, X, &gap);
+                    orc_in_box(F->g[F->L - 1], X, &gap);
                     vm = fmin(vm, gap);
                 }
             }
             for (int m = 0; m < last; ++m)
                 sgap = fmin(sgap, fmin(fabs(sm[m] - (double)b->smin), fabs(sm[m] - (double)b->smax)));
-            for (int m = 0; m <= last && m < taken; ++m)
-                for (int a = 0; a < 3; ++a) {
-                    const double c = (P[a] + tm[m] * L[a] - (double)g.org[a]) / (double)g.h - 0.5;
-                    cgap = fmin(cgap, fabs(c - nearbyint(c)));
-                }
+            for (int m = 0; m < taken; ++m) {
+                double X[3], lgap;
+                for (int a = 0; a < 3; ++a) X[a] = P[a] + tm[m] * L[a];
+                const orc_grid gl = F->g[orc_field_level(F, X, &lgap)];
+                vm = fmin(vm, lgap); /* a sample near a level boundary may switch level */
+                if (m <= last)
+                    for (int a = 0; a < 3; ++a) {
+                        const double c = (X[a] - (double)gl.org[a]) / (double)gl.h - 0.5;
+                        cgap = fmin(cgap, fabs(c - nearbyint(c)));
+                    }
+            }
             r_margin[q] = rm;
             s_margin[q] = sgap;
             c_margin[q] = cgap;
@@ -1219,6 +1286,53 @@ void orc_shadow_margin_ex(const double* fine, orc_grid g, const orc_shadow_ex* s
         free(sm);
         free(em);
     }
+}
+
+void orc_shadow_forward_ex(const double* fine, orc_grid g, const orc_shadow_ex* s, double* img)
+{
+    const int64_t zero = 0;
+    const orc_field F = {fine, &zero, &g, 1};
+    orc_shadow_forward_field(&F, s, img);
+}
+
+void orc_shadow_backward_ex(const double* fine, orc_grid g, const orc_shadow_ex* s, const double* grad_img,
+                            double* grad_fine)
+{
+    const int64_t zero = 0;
+    const orc_field F = {fine, &zero, &g, 1};
+    orc_shadow_backward_field(&F, s, grad_img, grad_fine);
+}
+
+void orc_shadow_margin_ex(const double* fine, orc_grid g, const orc_shadow_ex* s, double* r_margin,
+                          double* s_margin, double* c_margin, double* v_margin)
+{
+    const int64_t zero = 0;
+    const orc_field F = {fine, &zero, &g, 1};
+    orc_shadow_margin_field(&F, s, r_margin, s_margin, c_margin, v_margin);
+}
+
+/* the full shadow pass over a clip map (levels finest first, level l at fine + off[l]); a
+ * bounded march ends where it leaves the coarsest level's grid box */
+void orc_shadow_forward_clip(const double* fine, const int64_t* off, const orc_grid* g, int32_t L,
+                             const orc_shadow_ex* s, double* img)
+{
+    const orc_field F = {fine, off, g, L};
+    orc_shadow_forward_field(&F, s, img);
+}
+
+void orc_shadow_backward_clip(const double* fine, const int64_t* off, const orc_grid* g, int32_t L,
+                              const orc_shadow_ex* s, const double* grad_img, double* grad_fine)
+{
+    const orc_field F = {fine, off, g, L};
+    orc_shadow_backward_field(&F, s, grad_img, grad_fine);
+}
+
+void orc_shadow_margin_clip(const double* fine, const int64_t* off, const orc_grid* g, int32_t L,
+                            const orc_shadow_ex* s, double* r_margin, double* s_margin, double* c_margin,
+                            double* v_margin)
+{
+    const orc_field F = {fine, off, g, L};
+    orc_shadow_margin_field(&F, s, r_margin, s_margin, c_margin, v_margin);
 }
 
 /* ------------------------------------------------------------------------------------
