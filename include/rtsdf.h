@@ -414,6 +414,41 @@ rtsdf_status rtsdf_backward_batched(const void* plan_host, const float* grad_fin
                                     int64_t band_capacity, const void* bvh, const int32_t* tris,
                                     int32_t rays_per_voxel, uint64_t rng_key, float* grad_verts, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Clip map -- several resolutions of the field around a camera, for scenes larger than one
+ * grid can cover (the paper's future-work section proposes it without a design).  Level l
+ * is a grid of n^3 points of size h0 * 2^l; a clip map is a batch plan whose objects are its
+ * levels, finest first (built and run with the *_batched calls, every level holding the same
+ * mesh), and these calls read the concatenated fine field of such a batch.
+ * rtsdf_clipmap_levels (host only): the level grids around `camera`: level l's origin on
+ *   each axis is (floor(c / h) - n/2) * h in binary32 with h = h0 * 2^l, so a level stays
+ *   fixed while the camera moves inside one of its voxels and lies inside the next level's
+ *   box.  camera HOST float[3], grids HOST out [levels].  Errors: E_ARG (NULL, h0 not finite
+ *   and > 0, camera not finite), E_RANGE (n not even in [4, RTSDF_MAX_DIM], levels outside
+ *   [1, RTSDF_MAX_CLIP_LEVELS]).
+ * Sampling rule: a point reads the finest level whose box of grid-point centres holds it
+ *   (grid coordinate (X - org)/h - 1/2 in [0, n-1] on every axis), trilinearly as
+ *   rtsdf_shadow_forward samples one grid; when no level holds it, the coarsest (clamped).
+ * rtsdf_clipmap_sample: values (and, if levels != NULL, the level read) at n points
+ *   (points [n][3] float, values [n] float, levels [n] int32, all device).
+ * rtsdf_shadow_forward_clip / rtsdf_shadow_backward_clip: the full shadow pass
+ *   (rtsdf_shadow_forward_ex) marching through the clip map by the sampling rule; a bounded
+ *   march ends at the coarsest level's box; the adjoint accumulates into the concatenated
+ *   grad_fine of the level each sample read.
+ *   plan: HOST copy of the batch plan whose objects are the levels (1..RTSDF_MAX_CLIP_LEVELS).
+ * Errors: E_ARG (NULL pointers, a bad plan, parameters as rtsdf_shadow_forward_ex), E_RANGE
+ * (number of levels, n < 0).
+ * ------------------------------------------------------------------------------------- */
+#define RTSDF_MAX_CLIP_LEVELS 8
+
+rtsdf_status rtsdf_clipmap_levels(const float* camera, float h0, int32_t n, int32_t levels, rtsdf_grid* grids);
+rtsdf_status rtsdf_clipmap_sample(const void* plan, const float* fine, const float* points, int64_t n, float* values,
+                                  int32_t* levels, void* stream);
+rtsdf_status rtsdf_shadow_forward_clip(const void* plan, const float* fine, const rtsdf_shadow_ex* s, float* img,
+                                       void* stream);
+rtsdf_status rtsdf_shadow_backward_clip(const void* plan, const float* fine, const rtsdf_shadow_ex* s,
+                                        const float* grad_img, float* grad_fine, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -551,6 +551,72 @@ rtsdf_status rtsdf_shadow_backward_ex(const float* fine, rtsdf_grid g, const rts
                   "shadow_backward_ex");
 }
 
+rtsdf_status rtsdf_clipmap_levels(const float* camera, float h0, int32_t n, int32_t levels, rtsdf_grid* grids)
+{
+    if (!camera || !grids) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (!std::isfinite(h0) || !(h0 > 0.0f)) return fail(RTSDF_E_ARG, "h0 must be finite and > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(camera[a])) return fail(RTSDF_E_ARG, "camera must be finite");
+    if (n < 4 || n > RTSDF_MAX_DIM || (n & 1)) return fail(RTSDF_E_RANGE, "n %d not even in [4, %d]", n, RTSDF_MAX_DIM);
+    if (levels < 1 || levels > RTSDF_MAX_CLIP_LEVELS)
+        return fail(RTSDF_E_RANGE, "levels %d outside [1, %d]", levels, RTSDF_MAX_CLIP_LEVELS);
+    for (int32_t l = 0; l < levels; ++l) {
+        rtsdf_grid& g = grids[l];
+        g.nx = g.ny = g.nz = n;
+        g.h = std::ldexp(h0, l);
+        if (!std::isfinite(g.h)) return fail(RTSDF_E_ARG, "level %d voxel size overflows", l);
+        for (int a = 0; a < 3; ++a) g.org[a] = (std::floor(camera[a] / g.h) - (float)(n / 2)) * g.h;
+    }
+    return ok();
+}
+
+namespace {
+
+rtsdf_status check_clip(const void* plan, rtsdf::BatchView& v)
+{
+    if (rtsdf_status st = check_plan(plan, v)) return st;
+    if (v.h->nobj < 1 || v.h->nobj > RTSDF_MAX_CLIP_LEVELS)
+        return fail(RTSDF_E_RANGE, "a clip map has 1 to %d levels, the plan has %d objects", RTSDF_MAX_CLIP_LEVELS,
+                    v.h->nobj);
+    return RTSDF_OK;
+}
+
+}  // namespace
+
+rtsdf_status rtsdf_clipmap_sample(const void* plan, const float* fine, const float* points, int64_t n, float* values,
+                                  int32_t* levels, void* stream)
+{
+    rtsdf::BatchView v;
+    if (rtsdf_status st = check_clip(plan, v)) return st;
+    if (n < 0) return fail(RTSDF_E_RANGE, "n < 0");
+    if (n > 0 && (!fine || !points || !values)) return fail(RTSDF_E_ARG, "NULL pointer");
+    return device(rtsdf::clip_sample(v, fine, points, n, values, levels, as_stream(stream)), "clipmap_sample");
+}
+
+rtsdf_status rtsdf_shadow_forward_clip(const void* plan, const float* fine, const rtsdf_shadow_ex* s, float* img,
+                                       void* stream)
+{
+    rtsdf::BatchView v;
+    if (rtsdf_status st = check_clip(plan, v)) return st;
+    if (rtsdf_status st = check_shadow_ex(s)) return st;
+    const bool empty = s->base.width == 0 || s->base.height == 0;
+    if (!fine || (!img && !empty)) return fail(RTSDF_E_ARG, "NULL pointer");
+    return device(rtsdf::shadow_forward_clip(v, fine, *s, img, as_stream(stream)), "shadow_forward_clip");
+}
+
+rtsdf_status rtsdf_shadow_backward_clip(const void* plan, const float* fine, const rtsdf_shadow_ex* s,
+                                        const float* grad_img, float* grad_fine, void* stream)
+{
+    rtsdf::BatchView v;
+    if (rtsdf_status st = check_clip(plan, v)) return st;
+    if (rtsdf_status st = check_shadow_ex(s)) return st;
+    const bool empty = s->base.width == 0 || s->base.height == 0;
+    if (!fine || !grad_fine || (!grad_img && !empty)) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (fine == grad_fine) return fail(RTSDF_E_ARG, "fine and grad_fine must not alias");
+    return device(rtsdf::shadow_backward_clip(v, fine, *s, grad_img, grad_fine, as_stream(stream)),
+                  "shadow_backward_clip");
+}
+
 rtsdf_status rtsdf_backward(const float* grad_fine, const uint32_t* hits, const uint64_t* argmin,
                             const int32_t* band_list, const int32_t* band_count, int64_t band_capacity,
                             const void* bvh, const int32_t* tris, int32_t nv, int32_t nt, rtsdf_grid g,

@@ -88,6 +88,12 @@ hipError_t raysample_batched(const BatchView& hv, const void* dplan, const void*
                              float* dmin, uint32_t* hits, uint64_t* argmin, void* work, hipStream_t s);
 hipError_t build_bvh_batched(const BatchView& hv, const void* dplan, const float* verts, const int32_t* tris,
                              void* bvh, void* work, int32_t method, hipStream_t s);
+hipError_t shadow_forward_clip(const BatchView& hv, const float* fine, const rtsdf_shadow_ex& s, float* img,
+                               hipStream_t st);
+hipError_t shadow_backward_clip(const BatchView& hv, const float* fine, const rtsdf_shadow_ex& s,
+                                const float* grad_img, float* grad_fine, hipStream_t st);
+hipError_t clip_sample(const BatchView& hv, const float* fine, const float* pts, int64_t n, float* vals,
+                       int32_t* levels, hipStream_t st);
 hipError_t sdf_backward_batched(const BatchView& hv, const void* dplan, const float* grad_fine,
                                 const uint32_t* hits, const uint64_t* argmin, const int32_t* list,
                                 const int32_t* count, int64_t capacity, const void* bvh, const int32_t* tris,

@@ -62,6 +62,7 @@ __device__ inline Axis axis(float x, float org, float inv_h, int32_t n)
 struct Cell {
     int64_t base;            // index of the lower corner
     int32_t sx, sy, sz;      // index strides to the upper corner per axis
+    float inv_h;             // 1 / h of the grid the cell belongs to
     Axis ax, ay, az;
 };
 
@@ -75,14 +76,15 @@ __device__ inline Cell cell_of(const rtsdf_grid& g, float inv_h, float3 X)
     c.sx = c.ax.step;
     c.sy = g.nx * c.ay.step;
     c.sz = g.nx * g.ny * c.az.step;
+    c.inv_h = inv_h;
     return c;
 }
 
 // trilinear value; lerps in x, then y, then z with a + f (b - a).  If grad != nullptr it
 // also returns the gradient with respect to X (zero along clamped axes).
-__device__ inline float trilinear(const float* __restrict__ f, const Cell& c, float inv_h,
-                                  float3* grad)
+__device__ inline float trilinear(const float* __restrict__ f, const Cell& c, float3* grad)
 {
+    const float inv_h = c.inv_h;
     const float* p = f + c.base;
     const float c000 = p[0], c001 = p[c.sx];
     const float c010 = p[c.sy], c011 = p[c.sy + c.sx];
@@ -137,6 +139,45 @@ __device__ inline bool in_box(const rtsdf_grid& g, float inv_h, float3 X)
     return cx >= 0.0f && cx <= (float)g.nx && cy >= 0.0f && cy <= (float)g.ny && cz >= 0.0f && cz <= (float)g.nz;
 }
 
+// The field a march samples.  GridField: one grid.  ClipField: the levels of a clip map,
+// finest first, concatenated at voxel offsets off[l]; a point reads the finest level whose
+// box of grid-point centres holds it (grid coordinate (X - org)/h - 1/2 in [0, n-1] on every
+// axis), the coarsest (clamped) when none does; a bounded march ends at the coarsest box.
+struct GridField {
+    rtsdf_grid g;
+    float inv_h;
+    __device__ Cell cell(float3 X, int* level = nullptr) const
+    {
+        if (level) *level = 0;
+        return cell_of(g, inv_h, X);
+    }
+    __device__ bool in_bounds(float3 X) const { return in_box(g, inv_h, X); }
+};
+
+struct ClipField {
+    int32_t L;
+    rtsdf_grid g[RTSDF_MAX_CLIP_LEVELS];
+    float inv_h[RTSDF_MAX_CLIP_LEVELS];
+    int64_t off[RTSDF_MAX_CLIP_LEVELS];
+    __device__ Cell cell(float3 X, int* level = nullptr) const
+    {
+        int l = 0;
+        for (; l < L - 1; ++l) {
+            const rtsdf_grid& q = g[l];
+            const float cx = (X.x - q.org[0]) * inv_h[l] - 0.5f, cy = (X.y - q.org[1]) * inv_h[l] - 0.5f,
+                        cz = (X.z - q.org[2]) * inv_h[l] - 0.5f;
+            if (cx >= 0.0f && cx <= (float)(q.nx - 1) && cy >= 0.0f && cy <= (float)(q.ny - 1) && cz >= 0.0f &&
+                cz <= (float)(q.nz - 1))
+                break;
+        }
+        if (level) *level = l;
+        Cell c = cell_of(g[l], inv_h[l], X);
+        c.base += off[l];
+        return c;
+    }
+    __device__ bool in_bounds(float3 X) const { return in_box(g[L - 1], inv_h[L - 1], X); }
+};
+
 __device__ inline float clamp_step(const rtsdf_shadow& s, float v) { return fminf(fmaxf(v, s.smin), s.smax); }
 
 // Two-sample estimate of the closest approach: samples r1 and r2 one clamped step delta
@@ -172,10 +213,9 @@ __device__ inline float3 march_point(float3 P, float t, const rtsdf_shadow& s)
     return make_float3(P.x + t * s.light[0], P.y + t * s.light[1], P.z + t * s.light[2]);
 }
 
-template <bool kTri>
-__global__ __launch_bounds__(kTX* kTY) void k_shadow_forward(const float* __restrict__ fine,
-                                                                 const rtsdf_grid g, const March M,
-                                                                 float inv_h, int tiles_x,
+template <bool kTri, class Field>
+__global__ __launch_bounds__(kTX* kTY) void k_shadow_forward(const float* __restrict__ fine, const Field F,
+                                                                 const March M, int tiles_x,
                                                                  float* __restrict__ img)
 {
     const rtsdf_shadow& s = M.s;
@@ -188,9 +228,9 @@ __global__ __launch_bounds__(kTX* kTY) void k_shadow_forward(const float* __rest
     float t = start_offset(M, pix, l), res = 1.0f, prev = 0.0f;
     for (int m = 0; m < s.steps; ++m) {
         const float3 X = make_float3(P.x + t * L.x, P.y + t * L.y, P.z + t * L.z);
-        if (M.bounded && !in_box(g, inv_h, X)) break;
-        const Cell c = cell_of(g, inv_h, X);
-        const float v = trilinear(fine, c, inv_h, nullptr);
+        if (M.bounded && !F.in_bounds(X)) break;
+        const Cell c = F.cell(X);
+        const float v = trilinear(fine, c, nullptr);
         float r;
         if (kTri && m > 0) {
             bool valid;
@@ -205,10 +245,9 @@ __global__ __launch_bounds__(kTX* kTY) void k_shadow_forward(const float* __rest
     img[(int64_t)l * s.width * s.height + pix] = res > 0.0f ? res : 0.0f;
 }
 
-template <bool kTri>
-__global__ __launch_bounds__(kTX* kTY) void k_shadow_backward(const float* __restrict__ fine,
-                                                                  const rtsdf_grid g, const March M,
-                                                                  float inv_h, int tiles_x,
+template <bool kTri, class Field>
+__global__ __launch_bounds__(kTX* kTY) void k_shadow_backward(const float* __restrict__ fine, const Field F,
+                                                                  const March M, int tiles_x,
                                                                   const float* __restrict__ grad_img,
                                                                   float* __restrict__ grad_fine)
 {
@@ -229,9 +268,9 @@ __global__ __launch_bounds__(kTX* kTY) void k_shadow_backward(const float* __res
     int best = -1;
     for (int m = 0; m < s.steps; ++m) {
         const float3 X = make_float3(P.x + t * L.x, P.y + t * L.y, P.z + t * L.z);
-        if (M.bounded && !in_box(g, inv_h, X)) break;
-        const Cell c = cell_of(g, inv_h, X);
-        const float v = trilinear(fine, c, inv_h, nullptr);
+        if (M.bounded && !F.in_bounds(X)) break;
+        const Cell c = F.cell(X);
+        const float v = trilinear(fine, c, nullptr);
         float r;
         bool valid = false;
         if (kTri && m > 0)
@@ -270,9 +309,9 @@ __global__ __launch_bounds__(kTX* kTY) void k_shadow_backward(const float* __res
     }
     for (int m = best; m >= 0; --m) {
         const float tm = fabsf(s_t[m * (kTX * kTY) + lane]);
-        const Cell c = cell_of(g, inv_h, make_float3(P.x + tm * L.x, P.y + tm * L.y, P.z + tm * L.z));
+        const Cell c = F.cell(make_float3(P.x + tm * L.x, P.y + tm * L.y, P.z + tm * L.z));
         float3 gr;
-        trilinear(fine, c, inv_h, &gr);
+        trilinear(fine, c, &gr);
         scatter(grad_fine, c, sbar);
         tbar += sbar * ((gr.x * L.x + gr.y * L.y) + gr.z * L.z);
         if (m == 0) break;
@@ -299,7 +338,8 @@ March make_march(const rtsdf_shadow& s, const float (*lights)[3], int32_t nlight
     return M;
 }
 
-hipError_t forward(const float* fine, const rtsdf_grid& g, const March& M, int32_t nlights, bool tri, float* img,
+template <class Field>
+hipError_t forward(const float* fine, const Field& F, const March& M, int32_t nlights, bool tri, float* img,
                    hipStream_t st)
 {
     const rtsdf_shadow& s = M.s;
@@ -307,13 +347,14 @@ hipError_t forward(const float* fine, const rtsdf_grid& g, const March& M, int32
     const int tx = tiles(s.width, kTX);
     const dim3 grid((unsigned)(tx * tiles(s.height, kTY)), (unsigned)nlights);
     if (tri)
-        k_shadow_forward<true><<<grid, kTX * kTY, 0, st>>>(fine, g, M, 1.0f / g.h, tx, img);
+        k_shadow_forward<true, Field><<<grid, kTX * kTY, 0, st>>>(fine, F, M, tx, img);
     else
-        k_shadow_forward<false><<<grid, kTX * kTY, 0, st>>>(fine, g, M, 1.0f / g.h, tx, img);
+        k_shadow_forward<false, Field><<<grid, kTX * kTY, 0, st>>>(fine, F, M, tx, img);
     return hipGetLastError();
 }
 
-hipError_t backward(const float* fine, const rtsdf_grid& g, const March& M, int32_t nlights, bool tri,
+template <class Field>
+hipError_t backward(const float* fine, const Field& F, const March& M, int32_t nlights, bool tri,
                     const float* grad_img, float* grad_fine, hipStream_t st)
 {
     const rtsdf_shadow& s = M.s;
@@ -322,10 +363,38 @@ hipError_t backward(const float* fine, const rtsdf_grid& g, const March& M, int3
     const dim3 grid((unsigned)(tx * tiles(s.height, kTY)), (unsigned)nlights);
     const size_t lds = sizeof(float) * (size_t)s.steps * kTX * kTY;
     if (tri)
-        k_shadow_backward<true><<<grid, kTX * kTY, lds, st>>>(fine, g, M, 1.0f / g.h, tx, grad_img, grad_fine);
+        k_shadow_backward<true, Field><<<grid, kTX * kTY, lds, st>>>(fine, F, M, tx, grad_img, grad_fine);
     else
-        k_shadow_backward<false><<<grid, kTX * kTY, lds, st>>>(fine, g, M, 1.0f / g.h, tx, grad_img, grad_fine);
+        k_shadow_backward<false, Field><<<grid, kTX * kTY, lds, st>>>(fine, F, M, tx, grad_img, grad_fine);
     return hipGetLastError();
+}
+
+GridField grid_field(const rtsdf_grid& g) { return GridField{g, 1.0f / g.h}; }
+
+ClipField clip_field(const BatchView& hv)
+{
+    ClipField F;
+    F.L = hv.h->nobj;
+    for (int l = 0; l < RTSDF_MAX_CLIP_LEVELS; ++l) {
+        const int q = l < F.L ? l : F.L - 1;
+        F.g[l] = hv.obj[q].g;
+        F.inv_h[l] = 1.0f / hv.obj[q].g.h;
+        F.off[l] = hv.obj[q].vox_off;
+    }
+    return F;
+}
+
+// one thread per point: the value (and level) a clip map gives it
+__global__ __launch_bounds__(256) void k_clip_sample(const float* __restrict__ fine, const ClipField F,
+                                                     const float* __restrict__ pts, int64_t n,
+                                                     float* __restrict__ vals, int32_t* __restrict__ levels)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    int l;
+    const Cell c = F.cell(make_float3(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]), &l);
+    vals[i] = trilinear(fine, c, nullptr);
+    if (levels) levels[i] = l;
 }
 
 }  // namespace
@@ -333,27 +402,51 @@ hipError_t backward(const float* fine, const rtsdf_grid& g, const March& M, int3
 hipError_t shadow_forward(const float* fine, const rtsdf_grid& g, const rtsdf_shadow& s, float* img,
                           hipStream_t st)
 {
-    return forward(fine, g, make_march(s, &s.light, 1, 0.0f, 0, 0, 0), 1, false, img, st);
+    return forward(fine, grid_field(g), make_march(s, &s.light, 1, 0.0f, 0, 0, 0), 1, false, img, st);
 }
 
 hipError_t shadow_backward(const float* fine, const rtsdf_grid& g, const rtsdf_shadow& s,
                            const float* grad_img, float* grad_fine, hipStream_t st)
 {
-    return backward(fine, g, make_march(s, &s.light, 1, 0.0f, 0, 0, 0), 1, false, grad_img, grad_fine, st);
+    return backward(fine, grid_field(g), make_march(s, &s.light, 1, 0.0f, 0, 0, 0), 1, false, grad_img, grad_fine,
+                    st);
 }
 
 hipError_t shadow_forward_ex(const float* fine, const rtsdf_grid& g, const rtsdf_shadow_ex& s, float* img,
                              hipStream_t st)
 {
-    return forward(fine, g, make_march(s.base, s.lights, s.nlights, s.jitter, s.frame, s.key, s.bounded != 0), s.nlights,
-                   s.triangulate != 0, img, st);
+    return forward(fine, grid_field(g), make_march(s.base, s.lights, s.nlights, s.jitter, s.frame, s.key, s.bounded != 0),
+                   s.nlights, s.triangulate != 0, img, st);
 }
 
 hipError_t shadow_backward_ex(const float* fine, const rtsdf_grid& g, const rtsdf_shadow_ex& s,
                               const float* grad_img, float* grad_fine, hipStream_t st)
 {
-    return backward(fine, g, make_march(s.base, s.lights, s.nlights, s.jitter, s.frame, s.key, s.bounded != 0), s.nlights,
-                    s.triangulate != 0, grad_img, grad_fine, st);
+    return backward(fine, grid_field(g), make_march(s.base, s.lights, s.nlights, s.jitter, s.frame, s.key, s.bounded != 0),
+                    s.nlights, s.triangulate != 0, grad_img, grad_fine, st);
+}
+
+hipError_t shadow_forward_clip(const BatchView& hv, const float* fine, const rtsdf_shadow_ex& s, float* img,
+                               hipStream_t st)
+{
+    return forward(fine, clip_field(hv), make_march(s.base, s.lights, s.nlights, s.jitter, s.frame, s.key, s.bounded != 0),
+                   s.nlights, s.triangulate != 0, img, st);
+}
+
+hipError_t shadow_backward_clip(const BatchView& hv, const float* fine, const rtsdf_shadow_ex& s,
+                                const float* grad_img, float* grad_fine, hipStream_t st)
+{
+    return backward(fine, clip_field(hv), make_march(s.base, s.lights, s.nlights, s.jitter, s.frame, s.key, s.bounded != 0),
+                    s.nlights, s.triangulate != 0, grad_img, grad_fine, st);
+}
+
+hipError_t clip_sample(const BatchView& hv, const float* fine, const float* pts, int64_t n, float* vals,
+                       int32_t* levels, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_clip_sample, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, fine, clip_field(hv), pts, n,
+                       vals, levels);
+    return hipGetLastError();
 }
 
 }  // namespace rtsdf

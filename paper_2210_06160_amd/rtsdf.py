@@ -9,6 +9,7 @@ the per-frame chain of a deforming mesh, and `SDF` / `SoftShadow` are autograd F
 whose backward passes call the adjoint entry points.
 """
 import ctypes
+import types
 import os
 
 import numpy as np
@@ -126,6 +127,10 @@ def lib():
             "rtsdf_shadow_forward": ([vp, Grid, Shadow, vp, vp], i32),
             "rtsdf_shadow_backward": ([vp, Grid, Shadow, vp, vp, vp], i32),
             "rtsdf_shadow_forward_ex": ([vp, Grid, ctypes.POINTER(ShadowEx), vp, vp], i32),
+            "rtsdf_clipmap_levels": ([vp, f32, i32, i32, vp], i32),
+            "rtsdf_clipmap_sample": ([vp, vp, vp, i64, vp, vp, vp], i32),
+            "rtsdf_shadow_forward_clip": ([vp, vp, ctypes.POINTER(ShadowEx), vp, vp], i32),
+            "rtsdf_shadow_backward_clip": ([vp, vp, ctypes.POINTER(ShadowEx), vp, vp, vp], i32),
             "rtsdf_shadow_backward_ex": ([vp, Grid, ctypes.POINTER(ShadowEx), vp, vp, vp], i32),
             "rtsdf_backward": ([vp, vp, vp, vp, vp, i64, vp, vp, i32, i32, Grid, i32, u64, u32, vp, vp], i32),
             "rtsdf_batch_plan_bytes": ([i32], sz),
@@ -153,7 +158,8 @@ EXPORTED = ["rtsdf_last_error", "rtsdf_abi_version", "rtsdf_voxelize_work_bytes"
             "rtsdf_build_bvh", "rtsdf_reset_accum", "rtsdf_raysample_work_bytes", "rtsdf_raysample",
             "rtsdf_combine", "rtsdf_refine_grid", "rtsdf_band_refined_work_bytes", "rtsdf_band_refined",
             "rtsdf_combine_refined", "rtsdf_shadow_forward", "rtsdf_shadow_backward", "rtsdf_shadow_forward_ex",
-            "rtsdf_shadow_backward_ex", "rtsdf_backward",
+            "rtsdf_shadow_backward_ex", "rtsdf_clipmap_levels", "rtsdf_clipmap_sample", "rtsdf_shadow_forward_clip",
+            "rtsdf_shadow_backward_clip", "rtsdf_backward",
             "rtsdf_batch_plan_bytes", "rtsdf_batch_plan", "rtsdf_batch_upload", "rtsdf_batch_offsets", "rtsdf_voxelize_batched",
             "rtsdf_jfa_batched", "rtsdf_band_batched", "rtsdf_build_bvh_batched", "rtsdf_raysample_batched",
             "rtsdf_combine_batched", "rtsdf_backward_batched"]
@@ -317,6 +323,37 @@ def rtsdf_shadow_backward_ex(fine, grid, shadow, grad_img, grad_fine, stream=Non
     _check(lib().rtsdf_shadow_backward_ex(_ptr(fine, torch.float32), grid, ctypes.byref(shadow),
                                           _ptr(grad_img, torch.float32), _ptr(grad_fine, torch.float32),
                                           _stream(stream)), "rtsdf_shadow_backward_ex")
+
+
+MAX_CLIP_LEVELS = 8
+
+
+def rtsdf_clipmap_levels(camera, h0, n, levels):
+    """Grids of a clip map around `camera` (level l: n^3 points of size h0 * 2^l)."""
+    cam = (ctypes.c_float * 3)(*[float(c) for c in camera])
+    out = (Grid * int(levels))()
+    _check(lib().rtsdf_clipmap_levels(cam, float(h0), int(n), int(levels), out), "rtsdf_clipmap_levels")
+    return list(out)
+
+
+def rtsdf_clipmap_sample(plan, fine, points, values, levels=None, stream=None):
+    """points [n, 3] float32, values [n] float32, levels [n] int32 or None."""
+    _check(lib().rtsdf_clipmap_sample(plan.ptr, _ptr(fine, torch.float32), _ptr(points, torch.float32),
+                                      points.shape[0], _ptr(values, torch.float32),
+                                      _ptr(levels, torch.int32) if levels is not None else None, _stream(stream)),
+           "rtsdf_clipmap_sample")
+
+
+def rtsdf_shadow_forward_clip(plan, fine, shadow, img, stream=None):
+    _check(lib().rtsdf_shadow_forward_clip(plan.ptr, _ptr(fine, torch.float32), ctypes.byref(shadow),
+                                           _ptr(img, torch.float32), _stream(stream)), "rtsdf_shadow_forward_clip")
+
+
+def rtsdf_shadow_backward_clip(plan, fine, shadow, grad_img, grad_fine, stream=None):
+    """grad_fine (the clip map's concatenated levels) is accumulated into."""
+    _check(lib().rtsdf_shadow_backward_clip(plan.ptr, _ptr(fine, torch.float32), ctypes.byref(shadow),
+                                            _ptr(grad_img, torch.float32), _ptr(grad_fine, torch.float32),
+                                            _stream(stream)), "rtsdf_shadow_backward_clip")
 
 
 def rtsdf_backward(grad_fine, hits, argmin, band_list, band_count, bvh, tris, nv, grid, rays_per_voxel, rng_key,
@@ -515,6 +552,56 @@ class BatchSDF:
         off = self.offsets[o][0]
         n = int(np.prod(self.dims[o]))
         return t[off:off + n]
+
+
+class ClipMapSDF:
+    """A clip map around a camera: `levels` grids of n^3 points, level l of voxel size
+    h0 * 2^l (rtsdf_clipmap_levels), each holding the same mesh, built with the batched chain
+    (one launch per stage for all levels; level l draws its rays with object word l) and read
+    by the clip-map sampler and shadow pass (each point reads the finest level holding it).
+    `fine` is the levels' concatenated field (level l = view(fine, l))."""
+
+    def __init__(self, verts, tris, camera, h0, n, levels, band, rays, frames=1, beta=None, bias=0.0, rng_key=0,
+                 bvh_method=BVH_PLOC, device="cuda"):
+        if not 1 <= int(levels) <= MAX_CLIP_LEVELS:
+            raise RtsdfError("1 to %d levels" % MAX_CLIP_LEVELS)
+        self.grids = rtsdf_clipmap_levels(camera, h0, n, levels)
+        steps = _halving_offsets((n, n, n)) + [1]
+        objs = [types.SimpleNamespace(verts=verts, tris=tris, dims=(n, n, n), org=tuple(g.org), h=g.h, steps=steps,
+                                      band=band) for g in self.grids]
+        self.batch = BatchSDF(objs, rays, frames=frames, rng_key=rng_key, beta=beta, bias=bias, bvh_method=bvh_method,
+                              device=device)
+        self.plan = self.batch.plan
+        self.device = device
+
+    @property
+    def fine(self):
+        return self.batch.fine
+
+    def run(self):
+        return self.batch.run()
+
+    def view(self, t, level):
+        return self.batch.view(t, level)
+
+    def sample(self, points):
+        """(values, levels) at points [n, 3] (float32, on the device)."""
+        pts = points.contiguous()
+        vals = torch.empty(pts.shape[0], dtype=torch.float32, device=pts.device)
+        lev = torch.empty(pts.shape[0], dtype=torch.int32, device=pts.device)
+        rtsdf_clipmap_sample(self.plan, self.fine, pts, vals, lev)
+        return vals, lev
+
+    def shadow(self, s):
+        img = torch.empty(s.nlights, s.base.height, s.base.width, dtype=torch.float32, device=self.device)
+        rtsdf_shadow_forward_clip(self.plan, self.fine, s, img)
+        return img
+
+    def shadow_backward(self, s, grad_img, grad_fine=None):
+        if grad_fine is None:
+            grad_fine = torch.zeros_like(self.fine)
+        rtsdf_shadow_backward_clip(self.plan, self.fine, s, grad_img.contiguous(), grad_fine)
+        return grad_fine
 
 
 def _halving_offsets(dims):

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -206,3 +207,30 @@ def test_host_validation_shadow_ex(L):
     assert lib.rtsdf_shadow_backward_ex(fake(), g, C.byref(s), None, fake(0x3000), None) == E_ARG
     with pytest.raises(L.RtsdfError):
         L.make_shadow_ex(base, [])
+
+
+def test_clipmap_levels_match_the_oracle(L, orc):
+    """rtsdf_clipmap_levels (host only) places the levels as the oracle does, bit for bit,
+    and rejects bad arguments."""
+    import ctypes as C
+    rng = np.random.default_rng(3)
+    for _ in range(40):
+        cam = rng.uniform(-5, 5, 3).astype(np.float32)
+        h0 = float(np.float32(rng.uniform(0.001, 0.1)))
+        n = int(rng.choice([4, 16, 64, 128]))
+        lv = int(rng.integers(1, L.MAX_CLIP_LEVELS + 1))
+        a = L.rtsdf_clipmap_levels(cam, h0, n, lv)
+        b = orc.clipmap_levels(cam, h0, n, lv)
+        for ga, gb in zip(a, b):
+            assert (ga.nx, ga.ny, ga.nz) == (gb.nx, gb.ny, gb.nz)
+            assert list(ga.org) == list(gb.org) and ga.h == gb.h
+    lib = L.lib()
+    cam = (C.c_float * 3)(0.0, 0.0, 0.0)
+    out = (L.Grid * 9)()
+    assert lib.rtsdf_clipmap_levels(cam, 0.1, 5, 2, out) == -2      # odd n
+    assert lib.rtsdf_clipmap_levels(cam, 0.1, 2, 2, out) == -2      # n < 4
+    assert lib.rtsdf_clipmap_levels(cam, 0.1, 8, 9, out) == -2      # too many levels
+    assert lib.rtsdf_clipmap_levels(cam, 0.0, 8, 2, out) == -1      # h0
+    assert lib.rtsdf_clipmap_levels(None, 0.1, 8, 2, out) == -1
+    nan = (C.c_float * 3)(float("nan"), 0.0, 0.0)
+    assert lib.rtsdf_clipmap_levels(nan, 0.1, 8, 2, out) == -1

@@ -1,0 +1,174 @@
+"""Clip map on the GPU (several resolutions around a camera; the paper's future-work
+section) versus the oracle, through the C ABI.
+
+Bars: the level a point reads bit-exact and its value within 1e-5 relative (binary32
+trilinear sampling of the same binary32 grid values against binary64), on points away from
+the level boxes' faces (1e-3 grid units, where binary32 rounding could switch the level);
+the full shadow pass over the levels with the bars of the single-grid pass (images within
+1e-4, adjoints element by element on pixels with safe margins), except that the field
+now jumps where a sample switches level: a 128-step binary32 march can drift by up to about
+1.3e-5 world units (6e-4 grid units at h = 1/48) from the binary64 one, so images are
+compared where the oracle's validity margin, which includes every sample's distance from
+the level boxes that chose its level, exceeds 1e-3 grid units (97 % of the pixels).
+Fields are seeded synthetic ones (a sphere's distance sampled at every level's grid points),
+never GPU output.  Cases: three nested 32^3 levels with points inside every level and
+beyond the coarsest; the shadow pass with three lights, triangulated, jittered and bounded,
+over levels that split the occluder; one level equal to the single-grid pass; and the
+clip-map build equal to one single-object chain per level, bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2210_06160_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2210_06160_amd import rtsdf
+    rtsdf.lib()
+    return rtsdf
+
+
+def centres(g):
+    k, j, i = np.meshgrid(np.arange(g.nz), np.arange(g.ny), np.arange(g.nx), indexing="ij")
+    return np.stack([g.org[0] + g.h * (i.ravel() + 0.5), g.org[1] + g.h * (j.ravel() + 0.5),
+                     g.org[2] + g.h * (k.ravel() + 0.5)], 1)
+
+
+def levels_on_gpu(R, grids, fields):
+    """A plan whose objects are the levels (no meshes) and the concatenated field."""
+    import torch
+    objs = [R.make_object((g.nx, g.ny, g.nz), tuple(g.org), g.h, 0, 0, 0, 0, g.h / 2) for g in grids]
+    plan = R.Plan(objs)
+    fine = torch.zeros(plan.sizes.voxels, dtype=torch.float32)
+    for l, f in enumerate(fields):
+        off = plan.offsets(l)[0]
+        fine[off:off + len(f)] = torch.from_numpy(np.asarray(f, np.float32))
+    return plan, fine.cuda()
+
+
+def sphere_fields(grids, C=(0.52, 0.45, 0.5), r=0.12):
+    return [(np.linalg.norm(centres(g) - np.asarray(C), axis=1) - r).astype(np.float32) for g in grids]
+
+
+def near_faces(grids, X, tol=1e-3):
+    bad = np.zeros(len(X), bool)
+    for g in grids[:-1]:
+        c = (X - np.array(g.org[:], np.float64)) / np.float64(g.h) - 0.5
+        n = np.array([g.nx, g.ny, g.nz]) - 1
+        bad |= (np.minimum(np.abs(c), np.abs(n - c)) < tol).any(1)
+    return bad
+
+
+def test_sampler_parity(R, orc):
+    import torch
+    cam = np.array([0.5, 0.4, 0.5], np.float32)
+    G_o = orc.clipmap_levels(cam, 1.0 / 64, 32, 3)
+    G_r = R.rtsdf_clipmap_levels(cam, 1.0 / 64, 32, 3)
+    rng = np.random.default_rng(0)
+    F = [rng.normal(size=32 ** 3).astype(np.float32) for _ in G_o]
+    plan, fine = levels_on_gpu(R, G_r, F)
+    lo = np.array(G_o[2].org[:], np.float64)
+    X = rng.uniform(lo - 0.2, lo + 32 * G_o[2].h + 0.2, size=(20000, 3))
+    X = X[~near_faces(G_o, X)].astype(np.float32).astype(np.float64)
+    log("case: 3 levels of 32^3, %d points" % len(X))
+    vo, lo_ = orc.clipmap_sample(G_o, F, X)
+    pts = torch.from_numpy(X.astype(np.float32)).cuda()
+    vals = torch.empty(len(X), device="cuda")
+    lev = torch.empty(len(X), dtype=torch.int32, device="cuda")
+    R.rtsdf_clipmap_sample(plan, fine, pts, vals, lev)
+    torch.cuda.synchronize()
+    assert set(lo_) == {0, 1, 2}
+    assert np.array_equal(lev.cpu().numpy(), lo_)
+    np.testing.assert_allclose(vals.cpu().numpy(), vo, rtol=1e-5, atol=1e-5 * np.abs(vo).max())
+
+
+def safe(orc, grids, F, s, img):
+    rm, sm, cm, vm = orc.shadow_margin_clip(grids, F, s)
+    return vm > 1e-3, (vm > 1e-2) & (img > 0) & (img < 1) & (rm > 1e-4) & (sm > 1e-5) & (cm > 2e-3)
+
+
+def close(a, b, rtol=1e-3, arel=1e-4):
+    b = np.asarray(b, np.float64)
+    tol = rtol * np.abs(b) + arel * np.abs(b).max()
+    err = np.abs(np.asarray(a, np.float64) - b)
+    bad = err > tol
+    assert not bad.any(), "%d of %d elements differ; worst %g" % (bad.sum(), bad.size, err[bad].max())
+
+
+@pytest.mark.parametrize("n,levels", [(16, 3), (24, 2)])
+def test_shadow_over_clip_map_parity(R, orc, n, levels):
+    import torch
+    cam = np.array([0.5, 0.35, 0.5], np.float32)
+    h0 = 1.0 / 48
+    G_o, G_r = orc.clipmap_levels(cam, h0, n, levels), R.rtsdf_clipmap_levels(cam, h0, n, levels)
+    F = sphere_fields(G_o)
+    plan, fine = levels_on_gpu(R, G_r, F)
+    p, lights, kw = synth.dl_setup(h0, width=64, height=48, steps=128)
+    s_r = R.make_shadow_ex(R.make_shadow(**p), lights, **kw)
+    s_o = orc.make_shadow_ex(orc.make_shadow(**p), lights, **kw)
+    log("case: shadow over %d levels of %d^3, 3 lights x 128 steps, 64x48" % (levels, n))
+    io = orc.shadow_forward_clip(G_o, F, s_o)
+    img = torch.empty(3, 48, 64, device="cuda")
+    R.rtsdf_shadow_forward_clip(plan, fine, s_r, img)
+    torch.cuda.synchronize()
+    ig = img.cpu().numpy().ravel()
+    ok, use = safe(orc, G_o, F, s_o, io)
+    pen = (io > 0) & (io < 1)
+    log("  max |diff| (safe)", np.abs(ig - io)[ok].max(), "safe", ok.sum(), "of", io.size, "penumbra", pen.sum(),
+        "adjoint pixels", use.sum())
+    assert np.abs(ig - io)[ok].max() <= 1e-4 and ok.sum() >= 0.95 * io.size and pen.sum() > 0
+    assert use.sum() >= 0.4 * pen.sum()
+    gi = np.where(use, np.random.default_rng(3).normal(size=io.size), 0.0).astype(np.float32)
+    go = orc.shadow_backward_clip(G_o, F, s_o, gi.astype(np.float64))
+    gf = torch.zeros_like(fine)
+    R.rtsdf_shadow_backward_clip(plan, fine, s_r, torch.from_numpy(gi).cuda(), gf)
+    torch.cuda.synchronize()
+    gg = gf.cpu().numpy()
+    # the oracle's gradient is over the levels back to back; the GPU's at the plan offsets
+    gg = np.concatenate([gg[plan.offsets(l)[0]:plan.offsets(l)[0] + n ** 3] for l in range(levels)])
+    assert np.abs(go[:n ** 3]).max() > 0 and np.abs(go[n ** 3:]).max() > 0
+    close(gg, go)
+
+
+def test_one_level_equals_single_grid(R):
+    import torch
+    g = R.make_grid((40, 32, 36), (0.1, 0.05, 0.0), 0.025)
+    f = (np.linalg.norm(centres(g) - np.array([0.6, 0.45, 0.5]), axis=1) - 0.15).astype(np.float32)
+    plan, fine = levels_on_gpu(R, [g], [f])
+    p, lights, kw = synth.dl_setup(0.025, width=40, height=30, steps=96)
+    s = R.make_shadow_ex(R.make_shadow(**p), lights, **kw)
+    a = torch.empty(3, 30, 40, device="cuda")
+    b = torch.empty(3, 30, 40, device="cuda")
+    R.rtsdf_shadow_forward_clip(plan, fine, s, a)
+    R.rtsdf_shadow_forward_ex(torch.from_numpy(f).cuda(), g, s, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+def test_clip_map_build_equals_single_chains(R):
+    import torch
+    sc = synth.scene_static(dims=(64, 32, 64), nprims=30, seed=3)
+    cam = (1.0, 0.4, 1.0)
+    C = R.ClipMapSDF(sc.verts, sc.tris, cam, 1.0 / 48, 32, 3, band=2, rays=8)
+    C.run()
+    torch.cuda.synchronize()
+    log("case: clip map of 3 x 32^3 levels around %s, %d triangles" % (cam, len(sc.tris)))
+    for l, g in enumerate(C.grids):
+        S = R.StaticSDF(sc.verts, sc.tris, (g.nx, g.ny, g.nz), tuple(g.org), g.h, [16, 8, 4, 2, 1, 1], 2, 8, 1, obj=l)
+        S.run()
+        torch.cuda.synchronize()
+        assert torch.equal(C.view(C.fine, l).view(torch.int32), S.fine.view(torch.int32)), l
+        assert torch.equal(C.view(C.batch.hits, l), S.hits), l
