@@ -34,7 +34,8 @@ def parse():
     p.add_argument("--no-batch", action="store_true", help="skip the batched-objects measurement")
     p.add_argument("--no-two-level", action="store_true", help="skip the two-level (coarse/fine) measurement")
     p.add_argument("--no-dl", action="store_true", help="skip the full shadow pass measurement")
-    p.add_argument("--only", choices=["static", "deform", "grad", "batch", "two_level", "tables", "dl"],
+    p.add_argument("--no-clipmap", action="store_true", help="skip the clip-map measurement")
+    p.add_argument("--only", choices=["static", "deform", "grad", "batch", "two_level", "tables", "dl", "clipmap"],
                    help="run one workload alone and print its record (for profiling)")
     p.add_argument("--cpu-sample", type=int, default=4000000,
                    help="masked voxels ray-sampled by the oracle (about 6 s on 16 host cores)")
@@ -311,6 +312,48 @@ def dl_bench(torch, rtsdf, synth, reps=20):
     return out
 
 
+def clipmap_bench(torch, rtsdf, synth, reps=5):
+    """A clip map around a camera in a scene larger than one grid (an 8 x 1 x 8 box, 800
+    primitives): 4 levels of 128^3 with voxels 1/64 .. 1/8 (level 3 spans 16 units), built
+    by the batched chain (2-voxel masks, 8 rays, one frame), then the full shadow pass over
+    it (1920 x 1080, three lights, 128 steps, a receiver patch of 4 x 4 units around the
+    camera).  Beside it, the same chain on one grid covering the box at the finest voxel size
+    (512 x 128 x 512).  Medians of `reps` (HIP events)."""
+    import numpy as np
+    v, t = synth.scene_world()
+    cam = (4.0, 0.4, 4.0)
+    C = rtsdf.ClipMapSDF(v, t, cam, 1.0 / 64, 128, 4, band=2, rays=8)
+
+    def med(fn):
+        ts = []
+        for it in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            if it:
+                ts.append(a.elapsed_time(b))
+        return statistics.median(ts)
+
+    build = med(C.run)
+    p, lights, kw = synth.dl_setup(1.0 / 64, width=1920, height=1080)
+    p.update(x0=2.0, z0=2.0, dx=4.0 / 1920, dz=4.0 / 1080)
+    s = rtsdf.make_shadow_ex(rtsdf.make_shadow(**p), lights, **kw)
+    img = torch.empty(3, 1080, 1920, device="cuda")
+    dl = med(lambda: rtsdf.rtsdf_shadow_forward_clip(C.plan, C.fine, s, img))
+    vox = sum(g.nx * g.ny * g.nz for g in C.grids)
+    out = {"workload": "world 8x1x8, %d triangles, camera %s" % (len(t), list(cam)), "levels": 4, "n": 128,
+           "h0": 1.0 / 64, "voxels": vox, "build_ms": round(build, 3), "dl_1920x1080x3_ms": round(dl, 3),
+           "lit_fraction": round(float((img == 1).float().mean().item()), 4)}
+    del C
+    torch.cuda.empty_cache()
+    S = rtsdf.StaticSDF(v, t, (512, 128, 512), (0.0, 0.0, 0.0), 1.0 / 64, synth.jfa_offsets((512, 128, 512), extra=1),
+                        2, 8, 1)
+    out["single_grid_512x128x512"] = {"voxels": 512 * 128 * 512, "build_ms": round(med(S.run), 3)}
+    return out
+
+
 def grad_bench(torch, rtsdf, synth, reps=20):
     """Gradient workload (icosphere of 20,480 triangles on 128^3, 16 rays, 512^2 soft shadow):
     forward = the SDF chain + shadow image + loss, backward = shadow adjoint + SDF term +
@@ -491,13 +534,13 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n, "copy_calibration_bytes_written": n, "dispatches": 3}))
         return
-    if args.only in ("deform", "grad", "batch", "two_level", "tables", "dl"):
+    if args.only in ("deform", "grad", "batch", "two_level", "tables", "dl", "clipmap"):
         fn = {"deform": deform_bench, "grad": grad_bench, "batch": batch_bench, "two_level": two_level_bench,
-              "tables": tables_bench, "dl": dl_bench}[args.only]
+              "tables": tables_bench, "dl": dl_bench, "clipmap": clipmap_bench}[args.only]
         print(json.dumps({args.only: fn(torch, rtsdf, synth)}))
         return
     if args.only == "static":
-        args.no_deform = args.no_grad = args.no_batch = args.no_two_level = args.no_dl = True
+        args.no_deform = args.no_grad = args.no_batch = args.no_two_level = args.no_dl = args.no_clipmap = True
     sc = synth.scene_static()
     S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
     N = S.g.n
@@ -562,6 +605,8 @@ def main():
         out["two_level"] = two_level_bench(torch, rtsdf, synth)
     if not args.no_dl:
         out["dl"] = dl_bench(torch, rtsdf, synth)
+    if not args.no_clipmap:
+        out["clipmap"] = clipmap_bench(torch, rtsdf, synth)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample)
     print(json.dumps(out))

@@ -310,6 +310,27 @@ def shadow_setup(h, width=512, height=512, plane_y=0.1, light=(0.35, 1.0, 0.25),
                 light=tuple(float(a) for a in l), k=k, steps=steps, smin=h / 2.0, smax=smax, t0=h)
 
 
+def scene_world(extent=8.0, nprims=800, seed=7):
+    """A scene larger than one grid covers well, for the clip map: the static scene's
+    primitives (boxes, UV spheres, tori, log-normal scales with median 0.1) over the box
+    [0,extent] x [0,1] x [0,extent] on a ground quad at y = 0.05.  Returns (verts, tris)."""
+    rng = np.random.default_rng(seed)
+    meshes = [(np.array([[0.0, 0.05, 0.0], [0.0, 0.05, extent], [extent, 0.05, extent], [extent, 0.05, 0.0]],
+                        np.float32), np.array([[0, 1, 2], [0, 2, 3]], np.int32))]
+    for _ in range(nprims):
+        kind = rng.integers(0, 3)
+        c = (rng.uniform(0.0, extent), rng.uniform(0.05, 1.0), rng.uniform(0.0, extent))
+        s = rng.lognormal(np.log(0.1), 0.5)
+        rot = random_rotation(rng)
+        if kind == 0:
+            meshes.append(box(s * rng.uniform(0.5, 1.0, size=3), c, rot))
+        elif kind == 1:
+            meshes.append(uv_sphere(s, c, rot=rot))
+        else:
+            meshes.append(torus(s, 0.35 * s, c, rot=rot))
+    return merge(meshes)
+
+
 DL_LIGHTS = ((0.35, 1.0, 0.25), (-0.5, 1.0, 0.2), (0.15, 1.0, -0.45))
 
 
