@@ -106,10 +106,7 @@ __global__ __launch_bounds__(kThreads) void k_sdf_backward(
                 uint32_t s2 = child_key(box_entry(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, inv, oinv, tb), ch.z, 2u);
                 uint32_t s3 = child_key(box_entry(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, inv, oinv, tb), ch.w, 3u);
                 sort4(s0, s1, s2, s3);
-                auto code_of = [&](uint32_t key) {
-                    const uint32_t sl = key & 3u;
-                    return sl == 0u ? ch.x : (sl == 1u ? ch.y : (sl == 2u ? ch.z : ch.w));
-                };
+                auto code_of = [&](uint32_t key) { return child_of(ch, key); };
                 auto t_of = [](uint32_t key) { return __uint_as_float(key & ~3u); };
                 if (s3 != kMiss) push(code_of(s3), t_of(s3));
                 if (s2 != kMiss) push(code_of(s2), t_of(s2));

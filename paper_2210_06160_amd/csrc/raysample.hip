@@ -272,10 +272,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
             uint32_t s2 = child_key(box_entry(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, inv, oinv, tb), ch.z, 2u);
             uint32_t s3 = child_key(box_entry(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, inv, oinv, tb), ch.w, 3u);
             sort4(s0, s1, s2, s3);
-            auto code_of = [&](uint32_t key) {
-                const uint32_t q = key & 3u;
-                return q == 0u ? ch.x : (q == 1u ? ch.y : (q == 2u ? ch.z : ch.w));
-            };
+            auto code_of = [&](uint32_t key) { return child_of(ch, key); };
             auto t_of = [](uint32_t key) { return __uint_as_float(key & ~3u); };
             if (s3 != kMiss) push(code_of(s3), t_of(s3));
             if (s2 != kMiss) push(code_of(s2), t_of(s2));

@@ -32,6 +32,15 @@ __device__ inline uint32_t child_key(float t, int32_t code, uint32_t slot)
                                                                       : ((__float_as_uint(t) & ~3u) | slot);
 }
 
+// child code named by a sort key's slot (its two low bits), by selects rather than branches
+__device__ inline int32_t child_of(const int4& ch, uint32_t key)
+{
+    const bool odd = (key & 1u) != 0u;
+    const int32_t lo = odd ? ch.y : ch.x;
+    const int32_t hi = odd ? ch.w : ch.z;
+    return (key & 2u) != 0u ? hi : lo;
+}
+
 // reciprocal for slab tests only (rounding there is harmless; see the file comment)
 __device__ inline float slab_rcp(float a)
 {
