@@ -274,9 +274,25 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
             sort4(s0, s1, s2, s3);
             auto code_of = [&](uint32_t key) { return child_of(ch, key); };
             auto t_of = [](uint32_t key) { return __uint_as_float(key & ~3u); };
-            if (s3 != kMiss) push(code_of(s3), t_of(s3));
-            if (s2 != kMiss) push(code_of(s2), t_of(s2));
-            if (s1 != kMiss) push(code_of(s1), t_of(s1));
+            // misses sort last, so the valid keys are a prefix: push the valid ones of s1..s3,
+            // farthest first; with room in LDS all three slots are written unconditionally
+            // (slots past the new top are dead) and only the top moves
+            const int nv = (int)(s1 != kMiss) + (int)(s2 != kMiss) + (int)(s3 != kMiss);
+            if (sp + 3 <= kLdsDepth) {
+                const uint32_t k1 = nv == 3 ? s3 : (nv == 2 ? s2 : s1);
+                const uint32_t k2 = nv == 3 ? s2 : s1;
+                auto entry = [&](uint32_t key) {
+                    return ((uint64_t)(key & ~3u) << 32) | (uint32_t)code_of(key);
+                };
+                s_stk[sp][tid] = entry(k1);
+                s_stk[sp + 1][tid] = entry(k2);
+                s_stk[sp + 2][tid] = entry(s1);
+                sp += nv;
+            } else {
+                if (s3 != kMiss) push(code_of(s3), t_of(s3));
+                if (s2 != kMiss) push(code_of(s2), t_of(s2));
+                if (s1 != kMiss) push(code_of(s1), t_of(s1));
+            }
             node = -1;
             if (s0 != kMiss) {
                 const int32_t c0 = code_of(s0);
