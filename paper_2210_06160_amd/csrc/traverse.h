@@ -24,6 +24,20 @@ __device__ inline float box_entry(float lx, float ly, float lz, float hx, float 
     return tmin <= tmax ? tmin : __int_as_float(0x7f800000);
 }
 
+// The same test with each axis's near and far planes fetched by the ray's direction signs
+// (near = lo where the reciprocal is positive, else hi): the slab intervals and so the
+// result equal box_entry's, without ordering each axis's two planes.
+__device__ inline float box_entry_nf(float nx, float ny, float nz, float fx, float fy, float fz, float3 inv,
+                                     float3 oinv, float tbest)
+{
+    const float x0 = fmaf(nx, inv.x, -oinv.x), x1 = fmaf(fx, inv.x, -oinv.x);
+    const float y0 = fmaf(ny, inv.y, -oinv.y), y1 = fmaf(fy, inv.y, -oinv.y);
+    const float z0 = fmaf(nz, inv.z, -oinv.z), z1 = fmaf(fz, inv.z, -oinv.z);
+    const float tmin = fmaxf(fmaxf(x0, y0), fmaxf(z0, 0.0f));
+    const float tmax = fminf(fminf(x1, y1), fminf(z1, tbest));
+    return tmin <= tmax ? tmin : __int_as_float(0x7f800000);
+}
+
 // sort key of child `slot`: entry distance (>= 0, so its bits are ordered) rounded down to a
 // multiple of 4 ulp, slot in the low two bits; kMiss if the box is missed or the slot empty
 __device__ inline uint32_t child_key(float t, int32_t code, uint32_t slot)
