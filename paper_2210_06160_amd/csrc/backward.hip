@@ -82,6 +82,7 @@ __global__ __launch_bounds__(kThreads) void k_sdf_backward(
         const float3 w = sphere_direction(k0, k1, lvid, frame, j, lobj);
         const float3 inv = make_float3(slab_rcp(w.x), slab_rcp(w.y), slab_rcp(w.z));
         const float3 oinv = make_float3(o.x * inv.x, o.y * inv.y, o.z * inv.z);
+        const NearPlanes np = near_planes(inv);
 
         float tb = inf;
         int32_t bid = kNone, bpos = -1;
@@ -98,13 +99,9 @@ __global__ __launch_bounds__(kThreads) void k_sdf_backward(
         int32_t cur = root;
         while (true) {
             if (cur >= 0) {
-                const Bvh4Node* N = nodes + cur;
-                const float4 lx = N->lox, ly = N->loy, lz = N->loz, hx = N->hix, hy = N->hiy, hz = N->hiz;
-                const int4 ch = N->child;
-                uint32_t s0 = child_key(box_entry(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, inv, oinv, tb), ch.x, 0u);
-                uint32_t s1 = child_key(box_entry(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, inv, oinv, tb), ch.y, 1u);
-                uint32_t s2 = child_key(box_entry(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, inv, oinv, tb), ch.z, 2u);
-                uint32_t s3 = child_key(box_entry(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, inv, oinv, tb), ch.w, 3u);
+                uint32_t s0, s1, s2, s3;
+                int4 ch;
+                node_keys(nodes + cur, np, inv, oinv, tb, s0, s1, s2, s3, ch);
                 sort4(s0, s1, s2, s3);
                 auto code_of = [&](uint32_t key) { return child_of(ch, key); };
                 auto t_of = [](uint32_t key) { return __uint_as_float(key & ~3u); };

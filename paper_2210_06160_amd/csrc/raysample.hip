@@ -46,10 +46,6 @@ constexpr int32_t kChunkRays = RTSDF_RAY_CHUNK_RAYS;   // ... and at least this 
 constexpr int32_t kStartBatch = RTSDF_RAY_START_BATCH;  // idle lanes restarted together
 constexpr int kMinWaves = 6;         // waves per SIMD the register budget must allow
 constexpr int kRanges = RTSDF_RAY_RANGES;  // unit ranges, each with its own cursor
-// byte offsets of a node's plane arrays
-constexpr int32_t kLoX = (int32_t)offsetof(Bvh4Node, lox), kLoY = (int32_t)offsetof(Bvh4Node, loy);
-constexpr int32_t kLoZ = (int32_t)offsetof(Bvh4Node, loz), kHiX = (int32_t)offsetof(Bvh4Node, hix);
-constexpr int32_t kHiY = (int32_t)offsetof(Bvh4Node, hiy), kHiZ = (int32_t)offsetof(Bvh4Node, hiz);
 constexpr int kSub = kRanges / kXcds;      // ranges per XCD
 constexpr int kCursorStride = 32;          // cursors are 128 bytes apart
 static_assert(kSub * kXcds == kRanges, "ranges split evenly over the XCDs");
@@ -143,7 +139,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
     float3 o = make_float3(0.f, 0.f, 0.f);
     bool alive = true, active = false;
     float3 w = o, inv = o, oinv = o;
-    int32_t near_x = 0, near_y = 0, near_z = 0;
+    NearPlanes np{kLoX, kLoY, kLoZ};
     float tb = inf;
     int32_t bid = kNone;
     bool bfr = false;
@@ -244,10 +240,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
             w = sphere_direction(k0, k1, lvid, frame, j, lobj);
             inv = make_float3(slab_rcp(w.x), slab_rcp(w.y), slab_rcp(w.z));
             oinv = make_float3(o.x * inv.x, o.y * inv.y, o.z * inv.z);
-            // byte offsets, within a node, of each axis's near planes for this ray's direction
-            near_x = inv.x > 0.0f ? kLoX : kHiX;
-            near_y = inv.y > 0.0f ? kLoY : kHiY;
-            near_z = inv.z > 0.0f ? kLoZ : kHiZ;
+            np = near_planes(inv);
             tb = inf;
             bid = kNone;
             sp = 0;
@@ -273,16 +266,9 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
         }
         // ... and one node visit per iteration
         if (node >= 0) {
-            const char* N = (const char*)(nodes + node);
-            auto planes = [&](int32_t off) { return *(const float4*)(N + off); };
-            const float4 nx = planes(near_x), ny = planes(near_y), nz = planes(near_z);
-            const float4 fx = planes(near_x ^ (kLoX ^ kHiX)), fy = planes(near_y ^ (kLoY ^ kHiY)),
-                         fz = planes(near_z ^ (kLoZ ^ kHiZ));
-            const int4 ch = ((const Bvh4Node*)N)->child;
-            uint32_t s0 = child_key(box_entry_nf(nx.x, ny.x, nz.x, fx.x, fy.x, fz.x, inv, oinv, tb), ch.x, 0u);
-            uint32_t s1 = child_key(box_entry_nf(nx.y, ny.y, nz.y, fx.y, fy.y, fz.y, inv, oinv, tb), ch.y, 1u);
-            uint32_t s2 = child_key(box_entry_nf(nx.z, ny.z, nz.z, fx.z, fy.z, fz.z, inv, oinv, tb), ch.z, 2u);
-            uint32_t s3 = child_key(box_entry_nf(nx.w, ny.w, nz.w, fx.w, fy.w, fz.w, inv, oinv, tb), ch.w, 3u);
+            uint32_t s0, s1, s2, s3;
+            int4 ch;
+            node_keys(nodes + node, np, inv, oinv, tb, s0, s1, s2, s3, ch);
             sort4(s0, s1, s2, s3);
             auto code_of = [&](uint32_t key) { return child_of(ch, key); };
             auto t_of = [](uint32_t key) { return __uint_as_float(key & ~3u); };

@@ -13,20 +13,10 @@ constexpr int kMaxStack = 176;  // <= 3 pushes per level + 1; tree depth <= 56
 constexpr int32_t kNone = 0x7FFFFFFF;
 constexpr uint32_t kMiss = 0xFFFFFFFFu;
 
-__device__ inline float box_entry(float lx, float ly, float lz, float hx, float hy, float hz, float3 inv,
-                                  float3 oinv, float tbest)
-{
-    const float x0 = fmaf(lx, inv.x, -oinv.x), x1 = fmaf(hx, inv.x, -oinv.x);
-    const float y0 = fmaf(ly, inv.y, -oinv.y), y1 = fmaf(hy, inv.y, -oinv.y);
-    const float z0 = fmaf(lz, inv.z, -oinv.z), z1 = fmaf(hz, inv.z, -oinv.z);
-    const float tmin = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
-    const float tmax = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tbest));
-    return tmin <= tmax ? tmin : __int_as_float(0x7f800000);
-}
-
-// The same test with each axis's near and far planes fetched by the ray's direction signs
-// (near = lo where the reciprocal is positive, else hi): the slab intervals and so the
-// result equal box_entry's, without ordering each axis's two planes.
+// Entry parameter of a child box, or +inf if the ray misses it or enters it beyond tbest:
+// the slab test with each axis's near and far planes (near = lo where the reciprocal is
+// positive, else hi -- the ray's direction signs fix which plane is nearer, so the two
+// planes of an axis need no ordering), the interval clipped to [0, tbest].
 __device__ inline float box_entry_nf(float nx, float ny, float nz, float fx, float fy, float fz, float3 inv,
                                      float3 oinv, float tbest)
 {
@@ -36,6 +26,21 @@ __device__ inline float box_entry_nf(float nx, float ny, float nz, float fx, flo
     const float tmin = fmaxf(fmaxf(x0, y0), fmaxf(z0, 0.0f));
     const float tmax = fminf(fminf(x1, y1), fminf(z1, tbest));
     return tmin <= tmax ? tmin : __int_as_float(0x7f800000);
+}
+
+// byte offsets of a node's plane arrays, and of each axis's near planes for a ray whose
+// slab reciprocals are `inv` (far = near ^ (lo ^ hi))
+constexpr int32_t kLoX = (int32_t)offsetof(Bvh4Node, lox), kLoY = (int32_t)offsetof(Bvh4Node, loy);
+constexpr int32_t kLoZ = (int32_t)offsetof(Bvh4Node, loz), kHiX = (int32_t)offsetof(Bvh4Node, hix);
+constexpr int32_t kHiY = (int32_t)offsetof(Bvh4Node, hiy), kHiZ = (int32_t)offsetof(Bvh4Node, hiz);
+
+struct NearPlanes {
+    int32_t x, y, z;
+};
+
+__device__ inline NearPlanes near_planes(float3 inv)
+{
+    return NearPlanes{inv.x > 0.0f ? kLoX : kHiX, inv.y > 0.0f ? kLoY : kHiY, inv.z > 0.0f ? kLoZ : kHiZ};
 }
 
 // sort key of child `slot`: entry distance (>= 0, so its bits are ordered) rounded down to a
@@ -59,6 +64,21 @@ __device__ inline int32_t child_of(const int4& ch, uint32_t key)
 __device__ inline float slab_rcp(float a)
 {
     return __builtin_amdgcn_rcpf(fabsf(a) < 1e-20f ? copysignf(1e-20f, a) : a);
+}
+
+// the four children's sort keys of `node` (slab test with the ray's near / far planes)
+__device__ inline void node_keys(const Bvh4Node* node, NearPlanes np, float3 inv, float3 oinv, float tb,
+                                 uint32_t& s0, uint32_t& s1, uint32_t& s2, uint32_t& s3, int4& ch)
+{
+    const char* N = (const char*)node;
+    auto planes = [&](int32_t off) { return *(const float4*)(N + off); };
+    const float4 nx = planes(np.x), ny = planes(np.y), nz = planes(np.z);
+    const float4 fx = planes(np.x ^ (kLoX ^ kHiX)), fy = planes(np.y ^ (kLoY ^ kHiY)), fz = planes(np.z ^ (kLoZ ^ kHiZ));
+    ch = node->child;
+    s0 = child_key(box_entry_nf(nx.x, ny.x, nz.x, fx.x, fy.x, fz.x, inv, oinv, tb), ch.x, 0u);
+    s1 = child_key(box_entry_nf(nx.y, ny.y, nz.y, fx.y, fy.y, fz.y, inv, oinv, tb), ch.y, 1u);
+    s2 = child_key(box_entry_nf(nx.z, ny.z, nz.z, fx.z, fy.z, fz.z, inv, oinv, tb), ch.z, 2u);
+    s3 = child_key(box_entry_nf(nx.w, ny.w, nz.w, fx.w, fy.w, fz.w, inv, oinv, tb), ch.w, 3u);
 }
 
 // sorting network: afterwards s0 <= s1 <= s2 <= s3
