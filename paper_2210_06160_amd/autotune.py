@@ -26,7 +26,7 @@ TUNING_H = os.path.join(HERE, "csrc", "tuning.h")
 
 GROUPS = {
     "jfa": {"RTSDF_JFA_CHUNK": [16, 32, 64], "RTSDF_JFA_ROWS": [2, 4, 8]},
-    "ray": {"RTSDF_RAY_CHUNK": [32, 64, 128], "RTSDF_RAY_START_BATCH": [10, 12, 14]},
+    "ray": {"RTSDF_RAY_CHUNK": [32], "RTSDF_RAY_START_BATCH": [10, 12, 14], "RTSDF_RAY_WAVES": [6, 7, 8]},
     "shadow": {"RTSDF_SHADOW_TILE_X": [1, 2, 4, 8]},
     "ray_small": {"RTSDF_RAY_RANGES": [8, 32, 64], "RTSDF_RAY_CHUNK_SMALL": [16, 32, 128],
                   "RTSDF_RAY_CHUNK_RAYS": [32, 64, 128]},

@@ -30,20 +30,23 @@ __global__ __launch_bounds__(kThreads) void k_sdf_backward(
     const int32_t* __restrict__ tri_index, int32_t x, uint32_t k0, uint32_t k1, uint32_t obj,
     float* __restrict__ grad_verts, const char* plan, int32_t nobj)
 {
-    __shared__ uint64_t s_stk[kLdsDepth][kThreads];  // (t bits << 32) | child code
-    int32_t p_code[kMaxStack - kLdsDepth];
-    float p_t[kMaxStack - kLdsDepth];
+    __shared__ uint64_t s_stk[kLdsDepth][kThreads];  // child keys: (entry t bits << 32) | code
+    // spilled entries as two 32-bit arrays: a 64-bit array would let the compiler merge its
+    // reads with the LDS reads into one flat load, which occupies the vector-memory path
+    // even for LDS addresses
+    uint32_t p_t[kMaxStack - kLdsDepth];
+    uint32_t p_code[kMaxStack - kLdsDepth];
 
     int32_t nt = 0, root = 0;
     float pad = 0.0f;
-    const Bvh4Node* __restrict__ nodes = nullptr;
+    const char* __restrict__ nodes = nullptr;
     const BvhTri* __restrict__ tris = nullptr;
     auto use_bvh = [&](const char* b) {
         const BvhHeader* H = (const BvhHeader*)b;
         nt = H->nt;
         root = H->root;
         pad = H->pad;
-        nodes = (const Bvh4Node*)(b + 256);
+        nodes = b + 256;
         tris = (const BvhTri*)(b + 256 + sizeof(Bvh4Node) * (size_t)(nt > 1 ? nt - 1 : 1));
     };
     if (!kBatch) {
@@ -87,29 +90,26 @@ __global__ __launch_bounds__(kThreads) void k_sdf_backward(
         float tb = inf;
         int32_t bid = kNone, bpos = -1;
         int sp = 0;
-        auto push = [&](int32_t c, float t) {
+        auto push = [&](uint64_t word) {
             if (sp < kLdsDepth) {
-                s_stk[sp][tid] = ((uint64_t)__float_as_uint(t) << 32) | (uint32_t)c;
+                s_stk[sp][tid] = word;
             } else {
-                p_code[sp - kLdsDepth] = c;
-                p_t[sp - kLdsDepth] = t;
+                p_t[sp - kLdsDepth] = (uint32_t)(word >> 32);
+                p_code[sp - kLdsDepth] = (uint32_t)word;
             }
             ++sp;
         };
         int32_t cur = root;
         while (true) {
             if (cur >= 0) {
-                uint32_t s0, s1, s2, s3;
-                int4 ch;
-                node_keys(nodes + cur, np, inv, oinv, tb, s0, s1, s2, s3, ch);
+                ChildKey s0, s1, s2, s3;
+                node_keys(fetch_node(nodes, (uint32_t)cur, np), inv, oinv, tb, s0, s1, s2, s3);
                 sort4(s0, s1, s2, s3);
-                auto code_of = [&](uint32_t key) { return child_of(ch, key); };
-                auto t_of = [](uint32_t key) { return __uint_as_float(key & ~3u); };
-                if (s3 != kMiss) push(code_of(s3), t_of(s3));
-                if (s2 != kMiss) push(code_of(s2), t_of(s2));
-                if (s1 != kMiss) push(code_of(s1), t_of(s1));
-                if (s0 != kMiss) {
-                    cur = code_of(s0);
+                if (entered(s3)) push(stack_word(s3));
+                if (entered(s2)) push(stack_word(s2));
+                if (entered(s1)) push(stack_word(s1));
+                if (entered(s0)) {
+                    cur = s0.code;
                     continue;
                 }
             } else {
@@ -131,18 +131,14 @@ __global__ __launch_bounds__(kThreads) void k_sdf_backward(
             cur = kBvhEmptySlot;
             while (sp > 0) {
                 const int top = --sp;
-                int32_t e;
-                float t;
+                uint64_t word;
                 if (top < kLdsDepth) {
-                    const uint64_t v = s_stk[top][tid];
-                    e = (int32_t)(uint32_t)v;
-                    t = __uint_as_float((uint32_t)(v >> 32));
+                    word = s_stk[top][tid];
                 } else {
-                    e = p_code[top - kLdsDepth];
-                    t = p_t[top - kLdsDepth];
+                    word = ((uint64_t)p_t[top - kLdsDepth] << 32) | p_code[top - kLdsDepth];
                 }
-                if (t <= tb) {
-                    cur = e;
+                if (word_t(word) <= tb) {
+                    cur = word_code(word);
                     break;
                 }
             }

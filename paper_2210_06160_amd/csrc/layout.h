@@ -104,13 +104,17 @@ __host__ __device__ inline int32_t jfa_offset(int32_t k0, int32_t nhalf, int32_t
     return p < nhalf ? (k0 >> p) : 1;
 }
 
-// ---- BVH blob layout (lbvh.hip writes it, raysample.hip reads it) ----------------------
+// ---- BVH blob layout (lbvh.hip writes it, raysample.hip and backward.hip read it) --------
 // [header 256 B][4-wide nodes: max(nt-1, 1) x Bvh4Node][triangles: nt x BvhTri]
 // A 4-wide node is stored at the index of the binary radix-tree node it was collapsed
 // from (only some indices are reachable).  Child codes: c >= 0 is a node index,
 // kBvhEmptySlot an unused slot, any other c < 0 a leaf range ~c = first | (count-1) << 26
-// of `count` (1..kLeafMax) consecutive triangles in sorted order.
+// of `count` (1..kLeafMax) consecutive triangles in sorted order.  An unused slot's box is
+// the empty box lo = +inf, hi = -inf, which no ray enters.
 constexpr int32_t kBvhEmptySlot = (int32_t)0x80000000;
+// Triangles of one hierarchy: fewer than 2^25 nodes keep a node's byte offset (node * 128)
+// within 32 bits, which traversal uses to address a node's planes.
+constexpr int32_t kBvhMaxTris = 1 << 25;
 constexpr int kLeafMax = RTSDF_LEAF_MAX;
 
 struct BvhHeader {

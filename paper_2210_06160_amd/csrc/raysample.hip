@@ -38,13 +38,15 @@ namespace rtsdf {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kLdsDepth = 12;
+constexpr int kMinWaves = RTSDF_RAY_WAVES;  // waves per SIMD the register budget allows
+// LDS stack entries per lane: the CU's 160 KB shared by kMinWaves waves on each of 4 SIMDs
+constexpr int kLdsDepth = 163840 / (4 * kMinWaves) / (64 * (int)sizeof(uint64_t));
+static_assert(kLdsDepth >= 4 && kLdsDepth < kMaxStack, "stack depth");
 constexpr int kXcds = 8;
 constexpr int32_t kChunk = RTSDF_RAY_CHUNK;            // work units a wave takes per cursor atomic
 constexpr int32_t kChunkSmall = RTSDF_RAY_CHUNK_SMALL;  // ... when there are few units per lane
 constexpr int32_t kChunkRays = RTSDF_RAY_CHUNK_RAYS;   // ... and at least this many rays
 constexpr int32_t kStartBatch = RTSDF_RAY_START_BATCH;  // idle lanes restarted together
-constexpr int kMinWaves = 6;         // waves per SIMD the register budget must allow
 constexpr int kRanges = RTSDF_RAY_RANGES;  // unit ranges, each with its own cursor
 constexpr int kSub = kRanges / kXcds;      // ranges per XCD
 constexpr int kCursorStride = 32;          // cursors are 128 bytes apart
@@ -86,21 +88,24 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
                                                         int32_t* __restrict__ cursors, const char* plan,
                                                         int32_t nobj)
 {
-    __shared__ uint64_t s_stk[kLdsDepth][kThreads];  // (t bits << 32) | child code
-    int32_t p_code[kMaxStack - kLdsDepth];
-    float p_t[kMaxStack - kLdsDepth];
+    __shared__ uint64_t s_stk[kLdsDepth][kThreads];  // child keys: (entry t bits << 32) | code
+    // spilled entries as two 32-bit arrays: a 64-bit array would let the compiler merge its
+    // reads with the LDS reads into one flat load, which occupies the vector-memory path
+    // even for LDS addresses
+    uint32_t p_t[kMaxStack - kLdsDepth];
+    uint32_t p_code[kMaxStack - kLdsDepth];
 
     // the hierarchy and grid of the current voxel (fixed for a single object)
     int32_t nt = 0, root = 0;
     float pad = 0.0f;
-    const Bvh4Node* __restrict__ nodes = nullptr;
+    const char* __restrict__ nodes = nullptr;
     const BvhTri* __restrict__ tris = nullptr;
     auto use_bvh = [&](const char* b) {
         const BvhHeader* H = (const BvhHeader*)b;
         nt = H->nt;
         root = H->root;
         pad = H->pad;
-        nodes = (const Bvh4Node*)(b + 256);
+        nodes = b + 256;
         tris = (const BvhTri*)(b + 256 + sizeof(Bvh4Node) * (size_t)(nt > 1 ? nt - 1 : 1));
     };
     rtsdf_grid lg = g;
@@ -147,12 +152,12 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
     int32_t pfirst = 0, pcount = 0;  // pending leaf range
     int sp = 0;
 
-    auto push = [&](int32_t code, float t) {
+    auto push = [&](uint64_t word) {
         if (sp < kLdsDepth) {
-            s_stk[sp][tid] = ((uint64_t)__float_as_uint(t) << 32) | (uint32_t)code;
+            s_stk[sp][tid] = word;
         } else {
-            p_code[sp - kLdsDepth] = code;
-            p_t[sp - kLdsDepth] = t;
+            p_t[sp - kLdsDepth] = (uint32_t)(word >> 32);
+            p_code[sp - kLdsDepth] = (uint32_t)word;
         }
         ++sp;
     };
@@ -266,61 +271,50 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
         }
         // ... and one node visit per iteration
         if (node >= 0) {
-            uint32_t s0, s1, s2, s3;
-            int4 ch;
-            node_keys(nodes + node, np, inv, oinv, tb, s0, s1, s2, s3, ch);
+            ChildKey s0, s1, s2, s3;
+            node_keys(fetch_node(nodes, (uint32_t)node, np), inv, oinv, tb, s0, s1, s2, s3);
             sort4(s0, s1, s2, s3);
-            auto code_of = [&](uint32_t key) { return child_of(ch, key); };
-            auto t_of = [](uint32_t key) { return __uint_as_float(key & ~3u); };
-            // misses sort last, so the valid keys are a prefix: push the valid ones of s1..s3,
+            // entered boxes sort first, so they are a prefix: push the entered ones of s1..s3,
             // farthest first; with room in LDS all three slots are written unconditionally
             // (slots past the new top are dead) and only the top moves
-            const int nv = (int)(s1 != kMiss) + (int)(s2 != kMiss) + (int)(s3 != kMiss);
+            const int nv = (int)entered(s1) + (int)entered(s2) + (int)entered(s3);
             if (sp + 3 <= kLdsDepth) {
-                const uint32_t k1 = nv == 3 ? s3 : (nv == 2 ? s2 : s1);
-                const uint32_t k2 = nv == 3 ? s2 : s1;
-                auto entry = [&](uint32_t key) {
-                    return ((uint64_t)(key & ~3u) << 32) | (uint32_t)code_of(key);
-                };
-                s_stk[sp][tid] = entry(k1);
-                s_stk[sp + 1][tid] = entry(k2);
-                s_stk[sp + 2][tid] = entry(s1);
+                s_stk[sp][tid] = stack_word(nv == 3 ? s3 : (nv == 2 ? s2 : s1));
+                s_stk[sp + 1][tid] = stack_word(nv == 3 ? s2 : s1);
+                s_stk[sp + 2][tid] = stack_word(s1);
                 sp += nv;
             } else {
-                if (s3 != kMiss) push(code_of(s3), t_of(s3));
-                if (s2 != kMiss) push(code_of(s2), t_of(s2));
-                if (s1 != kMiss) push(code_of(s1), t_of(s1));
+                if (entered(s3)) push(stack_word(s3));
+                if (entered(s2)) push(stack_word(s2));
+                if (entered(s1)) push(stack_word(s1));
             }
             node = -1;
-            if (s0 != kMiss) {
-                const int32_t c0 = code_of(s0);
+            if (entered(s0)) {
+                const int32_t c0 = s0.code;
                 if (c0 >= 0) {
                     node = c0;
                 } else if (pcount == 0) {
                     pfirst = leaf_first(c0);
                     pcount = leaf_count(c0);
                 } else {
-                    push(c0, t_of(s0));
+                    push(stack_word(s0));
                 }
             }
         }
         // refill node / pending leaf from the stack
         while (node < 0 && sp > 0) {
             const int top = sp - 1;
-            int32_t e;
-            float t;
+            uint64_t word;
             if (top < kLdsDepth) {
-                const uint64_t v = s_stk[top][tid];
-                e = (int32_t)(uint32_t)v;
-                t = __uint_as_float((uint32_t)(v >> 32));
+                word = s_stk[top][tid];
             } else {
-                e = p_code[top - kLdsDepth];
-                t = p_t[top - kLdsDepth];
+                word = ((uint64_t)p_t[top - kLdsDepth] << 32) | p_code[top - kLdsDepth];
             }
-            if (t > tb) {
+            if (word_t(word) > tb) {
                 sp = top;
                 continue;
             }
+            const int32_t e = word_code(word);
             if (e >= 0) {
                 node = e;
                 sp = top;

@@ -51,16 +51,12 @@ __device__ inline float3 cross3(float3 a, float3 b)
     return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 
-__device__ inline float min3f(float a, float b, float c)
-{
-    const float m = a < b ? a : b;
-    return m < c ? m : c;
-}
-__device__ inline float max3f(float a, float b, float c)
-{
-    const float m = a > b ? a : b;
-    return m > c ? m : c;
-}
+// Least and greatest of three finite values.  fminf / fmaxf may return either zero when
+// given -0 and +0; the box test below cannot tell the two apart (x - pad and x + pad are
+// the same for both zeros when pad != 0, and comparisons treat them as equal), so its
+// decisions are those of any other exact min / max.
+__device__ inline float min3f(float a, float b, float c) { return fminf(fminf(a, b), c); }
+__device__ inline float max3f(float a, float b, float c) { return fmaxf(fmaxf(a, b), c); }
 
 // Moller-Trumbore (1997).  Returns t > 0 on a hit (and sets front = det > 0, i.e. the ray
 // meets the outward face), or a negative value on a miss.  A hit also needs the computed
@@ -83,10 +79,11 @@ __device__ inline float hit_triangle(float3 o, float3 w, float3 v0, float3 v1, f
     const float t = dot3(e2, Q) * inv;
     if (!(t > 0.0f)) return -1.0f;
     const float qx = o.x + t * w.x, qy = o.y + t * w.y, qz = o.z + t * w.z;
-    if (!(qx >= min3f(v0.x, v1.x, v2.x) - pad && qx <= max3f(v0.x, v1.x, v2.x) + pad &&
-          qy >= min3f(v0.y, v1.y, v2.y) - pad && qy <= max3f(v0.y, v1.y, v2.y) + pad &&
-          qz >= min3f(v0.z, v1.z, v2.z) - pad && qz <= max3f(v0.z, v1.z, v2.z) + pad))
-        return -1.0f;
+    // all six bounds evaluated (no short circuit): one straight-line test per wave
+    const bool in_x = (qx >= min3f(v0.x, v1.x, v2.x) - pad) & (qx <= max3f(v0.x, v1.x, v2.x) + pad);
+    const bool in_y = (qy >= min3f(v0.y, v1.y, v2.y) - pad) & (qy <= max3f(v0.y, v1.y, v2.y) + pad);
+    const bool in_z = (qz >= min3f(v0.z, v1.z, v2.z) - pad) & (qz <= max3f(v0.z, v1.z, v2.z) + pad);
+    if (!(in_x & in_y & in_z)) return -1.0f;
     front = det > 0.0f;
     return t;
 }

@@ -32,6 +32,11 @@
 #ifndef RTSDF_RAY_START_BATCH
 #define RTSDF_RAY_START_BATCH 12
 #endif
+// ... waves per SIMD the kernel is built for (its register budget, and the depth of its
+// per-lane LDS stack, which shares the CU's 160 KB among that many waves)
+#ifndef RTSDF_RAY_WAVES
+#define RTSDF_RAY_WAVES 6
+#endif
 
 // soft shadows: pixels per wave along x (the tile is RTSDF_SHADOW_TILE_X x 64/RTSDF_SHADOW_TILE_X)
 #ifndef RTSDF_SHADOW_TILE_X

@@ -3,8 +3,9 @@
 A blob is valid when: the header holds the triangle count and the hit padding; the leaf
 ranges reachable from the root partition the positions [0, nt) exactly once; every child
 box contains the boxes of all triangles under it (widened by twice the padding, see
-traverse.h); and the triangle records are a permutation of the input triangles with their
-vertices.  Returns the number of reachable 4-wide nodes.
+traverse.h); every unused slot of a reachable node holds the empty box lo = +inf,
+hi = -inf (traversal rejects unused slots by the slab test alone); and the triangle records
+are a permutation of the input triangles with their vertices.  Returns the number of reachable 4-wide nodes.
 """
 import numpy as np
 
@@ -60,6 +61,8 @@ def check(blob, verts, tris, pad):
         for q in range(4):
             ch = int(nodes[c]["child"][q])
             if ch == EMPTY:
+                assert (nodes[c]["lo"][:, q] == np.inf).all() and (nodes[c]["hi"][:, q] == -np.inf).all(), \
+                    "unused slot %d of node %d is not the empty box" % (q, c)
                 continue
             f, n = span(ch)
             if ch < 0:

@@ -1,12 +1,13 @@
 """The BVH blob validator used by the GPU tests, pinned on a hand-built blob: it accepts a
-correct two-leaf hierarchy and rejects a shrunk box, a duplicated leaf and a wrong vertex."""
+correct two-leaf hierarchy and rejects a shrunk box, a duplicated leaf, a wrong vertex and
+an unused slot whose box is not the empty one."""
 import numpy as np
 import pytest
 
 from bvh_check import NODE, TRI, check
 
 
-def blob(verts, tris, pad, shrink=False, dup=False, bad_vertex=False):
+def blob(verts, tris, pad, shrink=False, dup=False, bad_vertex=False, open_slot=False):
     nt = len(tris)
     nodes = np.zeros(max(nt - 1, 1), NODE)
     recs = np.zeros(nt, TRI)
@@ -29,6 +30,9 @@ def blob(verts, tris, pad, shrink=False, dup=False, bad_vertex=False):
         nodes[0]["child"][q] = ~(f | ((n - 1) << 26))
     if shrink:
         nodes[0]["hi"][0, 0] -= 0.1
+    if open_slot:   # an unused slot whose box a ray could enter
+        nodes[0]["lo"][:, 3] = 0.0
+        nodes[0]["hi"][:, 3] = 1.0
     hdr = np.zeros(64, np.int32)
     hdr[0], hdr[1] = nt, 0
     hdr[2] = np.float32(pad).view(np.int32)
@@ -47,7 +51,7 @@ def test_accepts_valid_blob():
     assert check(blob(v, t, 0.01), v, t, 0.01) == 1
 
 
-@pytest.mark.parametrize("bad", ["shrink", "dup", "bad_vertex"])
+@pytest.mark.parametrize("bad", ["shrink", "dup", "bad_vertex", "open_slot"])
 def test_rejects_corrupt_blob(bad):
     v, t = mesh()
     with pytest.raises(AssertionError):
