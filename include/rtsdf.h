@@ -117,12 +117,13 @@ rtsdf_status rtsdf_band(const int32_t* seeds, rtsdf_grid g, int32_t band_vox, in
  *   RTSDF_BVH_PLOC: parallel locally-ordered clustering (Meister & Bittner 2018: merge
  *                   mutual nearest neighbours by merged-box area within +-16 clusters
  *                   in Morton order; about 30 % fewer node visits per ray),
- * collapsed to a 4-wide hierarchy.  Triangle boxes are widened by 2 * h/256 so that
- * traversal returns exactly the brute-force closest hit of the hit test described at
- * rtsdf_raysample, whichever tree is built.  The blob is self-contained (it copies the
+ * collapsed to a 4-wide hierarchy whose child boxes are quantised to 8 bits per plane
+ * (rounded outward).  Triangle boxes are widened by 2 * h/256 so that traversal returns
+ * exactly the brute-force closest hit of the hit test described at rtsdf_raysample,
+ * whichever tree is built.  The blob is self-contained (it copies the
  * triangles).
  *   bvh   [rtsdf_bvh_bytes(nt)] out      work [rtsdf_bvh_work_bytes(nt)]
- * Errors: E_ARG, E_RANGE (nt outside [0, 2^25], unknown method), E_SIZE.
+ * Errors: E_ARG, E_RANGE (nt outside [0, 2^26], unknown method), E_SIZE.
  * ------------------------------------------------------------------------------------- */
 #define RTSDF_BVH_LBVH 0
 #define RTSDF_BVH_PLOC 1
@@ -320,7 +321,7 @@ rtsdf_status rtsdf_shadow_backward_ex(const float* fine, rtsdf_grid g, const rts
  *   bvh: rtsdf_build_bvh output for these tris; tris [nt*3] int32 (indices < nv)
  *   rays_per_voxel, rng_key, obj: as passed to rtsdf_raysample
  *   grad_verts [nv*3] float, ACCUMULATED with binary32 atomic adds
- * Errors: E_ARG, E_RANGE (rays_per_voxel, obj, nv < 0, nt outside [0, 2^25]).
+ * Errors: E_ARG, E_RANGE (rays_per_voxel, obj, nv < 0, nt outside [0, 2^26]).
  * ------------------------------------------------------------------------------------- */
 rtsdf_status rtsdf_backward(const float* grad_fine, const uint32_t* hits, const uint64_t* argmin,
                             const int32_t* band_list, const int32_t* band_count,
@@ -371,9 +372,8 @@ typedef struct rtsdf_batch_sizes {
 size_t rtsdf_batch_plan_bytes(int32_t nobj);
 /* Builds the plan from objs (HOST, nobj in [1, 65536]) into plan_host (host work only) and
  * records plan_device as the address of its device copy.  Errors: E_ARG (null pointers, a
- * bad grid or parameter), E_RANGE (counts: an object has at most 2^25 triangles, and the
- * batch must stay below 2^31 grid points and vertices and 2^26 triangles), E_SIZE
- * (plan_bytes too small). */
+ * bad grid or parameter), E_RANGE (counts; the batch must stay below 2^31 grid points and
+ * vertices and 2^26 triangles), E_SIZE (plan_bytes too small). */
 rtsdf_status rtsdf_batch_plan(const rtsdf_object* objs, int32_t nobj, void* plan_host, void* plan_device,
                               size_t plan_bytes, rtsdf_batch_sizes* sizes);
 /* Copies the host plan to its device copy on `stream` and waits for the copy (this call

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kThreads) void k_sdf_backward(
         while (true) {
             if (cur >= 0) {
                 ChildKey s0, s1, s2, s3;
-                node_keys(fetch_node(nodes, (uint32_t)cur, np), inv, oinv, tb, s0, s1, s2, s3);
+                node_keys(fetch_node(nodes, (uint32_t)cur), np, inv, oinv, tb, s0, s1, s2, s3);
                 sort4(s0, s1, s2, s3);
                 if (entered(s3)) push(stack_word(s3));
                 if (entered(s2)) push(stack_word(s2));

@@ -372,7 +372,7 @@ rtsdf_status rtsdf_build_bvh(const float* verts, int32_t nv, const int32_t* tris
 {
     if (method != RTSDF_BVH_LBVH && method != RTSDF_BVH_PLOC) return fail(RTSDF_E_RANGE, "unknown method %d", method);
     if (rtsdf_status st = check_grid(g)) return st;
-    if (nv < 0 || nt < 0 || nt > rtsdf::kBvhMaxTris) return fail(RTSDF_E_RANGE, "nt %d outside [0, 2^25]", nt);
+    if (nv < 0 || nt < 0 || nt > rtsdf::kBvhMaxTris) return fail(RTSDF_E_RANGE, "nt %d outside [0, 2^26]", nt);
     if (!bvh) return fail(RTSDF_E_ARG, "bvh is NULL");
     if (nt > 0 && (!verts || !tris || !work)) return fail(RTSDF_E_ARG, "verts, tris or work is NULL");
     if (nt > 0 && nv == 0) return fail(RTSDF_E_RANGE, "triangles given but no vertices");
@@ -624,7 +624,7 @@ rtsdf_status rtsdf_backward(const float* grad_fine, const uint32_t* hits, const 
                             void* stream)
 {
     if (rtsdf_status st = check_grid(g)) return st;
-    if (nv < 0 || nt < 0 || nt > rtsdf::kBvhMaxTris) return fail(RTSDF_E_RANGE, "nv, nt outside [0, 2^25]");
+    if (nv < 0 || nt < 0 || nt > rtsdf::kBvhMaxTris) return fail(RTSDF_E_RANGE, "nv, nt outside [0, 2^26]");
     if (!grad_fine || !hits || !argmin || !band_list || !band_count || !bvh)
         return fail(RTSDF_E_ARG, "NULL pointer");
     if (nt > 0 && (!tris || !grad_verts || nv == 0)) return fail(RTSDF_E_ARG, "tris or grad_verts is NULL");

@@ -109,12 +109,11 @@ __host__ __device__ inline int32_t jfa_offset(int32_t k0, int32_t nhalf, int32_t
 // A 4-wide node is stored at the index of the binary radix-tree node it was collapsed
 // from (only some indices are reachable).  Child codes: c >= 0 is a node index,
 // kBvhEmptySlot an unused slot, any other c < 0 a leaf range ~c = first | (count-1) << 26
-// of `count` (1..kLeafMax) consecutive triangles in sorted order.  An unused slot's box is
-// the empty box lo = +inf, hi = -inf, which no ray enters.
+// of `count` (1..kLeafMax) consecutive triangles in sorted order.
 constexpr int32_t kBvhEmptySlot = (int32_t)0x80000000;
-// Triangles of one hierarchy: fewer than 2^25 nodes keep a node's byte offset (node * 128)
-// within 32 bits, which traversal uses to address a node's planes.
-constexpr int32_t kBvhMaxTris = 1 << 25;
+// Triangles of one hierarchy: at most 2^26 (the leaf code's first field); fewer than 2^26
+// nodes keep a node's byte offset (node * 64) within 32 bits, which traversal relies on.
+constexpr int32_t kBvhMaxTris = 1 << 26;
 constexpr int kLeafMax = RTSDF_LEAF_MAX;
 
 struct BvhHeader {
@@ -123,12 +122,21 @@ struct BvhHeader {
     float pad;        // hit-test widening (h / 256)
     int32_t reserved[61];
 };
-struct alignas(16) Bvh4Node {  // structure of arrays over the 4 children
-    float4 lox, loy, loz;
-    float4 hix, hiy, hiz;
+// A 4-wide node (64 bytes).  The children's boxes are quantised to 8 bits per plane on a
+// grid anchored at the node box's low corner o with a power-of-two step s per axis: child
+// q's low plane on axis a is o_a + s_a * byte q of lo[a], its high plane o_a + s_a * byte q
+// of hi[a].  Low planes are rounded down and high planes up (in exact arithmetic), so each
+// quantised box contains its child's box.  Unused slots (code kBvhEmptySlot) hold lo bytes
+// 255 and hi bytes 0; traversal rejects them by their code.
+struct alignas(64) Bvh4Node {
+    float ox, oy, oz;   // o: the node box's low corner
+    uint32_t exps;      // biased exponents of the steps: s_a = 2^(e_a - 127), e = ex | ey << 8 | ez << 16
     int4 child;
-    int4 unused;
+    uint32_t lo[3];     // byte q: child q's low plane on x, y, z
+    uint32_t hi[3];     // byte q: child q's high plane on x, y, z
+    uint32_t unused[2];
 };
+static_assert(sizeof(Bvh4Node) == 64, "node size");
 struct alignas(16) BvhTri {   // triangle in sorted (leaf) order
     float4 v0;    // xyz = v0, w = bits of the original triangle index
     float4 v1;    // xyz = v1

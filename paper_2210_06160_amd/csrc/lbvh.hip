@@ -776,29 +776,51 @@ __global__ __launch_bounds__(256) void k_collapse4(Args a, const BinNode* __rest
         s[best] = child_slot(nodes, c, true);
         ++m;
     }
-    const float inf = __int_as_float(0x7f800000);
-    float lx[4], ly[4], lz[4], hx[4], hy[4], hz[4];
-    int32_t cc[4];
-    for (int q = 0; q < 4; ++q) {
-        if (q < m) {
-            lx[q] = s[q].lo.x; ly[q] = s[q].lo.y; lz[q] = s[q].lo.z;
-            hx[q] = s[q].hi.x; hy[q] = s[q].hi.y; hz[q] = s[q].hi.z;
-            cc[q] = s[q].count <= kLeafMax ? leaf_code(s[q].first, s[q].count) : s[q].code;
-        } else {
-            lx[q] = ly[q] = lz[q] = inf;
-            hx[q] = hy[q] = hz[q] = -inf;
-            cc[q] = kBvhEmptySlot;
-        }
+    // the node box (the children's union) and, per axis, the least power-of-two step s with
+    // 255 s >= the box's extent; planes are quantised in binary64, where the differences of
+    // binary32 coordinates and the division by s are exact for coordinates of comparable
+    // magnitude (any rounding elsewhere stays far below the boxes' 2 * pad widening)
+    float3 blo = s[0].lo, bhi = s[0].hi;
+    for (int q = 1; q < m; ++q) {
+        blo = make_float3(fminf(blo.x, s[q].lo.x), fminf(blo.y, s[q].lo.y), fminf(blo.z, s[q].lo.z));
+        bhi = make_float3(fmaxf(bhi.x, s[q].hi.x), fmaxf(bhi.y, s[q].hi.y), fmaxf(bhi.z, s[q].hi.z));
     }
+    const float bl[3] = {blo.x, blo.y, blo.z}, bh[3] = {bhi.x, bhi.y, bhi.z};
     Bvh4Node o;
-    o.lox = make_float4(lx[0], lx[1], lx[2], lx[3]);
-    o.loy = make_float4(ly[0], ly[1], ly[2], ly[3]);
-    o.loz = make_float4(lz[0], lz[1], lz[2], lz[3]);
-    o.hix = make_float4(hx[0], hx[1], hx[2], hx[3]);
-    o.hiy = make_float4(hy[0], hy[1], hy[2], hy[3]);
-    o.hiz = make_float4(hz[0], hz[1], hz[2], hz[3]);
+    o.ox = blo.x;
+    o.oy = blo.y;
+    o.oz = blo.z;
+    o.exps = 0u;
+    for (int ax = 0; ax < 3; ++ax) {
+        const double ext = (double)bh[ax] - (double)bl[ax];
+        int k = -126;
+        if (ext > 0.0) {
+            int p;
+            frexp(ext / 255.0, &p);   // ext / 255 < 2^p
+            k = max(p, -126);
+        }
+        const double step = ldexp(1.0, k);
+        o.exps |= (uint32_t)(k + 127) << (8 * ax);
+        uint32_t lw = 0u, hw = 0u;
+        for (int q = 0; q < 4; ++q) {
+            uint32_t ql = 255u, qh = 0u;  // unused slot: an inverted box
+            if (q < m) {
+                const float cl = ax == 0 ? s[q].lo.x : (ax == 1 ? s[q].lo.y : s[q].lo.z);
+                const float ch = ax == 0 ? s[q].hi.x : (ax == 1 ? s[q].hi.y : s[q].hi.z);
+                ql = (uint32_t)min(max(floor(((double)cl - (double)bl[ax]) / step), 0.0), 255.0);
+                qh = (uint32_t)min(max(ceil(((double)ch - (double)bl[ax]) / step), 0.0), 255.0);
+            }
+            lw |= ql << (8 * q);
+            hw |= qh << (8 * q);
+        }
+        o.lo[ax] = lw;
+        o.hi[ax] = hw;
+    }
+    int32_t cc[4];
+    for (int q = 0; q < 4; ++q)
+        cc[q] = q >= m ? kBvhEmptySlot : (s[q].count <= kLeafMax ? leaf_code(s[q].first, s[q].count) : s[q].code);
     o.child = make_int4(cc[0], cc[1], cc[2], cc[3]);
-    o.unused = make_int4(0, 0, 0, 0);
+    o.unused[0] = o.unused[1] = 0u;
     ((Bvh4Node*)(bvh + sg.bvh_off + 256))[i] = o;
 }
 

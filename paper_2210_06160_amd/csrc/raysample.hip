@@ -39,6 +39,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMinWaves = RTSDF_RAY_WAVES;  // waves per SIMD the register budget allows
+constexpr int kPopTrips = RTSDF_RAY_POP_TRIPS;  // stack pops per lane and iteration (0: no limit)
 // LDS stack entries per lane: the CU's 160 KB shared by kMinWaves waves on each of 4 SIMDs
 constexpr int kLdsDepth = 163840 / (4 * kMinWaves) / (64 * (int)sizeof(uint64_t));
 static_assert(kLdsDepth >= 4 && kLdsDepth < kMaxStack, "stack depth");
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
     float3 o = make_float3(0.f, 0.f, 0.f);
     bool alive = true, active = false;
     float3 w = o, inv = o, oinv = o;
-    NearPlanes np{kLoX, kLoY, kLoZ};
+    NearPlanes np{true, true, true};
     float tb = inf;
     int32_t bid = kNone;
     bool bfr = false;
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
         // ... and one node visit per iteration
         if (node >= 0) {
             ChildKey s0, s1, s2, s3;
-            node_keys(fetch_node(nodes, (uint32_t)node, np), inv, oinv, tb, s0, s1, s2, s3);
+            node_keys(fetch_node(nodes, (uint32_t)node), np, inv, oinv, tb, s0, s1, s2, s3);
             sort4(s0, s1, s2, s3);
             // entered boxes sort first, so they are a prefix: push the entered ones of s1..s3,
             // farthest first; with room in LDS all three slots are written unconditionally
@@ -302,7 +303,8 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
             }
         }
         // refill node / pending leaf from the stack
-        while (node < 0 && sp > 0) {
+        int trips = 0;
+        while (node < 0 && sp > 0 && (kPopTrips == 0 || trips++ < kPopTrips)) {
             const int top = sp - 1;
             uint64_t word;
             if (top < kLdsDepth) {

@@ -1,8 +1,9 @@
 // Helpers shared by the kernels that trace rays through the 4-wide hierarchy written by
-// lbvh.hip: the slab test of a child box, the sort key of a child, and bounds of the
-// per-lane traversal stack.  Box tests may round freely: every triangle box is widened by
-// 2*pad while a hit's computed point must lie within pad of its triangle's box, so a box
-// holding a hit is never culled and traversal returns the brute-force least (t, index).
+// lbvh.hip: the slab test of a quantised child box, the sort key of a child, and bounds of
+// the per-lane traversal stack.  Box tests may round freely: every triangle box is widened
+// by 2*pad, the quantised boxes contain those, and a hit's computed point must lie within
+// pad of its triangle's box, so a box holding a hit is never culled and traversal returns
+// the brute-force least (t, index).
 #pragma once
 
 #include "sampling.h"
@@ -12,30 +13,22 @@ namespace rtsdf {
 constexpr int kMaxStack = 176;  // <= 3 pushes per level + 1; tree depth <= 56
 constexpr int32_t kNone = 0x7FFFFFFF;
 
-// byte offsets of a node's plane arrays (all below 128, the node's size and alignment)
-constexpr uint32_t kLoX = (uint32_t)offsetof(Bvh4Node, lox), kLoY = (uint32_t)offsetof(Bvh4Node, loy);
-constexpr uint32_t kLoZ = (uint32_t)offsetof(Bvh4Node, loz), kHiX = (uint32_t)offsetof(Bvh4Node, hix);
-constexpr uint32_t kHiY = (uint32_t)offsetof(Bvh4Node, hiy), kHiZ = (uint32_t)offsetof(Bvh4Node, hiz);
-constexpr uint32_t kChild = (uint32_t)offsetof(Bvh4Node, child);
-static_assert(sizeof(Bvh4Node) == 128 && kChild < 128, "node byte offsets are node * 128 | field");
-
-// Per-ray byte offsets of each axis's near planes: lo where the slab reciprocal is
-// positive, else hi (the direction's signs fix which plane is nearer, so the two planes of
-// an axis need no ordering); an axis's far planes are at near ^ (lo ^ hi).
+// Per-ray choice of each axis's near planes: the low planes where the slab reciprocal is
+// positive, else the high ones (the direction's signs fix which plane is nearer, so the two
+// planes of an axis need no ordering).
 struct NearPlanes {
-    uint32_t x, y, z;
+    bool x, y, z;
 };
 
 __device__ inline NearPlanes near_planes(float3 inv)
 {
-    return NearPlanes{inv.x > 0.0f ? kLoX : kHiX, inv.y > 0.0f ? kLoY : kHiY, inv.z > 0.0f ? kLoZ : kHiZ};
+    return NearPlanes{inv.x > 0.0f, inv.y > 0.0f, inv.z > 0.0f};
 }
 
 // A child's key: its entry parameter's bits (>= 0, so they order as unsigned) and its code;
 // on the traversal stack the two form one 64-bit word (t bits high).  A box the ray misses,
-// or enters beyond tbest, gets t bits kMissT and sorts after every entered box.  Unused slots
-// hold the empty box lo = +inf, hi = -inf (entry +inf, exit -inf for every direction), so
-// the slab test alone rejects them.
+// or enters beyond tbest, and an unused slot, get t bits kMissT and sort after every entered
+// box.
 constexpr uint32_t kMissT = 0xFFFFFFFFu;
 struct ChildKey {
     uint32_t t;
@@ -46,17 +39,18 @@ __device__ inline uint64_t stack_word(const ChildKey& k) { return ((uint64_t)k.t
 __device__ inline float word_t(uint64_t w) { return __uint_as_float((uint32_t)(w >> 32)); }
 __device__ inline int32_t word_code(uint64_t w) { return (int32_t)(uint32_t)w; }
 
-// Slab test of one child box with the ray's near and far planes, the interval clipped to
+// Slab test of one child box given its near and far planes on each axis as parameters
+// t = q * a + b of the quantised plane q (see node_keys), the interval clipped to
 // [0, tbest]; returns the child's key.
-__device__ inline ChildKey box_key(float nx, float ny, float nz, float fx, float fy, float fz, float3 inv,
-                                   float3 oinv, float tbest, int32_t code)
+__device__ inline ChildKey box_key(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t fx, uint32_t fy, uint32_t fz,
+                                   float3 a, float3 b, float tbest, int32_t code)
 {
-    const float x0 = fmaf(nx, inv.x, -oinv.x), x1 = fmaf(fx, inv.x, -oinv.x);
-    const float y0 = fmaf(ny, inv.y, -oinv.y), y1 = fmaf(fy, inv.y, -oinv.y);
-    const float z0 = fmaf(nz, inv.z, -oinv.z), z1 = fmaf(fz, inv.z, -oinv.z);
+    const float x0 = fmaf((float)nx, a.x, b.x), x1 = fmaf((float)fx, a.x, b.x);
+    const float y0 = fmaf((float)ny, a.y, b.y), y1 = fmaf((float)fy, a.y, b.y);
+    const float z0 = fmaf((float)nz, a.z, b.z), z1 = fmaf((float)fz, a.z, b.z);
     const float tmin = fmaxf(fmaxf(x0, y0), fmaxf(z0, 0.0f));
     const float tmax = fminf(fminf(x1, y1), fminf(z1, tbest));
-    return ChildKey{tmin <= tmax ? __float_as_uint(tmin) : kMissT, code};
+    return ChildKey{(tmin <= tmax && code != kBvhEmptySlot) ? __float_as_uint(tmin) : kMissT, code};
 }
 
 // reciprocal for slab tests only (rounding there is harmless; see the file comment)
@@ -65,38 +59,56 @@ __device__ inline float slab_rcp(float a)
     return __builtin_amdgcn_rcpf(fabsf(a) < 1e-20f ? copysignf(1e-20f, a) : a);
 }
 
-// What a ray reads of a node: its near and far planes per axis and the child codes.
+// What a ray reads of a node: origin and step exponents, child codes, and the quantised
+// planes (lo x, lo y, lo z, hi x | hi y, hi z), in four loads.
 struct NodeFetch {
-    float4 nx, ny, nz, fx, fy, fz;
+    float4 hdr;
     int4 ch;
+    uint4 qa;
+    uint2 qb;
 };
 
 // Reads node `node` of the node array at `nodes` (byte offsets are 32-bit: a hierarchy
-// holds fewer than 2^25 nodes).
-__device__ inline NodeFetch fetch_node(const char* __restrict__ nodes, uint32_t node, const NearPlanes& np)
+// holds fewer than 2^26 nodes).
+__device__ inline NodeFetch fetch_node(const char* __restrict__ nodes, uint32_t node)
 {
-    const uint32_t b = node << 7;
-    const uint32_t ax = b | np.x, ay = b | np.y, az = b | np.z;
-    auto planes = [&](uint32_t off) { return *(const float4*)(nodes + off); };
+    const uint32_t b = node << 6;
     NodeFetch f;
-    f.nx = planes(ax);
-    f.ny = planes(ay);
-    f.nz = planes(az);
-    f.fx = planes(ax ^ (kLoX ^ kHiX));
-    f.fy = planes(ay ^ (kLoY ^ kHiY));
-    f.fz = planes(az ^ (kLoZ ^ kHiZ));
-    f.ch = *(const int4*)(nodes + b + kChild);
+    f.hdr = *(const float4*)(nodes + b);
+    f.ch = *(const int4*)(nodes + b + offsetof(Bvh4Node, child));
+    f.qa = *(const uint4*)(nodes + b + offsetof(Bvh4Node, lo));
+    f.qb = *(const uint2*)(nodes + b + offsetof(Bvh4Node, hi[1]));
     return f;
 }
 
-// The four children's keys of a fetched node.
-__device__ inline void node_keys(const NodeFetch& f, float3 inv, float3 oinv, float tb, ChildKey& s0, ChildKey& s1,
-                                 ChildKey& s2, ChildKey& s3)
+// byte q of a quantised plane word
+__device__ inline uint32_t plane_byte(uint32_t w, int q) { return (w >> (8 * q)) & 0xFFu; }
+
+// The step 2^(e - 127) of the biased exponent in bits [sh, sh + 8) of e.
+__device__ inline float axis_step(uint32_t e, int sh) { return __uint_as_float(((e >> sh) & 0xFFu) << 23); }
+
+// The four children's keys of a fetched node.  On axis a a quantised plane q lies at
+// o_a + q s_a, where the ray is at parameter (o_a + q s_a - origin_a) inv_a = q (s_a inv_a)
+// + (o_a inv_a - origin_a inv_a).
+__device__ inline void node_keys(const NodeFetch& f, const NearPlanes& np, float3 inv, float3 oinv, float tb,
+                                 ChildKey& s0, ChildKey& s1, ChildKey& s2, ChildKey& s3)
 {
-    s0 = box_key(f.nx.x, f.ny.x, f.nz.x, f.fx.x, f.fy.x, f.fz.x, inv, oinv, tb, f.ch.x);
-    s1 = box_key(f.nx.y, f.ny.y, f.nz.y, f.fx.y, f.fy.y, f.fz.y, inv, oinv, tb, f.ch.y);
-    s2 = box_key(f.nx.z, f.ny.z, f.nz.z, f.fx.z, f.fy.z, f.fz.z, inv, oinv, tb, f.ch.z);
-    s3 = box_key(f.nx.w, f.ny.w, f.nz.w, f.fx.w, f.fy.w, f.fz.w, inv, oinv, tb, f.ch.w);
+    const uint32_t e = __float_as_uint(f.hdr.w);
+    const float3 a = make_float3(axis_step(e, 0) * inv.x, axis_step(e, 8) * inv.y, axis_step(e, 16) * inv.z);
+    const float3 b = make_float3(fmaf(f.hdr.x, inv.x, -oinv.x), fmaf(f.hdr.y, inv.y, -oinv.y),
+                                 fmaf(f.hdr.z, inv.z, -oinv.z));
+    const uint32_t lx = f.qa.x, ly = f.qa.y, lz = f.qa.z, hx = f.qa.w, hy = f.qb.x, hz = f.qb.y;
+    const uint32_t nx = np.x ? lx : hx, fx = np.x ? hx : lx;
+    const uint32_t ny = np.y ? ly : hy, fy = np.y ? hy : ly;
+    const uint32_t nz = np.z ? lz : hz, fz = np.z ? hz : lz;
+    auto key = [&](int q, int32_t code) {
+        return box_key(plane_byte(nx, q), plane_byte(ny, q), plane_byte(nz, q), plane_byte(fx, q), plane_byte(fy, q),
+                       plane_byte(fz, q), a, b, tb, code);
+    };
+    s0 = key(0, f.ch.x);
+    s1 = key(1, f.ch.y);
+    s2 = key(2, f.ch.z);
+    s3 = key(3, f.ch.w);
 }
 
 // sorting network on the keys' entry parameters: afterwards s0 .. s3 enter in increasing

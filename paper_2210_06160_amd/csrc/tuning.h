@@ -37,6 +37,11 @@
 #ifndef RTSDF_RAY_WAVES
 #define RTSDF_RAY_WAVES 6
 #endif
+// ... and the most stack entries a lane pops per loop iteration (0: until it finds work); a
+// lane that needs more pops carries on in the next iteration
+#ifndef RTSDF_RAY_POP_TRIPS
+#define RTSDF_RAY_POP_TRIPS 2
+#endif
 
 // soft shadows: pixels per wave along x (the tile is RTSDF_SHADOW_TILE_X x 64/RTSDF_SHADOW_TILE_X)
 #ifndef RTSDF_SHADOW_TILE_X

@@ -2,14 +2,25 @@
 
 A blob is valid when: the header holds the triangle count and the hit padding; the leaf
 ranges reachable from the root partition the positions [0, nt) exactly once; every child
-box contains the boxes of all triangles under it (widened by twice the padding, see
-traverse.h); every unused slot of a reachable node holds the empty box lo = +inf,
-hi = -inf (traversal rejects unused slots by the slab test alone); and the triangle records
-are a permutation of the input triangles with their vertices.  Returns the number of reachable 4-wide nodes.
+box, decoded from its 8-bit planes (origin + byte * 2^(e - 127) per axis, exactly in
+binary64), contains the boxes of all triangles under it (widened by twice the padding, see
+traverse.h); every unused slot of a reachable node holds low bytes 255 and high bytes 0;
+and the triangle records are a permutation of the input triangles with their vertices.  Returns the number of reachable 4-wide nodes.
 """
 import numpy as np
 
-NODE = np.dtype([("lo", "<f4", (3, 4)), ("hi", "<f4", (3, 4)), ("child", "<i4", (4,)), ("unused", "<i4", (4,))])
+NODE = np.dtype([("o", "<f4", (3,)), ("exps", "<u4"), ("child", "<i4", (4,)), ("lo", "<u4", (3,)), ("hi", "<u4", (3,)),
+                 ("unused", "<u4", (2,))])
+
+
+def child_box(node, q):
+    """Binary64 low and high corners of child q's quantised box."""
+    e = np.array([(int(node["exps"]) >> (8 * a)) & 0xFF for a in range(3)])
+    step = np.ldexp(1.0, e - 127)
+    o = node["o"].astype(np.float64)
+    lq = np.array([(int(node["lo"][a]) >> (8 * q)) & 0xFF for a in range(3)], np.float64)
+    hq = np.array([(int(node["hi"][a]) >> (8 * q)) & 0xFF for a in range(3)], np.float64)
+    return o + lq * step, o + hq * step
 TRI = np.dtype([("v", "<f4", (3, 4))])
 EMPTY = -2 ** 31
 
@@ -61,13 +72,14 @@ def check(blob, verts, tris, pad):
         for q in range(4):
             ch = int(nodes[c]["child"][q])
             if ch == EMPTY:
-                assert (nodes[c]["lo"][:, q] == np.inf).all() and (nodes[c]["hi"][:, q] == -np.inf).all(), \
-                    "unused slot %d of node %d is not the empty box" % (q, c)
+                assert all((int(nodes[c]["lo"][a]) >> (8 * q)) & 0xFF == 255 and
+                           (int(nodes[c]["hi"][a]) >> (8 * q)) & 0xFF == 0 for a in range(3)), \
+                    "unused slot %d of node %d is not the inverted box" % (q, c)
                 continue
             f, n = span(ch)
             if ch < 0:
                 covered[f:f + n] += 1
-            blo, bhi = nodes[c]["lo"][:, q], nodes[c]["hi"][:, q]
+            blo, bhi = child_box(nodes[c], q)
             assert (lo_t[f:f + n].min(axis=0) >= blo).all() and (hi_t[f:f + n].max(axis=0) <= bhi).all(), \
                 "child box of node %d misses a triangle" % c
             lo = f if lo is None else min(lo, f)

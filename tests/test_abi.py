@@ -66,7 +66,7 @@ def test_host_validation(L):
     assert lib.rtsdf_band(fake(), g, 2, fake(), fake(), fake(), 0, None) == E_SIZE
     # bvh
     assert lib.rtsdf_build_bvh(fake(), 3, fake(), 1, g, 1, fake(), 10, fake(), 1 << 20, None) == E_SIZE
-    assert lib.rtsdf_build_bvh(fake(), 3, fake(), (1 << 25) + 1, g, 1, fake(), 1 << 40, fake(), 1 << 40,
+    assert lib.rtsdf_build_bvh(fake(), 3, fake(), (1 << 26) + 1, g, 1, fake(), 1 << 40, fake(), 1 << 40,
                                None) == E_RANGE
     assert lib.rtsdf_build_bvh(fake(), 3, fake(), 1, g, 2, fake(), 1 << 20, fake(), 1 << 20, None) == E_RANGE
     # raysample

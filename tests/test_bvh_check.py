@@ -1,10 +1,31 @@
 """The BVH blob validator used by the GPU tests, pinned on a hand-built blob: it accepts a
 correct two-leaf hierarchy and rejects a shrunk box, a duplicated leaf, a wrong vertex and
-an unused slot whose box is not the empty one."""
+an unused slot whose quantised box is not inverted."""
 import numpy as np
 import pytest
 
 from bvh_check import NODE, TRI, check
+
+
+def quantise(node, boxes):
+    """Writes the quantised child boxes [(lo, hi) per slot, None for unused] into node."""
+    used = [bx for bx in boxes if bx is not None]
+    blo = np.min([bx[0] for bx in used], axis=0).astype(np.float32)
+    bhi = np.max([bx[1] for bx in used], axis=0).astype(np.float32)
+    node["o"] = blo
+    exps, lo, hi = 0, [0, 0, 0], [0, 0, 0]
+    for a in range(3):
+        ext = float(bhi[a]) - float(blo[a])
+        k = max(int(np.frexp(ext / 255.0)[1]), -126) if ext > 0 else -126
+        exps |= (k + 127) << (8 * a)
+        step = np.ldexp(1.0, k)
+        for q, bx in enumerate(boxes):
+            ql, qh = (255, 0) if bx is None else (
+                int(np.clip(np.floor((float(bx[0][a]) - float(blo[a])) / step), 0, 255)),
+                int(np.clip(np.ceil((float(bx[1][a]) - float(blo[a])) / step), 0, 255)))
+            lo[a] |= ql << (8 * q)
+            hi[a] |= qh << (8 * q)
+    node["exps"], node["lo"], node["hi"] = exps, lo, hi
 
 
 def blob(verts, tris, pad, shrink=False, dup=False, bad_vertex=False, open_slot=False):
@@ -21,18 +42,17 @@ def blob(verts, tris, pad, shrink=False, dup=False, bad_vertex=False, open_slot=
     ranges = [(0, 3), (3, 1)]
     if dup:
         ranges = [(0, 3), (2, 2)]
-    nodes[0]["lo"][:] = np.inf
-    nodes[0]["hi"][:] = -np.inf
+    boxes = [None] * 4
     nodes[0]["child"][:] = -2 ** 31
     for q, (f, n) in enumerate(ranges):
-        nodes[0]["lo"][:, q] = lo[f:f + n].min(0)
-        nodes[0]["hi"][:, q] = hi[f:f + n].max(0)
+        boxes[q] = (lo[f:f + n].min(0), hi[f:f + n].max(0))
         nodes[0]["child"][q] = ~(f | ((n - 1) << 26))
-    if shrink:
-        nodes[0]["hi"][0, 0] -= 0.1
-    if open_slot:   # an unused slot whose box a ray could enter
-        nodes[0]["lo"][:, 3] = 0.0
-        nodes[0]["hi"][:, 3] = 1.0
+    quantise(nodes[0], boxes)
+    if shrink:   # child 0's high x plane one step lower than its triangles need
+        w = int(nodes[0]["hi"][0])
+        nodes[0]["hi"][0] = (w & ~0xFF) | max((w & 0xFF) - 1, 0)
+    if open_slot:   # an unused slot whose quantised box is not inverted
+        nodes[0]["lo"][0] = int(nodes[0]["lo"][0]) & ~(0xFF << 24)
     hdr = np.zeros(64, np.int32)
     hdr[0], hdr[1] = nt, 0
     hdr[2] = np.float32(pad).view(np.int32)
