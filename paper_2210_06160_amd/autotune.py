@@ -26,8 +26,7 @@ TUNING_H = os.path.join(HERE, "csrc", "tuning.h")
 
 GROUPS = {
     "jfa": {"RTSDF_JFA_CHUNK": [16, 32, 64], "RTSDF_JFA_ROWS": [2, 4, 8]},
-    "ray": {"RTSDF_RAY_CHUNK": [32], "RTSDF_RAY_START_BATCH": [10, 12, 14], "RTSDF_RAY_WAVES": [6, 7, 8]},
-    "ray_pop": {"RTSDF_RAY_POP_TRIPS": [0, 1, 2, 3, 4]},
+    "ray": {"RTSDF_RAY_START_BATCH": [8, 12, 16], "RTSDF_RAY_WAVES": [6, 7], "RTSDF_RAY_POP_TRIPS": [1, 2]},
     "shadow": {"RTSDF_SHADOW_TILE_X": [1, 2, 4, 8]},
     "ray_small": {"RTSDF_RAY_RANGES": [8, 32, 64], "RTSDF_RAY_CHUNK_SMALL": [16, 32, 128],
                   "RTSDF_RAY_CHUNK_RAYS": [32, 64, 128]},
@@ -88,7 +87,7 @@ def time_candidate(group, path, reps):
                 out.append(a.elapsed_time(b))
         return statistics.median(out)
 
-    if group in ("jfa", "ray", "ray_pop"):
+    if group in ("jfa", "ray"):
         sc = synth.scene_static()
         S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
         S.voxelize()

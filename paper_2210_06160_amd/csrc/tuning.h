@@ -35,7 +35,7 @@
 // ... waves per SIMD the kernel is built for (its register budget, and the depth of its
 // per-lane LDS stack, which shares the CU's 160 KB among that many waves)
 #ifndef RTSDF_RAY_WAVES
-#define RTSDF_RAY_WAVES 6
+#define RTSDF_RAY_WAVES 7
 #endif
 // ... and the most stack entries a lane pops per loop iteration (0: until it finds work); a
 // lane that needs more pops carries on in the next iteration
