@@ -51,7 +51,7 @@
 // hierarchy shape: most triangles in a leaf of the 4-wide tree, and the PLOC neighbourhood
 // radius (positions searched on each side for a cluster's nearest neighbour)
 #ifndef RTSDF_LEAF_MAX
-#define RTSDF_LEAF_MAX 3
+#define RTSDF_LEAF_MAX 2
 #endif
 #ifndef RTSDF_PLOC_RADIUS
 #define RTSDF_PLOC_RADIUS 16
