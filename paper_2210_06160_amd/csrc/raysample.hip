@@ -23,8 +23,9 @@
 // Traversal of the 4-wide hierarchy: the four child boxes are tested at once, the hits are
 // sorted by entry distance (packed into uint keys with the slot in the two low bits, the
 // distance rounded down, which can only keep more boxes), the nearest node is visited next
-// and the others go on a per-lane stack of (child code, entry t) in LDS that spills to
-// private memory past kLdsDepth.  Leaf ranges are tested one triangle per iteration.  A box
+// and the others go on a per-lane stack of (child code, entry t) in LDS (t rounded down to
+// its top 16 bits there, which can only keep more boxes) that spills to private memory past
+// kLdsDepth.  Leaf ranges are tested one triangle per iteration.  A box
 // is culled only when its entry parameter exceeds the best hit so far (ties are still
 // visited, because the tie-break is the triangle index).  Box tests may round freely:
 // every triangle box is widened by 2*pad while a hit's computed point must lie within pad
@@ -38,11 +39,17 @@ namespace rtsdf {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kMinWaves = RTSDF_RAY_WAVES;  // waves per SIMD the register budget allows
+// waves per SIMD the register budget allows: single-object and batched instances (the
+// latter keeps its object's grid and hierarchy per lane, and needs more registers)
+template <bool kBatch>
+constexpr int kMinWaves = kBatch ? RTSDF_RAY_WAVES_BATCH : RTSDF_RAY_WAVES;
 constexpr int kPopTrips = RTSDF_RAY_POP_TRIPS;  // stack pops per lane and iteration (0: no limit)
-// LDS stack entries per lane: the CU's 160 KB shared by kMinWaves waves on each of 4 SIMDs
-constexpr int kLdsDepth = 163840 / (4 * kMinWaves) / (64 * (int)sizeof(uint64_t));
-static_assert(kLdsDepth >= 4 && kLdsDepth < kMaxStack, "stack depth");
+// LDS stack entries per lane (6 bytes each: a child code and the top 16 bits of its entry
+// t): the CU's 160 KB shared by kMinWaves waves on each of 4 SIMDs
+template <bool kBatch>
+constexpr int kLdsDepth = 163840 / (4 * kMinWaves<kBatch>) / (64 * 6);
+static_assert(kLdsDepth<false> >= 4 && kLdsDepth<false> < kMaxStack, "stack depth");
+static_assert(kLdsDepth<true> >= 4 && kLdsDepth<true> < kMaxStack, "stack depth");
 constexpr int kXcds = 8;
 constexpr int32_t kChunk = RTSDF_RAY_CHUNK;            // work units a wave takes per cursor atomic
 constexpr int32_t kChunkSmall = RTSDF_RAY_CHUNK_SMALL;  // ... when there are few units per lane
@@ -79,7 +86,7 @@ __global__ void k_cursor_reset(int32_t* cursors)
 // kBatch: the mask list indexes concatenated grids; each voxel's object (binary search over
 // the plan's voxel prefix) supplies its grid, its hierarchy and the counter's object word.
 template <bool kBatch>
-__global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* __restrict__ bvh, const rtsdf_grid g,
+__global__ __launch_bounds__(kThreads, kMinWaves<kBatch>) void k_raysample(const char* __restrict__ bvh, const rtsdf_grid g,
                                                         const int32_t* __restrict__ list,
                                                         const int32_t* __restrict__ count_p, int32_t x,
                                                         uint32_t k0, uint32_t k1, uint32_t frame,
@@ -89,12 +96,15 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
                                                         int32_t* __restrict__ cursors, const char* plan,
                                                         int32_t nobj)
 {
-    __shared__ uint64_t s_stk[kLdsDepth][kThreads];  // child keys: (entry t bits << 32) | code
-    // spilled entries as two 32-bit arrays: a 64-bit array would let the compiler merge its
-    // reads with the LDS reads into one flat load, which occupies the vector-memory path
-    // even for LDS addresses
-    uint32_t p_t[kMaxStack - kLdsDepth];
-    uint32_t p_code[kMaxStack - kLdsDepth];
+    constexpr int kDepth = kLdsDepth<kBatch>;
+    // The stack: child codes, and their entry t's top 16 bits (t rounded down, so that a pop
+    // culls no box the exact t would keep); spilled entries keep the whole t.
+    __shared__ int32_t s_code[kDepth][kThreads];
+    __shared__ uint16_t s_t16[kDepth][kThreads];
+    // spilled entries as one 64-bit word (t bits high): an array shaped like an LDS one lets
+    // the compiler merge the two reads into one flat load, which occupies the vector-memory
+    // path even for LDS addresses
+    uint64_t p_key[kMaxStack - kDepth];
 
     // the hierarchy and grid of the current voxel (fixed for a single object)
     int32_t nt = 0, root = 0;
@@ -153,12 +163,15 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
     int32_t pfirst = 0, pcount = 0;  // pending leaf range
     int sp = 0;
 
-    auto push = [&](uint64_t word) {
-        if (sp < kLdsDepth) {
-            s_stk[sp][tid] = word;
+    auto put = [&](int at, const ChildKey& k) {
+        s_code[at][tid] = k.code;
+        s_t16[at][tid] = (uint16_t)(k.t >> 16);
+    };
+    auto push = [&](const ChildKey& k) {
+        if (sp < kDepth) {
+            put(sp, k);
         } else {
-            p_t[sp - kLdsDepth] = (uint32_t)(word >> 32);
-            p_code[sp - kLdsDepth] = (uint32_t)word;
+            p_key[sp - kDepth] = stack_word(k);
         }
         ++sp;
     };
@@ -279,15 +292,15 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
             // farthest first; with room in LDS all three slots are written unconditionally
             // (slots past the new top are dead) and only the top moves
             const int nv = (int)entered(s1) + (int)entered(s2) + (int)entered(s3);
-            if (sp + 3 <= kLdsDepth) {
-                s_stk[sp][tid] = stack_word(nv == 3 ? s3 : (nv == 2 ? s2 : s1));
-                s_stk[sp + 1][tid] = stack_word(nv == 3 ? s2 : s1);
-                s_stk[sp + 2][tid] = stack_word(s1);
+            if (sp + 3 <= kDepth) {
+                put(sp, nv == 3 ? s3 : (nv == 2 ? s2 : s1));
+                put(sp + 1, nv == 3 ? s2 : s1);
+                put(sp + 2, s1);
                 sp += nv;
             } else {
-                if (entered(s3)) push(stack_word(s3));
-                if (entered(s2)) push(stack_word(s2));
-                if (entered(s1)) push(stack_word(s1));
+                if (entered(s3)) push(s3);
+                if (entered(s2)) push(s2);
+                if (entered(s1)) push(s1);
             }
             node = -1;
             if (entered(s0)) {
@@ -298,7 +311,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
                     pfirst = leaf_first(c0);
                     pcount = leaf_count(c0);
                 } else {
-                    push(stack_word(s0));
+                    push(s0);
                 }
             }
         }
@@ -306,17 +319,20 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void k_raysample(const char* _
         int trips = 0;
         while (node < 0 && sp > 0 && (kPopTrips == 0 || trips++ < kPopTrips)) {
             const int top = sp - 1;
-            uint64_t word;
-            if (top < kLdsDepth) {
-                word = s_stk[top][tid];
+            uint32_t tbits;
+            int32_t e;
+            if (top < kDepth) {
+                tbits = (uint32_t)s_t16[top][tid] << 16;
+                e = s_code[top][tid];
             } else {
-                word = ((uint64_t)p_t[top - kLdsDepth] << 32) | p_code[top - kLdsDepth];
+                const uint64_t w = p_key[top - kDepth];
+                tbits = (uint32_t)(w >> 32);
+                e = word_code(w);
             }
-            if (word_t(word) > tb) {
+            if (__uint_as_float(tbits) > tb) {
                 sp = top;
                 continue;
             }
-            const int32_t e = word_code(word);
             if (e >= 0) {
                 node = e;
                 sp = top;

@@ -32,10 +32,14 @@
 #ifndef RTSDF_RAY_START_BATCH
 #define RTSDF_RAY_START_BATCH 12
 #endif
-// ... waves per SIMD the kernel is built for (its register budget, and the depth of its
-// per-lane LDS stack, which shares the CU's 160 KB among that many waves)
+// ... waves per SIMD the single-object and the batched kernel are built for (their register
+// budgets, and the depth of their per-lane LDS stacks, which share the CU's 160 KB among that
+// many waves)
 #ifndef RTSDF_RAY_WAVES
 #define RTSDF_RAY_WAVES 7
+#endif
+#ifndef RTSDF_RAY_WAVES_BATCH
+#define RTSDF_RAY_WAVES_BATCH 6
 #endif
 // ... and the most stack entries a lane pops per loop iteration (0: until it finds work); a
 // lane that needs more pops carries on in the next iteration
