@@ -25,7 +25,8 @@
 // distance rounded down, which can only keep more boxes), the nearest node is visited next
 // and the others go on a per-lane stack of (child code, entry t) in LDS (t rounded down to
 // its top 16 bits there, which can only keep more boxes) that spills to private memory past
-// kLdsDepth.  Leaf ranges are tested one triangle per iteration.  A box
+// kLdsDepth.  Leaf ranges are tested one triangle per iteration; a lane holds up to two
+// pending ranges, so that meeting a second leaf does not stop its traversal.  A box
 // is culled only when its entry parameter exceeds the best hit so far (ties are still
 // visited, because the tie-break is the triangle index).  Box tests may round freely:
 // every triangle box is widened by 2*pad while a hit's computed point must lie within pad
@@ -161,6 +162,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves<kBatch>) void k_raysample(const
     bool bfr = false;
     int32_t node = -1;
     int32_t pfirst = 0, pcount = 0;  // pending leaf range
+    int32_t pfirst2 = 0, pcount2 = 0;  // a second one (only while the first is pending)
     int sp = 0;
 
     auto put = [&](int at, const ChildKey& k) {
@@ -265,6 +267,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves<kBatch>) void k_raysample(const
             sp = 0;
             node = -1;
             pcount = 0;
+            pcount2 = 0;
             if (nt > 0) {
                 if (root >= 0) {
                     node = root;
@@ -282,6 +285,11 @@ __global__ __launch_bounds__(kThreads, kMinWaves<kBatch>) void k_raysample(const
             test_leaf(tris, pfirst, o, w, pad, tb, bid, bfr);
             ++pfirst;
             --pcount;
+            if (pcount == 0) {
+                pfirst = pfirst2;
+                pcount = pcount2;
+                pcount2 = 0;
+            }
         }
         // ... and one node visit per iteration
         if (node >= 0) {
@@ -310,6 +318,9 @@ __global__ __launch_bounds__(kThreads, kMinWaves<kBatch>) void k_raysample(const
                 } else if (pcount == 0) {
                     pfirst = leaf_first(c0);
                     pcount = leaf_count(c0);
+                } else if (pcount2 == 0) {
+                    pfirst2 = leaf_first(c0);
+                    pcount2 = leaf_count(c0);
                 } else {
                     push(s0);
                 }
@@ -339,6 +350,10 @@ __global__ __launch_bounds__(kThreads, kMinWaves<kBatch>) void k_raysample(const
             } else if (pcount == 0) {
                 pfirst = leaf_first(e);
                 pcount = leaf_count(e);
+                sp = top;
+            } else if (pcount2 == 0) {
+                pfirst2 = leaf_first(e);
+                pcount2 = leaf_count(e);
                 sp = top;
             } else {
                 break;
