@@ -3,7 +3,9 @@ ranges partition the triangles, child boxes contain their triangles, records mat
 mesh), ray sampling bit-identical whichever tree is built (culling is exact), and the
 batched build equal byte for byte to the single-object build of every object.
 Cases: 1, 2, 3, 4 and 5 triangles, triangles sharing one centroid, the 32^3 icosphere, a
-reduced static scene, a mixed batch, and the full static scene (PLOC)."""
+grid of coplanar triangles (nodes flat on one axis, the smallest quantisation steps), an
+icosphere a thousand units from the origin, a reduced static scene, a mixed batch, and the
+full static scene (PLOC)."""
 import sys
 
 import numpy as np
@@ -42,6 +44,17 @@ def build(R, verts, tris, dims, h, method):
     return bvh.cpu().numpy()
 
 
+def flat_grid(n, y):
+    """2 n^2 triangles tiling a square of the plane at height y: nodes flat on y."""
+    xs = np.linspace(0.1, 0.9, n + 1, dtype=np.float32)
+    X, Z = np.meshgrid(xs, xs, indexing="ij")
+    v = np.stack([X.ravel(), np.full(X.size, y, np.float32), Z.ravel()], 1).astype(np.float32)
+    idx = lambda i, j: i * (n + 1) + j
+    t = [[idx(i, j), idx(i, j + 1), idx(i + 1, j + 1)] for i in range(n) for j in range(n)]
+    t += [[idx(i, j), idx(i + 1, j + 1), idx(i + 1, j)] for i in range(n) for j in range(n)]
+    return v, np.array(t, np.int32)
+
+
 def small_meshes():
     rng = np.random.default_rng(3)
     out = []
@@ -58,6 +71,10 @@ def small_meshes():
     out.append(("same-centroid", np.concatenate(tris_v).astype(np.float32), np.arange(24, dtype=np.int32).reshape(8, 3)))
     v, t = synth.icosphere(1, 0.3, (0.5, 0.5, 0.5))
     out.append(("icosphere80", v, t))
+    out.append(("flat-grid", *flat_grid(8, 0.25)))
+    # small triangles a thousand units from the origin (quantised against a far node corner)
+    v, t = synth.icosphere(1, 0.3, (0.5, 0.5, 0.5))
+    out.append(("far-icosphere80", (v + np.float32(1000.0)).astype(np.float32), t))
     sc = synth.scene_static(dims=(100, 50, 100), nprims=40, seed=1)
     out.append(("static-reduced", sc.verts, sc.tris))
     return out

@@ -5,7 +5,9 @@ fine values within 1e-5 relative (bit-exact is expected: both sides use the same
 operation order, correctly rounded '/' and sqrt, no contraction).
 Sizes: the 32^3 icosphere; a 100x50x100 static scene compared element by element; and the
 full 400x200x400 static scene in the launch configuration the benchmark times, compared
-in full for the integer stages and on sampled voxels for the ray stages.
+in full for the integer stages and on sampled voxels for the ray stages.  Edge cases: an
+empty mesh, one triangle (a single-leaf hierarchy), two triangles on a voxel face, and a
+grid of 128 coplanar triangles (hierarchy nodes flat on one axis).
 """
 import sys
 
@@ -178,6 +180,24 @@ def test_edge_cases(R, orc):
     G = gpu_pipeline(R, sc)
     O = oracle_pipeline(orc, sc)
     assert np.array_equal(G["seeds0"], O["seeds0"]) and np.array_equal(G["jfa"], O["jfa"])
+    compare_rays(G, O, O["vids"])
+    # 128 coplanar triangles on that face plus a tilted pair above it: hierarchy nodes flat on
+    # y, whose quantised boxes use the smallest steps (the hit test's widening must still
+    # cover them)
+    xs = np.linspace(0.05, 0.45, 9, dtype=np.float32)
+    X, Z = np.meshgrid(xs, xs, indexing="ij")
+    v = np.stack([X.ravel(), np.full(X.size, 0.25, np.float32), Z.ravel()], 1)
+    k = lambda i, j: i * 9 + j
+    t = [[k(i, j), k(i, j + 1), k(i + 1, j + 1)] for i in range(8) for j in range(8)]
+    t += [[k(i, j), k(i + 1, j + 1), k(i + 1, j)] for i in range(8) for j in range(8)]
+    extra = np.array([[0.1, 0.3, 0.1], [0.35, 0.4, 0.15], [0.2, 0.33, 0.4], [0.3, 0.28, 0.3]], np.float32)
+    sc.verts = np.concatenate([v, extra]).astype(np.float32)
+    sc.tris = np.array(t + [[81, 82, 83], [81, 83, 84]], np.int32)
+    log("case: flat grid of 128 triangles + 2, 16^3")
+    G = gpu_pipeline(R, sc)
+    O = oracle_pipeline(orc, sc)
+    assert np.array_equal(G["seeds0"], O["seeds0"]) and np.array_equal(G["jfa"], O["jfa"])
+    assert np.array_equal(G["band"], O["band"])
     compare_rays(G, O, O["vids"])
 
 
