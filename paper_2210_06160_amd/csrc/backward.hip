@@ -9,8 +9,9 @@
 // d moves the plane at the hit point by b_k d, so dt/dv_k = b_k n / (n . w).
 //
 // One lane per listed grid point (grid-stride); a closest-hit traversal of the 4-wide
-// hierarchy with a per-lane stack in LDS that spills to private memory; the gradient is
-// scattered to the three vertices with binary32 atomic adds.
+// hierarchy with a per-lane stack in LDS that spills to private memory, in the iteration
+// structure of ray sampling; the gradient is scattered to the three vertices with binary32
+// atomic adds.
 #include "traverse.h"
 
 namespace rtsdf {
@@ -99,50 +100,84 @@ __global__ __launch_bounds__(kThreads) void k_sdf_backward(
             }
             ++sp;
         };
-        int32_t cur = root;
-        while (true) {
-            if (cur >= 0) {
+        // The traversal loop of ray sampling: per iteration at most one triangle test and one
+        // node visit, at most two stack pops, and up to two pending leaf ranges (so that the
+        // lanes of a wave do similar work in every iteration).
+        int32_t node = -1, pfirst = 0, pcount = 0, pfirst2 = 0, pcount2 = 0;
+        if (root >= 0) {
+            node = root;
+        } else {
+            pfirst = leaf_first(root);
+            pcount = leaf_count(root);
+        }
+        auto take_leaf = [&](int32_t code) {  // false: both pending ranges are in use
+            if (pcount == 0) {
+                pfirst = leaf_first(code);
+                pcount = leaf_count(code);
+            } else if (pcount2 == 0) {
+                pfirst2 = leaf_first(code);
+                pcount2 = leaf_count(code);
+            } else {
+                return false;
+            }
+            return true;
+        };
+        while (node >= 0 || pcount > 0 || sp > 0) {
+            if (pcount > 0) {
+                const float4 a = tris[pfirst].v0, b = tris[pfirst].v1, c = tris[pfirst].v2;
+                bool fr = false;
+                const float t = hit_triangle(o, w, make_float3(a.x, a.y, a.z), make_float3(b.x, b.y, b.z),
+                                             make_float3(c.x, c.y, c.z), pad, fr);
+                const int32_t id = __float_as_int(a.w);
+                if (t > 0.0f && (t < tb || (t == tb && id < bid))) {
+                    tb = t;
+                    bid = id;
+                    bpos = pfirst;
+                }
+                ++pfirst;
+                if (--pcount == 0) {
+                    pfirst = pfirst2;
+                    pcount = pcount2;
+                    pcount2 = 0;
+                }
+            }
+            if (node >= 0) {
                 ChildKey s0, s1, s2, s3;
-                node_keys(fetch_node(nodes, (uint32_t)cur), np, inv, oinv, tb, s0, s1, s2, s3);
+                node_keys(fetch_node(nodes, (uint32_t)node), np, inv, oinv, tb, s0, s1, s2, s3);
                 sort4(s0, s1, s2, s3);
                 if (entered(s3)) push(stack_word(s3));
                 if (entered(s2)) push(stack_word(s2));
                 if (entered(s1)) push(stack_word(s1));
+                node = -1;
                 if (entered(s0)) {
-                    cur = s0.code;
-                    continue;
-                }
-            } else {
-                const int32_t first = leaf_first(cur), cnt = leaf_count(cur);
-                for (int32_t i = 0; i < cnt; ++i) {
-                    const float4 a = tris[first + i].v0, b = tris[first + i].v1, c = tris[first + i].v2;
-                    bool fr = false;
-                    const float t = hit_triangle(o, w, make_float3(a.x, a.y, a.z), make_float3(b.x, b.y, b.z),
-                                                 make_float3(c.x, c.y, c.z), pad, fr);
-                    const int32_t id = __float_as_int(a.w);
-                    if (t > 0.0f && (t < tb || (t == tb && id < bid))) {
-                        tb = t;
-                        bid = id;
-                        bpos = first + i;
+                    if (s0.code >= 0) {
+                        node = s0.code;
+                    } else if (!take_leaf(s0.code)) {
+                        push(stack_word(s0));
                     }
                 }
             }
-            // next entry whose box may still hold a hit no farther than the best so far
-            cur = kBvhEmptySlot;
-            while (sp > 0) {
-                const int top = --sp;
+            // next entries whose boxes may still hold a hit no farther than the best so far
+            for (int trips = 0; node < 0 && sp > 0 && trips < 2; ++trips) {
+                const int top = sp - 1;
                 uint64_t word;
                 if (top < kLdsDepth) {
                     word = s_stk[top][tid];
                 } else {
                     word = ((uint64_t)p_t[top - kLdsDepth] << 32) | p_code[top - kLdsDepth];
                 }
-                if (word_t(word) <= tb) {
-                    cur = word_code(word);
+                if (word_t(word) > tb) {
+                    sp = top;
+                    continue;
+                }
+                const int32_t e = word_code(word);
+                if (e >= 0) {
+                    node = e;
+                } else if (!take_leaf(e)) {
                     break;
                 }
+                sp = top;
             }
-            if (cur == kBvhEmptySlot) break;
         }
         if (bpos < 0) continue;
 
