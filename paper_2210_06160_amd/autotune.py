@@ -30,6 +30,7 @@ GROUPS = {
     "tree": {"RTSDF_LEAF_MAX": [2, 3, 4], "RTSDF_PLOC_RADIUS": [16, 32]},
     "waves": {"RTSDF_RAY_WAVES": [6, 7]},
     "restart": {"RTSDF_RAY_START_BATCH": [10, 12, 16], "RTSDF_RAY_POP_TRIPS": [1, 2, 3]},
+    "dist": {"RTSDF_RAY_CHUNK": [16, 32, 64], "RTSDF_RAY_RANGES": [8, 16]},
     "shadow": {"RTSDF_SHADOW_TILE_X": [1, 2, 4, 8]},
     "ray_small": {"RTSDF_RAY_RANGES": [8, 32, 64], "RTSDF_RAY_CHUNK_SMALL": [16, 32, 128],
                   "RTSDF_RAY_CHUNK_RAYS": [32, 64, 128]},
@@ -90,7 +91,7 @@ def time_candidate(group, path, reps):
                 out.append(a.elapsed_time(b))
         return statistics.median(out)
 
-    if group in ("jfa", "ray", "tree", "waves", "restart"):
+    if group in ("jfa", "ray", "tree", "waves", "restart", "dist"):
         sc = synth.scene_static()
         S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
         S.voxelize()
