@@ -88,8 +88,8 @@ __device__ inline uint32_t plane_byte(uint32_t w, int q) { return (w >> (8 * q))
 __device__ inline float axis_step(uint32_t e, int sh) { return __uint_as_float(((e >> sh) & 0xFFu) << 23); }
 
 // The four children's keys of a fetched node.  On axis a a quantised plane q lies at
-// o_a + q s_a, where the ray is at parameter (o_a + q s_a - origin_a) inv_a = q (s_a inv_a)
-// + (o_a inv_a - origin_a inv_a).
+// c_a + q s_a (c: the node's low corner), which the ray from p reaches at parameter
+// (c_a + q s_a - p_a) inv_a = q (s_a inv_a) + (c_a inv_a - p_a inv_a); oinv holds p inv.
 __device__ inline void node_keys(const NodeFetch& f, const NearPlanes& np, float3 inv, float3 oinv, float tb,
                                  ChildKey& s0, ChildKey& s1, ChildKey& s2, ChildKey& s3)
 {
