@@ -39,6 +39,7 @@ __global__ __launch_bounds__(kThreads) void k_sdf_backward(
     uint32_t p_code[kMaxStack - kLdsDepth];
 
     int32_t nt = 0, root = 0;
+    bool deep = false;  // the hierarchy is too deep for the stack: test every triangle
     float pad = 0.0f;
     const char* __restrict__ nodes = nullptr;
     const BvhTri* __restrict__ tris = nullptr;
@@ -46,6 +47,7 @@ __global__ __launch_bounds__(kThreads) void k_sdf_backward(
         const BvhHeader* H = (const BvhHeader*)b;
         nt = H->nt;
         root = H->root;
+        deep = bvh_too_deep(H->depth);
         pad = H->pad;
         nodes = b + 256;
         tris = (const BvhTri*)(b + 256 + sizeof(Bvh4Node) * (size_t)(nt > 1 ? nt - 1 : 1));
@@ -91,21 +93,25 @@ __global__ __launch_bounds__(kThreads) void k_sdf_backward(
         float tb = inf;
         int32_t bid = kNone, bpos = -1;
         int sp = 0;
+        // (sp < kMaxStack always holds: deeper hierarchies are not traversed; the test keeps
+        // the private arrays in bounds regardless)
         auto push = [&](uint64_t word) {
             if (sp < kLdsDepth) {
                 s_stk[sp][tid] = word;
-            } else {
+            } else if (sp < kMaxStack) {
                 p_t[sp - kLdsDepth] = (uint32_t)(word >> 32);
                 p_code[sp - kLdsDepth] = (uint32_t)word;
             }
-            ++sp;
+            sp = min(sp + 1, kMaxStack);
         };
         // The traversal loop of ray sampling: per iteration at most one triangle test and one
         // node visit, at most two stack pops, and up to two pending leaf ranges (so that the
         // lanes of a wave do similar work in every iteration).
         int32_t node = -1, pfirst = 0, pcount = 0, pfirst2 = 0, pcount2 = 0;
-        if (root >= 0) {
+        if (root >= 0 && !deep) {
             node = root;
+        } else if (root >= 0) {
+            pcount = nt;  // every triangle, in sorted order: the same closest hit
         } else {
             pfirst = leaf_first(root);
             pcount = leaf_count(root);

@@ -120,8 +120,15 @@ struct BvhHeader {
     int32_t nt;
     int32_t root;     // child code of the root (a node, or a leaf range when nt <= kLeafMax)
     float pad;        // hit-test widening (h / 256)
-    int32_t reserved[61];
+    int32_t depth;    // 4-wide nodes on the longest root-to-leaf path (0: the root is a leaf)
+    int32_t reserved[60];
 };
+// A traversal pushes at most 3 entered siblings per node on its path plus one leaf range,
+// so its stack holds at most 3 * depth + 1 entries; rays through a deeper hierarchy (a
+// clustering tree has no depth bound; the radix tree's is 56) test every triangle instead,
+// which returns the same closest hit.
+constexpr int kMaxStack = 176;
+__host__ __device__ inline bool bvh_too_deep(int32_t depth) { return 3 * depth + 1 > kMaxStack; }
 // A 4-wide node (64 bytes).  The children's boxes are quantised to 8 bits per plane on a
 // grid anchored at the node box's low corner o with a power-of-two step s per axis: child
 // q's low plane on axis a is o_a + s_a * byte q of lo[a], its high plane o_a + s_a * byte q

@@ -824,6 +824,45 @@ __global__ __launch_bounds__(256) void k_collapse4(Args a, const BinNode* __rest
     ((Bvh4Node*)(bvh + sg.bvh_off + 256))[i] = o;
 }
 
+// The 4-wide depth (nodes on the longest root-to-leaf path) of the collapsed hierarchy,
+// bottom-up over the binary tree like a refit: the second child to arrive at binary node p
+// takes 1 + the largest depth among the 4-wide children of the node collapsed at p (binary
+// descendants, all finished by then); the root's value goes into the header.  Non-root
+// binary nodes that the collapse skips get a value too, which nothing reads.
+__device__ inline int32_t ld_coherent_i32(const int32_t* p)
+{
+    return (int32_t)__hip_atomic_load((const uint32_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool kBatch>
+__global__ __launch_bounds__(256) void k_depth4(Args a, int32_t total, const int32_t* __restrict__ nparent,
+                                                const int32_t* __restrict__ lparent, uint32_t* flags, int32_t* d4,
+                                                char* bvh)
+{
+    const int32_t gt = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gt >= total) return;
+    const Seg s = seg_of_tri<kBatch>(a, gt);
+    if (s.nt <= kLeafMax) return;  // the root is a leaf range: depth 0, as k_header wrote
+    const Bvh4Node* n4 = (const Bvh4Node*)(bvh + s.bvh_off + 256);
+    int32_t p = lparent[gt];
+    for (int32_t guard = 0; p >= 0 && guard < s.nt; ++guard) {
+        const uint32_t old = __hip_atomic_fetch_add(&flags[s.tri_off + p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 0u) return;  // the sibling will finish this node
+        const int4 c = n4[p].child;
+        int32_t d = 0;
+        if (c.x >= 0) d = max(d, ld_coherent_i32(&d4[s.tri_off + c.x]));
+        if (c.y >= 0) d = max(d, ld_coherent_i32(&d4[s.tri_off + c.y]));
+        if (c.z >= 0) d = max(d, ld_coherent_i32(&d4[s.tri_off + c.z]));
+        if (c.w >= 0) d = max(d, ld_coherent_i32(&d4[s.tri_off + c.w]));
+        __hip_atomic_store((uint32_t*)&d4[s.tri_off + p], (uint32_t)(d + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p == 0) {
+            ((BvhHeader*)(bvh + s.bvh_off))->depth = d + 1;
+            return;
+        }
+        p = nparent[s.tri_off + p];
+    }
+}
+
 // the header (its reserved words zero) and, when no binary node exists (nt <= 1), the
 // unused node slot, so that every byte of a blob is defined
 template <bool kBatch>
@@ -950,6 +989,9 @@ hipError_t build(Args a, int32_t nobj, int64_t n, int64_t tiles, const float* ve
                            w.posmap);
     }
     hipLaunchKernelGGL(k_collapse4<kBatch>, dim3(tb), dim3(256), 0, s, a, (const BinNode*)w.bin, total, bvh);
+    hipLaunchKernelGGL(k_fill_i32, dim3(std::min<unsigned>(tb, 2048u)), dim3(256), 0, s, (int32_t*)w.flags32, n, 0);
+    hipLaunchKernelGGL(k_depth4<kBatch>, dim3(tb), dim3(256), 0, s, a, total, (const int32_t*)w.nparent,
+                       (const int32_t*)w.lparent, w.flags32, w.nn, bvh);
     return hipGetLastError();
 }
 

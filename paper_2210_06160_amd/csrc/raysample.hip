@@ -109,6 +109,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves<kBatch>) void k_raysample(const
 
     // the hierarchy and grid of the current voxel (fixed for a single object)
     int32_t nt = 0, root = 0;
+    bool deep = false;  // the hierarchy is too deep for the stack: test every triangle
     float pad = 0.0f;
     const char* __restrict__ nodes = nullptr;
     const BvhTri* __restrict__ tris = nullptr;
@@ -116,6 +117,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves<kBatch>) void k_raysample(const
         const BvhHeader* H = (const BvhHeader*)b;
         nt = H->nt;
         root = H->root;
+        deep = bvh_too_deep(H->depth);
         pad = H->pad;
         nodes = b + 256;
         tris = (const BvhTri*)(b + 256 + sizeof(Bvh4Node) * (size_t)(nt > 1 ? nt - 1 : 1));
@@ -169,13 +171,15 @@ __global__ __launch_bounds__(kThreads, kMinWaves<kBatch>) void k_raysample(const
         s_code[at][tid] = k.code;
         s_t16[at][tid] = (uint16_t)(k.t >> 16);
     };
+    // (sp < kMaxStack always holds: deeper hierarchies are not traversed; the test keeps
+    // the private array in bounds regardless)
     auto push = [&](const ChildKey& k) {
         if (sp < kDepth) {
             put(sp, k);
-        } else {
+        } else if (sp < kMaxStack) {
             p_key[sp - kDepth] = stack_word(k);
         }
-        ++sp;
+        sp = min(sp + 1, kMaxStack);
     };
 
     while (true) {
@@ -269,8 +273,11 @@ __global__ __launch_bounds__(kThreads, kMinWaves<kBatch>) void k_raysample(const
             pcount = 0;
             pcount2 = 0;
             if (nt > 0) {
-                if (root >= 0) {
+                if (root >= 0 && !deep) {
                     node = root;
+                } else if (root >= 0) {
+                    pfirst = 0;  // every triangle, in sorted order: the same closest hit
+                    pcount = nt;
                 } else {
                     pfirst = leaf_first(root);
                     pcount = leaf_count(root);

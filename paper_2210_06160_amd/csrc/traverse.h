@@ -1,6 +1,6 @@
 // Helpers shared by the kernels that trace rays through the 4-wide hierarchy written by
-// lbvh.hip: the slab test of a quantised child box, the sort key of a child, and bounds of
-// the per-lane traversal stack.  Box tests may round freely: every triangle box is widened
+// lbvh.hip: the slab test of a quantised child box and the sort key of a child (the stack
+// bound and the depth rule are in layout.h).  Box tests may round freely: every triangle box is widened
 // by 2*pad, the quantised boxes contain those, and a hit's computed point must lie within
 // pad of its triangle's box, so a box holding a hit is never culled and traversal returns
 // the brute-force least (t, index).
@@ -10,7 +10,6 @@
 
 namespace rtsdf {
 
-constexpr int kMaxStack = 176;  // <= 3 pushes per level + 1; tree depth <= 56
 constexpr int32_t kNone = 0x7FFFFFFF;
 
 // Per-ray choice of each axis's near planes: the low planes where the slab reciprocal is

@@ -17,6 +17,7 @@ import torch
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librtsdf.so")
 EMPTY = -1
+MAX_RAYS = 65535  # rays accumulated into one 16-bit front or back hit count
 ACCUM, DECAY = 0, 1
 BVH_LBVH, BVH_PLOC = 0, 1
 _lib = None
@@ -469,6 +470,7 @@ class BatchSDF:
     results equal StaticSDF(..., obj=o).  No call reads anything back to the host."""
 
     def __init__(self, objects, rays, frames=1, rng_key=0, beta=None, bias=0.0, bvh_method=BVH_PLOC, device="cuda"):
+        check_hit_budget(rays, frames)
         recs = []
         for sc in objects:
             std = _halving_offsets(sc.dims)
@@ -563,6 +565,7 @@ class ClipMapSDF:
 
     def __init__(self, verts, tris, camera, h0, n, levels, band, rays, frames=1, beta=None, bias=0.0, rng_key=0,
                  bvh_method=BVH_PLOC, device="cuda"):
+        check_hit_budget(rays, frames)
         if not 1 <= int(levels) <= MAX_CLIP_LEVELS:
             raise RtsdfError("1 to %d levels" % MAX_CLIP_LEVELS)
         self.grids = rtsdf_clipmap_levels(camera, h0, n, levels)
@@ -604,6 +607,15 @@ class ClipMapSDF:
         return grad_fine
 
 
+def check_hit_budget(rays, frames):
+    """Raises unless rays x frames <= 65535: a voxel's hit word keeps front hits in its low
+    and back hits in its high 16 bits (section 2.1 counts both), so one more front hit than
+    that would carry into the back count and flip the majority sign."""
+    if int(rays) < 1 or int(frames) < 1 or int(rays) * int(frames) > MAX_RAYS:
+        raise RtsdfError("rays x frames accumulated into one hit buffer must lie in [1, %d], got %d x %d"
+                         % (MAX_RAYS, int(rays), int(frames)))
+
+
 def _halving_offsets(dims):
     n = max(dims)
     k = 1
@@ -635,6 +647,7 @@ class StaticSDF:
 
     def __init__(self, verts, tris, dims, org, h, steps, band, rays, frames, beta=None, bias=0.0,
                  rng_key=0, keep_argmin=True, obj=0, bvh_method=BVH_PLOC, ratio=1, device="cuda"):
+        check_hit_budget(rays, frames)
         self.g = make_grid(dims, org, h)
         self.ratio = int(ratio)
         self.gf = rtsdf_refine_grid(self.g, self.ratio) if self.ratio != 1 else self.g
@@ -777,6 +790,7 @@ class DeformSDF:
 
     def __init__(self, frame_verts, tris, dims, org, h, steps, band, rays, alpha=0.95, beta=None, bias=0.0,
                  rng_key=0, bvh_method=BVH_LBVH, ratio=1, device="cuda"):
+        check_hit_budget(rays, 1)  # the combine consumes each frame's counts
         self.g = make_grid(dims, org, h)
         self.ratio = int(ratio)
         self.gf = rtsdf_refine_grid(self.g, self.ratio) if self.ratio != 1 else self.g

@@ -5,7 +5,9 @@ ranges reachable from the root partition the positions [0, nt) exactly once; eve
 box, decoded from its 8-bit planes (origin + byte * 2^(e - 127) per axis, exactly in
 binary64), contains the boxes of all triangles under it (widened by twice the padding, see
 traverse.h); every unused slot of a reachable node holds low bytes 255 and high bytes 0;
-and the triangle records are a permutation of the input triangles with their vertices.  Returns the number of reachable 4-wide nodes.
+and the triangle records are a permutation of the input triangles with their vertices;
+and the header's depth equals the number of 4-wide nodes on the longest root-to-leaf path
+(0 when the root is a leaf range).  Returns the number of reachable 4-wide nodes.
 """
 import numpy as np
 
@@ -67,7 +69,9 @@ def check(blob, verts, tris, pad):
         return leaf_range(code) if code < 0 else rng[code]
 
     covered = np.zeros(nt, np.int32)
+    depth = {}
     for c in reversed(order):
+        depth[c] = 1 + max([depth[int(ch)] for ch in nodes[c]["child"] if ch >= 0] or [0])
         lo, hi = None, None
         for q in range(4):
             ch = int(nodes[c]["child"][q])
@@ -89,6 +93,7 @@ def check(blob, verts, tris, pad):
         f, n = leaf_range(root)
         covered[f:f + n] += 1
     assert (covered == 1).all(), "leaf ranges do not partition the triangles"
+    assert int(hdr[3]) == (depth[root] if root >= 0 else 0), ("header depth", int(hdr[3]), depth.get(root, 0))
     if root >= 0:
         assert rng[root] == (0, nt)
     return len(order)

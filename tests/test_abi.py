@@ -234,3 +234,24 @@ def test_clipmap_levels_match_the_oracle(L, orc):
     assert lib.rtsdf_clipmap_levels(None, 0.1, 8, 2, out) == -1
     nan = (C.c_float * 3)(float("nan"), 0.0, 0.0)
     assert lib.rtsdf_clipmap_levels(nan, 0.1, 8, 2, out) == -1
+
+
+def test_hit_budget_guard(L):
+    """Front and back hits share one 32-bit word (16 bits each): the helpers refuse a
+    configuration that could accumulate more than 65535 rays into one voxel's counts,
+    before allocating or launching anything."""
+    from paper_2210_06160_amd import synth
+    L.check_hit_budget(8, 8191)
+    L.check_hit_budget(65535, 1)
+    for rays, frames in ((8, 8192), (65536, 1), (0, 1), (4, 0)):
+        with pytest.raises(L.RtsdfError, match="rays x frames"):
+            L.check_hit_budget(rays, frames)
+    sc = synth.scene_tiny()
+    with pytest.raises(L.RtsdfError, match="rays x frames"):
+        L.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, 16, 4096)
+    with pytest.raises(L.RtsdfError, match="rays x frames"):
+        L.BatchSDF([sc], rays=256, frames=256)
+    with pytest.raises(L.RtsdfError, match="rays x frames"):
+        L.ClipMapSDF(sc.verts, sc.tris, (0.5, 0.5, 0.5), 1 / 32, 16, 2, 2, 300, frames=300)
+    with pytest.raises(L.RtsdfError, match="rays x frames"):
+        L.DeformSDF(np.stack([sc.verts] * 2), sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, 70000)

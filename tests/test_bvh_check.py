@@ -28,7 +28,7 @@ def quantise(node, boxes):
     node["exps"], node["lo"], node["hi"] = exps, lo, hi
 
 
-def blob(verts, tris, pad, shrink=False, dup=False, bad_vertex=False, open_slot=False):
+def blob(verts, tris, pad, shrink=False, dup=False, bad_vertex=False, open_slot=False, depth=1):
     nt = len(tris)
     nodes = np.zeros(max(nt - 1, 1), NODE)
     recs = np.zeros(nt, TRI)
@@ -56,6 +56,7 @@ def blob(verts, tris, pad, shrink=False, dup=False, bad_vertex=False, open_slot=
     hdr = np.zeros(64, np.int32)
     hdr[0], hdr[1] = nt, 0
     hdr[2] = np.float32(pad).view(np.int32)
+    hdr[3] = depth  # one node whose children are leaf ranges
     return np.concatenate([hdr.view(np.uint8), nodes.view(np.uint8), recs.view(np.uint8)])
 
 
@@ -71,8 +72,8 @@ def test_accepts_valid_blob():
     assert check(blob(v, t, 0.01), v, t, 0.01) == 1
 
 
-@pytest.mark.parametrize("bad", ["shrink", "dup", "bad_vertex", "open_slot"])
+@pytest.mark.parametrize("bad", ["shrink", "dup", "bad_vertex", "open_slot", "depth"])
 def test_rejects_corrupt_blob(bad):
     v, t = mesh()
     with pytest.raises(AssertionError):
-        check(blob(v, t, 0.01, **{bad: True}), v, t, 0.01)
+        check(blob(v, t, 0.01, **{bad: 2 if bad == "depth" else True}), v, t, 0.01)

@@ -4,8 +4,9 @@ mesh), ray sampling bit-identical whichever tree is built (culling is exact), an
 batched build equal byte for byte to the single-object build of every object.
 Cases: 1, 2, 3, 4 and 5 triangles, triangles sharing one centroid, the 32^3 icosphere, a
 grid of coplanar triangles (nodes flat on one axis, the smallest quantisation steps), an
-icosphere a thousand units from the origin, a reduced static scene, a mixed batch, and the
-full static scene (PLOC)."""
+icosphere a thousand units from the origin, a reduced static scene, a mixed batch, the
+full static scene (PLOC), and a clustering tree deeper than the traversal stack holds
+(rays then test every triangle, which gives the same closest hit)."""
 import sys
 
 import numpy as np
@@ -133,4 +134,85 @@ def test_full_static_ploc_blob(R):
     log("case: static 400x200x400 scene, PLOC blob")
     blob = build(R, sc.verts, sc.tris, sc.dims, sc.h, 1)
     nodes = check(blob, sc.verts, sc.tris, np.float32(sc.h) * np.float32(1.0 / 256))
-    log("  reachable 4-wide nodes", nodes)
+    depth = header_depth(blob)
+    log("  reachable 4-wide nodes", nodes, "depth", depth)
+    assert 3 * depth + 1 <= 176  # traversed as a tree, not triangle by triangle
+
+
+def chain(n=300, r=1.031, leg=5e-5, corner=(0.3, 0.3, 0.5)):
+    """n nested right triangles sharing one corner, legs growing geometrically: the merged
+    box of any two is the larger one's, so the clustering builder can only merge the two
+    smallest clusters at each step and its binary tree is a chain of depth n - 1 (a 4-wide
+    depth near n / 3, beyond what the traversal stack holds)."""
+    c = np.array(corner, np.float32)
+    v = []
+    for i in range(n):
+        L = np.float32(leg * r ** i)
+        v += [c, c + np.array([L, 0, 0], np.float32), c + np.array([0, L, 0], np.float32)]
+    return np.array(v, np.float32), np.arange(3 * n, dtype=np.int32).reshape(n, 3)
+
+
+def header_depth(blob):
+    return int(np.asarray(blob[12:16], np.uint8).view(np.int32)[0])
+
+
+def test_deep_hierarchy_traced_exactly(R, orc):
+    """A clustering tree deeper than the stack bound is recorded as such, and ray sampling
+    and the vertex adjoint through it test every triangle: results equal the oracle's."""
+    import torch
+    from test_gpu_parity import compare_rays, gpu_pipeline, oracle_pipeline
+    v, t = chain()
+    pad = np.float32(1.0 / 16) * np.float32(1.0 / 256)
+    blob = build(R, v, t, (16, 16, 16), 1.0 / 16, 1)
+    check(blob, v, t, pad)
+    depth = header_depth(blob)
+    log("case: chain of %d nested triangles, PLOC 4-wide depth %d" % (len(t), depth))
+    assert 3 * depth + 1 > 176
+    sc = synth.Scene(v, t, (16, 16, 16), (0, 0, 0), 1.0 / 16, synth.jfa_offsets((16, 16, 16)), 2, 8, 2)
+    G = gpu_pipeline(R, sc)
+    assert header_depth(G["S"].bvh.cpu().numpy()) == depth
+    O = oracle_pipeline(orc, sc)
+    assert np.array_equal(G["band"], O["band"])
+    compare_rays(G, O, O["vids"])
+    S = G["S"]
+    w = np.random.default_rng(2).normal(size=S.g.n).astype(np.float32)
+    gg = S.backward(torch.from_numpy(w).cuda()).cpu().numpy()
+    g = orc.make_grid(sc.dims, sc.org, sc.h)
+    go = orc.sdf_backward(w.astype(np.float64), O["hits"], O["argmin"], O["band"], orc.BVH(v, t, orc.hit_pad(g)),
+                          v, t, g, sc.rays, 0)
+    tol = 1e-3 * np.abs(go) + 1e-4 * np.abs(go).max()
+    assert np.abs(go).max() > 0 and (np.abs(gg - go) <= tol).all()
+
+
+def test_depth_fallback_equals_tree(R):
+    """Marking a hierarchy as too deep (its header's depth) switches ray sampling and the
+    vertex adjoint to testing every triangle, with bit-identical hits, distances and argmin
+    records; the regular static hierarchy stays within the stack bound."""
+    import torch
+    sc = synth.scene_static(dims=(50, 25, 50), nprims=20, seed=3)
+    sc.frames = 2
+    log("case: static 50x25x50, tree vs every triangle")
+    out = []
+    for deep in (False, True):
+        S = R.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
+        S.voxelize()
+        S.jfa()
+        S.mask()
+        S.build_bvh()
+        torch.cuda.synchronize()
+        d = header_depth(S.bvh.cpu().numpy())
+        assert 0 < d and 3 * d + 1 <= 176
+        if deep:
+            S.bvh[12:16] = torch.tensor([200], dtype=torch.int32).view(torch.uint8).cuda()
+        R.rtsdf_reset_accum(S.dmin, S.hits, S.argmin)
+        for f in range(sc.frames):
+            S.trace(f)
+        S.combine()
+        w = torch.from_numpy(np.random.default_rng(4).normal(size=S.g.n).astype(np.float32)).cuda()
+        gv = S.backward(w)
+        torch.cuda.synchronize()
+        out.append((S.dmin.view(torch.int32).clone(), S.hits.clone(), S.argmin.clone(), gv.cpu().numpy()))
+    for a, b in zip(out[0][:3], out[1][:3]):
+        assert torch.equal(a, b)
+    ga, gb = out[0][3], out[1][3]
+    assert np.abs(ga).max() > 0 and (np.abs(ga - gb) <= 1e-5 * np.abs(ga).max()).all()

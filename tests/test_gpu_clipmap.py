@@ -129,8 +129,9 @@ def test_shadow_over_clip_map_parity(R, orc, n, levels):
     pen = (io > 0) & (io < 1)
     log("  max |diff| (safe)", np.abs(ig - io)[ok].max(), "safe", ok.sum(), "of", io.size, "penumbra", pen.sum(),
         "adjoint pixels", use.sum())
-    assert np.abs(ig - io)[ok].max() <= 1e-4 and ok.sum() >= 0.95 * io.size and pen.sum() > 0
-    assert use.sum() >= 0.4 * pen.sum()
+    # the oracle's margins keep 97.4 / 98.8 % of the pixels and 77 / 83 % of the penumbra adjoints
+    assert np.abs(ig - io)[ok].max() <= 1e-4 and ok.sum() >= 0.97 * io.size and pen.sum() > 0
+    assert use.sum() >= 0.76 * pen.sum()
     gi = np.where(use, np.random.default_rng(3).normal(size=io.size), 0.0).astype(np.float32)
     go = orc.shadow_backward_clip(G_o, F, s_o, gi.astype(np.float64))
     gf = torch.zeros_like(fine)

@@ -101,6 +101,11 @@ def test_shadow_forward_parity(R, orc, name, dims, w, hgt):
     assert ((io > 0) & (io < 1)).sum() > 0 and (io == 0).sum() > 0 and (io == 1).sum() > 0
 
 
+# least fraction of the penumbra pixels whose adjoint is compared, per case (just under what
+# the oracle's margins keep: a tighter margin rule would otherwise hide a regression)
+KEEP = {"sphere48-64x64": 0.95, "sphere48-61x37": 0.90, "sphere40x24x56-128x96": 0.72}
+
+
 def safe_pixels(orc, f, g, s, img):
     rm, sm, cm = orc.shadow_margin(f, g, s)
     return (img > 0) & (img < 1) & (rm > 1e-4) & (sm > 1e-5) & (cm > 2e-3)
@@ -117,8 +122,10 @@ def test_shadow_backward_parity(R, orc, name, dims, w, hgt):
     io = orc.shadow_forward(f, g_o, s_o)
     safe = safe_pixels(orc, f, g_o, s_o, io)
     gi = np.where(safe, np.random.default_rng(5).normal(size=io.size), 0.0).astype(np.float32)
-    log("  safe penumbra pixels", safe.sum(), "of", ((io > 0) & (io < 1)).sum())
-    assert safe.sum() >= 0.6 * ((io > 0) & (io < 1)).sum()
+    pen = ((io > 0) & (io < 1)).sum()
+    log("  safe penumbra pixels", safe.sum(), "of", pen, "excluded", pen - safe.sum())
+    # the oracle keeps 96 %, 91 % and 73 % of the penumbra pixels of these three cases
+    assert safe.sum() >= KEEP[name] * pen
     go = orc.shadow_backward(f, g_o, s_o, gi.astype(np.float64))
     gg = gpu_shadow_bwd(R, f, g_r, R.make_shadow(**p), gi)
     assert np.abs(go).max() > 0
@@ -145,7 +152,9 @@ def test_shadow_parity_grad_workload(R, orc, grad_scene):
     assert np.abs(ig - io).max() <= 1e-4
     safe = safe_pixels(orc, f, g_o, s_o, io)
     gi = np.where(safe, 2.0 * (io - sc.extra["target_img"]), 0.0).astype(np.float32)
-    log("  safe pixels", safe.sum(), "penumbra", ((io > 0) & (io < 1)).sum())
+    pen = ((io > 0) & (io < 1)).sum()
+    log("  safe pixels", safe.sum(), "penumbra", pen, "excluded", pen - safe.sum())
+    assert safe.sum() >= 0.87 * pen  # the oracle's margins keep 88.3 %
     go = orc.shadow_backward(f, g_o, s_o, gi.astype(np.float64))
     gg = gpu_shadow_bwd(R, f, g_r, R.make_shadow(**p), gi)
     close(gg, go)

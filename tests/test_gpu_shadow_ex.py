@@ -129,8 +129,9 @@ def test_three_lights_parity(R, orc, tri, jitter, bounded):
     assert err[ok].max() <= 1e-4
     if not tri and not bounded:
         assert ok.all()
-    assert ok.sum() >= 0.9 * io.size and pen.sum() > 0
-    assert use.sum() >= 0.3 * pen.sum()
+    # the oracle's margins keep >= 99.8 % of the pixels and 87-94 % of the penumbra adjoints
+    assert ok.sum() >= 0.997 * io.size and pen.sum() > 0
+    assert use.sum() >= 0.86 * pen.sum()
     gi = np.where(use, np.random.default_rng(7).normal(size=io.size), 0.0).astype(np.float32)
     go = orc.shadow_backward_ex(f, g_o, s_o, gi.astype(np.float64))
     gg = gpu_bwd(R, f, g_r, s_r, gi)
@@ -153,7 +154,7 @@ def test_eight_lights_max_steps_and_empty(R, orc):
     io = orc.shadow_forward_ex(f, g_o, s_o)
     ig = gpu_fwd(R, f, g_r, s_r)
     ok, _ = safe(orc, f, g_o, s_o, io)
-    assert np.abs(ig - io)[ok].max() <= 1e-4 and ok.sum() >= 0.9 * io.size
+    assert np.abs(ig - io)[ok].max() <= 1e-4 and ok.sum() >= 0.99 * io.size  # the oracle keeps all
     # an empty image is a no-op (NULL image pointers allowed)
     pe = dict(p, width=0)
     se = R.make_shadow_ex(R.make_shadow(**pe), lights)
@@ -180,8 +181,9 @@ def test_dl_workload_parity(R, orc):
     pen = (io > 0) & (io < 1)
     log("  max |diff| (safe)", np.abs(ig - io)[ok].max(), "safe", ok.sum(), "penumbra", pen.sum(),
         "adjoint pixels", use.sum())
-    assert np.abs(ig - io)[ok].max() <= 1e-4 and ok.sum() >= 0.9 * io.size
-    assert use.sum() >= 0.6 * pen.sum()
+    # the oracle's margins keep 99.7 % of the pixels and 82.6 % of the penumbra adjoints
+    assert np.abs(ig - io)[ok].max() <= 1e-4 and ok.sum() >= 0.996 * io.size
+    assert use.sum() >= 0.82 * pen.sum()
     gi = np.where(use, 2.0 * (io - np.tile(sc.extra["target_img"], 3)), 0.0).astype(np.float32)
     go = orc.shadow_backward_ex(f, g_o, s_o, gi.astype(np.float64))
     gg = gpu_bwd(R, f, g_r, s_r, gi)
