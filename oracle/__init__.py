@@ -114,6 +114,7 @@ def lib():
         L.orc_sdf_backward.restype = ctypes.c_int
         L.orc_sample.argtypes = [vp, Grid, vp, i64, vp, vp]
         L.orc_shadow_margin.argtypes = [vp, Grid, ctypes.POINTER(Shadow), vp, vp, vp]
+        L.orc_shadow_path.argtypes = [vp, Grid, ctypes.POINTER(Shadow), vp]
         L.orc_shadow_forward_ex.argtypes = [vp, Grid, ctypes.POINTER(ShadowEx), vp]
         L.orc_shadow_backward_ex.argtypes = [vp, Grid, ctypes.POINTER(ShadowEx), vp, vp]
         L.orc_shadow_margin_ex.argtypes = [vp, Grid, ctypes.POINTER(ShadowEx), vp, vp, vp, vp]
@@ -330,6 +331,16 @@ def shadow_backward(fine, g, s, grad_img):
     gf = np.zeros(len(f), np.float64)
     lib().orc_shadow_backward(_p(f), g, ctypes.byref(s), _p(gi), _p(gf))
     return gf
+
+
+def shadow_path(fine, g, s):
+    """Per-pixel hash of the march's discrete path (minimising step, clamped samples,
+    trilinear cells): equal hashes mean the image is one smooth function of the field
+    between the two fields (see orc_shadow_path)."""
+    f = np.ascontiguousarray(fine, np.float64)
+    sig = np.empty(s.width * s.height, np.uint64)
+    lib().orc_shadow_path(_p(f), g, ctypes.byref(s), _p(sig))
+    return sig
 
 
 def shadow_margin(fine, g, s):

@@ -1028,6 +1028,56 @@ void orc_shadow_backward(const double* fine, orc_grid g, const orc_shadow* s, co
     free(sm);
 }
 
+/* Each pixel's discrete march path, for checks that hold it fixed (finite differences of the
+ * adjoint, whose derivative exists only where the path does not change): a 64-bit FNV-1a
+ * hash of the minimising step (-1 when the pixel is clamped at 0 or keeps its initial 1),
+ * of which earlier samples were clamped to [smin, smax], and of the trilinear cell (and the
+ * in-range flags per axis) of every sample up to the minimising one.  Two fields whose paths
+ * hash alike take the same branches, so the image is one smooth function between them. */
+static uint64_t orc_fnv(uint64_t h, int64_t v)
+{
+    for (int b = 0; b < 8; ++b) {
+        h ^= (uint64_t)((v >> (8 * b)) & 0xFF);
+        h *= 0x100000001B3ull;
+    }
+    return h;
+}
+
+void orc_shadow_path(const double* fine, orc_grid g, const orc_shadow* s, uint64_t* sig)
+{
+#pragma omp parallel
+    {
+        double* tm = (double*)malloc(sizeof(double) * (size_t)s->steps);
+        double* sm = (double*)malloc(sizeof(double) * (size_t)s->steps);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t p = 0; p < (int64_t)s->width * s->height; ++p) {
+            double P[3];
+            int istar;
+            orc_pixel_origin(s, (int32_t)(p % s->width), (int32_t)(p / s->width), P);
+            orc_march(fine, g, s, P, tm, sm, &istar);
+            uint64_t h = orc_fnv(0xCBF29CE484222325ull, istar);
+            for (int m = 0; m <= istar; ++m) {
+                if (m < istar) h = orc_fnv(h, sm[m] <= (double)s->smin ? 1 : (sm[m] >= (double)s->smax ? 2 : 0));
+                const int32_t n[3] = {g.nx, g.ny, g.nz};
+                for (int a = 0; a < 3; ++a) {
+                    const double X = P[a] + tm[m] * (double)s->light[a];
+                    double c = (X - (double)g.org[a]) / (double)g.h - 0.5;
+                    const int inside = c > 0.0 && c < (double)(n[a] - 1);
+                    if (c < 0.0) c = 0.0;
+                    if (c > (double)(n[a] - 1)) c = (double)(n[a] - 1);
+                    int64_t b = (int64_t)floor(c);
+                    if (b > n[a] - 2) b = n[a] - 2;
+                    if (b < 0) b = 0;
+                    h = orc_fnv(h, 2 * b + inside);
+                }
+            }
+            sig[p] = h;
+        }
+        free(tm);
+        free(sm);
+    }
+}
+
 /* Decision margins of each pixel's march, for comparing implementations that round
  * differently: r_margin = the least |k s_m / t_m - res| over the steps other than the
  * minimising one, together with the distances of res from the 0 clamp and from the initial

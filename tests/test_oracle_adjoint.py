@@ -205,3 +205,113 @@ def test_full_chain_central_differences(orc):
         checked += 1
     print("checked", checked, "excluded", excluded)
     assert checked >= 6
+
+
+@pytest.mark.slow
+def test_gradient_workload_central_differences(orc):
+    """The gradient workload itself (128^3, icosphere of 20,480 triangles, 2-voxel mask, 16
+    rays, 512^2 shadow of 64 steps, loss against the ellipsoid field and a seeded image):
+    the oracle's binary64 adjoint (SDF term + shadow term, through each masked point's argmin
+    ray) against binary64 central differences of the loss with step 1e-4 on a dozen vertex
+    coordinates drawn at random among those the loss depends on, refined by Richardson with
+    step 5e-5.  A coordinate counts only where the
+    discrete state is unchanged at every perturbed point (seeds, mask, hit counts, argmin
+    ray codes, the argmin rays' triangles) and the two steps agree; excluded coordinates are
+    counted, and so do the shadow march's (each pixel's minimising step, clamped samples and
+    trilinear cells).  Perturbed states are recomputed in full by the oracle; of the argmin rays, those
+    whose triangle touches the moved vertex are re-traced one by one, every other record must
+    come back bit-identical."""
+    import time
+    t_start = time.time()
+    sc = synth.scene_grad()
+    g = orc.make_grid(sc.dims, sc.org, sc.h)
+    V32, T = sc.verts, sc.tris
+    steps, bandw, x, key = sc.steps, sc.band, sc.rays, 0
+    target = sc.extra["target"].astype(np.float64)
+    timg = sc.extra["target_img"].astype(np.float64)
+    s = orc.make_shadow(**sc.extra["shadow"])
+
+    def state(Vf):
+        seeds = orc.jfa(orc.voxelize(Vf, T, g), g, steps)
+        band = orc.band(seeds, g, bandw)
+        bvh = orc.BVH(Vf, T, orc.hit_pad(g))
+        dmin, hits, argmin = orc.raysample(bvh, g, band, x, key, 0)
+        return seeds, band, bvh, hits, argmin
+
+    def argmin_tri(bvh, band, argmin, q):
+        code = int(argmin[q]) & 0xFFFFFFFF
+        w, _ = orc.direction(key, int(band[q]), code // x, code % x)
+        ok, _, tri, _ = bvh.closest(orc.voxel_centre(g, band[q]), w)
+        return tri if ok else -1
+
+    seeds0, band0, bvh0, hits0, argmin0 = state(V32)
+    coarse, _ = orc.combine(seeds0, np.full(len(seeds0), np.inf, np.float32), np.zeros(len(seeds0), np.uint32), g,
+                            bandw, sc.h / 2, 0.0, 0)
+    use = np.flatnonzero(hits0 > 0)
+    tri0 = np.array([argmin_tri(bvh0, band0, argmin0, q) for q in use])
+    assert (tri0 >= 0).all()
+    codes0 = argmin0 & 0xFFFFFFFF
+    O = np.array([orc.voxel_centre(g, band0[q]) for q in use], np.float64)
+    W = np.array([orc.direction(key, int(band0[q]), int(codes0[q]) // x, int(codes0[q]) % x)[0] for q in use],
+                 np.float64)
+    sign = np.where((hits0[use] >> 16) > (hits0[use] & 0xFFFF), -1.0, 1.0)
+    tv = T[tri0]
+
+    def loss64(Vd):
+        a, b, c = Vd[tv[:, 0]], Vd[tv[:, 1]], Vd[tv[:, 2]]
+        n = np.cross(b - a, c - a)
+        t = np.einsum("ij,ij->i", n, a - O) / np.einsum("ij,ij->i", n, W)
+        fine = coarse.astype(np.float64).copy()
+        fine[band0[use]] = sign * t
+        img = orc.shadow_forward(fine, g, s)
+        return ((fine - target) ** 2).sum() + ((img - timg) ** 2).sum(), fine, img
+
+    L0, fine0, img0 = loss64(V32.astype(np.float64))
+    path0 = orc.shadow_path(fine0, g, s)
+    gfine = 2.0 * (fine0 - target) + orc.shadow_backward(fine0, g, s, 2.0 * (img0 - timg))
+    gv = orc.sdf_backward(gfine, hits0, argmin0, band0, bvh0, V32, T, g, x, key)
+
+    def unchanged(Vd32, vi):
+        seeds, band, bvh, hits, argmin = state(Vd32)
+        if not (np.array_equal(seeds, seeds0) and np.array_equal(band, band0) and np.array_equal(hits, hits0)
+                and np.array_equal(argmin & 0xFFFFFFFF, codes0)):
+            return False
+        touched = np.isin(tri0, np.flatnonzero((T == vi).any(axis=1)))
+        rest = use[~touched]
+        if not np.array_equal(argmin[rest], argmin0[rest]):
+            return False
+        return all(argmin_tri(bvh, band, argmin, q) == t for q, t in zip(use[touched], tri0[touched]))
+
+    rng = np.random.default_rng(4)
+    coords = rng.permutation(np.flatnonzero(np.abs(gv).ravel() > 0))
+    checked = excluded = 0
+    for c in coords:
+        if checked == 12 or checked + excluded == 80:
+            break
+        vi, ax = divmod(int(c), 3)
+        fds, ok = [], True
+        for hh in (1e-4, 5e-5):
+            vals = []
+            for sgn in (1, -1):
+                Vd = V32.astype(np.float64)
+                Vd[vi, ax] += sgn * hh
+                if not unchanged(Vd.astype(np.float32), vi):
+                    ok = False
+                    break
+                L, fine, _ = loss64(Vd)
+                if not np.array_equal(orc.shadow_path(fine, g, s), path0):  # a march decision flipped
+                    ok = False
+                    break
+                vals.append(L)
+            if not ok:
+                break
+            fds.append((vals[0] - vals[1]) / (2 * hh))
+        if not ok or abs(fds[0] - fds[1]) > 1e-4 * (1 + abs(fds[0])):
+            excluded += 1
+            continue
+        rich = (4.0 * fds[1] - fds[0]) / 3.0  # Richardson: cancels the O(h^2) term
+        assert abs(gv[vi, ax] - rich) <= 2e-6 * (1 + abs(rich)), (vi, ax, gv[vi, ax], fds)
+        checked += 1
+    print("masked points with hits", len(use), "checked", checked, "excluded", excluded,
+          "seconds %.1f" % (time.time() - t_start))
+    assert checked >= 6
