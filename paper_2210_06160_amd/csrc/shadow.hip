@@ -4,8 +4,9 @@
 // light and frame, and the closest-approach estimate may be triangulated from two
 // consecutive samples (section 2.5.2).
 //
-// One wave shades a tile of 64 pixels (8 x 8 unless tuned otherwise): neighbouring shadow rays march through
-// neighbouring cells, so a wave's trilinear gathers share cache lines.  Work-groups are
+// One wave shades a tile of 64 pixels (RTSDF_SHADOW_TILE_X wide: 4 x 16 as tuned):
+// neighbouring shadow rays march through neighbouring cells, so a wave's trilinear gathers
+// share cache lines.  Work-groups are
 // dealt to the eight XCDs round-robin; the tile order is remapped so that each XCD shades
 // one contiguous band of image rows and its L2 holds the part of the field those rays cross.
 // The field is read through eight scalar gathers per sample (it is 8 MiB at 128^3, so the
