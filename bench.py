@@ -20,14 +20,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+# Vector ALU ceiling from the unit counts: 256 CUs x 128 FP32 lanes per clock x 2.4 GHz =
+# 78.6 T lane-ops/s, the published FP32 vector rate (157.3 TFLOP/s) counted one FMA per lane
+# op.  The VALU probe (libvalupeak.so) shows which instructions issue at that rate (wave64
+# in 2 clocks: v_fma_f32, v_add_u32, ...) and which at half of it (4 clocks: v_mad_u32_u24,
+# v_min3_i32, v_dot2_i32_i16, ...); it is run live and reported beside the roofline.
+ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12  # T lane-ops/s
+ALU_PEAK_SINGLE_RATE_TOPS = 256 * 64 * 2.4e9 / 1e12  # ... for the half-rate instructions
+# Algorithmic lane-ops per ray of the method, independent of the hierarchy's width: about
+# 1.05 Philox4x32-10 calls per direction (Marsaglia's rejection accepts pi/4 per pair, two
+# pairs per call) x ~100 integer ops, 2 log2(T) ~ 34 box tests of a binary hierarchy over
+# T ~ 1e5 triangles x ~20 flops, and ~8.6 triangle tests x ~30 flops.
+OPS_PER_RAY = 1.05 * 100 + 34 * 20 + 8.6 * 30
 
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=3)
-    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-deform", action="store_true", help="skip the deforming-mesh (graph) measurement")
     p.add_argument("--no-grad", action="store_true", help="skip the gradient-workload measurement")
@@ -35,7 +46,11 @@ def parse():
     p.add_argument("--no-two-level", action="store_true", help="skip the two-level (coarse/fine) measurement")
     p.add_argument("--no-dl", action="store_true", help="skip the full shadow pass measurement")
     p.add_argument("--no-clipmap", action="store_true", help="skip the clip-map measurement")
-    p.add_argument("--only", choices=["static", "deform", "grad", "batch", "two_level", "tables", "dl", "clipmap"],
+    p.add_argument("--no-tables", action="store_true", help="skip the Tables 3-4 re-run")
+    p.add_argument("--no-valu", action="store_true", help="skip the VALU issue-rate probe")
+    p.add_argument("--no-jfa-passes", action="store_true", help="skip the per-pass jump-flooding timings")
+    p.add_argument("--only", choices=["static", "deform", "grad", "batch", "two_level", "tables", "dl", "clipmap",
+                                      "valu", "jfa"],
                    help="run one workload alone and print its record (for profiling)")
     p.add_argument("--cpu-sample", type=int, default=4000000,
                    help="masked voxels ray-sampled by the oracle (about 6 s on 16 host cores)")
@@ -400,7 +415,7 @@ def grad_bench(torch, rtsdf, synth, reps=20):
             "shadow_samples_per_s_fwd": round(sh.width * sh.height * sh.steps / (med["shadow_fwd"] / 1e3), 1)}
 
 
-def batch_bench(torch, rtsdf, synth, reps=3):
+def batch_bench(torch, rtsdf, synth, reps=20):
     """64 uneven objects (grids 32^3..256^3, 1k..200k triangles): the batched chain (one
     launch per stage and per JFA pass) against the plain loop of 64 single-object chains on
     the same stream; then the batched vertex adjoint against 64 looped adjoint calls.  Wall
@@ -471,6 +486,107 @@ def batch_bench(torch, rtsdf, synth, reps=3):
             "bwd_speedup": round(tp_bwd / tb_bwd, 3), "masked_voxels": masked}
 
 
+def valu_peak(torch, blocks=8192, iters=1024, reps=3):
+    """Measured VALU issue rate: the probe library's kernels issue blocks x 256 threads x
+    iters x 16 instructions of one kind per lane; lane-ops/s = that count / the launch's
+    median duration (HIP events on the launch stream)."""
+    import ctypes
+    from paper_2210_06160_amd import build as hb
+    L = ctypes.CDLL(hb.PROBE_LIB)
+    L.valu_peak_launch.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
+                                   ctypes.c_void_p, ctypes.c_void_p]
+    L.valu_peak_name.restype = ctypes.c_char_p
+    L.valu_peak_shape.restype = ctypes.c_char_p
+    per_trip = L.valu_peak_per_trip()
+    sink = torch.zeros(256, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = {"blocks": blocks, "threads_per_block": 256, "iters": iters, "per_trip": per_trip, "T_lane_ops_per_s": {}}
+    for op in range(L.valu_peak_ops()):
+        name = "%s %s" % (L.valu_peak_name(op).decode(), L.valu_peak_shape(op).decode())
+        ts = []
+        for it in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            rc = L.valu_peak_launch(op, blocks, iters, 12345 + it, sink.data_ptr(), stream.cuda_stream)
+            b.record()
+            torch.cuda.synchronize()
+            if rc != 0:
+                raise RuntimeError("valu probe %d failed (%d)" % (op, rc))
+            if it:
+                ts.append(a.elapsed_time(b))
+        ms = statistics.median(ts)
+        lane_ops = blocks * 256.0 * iters * per_trip
+        out["T_lane_ops_per_s"][name] = round(lane_ops / (ms / 1e3) / 1e12, 3)
+    return out
+
+
+def jfa_pass_bench(torch, rtsdf, synth, reps=20):
+    """Each jump-flooding pass of the static 400 x 200 x 400 scene timed on its own input
+    (the previous pass's output): median of `reps` launches per offset, HIP events."""
+    sc = synth.scene_static()
+    g = rtsdf.make_grid(sc.dims, sc.org, sc.h)
+    S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
+    S.voxelize()
+    cur = S.seeds.clone()
+    nxt = torch.empty_like(cur)
+    N = g.n
+    rows = []
+    for i, k in enumerate(sc.steps):
+        ts = []
+        for it in range(reps + 2):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            res = rtsdf.rtsdf_jfa(cur, nxt, g, [k])
+            b.record()
+            torch.cuda.synchronize()
+            if it >= 2:
+                ts.append(a.elapsed_time(b))
+        assert res.data_ptr() == nxt.data_ptr()
+        ms = statistics.median(ts)
+        empty_in = float((cur == rtsdf.EMPTY).float().mean().item())
+        rows.append({"pass": i, "k": int(k), "ms": round(ms, 4), "empty_input_frac": round(empty_in, 4),
+                     "algorithmic_GBps": round(8.0 * N / (ms / 1e3) / 1e9, 1)})
+        cur, nxt = nxt, cur
+    total = sum(r["ms"] for r in rows)
+    return {"grid": list(sc.dims), "passes": rows, "ms_total": round(total, 4),
+            "hbm_frac_mean": round(8.0 * N * len(rows) / (total / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def single_thread_rays(sc, band, sample):
+    """Rays per second of the oracle's ray sampling on one host thread: a child process with
+    OMP_NUM_THREADS=1 traces `sample` of the masked voxels for one frame."""
+    import subprocess
+    import tempfile
+    import numpy as np
+    rng = np.random.default_rng(1)
+    vids = np.sort(rng.choice(band, min(sample, len(band)), replace=False)).astype(np.int32)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "vids.npy")
+        np.save(path, vids)
+        code = ("import sys, time, json; sys.path.insert(0, %r)\n"
+                "import numpy as np, oracle as orc\n"
+                "from paper_2210_06160_amd import synth\n"
+                "sc = synth.scene_static(); g = orc.make_grid(sc.dims, sc.org, sc.h)\n"
+                "bvh = orc.BVH(sc.verts, sc.tris, orc.hit_pad(g)); v = np.load(%r)\n"
+                "t0 = time.perf_counter(); orc.raysample(bvh, g, v, sc.rays, 0, 0)\n"
+                "print(json.dumps(len(v) * sc.rays / (time.perf_counter() - t0)))\n") % (ROOT, path)
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        if r.returncode != 0:
+            raise RuntimeError("single-thread oracle leg failed:\n" + r.stderr)
+        return float(r.stdout.strip().splitlines()[-1])
+
+
 def cpu_baseline(sc, sample):
     """The oracle as it stands, on the host cores, on a bounded sample of the same step:
     voxelize, all jump-flooding passes, mask, hierarchy and combine over the full grid;
@@ -508,10 +624,12 @@ def cpu_baseline(sc, sample):
     t["combine"] = time.perf_counter() - t0
     total = sum(t.values())
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    one = single_thread_rays(sc, band, sample // 20)
     return {"value": N / total, "unit": "SDF voxels/s", "cores": cores, "kind": "oracle",
-            "rays_per_s": rays_s,
+            "cpu_model": cpu_model(), "rays_per_s": rays_s, "rays_per_s_1_thread": one,
             "sample": "full-grid voxelize/JFA/mask/BVH/combine; ray sampling of %d of %d masked voxels x %d "
-                      "rays for one frame, scaled to %d frames" % (len(vids), len(band), sc.rays, sc.frames),
+                      "rays for one frame, scaled to %d frames; the 1-thread ray rate from %d masked voxels" %
+                      (len(vids), len(band), sc.rays, sc.frames, min(sample // 20, len(band))),
             "stage_s": {k: round(v, 3) for k, v in t.items()}}
 
 
@@ -534,13 +652,17 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n, "copy_calibration_bytes_written": n, "dispatches": 3}))
         return
-    if args.only in ("deform", "grad", "batch", "two_level", "tables", "dl", "clipmap"):
+    if args.only == "valu":
+        print(json.dumps({"valu": valu_peak(torch)}))
+        return
+    if args.only in ("deform", "grad", "batch", "two_level", "tables", "dl", "clipmap", "jfa"):
         fn = {"deform": deform_bench, "grad": grad_bench, "batch": batch_bench, "two_level": two_level_bench,
-              "tables": tables_bench, "dl": dl_bench, "clipmap": clipmap_bench}[args.only]
+              "tables": tables_bench, "dl": dl_bench, "clipmap": clipmap_bench, "jfa": jfa_pass_bench}[args.only]
         print(json.dumps({args.only: fn(torch, rtsdf, synth)}))
         return
     if args.only == "static":
         args.no_deform = args.no_grad = args.no_batch = args.no_two_level = args.no_dl = args.no_clipmap = True
+        args.no_tables = args.no_valu = args.no_jfa_passes = True
     sc = synth.scene_static()
     S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
     N = S.g.n
@@ -555,36 +677,42 @@ def main():
     wall = time.perf_counter() - t0
     ms_step = 1e3 * wall / args.steps
     stages = {}
+    per_step = []
+    ray_launches = []
     for tm in timers:
-        for k, v in tm.durations().items():
+        d = tm.durations()
+        per_step.append(sum(d.values()))
+        for k, v in d.items():
             stages[k] = stages.get(k, 0.0) + v / args.steps
+        # each frame's ray-sampling launch, bracketed by its own events
+        ev = tm.events
+        ray_launches += [e0.elapsed_time(e1) for (n0, e0), (n1, e1) in zip(ev[:-1], ev[1:]) if n1 == "raysample"]
+    ms_median = statistics.median(per_step)
     band = int(S.band_count.item())
     rays = band * sc.rays * sc.frames
     rays_per_s = rays / (stages["raysample"] / 1e3)
     dominant = max(stages, key=stages.get)
-    launch_ms = stages["raysample"] / sc.frames
-    # ray sampling: bound by plain ALU issue (no dense contraction, no streaming).  Algorithmic
-    # lane-ops per ray on this scene: Philox + Marsaglia (~100) + 18.57 four-wide node visits
-    # x 64 (4 slab tests) + 8.62 triangle tests x 45, the visit and test counts of its PLOC
-    # hierarchy with exact (unquantised) boxes and leaves of up to 3 triangles, measured with an
-    # instrumented copy of the kernel; a fixed reference, so that looser boxes or another
-    # tree shape cannot raise the achieved rate
-    ops_per_ray = 100.0 + 18.57 * 64.0 + 8.62 * 45.0
-    achieved = band * sc.rays * ops_per_ray / (launch_ms / 1e3) / 1e12
+    launch_ms = statistics.median(ray_launches)
+    # ray sampling: bound by plain ALU issue (no dense contraction, no streaming); achieved =
+    # the method's algorithmic lane-ops per ray (OPS_PER_RAY) x rays per launch / the median
+    # launch duration
+    achieved = band * sc.rays * OPS_PER_RAY / (launch_ms / 1e3) / 1e12
     traffic = recorded_traffic()
     roof = {"kernel": "raysample", "bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
             "unit": "T lane-ops/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic,
             "launch_ms": round(launch_ms, 4), "units_per_launch": band * sc.rays,
-            "ops_per_unit": ops_per_ray}
+            "ops_per_unit": round(OPS_PER_RAY, 1),
+            "frac_of_single_rate_peak": round(achieved / ALU_PEAK_SINGLE_RATE_TOPS, 4)}
     jfa_ms = stages["jfa"]
     passes = len(sc.steps)
     jfa_gbs = 8.0 * N * passes / (jfa_ms / 1e3) / 1e9
     out = {
         "metric": "SDF voxels/s & rays/s at 400x200x400; batched/bwd vs plain, same GPU",
-        "value": round(N / (ms_step / 1e3), 1),
+        "value": round(N / (ms_median / 1e3), 1),
         "unit": "SDF voxels/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3),
+        "ms_per_step_median": round(ms_median, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+i32", "data": "synthetic",
         "config": {"workload": sc.name, "grid": list(sc.dims), "triangles": int(len(sc.tris)),
@@ -609,6 +737,15 @@ def main():
         out["dl"] = dl_bench(torch, rtsdf, synth)
     if not args.no_clipmap:
         out["clipmap"] = clipmap_bench(torch, rtsdf, synth)
+    if not args.no_tables:
+        out["tables"] = tables_bench(torch, rtsdf, synth)
+    if not args.no_jfa_passes:
+        out["jfa_passes"] = jfa_pass_bench(torch, rtsdf, synth)
+    if not args.no_valu:
+        v = valu_peak(torch)
+        out["roofline"]["measured_valu_T_lane_ops_per_s"] = {
+            k: v["T_lane_ops_per_s"][k] for k in ("v_fma_f32 I3", "v_add_u32 I2", "v_mad_u32_u24 I3", "v_min3_i32 I3")}
+        out["valu_probe"] = v
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample)
     print(json.dumps(out))

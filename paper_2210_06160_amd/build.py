@@ -17,6 +17,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librtsdf.so")
+# VALU issue-rate probe used by the benchmark to measure the integer-ALU peak (not the path)
+PROBE_SRC = "valu_peak.hip"
+PROBE_LIB = os.path.join(HERE, "libvalupeak.so")
 SOURCES = ["capi.cpp", "scan.hip", "voxelize.hip", "jfa.hip", "combine.hip", "lbvh.hip", "raysample.hip",
            "shadow.hip", "backward.hip"]
 ARCH = os.environ.get("RTSDF_ARCH", "gfx950")
@@ -46,9 +49,21 @@ def build(verbose=False, defines=None, out=OUT, lib=LIB):
     tmp = lib + ".tmp"
     subprocess.check_call(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, lib)
+    if lib == LIB:
+        build_probe()
     if verbose:
         print(lib)
     return lib
+
+
+def build_probe(out=OUT):
+    """Compiles and links the VALU issue-rate probe (libvalupeak.so)."""
+    os.makedirs(out, exist_ok=True)
+    obj = _compile(PROBE_SRC, out, {})
+    tmp = PROBE_LIB + ".tmp"
+    subprocess.check_call(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", obj, "-o", tmp])
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
 
 
 if __name__ == "__main__":
