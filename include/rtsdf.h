@@ -167,6 +167,26 @@ rtsdf_status rtsdf_raysample(const void* bvh, rtsdf_grid g, const int32_t* band_
                              void* work, size_t work_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * rtsdf_raysample_noalloc -- rtsdf_raysample without a work argument, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments (minus work / work_bytes), same
+ * results, same errors, plus E_SIZE if the call's work cursors would exceed the static
+ * scratch (4096 bytes; the cursors take 1 KiB whatever the input size) and E_DEVICE if
+ * the scratch's device address cannot be looked up.
+ * The cursors live in a static device array of 4096 bytes that the library holds on each
+ * GPU it runs on until the process ends; its device address is looked up once per GPU on
+ * the first call there.  The call allocates and frees nothing.  Every call on one GPU
+ * shares that GPU's array (each call clears it first, with a kernel): calls on one GPU that
+ * overlap in time -- on different streams, or from different host threads -- race and give
+ * wrong results; serialise them.
+ * ------------------------------------------------------------------------------------- */
+rtsdf_status rtsdf_raysample_noalloc(const void* bvh, rtsdf_grid g, const int32_t* band_list,
+                                     const int32_t* band_count, int64_t band_capacity,
+                                     int32_t rays_per_voxel, uint64_t rng_key, uint32_t frame,
+                                     uint32_t obj, float* dmin, uint32_t* hits, uint64_t* argmin,
+                                     void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * rtsdf_combine -- the fine field, elementwise over all N grid points.
  *   u = h * sqrt(d2) (binary32; +inf without a seed), c = u - beta (section 2.2), in band
  *   iff d2 <= band_vox^2 (section 2.3), sign negative iff back hits > front hits (2.1).

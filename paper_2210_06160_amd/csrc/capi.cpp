@@ -415,6 +415,29 @@ rtsdf_status rtsdf_raysample(const void* bvh, rtsdf_grid g, const int32_t* band_
                   "raysample");
 }
 
+rtsdf_status rtsdf_raysample_noalloc(const void* bvh, rtsdf_grid g, const int32_t* band_list,
+                                     const int32_t* band_count, int64_t band_capacity, int32_t rays_per_voxel,
+                                     uint64_t rng_key, uint32_t frame, uint32_t obj, float* dmin, uint32_t* hits,
+                                     uint64_t* argmin, void* stream)
+{
+    if (rtsdf_status st = check_grid(g)) return st;
+    if (!bvh || !band_list || !band_count || !dmin || !hits) return fail(RTSDF_E_ARG, "NULL pointer");
+    if (rays_per_voxel < 1 || rays_per_voxel > RTSDF_MAX_RAYS)
+        return fail(RTSDF_E_RANGE, "rays_per_voxel %d outside [1, %d]", rays_per_voxel, RTSDF_MAX_RAYS);
+    if (band_capacity < 0 || band_capacity > rtsdf::nvox(g))
+        return fail(RTSDF_E_RANGE, "band_capacity outside [0, N]");
+    if (obj >= (1u << 24)) return fail(RTSDF_E_RANGE, "obj %u >= 2^24", obj);
+    const size_t need = rtsdf::raysample_work_bytes(band_capacity, rays_per_voxel);
+    if (need > rtsdf::raysample_scratch_bytes())
+        return fail(RTSDF_E_SIZE, "raysample work %zu bytes exceeds the static scratch of %zu bytes", need,
+                    rtsdf::raysample_scratch_bytes());
+    void* scratch = nullptr;
+    if (rtsdf_status st = device(rtsdf::raysample_scratch(&scratch), "raysample scratch address")) return st;
+    return device(rtsdf::raysample(bvh, g, band_list, band_count, band_capacity, rays_per_voxel, rng_key, frame,
+                                   obj, dmin, hits, argmin, scratch, as_stream(stream)),
+                  "raysample_noalloc");
+}
+
 rtsdf_status rtsdf_combine(const int32_t* seeds, float* dmin, uint32_t* hits, rtsdf_grid g, int32_t band_vox,
                            float beta, float bias, int32_t mode, float alpha, int32_t first_frame,
                            int32_t consume, float* state, float* fine, void* stream)

@@ -45,6 +45,9 @@ hipError_t build_bvh(const float* verts, const int32_t* tris, int32_t nt, const 
 
 hipError_t reset_accum(float* dmin, uint32_t* hits, uint64_t* argmin, int64_t n, hipStream_t s);
 size_t raysample_work_bytes(int64_t capacity, int32_t x);
+// the allocation-free variant's work cursors: a static device array per GPU
+size_t raysample_scratch_bytes();
+hipError_t raysample_scratch(void** out);
 hipError_t raysample(const void* bvh, const rtsdf_grid& g, const int32_t* list,
                      const int32_t* count, int64_t capacity, int32_t x, uint64_t key,
                      uint32_t frame, uint32_t obj, float* dmin, uint32_t* hits, uint64_t* argmin,

@@ -32,6 +32,8 @@
 // every triangle box is widened by 2*pad while a hit's computed point must lie within pad
 // of its triangle's box, so a box holding a hit is never culled and the result equals the
 // brute-force least (t, triangle index).
+#include <mutex>
+
 #include "traverse.h"
 #include "tuning.h"
 
@@ -370,9 +372,41 @@ __global__ __launch_bounds__(kThreads, kMinWaves<kBatch>) void k_raysample(const
     }
 }
 
+// Work cursors of the allocation-free entry point: one array per GPU, held until the
+// process ends and shared by every call on that GPU.  Host code never passes this name to
+// a kernel (on the host it is only a stand-in for the symbol): it uses the device address
+// that scratch_ptr() looks up.
+constexpr size_t kScratchBytes = 4096;
+static_assert(sizeof(int32_t) * kRanges * kCursorStride <= kScratchBytes, "cursors fit the static scratch");
+static __device__ __align__(256) int32_t scratch[kScratchBytes / sizeof(int32_t)];
+
 }  // namespace
 
 size_t raysample_work_bytes(int64_t, int32_t) { return sizeof(int32_t) * kRanges * kCursorStride; }
+
+size_t raysample_scratch_bytes() { return kScratchBytes; }
+
+hipError_t raysample_scratch(void** out)
+{
+    // the array's address on each device, looked up once per device with that device current
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (p == nullptr) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
 
 hipError_t raysample(const void* bvh, const rtsdf_grid& g, const int32_t* list, const int32_t* count,
                      int64_t capacity, int32_t x, uint64_t key, uint32_t frame, uint32_t obj,

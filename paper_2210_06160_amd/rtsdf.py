@@ -120,6 +120,7 @@ def lib():
             "rtsdf_reset_accum": ([vp, vp, vp, i64, vp], i32),
             "rtsdf_raysample_work_bytes": ([i64, i32], sz),
             "rtsdf_raysample": ([vp, Grid, vp, vp, i64, i32, u64, u32, u32, vp, vp, vp, vp, sz, vp], i32),
+            "rtsdf_raysample_noalloc": ([vp, Grid, vp, vp, i64, i32, u64, u32, u32, vp, vp, vp, vp], i32),
             "rtsdf_combine": ([vp, vp, vp, Grid, i32, f32, f32, i32, f32, i32, i32, vp, vp, vp], i32),
             "rtsdf_refine_grid": ([Grid, i32, ctypes.POINTER(Grid)], i32),
             "rtsdf_band_refined_work_bytes": ([Grid, i32], sz),
@@ -157,6 +158,7 @@ def lib():
 EXPORTED = ["rtsdf_last_error", "rtsdf_abi_version", "rtsdf_voxelize_work_bytes", "rtsdf_voxelize",
             "rtsdf_jfa", "rtsdf_band_work_bytes", "rtsdf_band", "rtsdf_bvh_bytes", "rtsdf_bvh_work_bytes",
             "rtsdf_build_bvh", "rtsdf_reset_accum", "rtsdf_raysample_work_bytes", "rtsdf_raysample",
+            "rtsdf_raysample_noalloc",
             "rtsdf_combine", "rtsdf_refine_grid", "rtsdf_band_refined_work_bytes", "rtsdf_band_refined",
             "rtsdf_combine_refined", "rtsdf_shadow_forward", "rtsdf_shadow_backward", "rtsdf_shadow_forward_ex",
             "rtsdf_shadow_backward_ex", "rtsdf_clipmap_levels", "rtsdf_clipmap_sample", "rtsdf_shadow_forward_clip",
@@ -263,6 +265,19 @@ def rtsdf_raysample(bvh, grid, band_list, band_count, rays_per_voxel, rng_key, f
                                  _ptr(argmin, torch.int64) if argmin is not None else None, _ptr(work),
                                  work.numel(), _stream(stream)),
            "rtsdf_raysample")
+
+
+def rtsdf_raysample_noalloc(bvh, grid, band_list, band_count, rays_per_voxel, rng_key, frame, dmin, hits,
+                            argmin=None, obj=0, band_capacity=None, stream=None):
+    """rtsdf_raysample with the work cursors in the library's static per-GPU scratch (no
+    work tensor; calls that overlap on one GPU race)."""
+    cap = band_list.numel() if band_capacity is None else int(band_capacity)
+    _check(lib().rtsdf_raysample_noalloc(_ptr(bvh), grid, _ptr(band_list, torch.int32),
+                                         _ptr(band_count, torch.int32), cap, int(rays_per_voxel),
+                                         int(rng_key) & (2 ** 64 - 1), int(frame), int(obj),
+                                         _ptr(dmin, torch.float32), _ptr(hits, torch.int32),
+                                         _ptr(argmin, torch.int64) if argmin is not None else None, _stream(stream)),
+           "rtsdf_raysample_noalloc")
 
 
 def rtsdf_combine(seeds, dmin, hits, grid, band_vox, beta, bias, mode, fine, alpha=0.95, first_frame=True,

@@ -81,6 +81,20 @@ def test_host_validation(L):
                                fake(), lib.rtsdf_raysample_work_bytes(10, 4) - 1, None) == E_SIZE
     assert lib.rtsdf_raysample(fake(), g, fake(), fake(), 10, 4, 0, 0, 0, fake(), fake(), None,
                                None, 256, None) == E_ARG
+    # the allocation-free variant validates the same way, before it touches a device
+    for rays in (0, 65536):
+        assert lib.rtsdf_raysample_noalloc(fake(), g, fake(), fake(), 10, rays, 0, 0, 0, fake(), fake(), None,
+                                           None) == E_RANGE
+    assert lib.rtsdf_raysample_noalloc(fake(), g, fake(), fake(), 10, 4, 0, 0, 1 << 24, fake(), fake(), None,
+                                       None) == E_RANGE
+    assert lib.rtsdf_raysample_noalloc(fake(), g, fake(), fake(), 513, 4, 0, 0, 0, fake(), fake(), None,
+                                       None) == E_RANGE
+    assert lib.rtsdf_raysample_noalloc(fake(), bad, fake(), fake(), 10, 4, 0, 0, 0, fake(), fake(), None,
+                                       None) == E_RANGE
+    assert lib.rtsdf_raysample_noalloc(None, g, fake(), fake(), 10, 4, 0, 0, 0, fake(), fake(), None,
+                                       None) == E_ARG
+    assert lib.rtsdf_raysample_noalloc(fake(), g, fake(), fake(), 10, 4, 0, 0, 0, fake(), None, None,
+                                       None) == E_ARG
     # combine
     assert lib.rtsdf_combine(fake(), fake(), fake(), g, 2, 0.0, 0.0, 7, 0.9, 1, 0, fake(), fake(),
                              None) == E_RANGE
