@@ -6,21 +6,43 @@
 // increasing in that order: here rank 0 for the stored seed and 1 + L for the others,
 // L = 9 (ez+1) + 3 (ey+1) + (ex+1) (so 1..13 and 15..27).
 //
-// Kernel: each thread owns one (x, y) column and walks the z positions of one residue
-// class z = r + m*k (the only planes a pass with offset k couples), holding the 3 x 3
-// neighbourhoods of planes m-1, m, m+1 in registers, so each output loads one new plane
-// (9 values) instead of 27.  For every loaded seed s at column slot q = 3 (ey+1) + (ex+1)
-// the thread precomputes
+// Keys.  For a seed s loaded at column slot q = 3 (ey+1) + (ex+1) of a thread's column
+// (px, py) the thread computes once
 //     W = ((sx - px)^2 + (sy - py)^2 + sz^2) * 32 + 1 + q,
-// and for output z = pz a candidate from plane ez has the signed 32-bit key
+// and for an output at z = pz the candidate's signed 32-bit key is
 //     W + sz * (-64 pz) + 9 (ez+1) = (d2 - pz^2) * 32 + rank,
-// an order-preserving image of (d2, rank): one v_mad_i32_i24 per candidate, each plane's
-// nine keys reduced with v_min3_i32 before its rank offset 9 (ez+1) is added once (the
-// stored seed takes its mid-plane key minus 1 + 4, i.e. rank 0).  The winner's id is reloaded from its (recently cached)
-// position (the offset of each rank for the pass's k comes from a small LDS table, and the
-// nine gathers of a plane are buffer loads off a scalar plane base).  EMPTY (-1) unpacks to (1023, 1023, 4095), which makes w - 2 pz sz >= 8.39e6
-// > any real d2 (<= 3 * 1023^2), so it never wins against a seed; out-of-grid queries load
-// EMPTY.  Keys stay within +-2^30.
+// an order-preserving image of (d2, rank): one v_mad_i32_i24 per candidate.  A plane's
+// keys for one output are reduced (v_min3_i32) before that plane's rank offset 9 (ez+1)
+// is added once; the stored seed takes its mid-plane key minus 1 + 4 (rank 0).  The
+// winner's id is reloaded from the query its rank names (offsets from a 28-entry LDS
+// table per work-group).  EMPTY (-1) unpacks to (1023, 1023, 4095), whose key exceeds
+// 8.39e6 * 32 > any real d2 (<= 3 * 1023^2) for every output, so it never wins against a
+// seed.  Keys stay within +-2^30.
+//
+// Streaming.  A pass with offset k couples only the z positions of one residue class
+// z = r + m k.  Each thread owns one (x, y) column and walks the lattice points m of a
+// residue class in order; plane m contributes to outputs m + 1 (as their ez = -1 plane),
+// m (ez = 0, and the stored seed) and m - 1 (ez = +1), so each plane is loaded and its W
+// computed once for up to three outputs, held only as three running minima.  Which of the
+// three roles a plane has is fixed per work-group (first and last planes of a chain have
+// one or two), so each role set is its own instantiation.
+//
+// Work skipped without changing any result:
+//   - planes outside the grid (uniform per work-group);
+//   - neighbour rows y + ey k outside the grid (uniform per wave: a wave is one row of 64
+//     x-columns), and neighbour columns x + ex k outside the grid for every lane of the
+//     wave; a column valid for only some lanes reads EMPTY on the others (a select that
+//     only such waves run);
+//   - in the sparse early passes (most of the input EMPTY) a neighbour row whose three
+//     loaded columns are EMPTY on every lane.
+//
+// Work distribution.  A work-group is 64 x-columns x RTSDF_JFA_ROWS rows and a z task:
+// a chunk of one residue class's lattice points, or, when classes are short (large k),
+// several whole classes, so that per-group set-up is spread over about RTSDF_JFA_CHUNK
+// outputs per thread.  Work-groups are dealt to the 8 XCDs round-robin in launch order;
+// the launch index is remapped so that each XCD runs one contiguous range of tasks
+// (z-major), so the planes and rows that a task's neighbours read are fetched into one
+// XCD's L2 rather than into several.
 #include "internal.h"
 #include "tuning.h"
 
@@ -29,10 +51,12 @@ namespace rtsdf {
 namespace {
 
 constexpr int kBX = 64, kBY = RTSDF_JFA_ROWS;  // threads per block: 64 x-columns x kBY y-columns
-constexpr int kChunk = RTSDF_JFA_CHUNK;        // lattice points per block along z
+constexpr int kChunk = RTSDF_JFA_CHUNK;        // outputs per thread and work-group along z
 constexpr int kChunkSmall = 16;                // ... for passes that would launch few blocks
 constexpr int64_t kFewBlocks = 2048;           // below this many blocks, use kChunkSmall
-constexpr int32_t kEmptyV = 8000000;  // v >= this only for EMPTY
+constexpr int kXcds = 8;
+constexpr int32_t kEmptyV = 8000000;    // v >= this only for EMPTY
+constexpr int32_t kNoKey = 0x7F000000;  // no candidate yet: above every key, and + 18 does not overflow
 
 struct Cand {
     int32_t W;   // ((sx-px)^2 + (sy-py)^2 + sz^2) * 32 + 1 + q
@@ -73,164 +97,277 @@ __device__ inline void rank_table(int32_t* tab, int32_t nx, int32_t ny, int32_t 
 }
 
 // One plane of the input as a buffer resource: a scalar base and 32-bit byte offsets, so
-// the nine gathers of a plane need no per-lane address arithmetic.
+// the gathers of a plane need no per-lane address arithmetic.
 __device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const int32_t* in, uint32_t plane, int32_t z)
 {
     return __builtin_amdgcn_make_buffer_rsrc((void*)(in + (size_t)plane * (uint32_t)z), (short)0, 0x7FFFFFFF,
                                             0x00020000);
 }
 
-// work-group (bx, by, bz) of a pass over one grid: x-columns bx*64.., y-columns by*4..,
-// residue class r and chunk c of that class from bz; tab = rank_table(nx, ny, k)
-template <int kCh>
-__device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_t* __restrict__ out, int32_t nx,
-                                          int32_t ny, int32_t nz, int32_t k, int32_t chunks_per_residue,
-                                          int32_t bx, int32_t by, int32_t bz, const int32_t* tab)
+// z tasks of one pass: either chunks of kCh lattice points of one residue class
+// (per_res > 1 chunks per class, one class per task), or `group` whole classes per task
+struct ZTasks {
+    int32_t res;      // residue classes: min(k, nz)
+    int32_t per_res;  // chunks per class (>= 1)
+    int32_t group;    // classes per task (>= 1; > 1 only when per_res == 1)
+    int32_t count;    // tasks
+};
+
+__host__ __device__ inline ZTasks z_tasks(int32_t nz, int32_t k, int32_t ch)
 {
+    ZTasks t;
+    t.res = k < nz ? k : nz;
+    const int32_t mmax = (nz + k - 1) / k;  // lattice points of class 0 (the longest)
+    t.per_res = (mmax + ch - 1) / ch;
+    t.group = t.per_res > 1 ? 1 : (ch / mmax > 1 ? ch / mmax : 1);
+    t.count = t.per_res > 1 ? t.res * t.per_res : (t.res + t.group - 1) / t.group;
+    return t;
+}
+
+// What a thread knows about its column for one pass: for each of the 3 x 3 neighbour
+// columns q, its byte offset within a plane and a mask that is all ones when the column
+// lies outside the grid (OR-ed into the loaded id it makes that id EMPTY; its load reads
+// the thread's own column instead, which is always inside).
+struct Column {
+    uint32_t off[9];
+    int32_t inv[9];
+    short2_t pxy;
+};
+
+// Neighbour rows / columns a pass can reach anywhere in the grid: 3, or only the middle one
+// when the offset is at least the grid's extent on that axis.
+template <int kRows, int kCols>
+struct Slots {
+    static constexpr bool has(int q) { return (kRows == 3 || q / 3 == 1) && (kCols == 3 || q % 3 == 1); }
+};
+
+// Plane z's contribution to the outputs that have it as their ez = +1 plane (kPrev:
+// output z - k), their own plane (kCur: output z, with its stored seed) and their ez = -1
+// plane (kNext: output z + k).  kSparse: skip the plane's arithmetic when every id it
+// loaded is EMPTY on every lane of the wave.
+template <int kRows, int kCols, bool kSparse, bool kPrev, bool kCur, bool kNext>
+__device__ __forceinline__ void plane(const int32_t* __restrict__ in, uint32_t plane_elems, int32_t z, int32_t k,
+                                      const Column& c, int32_t& a_prev, int32_t& a_cur, int32_t& a_next)
+{
+    using S = Slots<kRows, kCols>;
+    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(in, plane_elems, z);
+    int32_t v[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        if (S::has(q)) v[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)c.off[q], 0, 0) | c.inv[q];
+    if (kSparse) {
+        int32_t all = -1;
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            if (S::has(q)) all &= v[q];
+        if (__builtin_amdgcn_readfirstlane((uint32_t)(__ballot(all != RTSDF_EMPTY) != 0ull)) == 0u) return;
+    }
+    const int32_t m_cur = -64 * z, m_prev = -64 * (z - k), m_next = -64 * (z + k);
+    int32_t kp[9], kc[9], kn[9];
+    int32_t self = kNoKey;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        kp[q] = kc[q] = kn[q] = kNoKey;
+        if (!S::has(q)) continue;
+        Cand cd = prep(v[q], c.pxy, q);
+        asm volatile("" : "+v"(cd.W));  // W once per seed; each key below is one multiply-add on it
+        if (kPrev) kp[q] = cand_key(cd, m_prev);
+        if (kCur) {
+            if (q == 4) self = cand_key(cd, m_cur) - 5;  // the stored seed: rank 0 instead of 1 + 4
+            else kc[q] = cand_key(cd, m_cur);
+        }
+        if (kNext) kn[q] = cand_key(cd, m_next);
+    }
+    if (kPrev) a_prev = min(a_prev, min9(kp) + 18);
+    if (kCur) a_cur = min(a_cur, min(min9(kc) + 9, self));
+    if (kNext) a_next = min(a_next, min9(kn));
+}
+
+// work-group `blk` (remapped task index) of a pass over one grid: x-columns bx*64..,
+// y-columns by*kBY.., z task bz; tab = rank_table(nx, ny, k)
+template <int kCh, int kRows, int kCols, bool kSparse>
+__device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_t* __restrict__ out, int32_t nx,
+                                          int32_t ny, int32_t nz, int32_t k, int64_t blk, const int32_t* tab)
+{
+    const int32_t gx = (nx + kBX - 1) / kBX, gy = (ny + kBY - 1) / kBY;
+    const int32_t bx = (int32_t)(blk % gx), by = (int32_t)((blk / gx) % gy), bz = (int32_t)(blk / ((int64_t)gx * gy));
     const int32_t x = bx * kBX + threadIdx.x;
     const int32_t y = by * kBY + threadIdx.y;
-    const int32_t r = bz / chunks_per_residue;
-    const int32_t c = bz - r * chunks_per_residue;
-    if (x >= nx || y >= ny || r >= nz) return;
-    const int32_t mcount = (nz - r + k - 1) / k;  // lattice points z = r + m k < nz
-    const int32_t m0 = c * kCh;
-    if (m0 >= mcount) return;
-    const int32_t m1 = min(m0 + kCh, mcount);
-    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;  // grids hold at most 2^30 points
+    if (x >= nx || y >= ny) return;
+    const uint32_t plane_elems = (uint32_t)nx * (uint32_t)ny;  // grids hold at most 2^30 points
 
-    // byte offsets of the 3 x 3 neighbourhood columns; out-of-grid columns read EMPTY
-    uint32_t off[9];
-    bool ok[9];
+    Column c;
+    const uint32_t own = 4u * ((uint32_t)x + (uint32_t)nx * (uint32_t)y);
 #pragma unroll
     for (int ey = -1; ey <= 1; ++ey)
 #pragma unroll
         for (int ex = -1; ex <= 1; ++ex) {
             const int q = 3 * (ey + 1) + (ex + 1);
             const int32_t qx = x + ex * k, qy = y + ey * k;
-            ok[q] = qx >= 0 && qx < nx && qy >= 0 && qy < ny;
-            off[q] = ok[q] ? 4u * ((uint32_t)qx + (uint32_t)nx * (uint32_t)qy) : 0u;  // bytes
+            const bool ok = qx >= 0 && qx < nx && qy >= 0 && qy < ny;
+            c.off[q] = ok ? 4u * ((uint32_t)qx + (uint32_t)nx * (uint32_t)qy) : own;  // bytes
+            c.inv[q] = ok ? 0 : -1;
         }
-
-    const short2_t pxy = __builtin_bit_cast(short2_t, (uint32_t)x | ((uint32_t)y << 16));
-    // planes outside the grid (m < 0 or z >= nz, uniform) load a valid plane and read EMPTY
-    auto load_plane = [&](int32_t m, Cand* dst) {
-        const int32_t z = r + m * k;
-        const bool pv = m >= 0 && z < nz;
-        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(in, plane, pv ? z : r);
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const int32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off[q], 0, 0);
-            dst[q] = prep(ok[q] && pv ? v : RTSDF_EMPTY, pxy, q);
-        }
-    };
+    c.pxy = __builtin_bit_cast(short2_t, (uint32_t)x | ((uint32_t)y << 16));
     const uint32_t pxy_idx = (uint32_t)x + (uint32_t)nx * (uint32_t)y;
-    // output for lattice point m from planes m-1 (lo), m (mid), m+1 (hi)
-    auto emit = [&](int32_t m, const Cand* lo, const Cand* mid, const Cand* hi) {
-        const int32_t pz = r + m * k;
-        const int32_t m64pz = -64 * pz;
-        int32_t a[9], b[9], c[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            a[q] = cand_key(lo[q], m64pz);
-            b[q] = cand_key(mid[q], m64pz);
-            c[q] = cand_key(hi[q], m64pz);
-        }
-        const int32_t self = b[4] - 5;  // the stored seed: rank 0 instead of 1 + 4
-        const int32_t mid8 = min(min(min(b[0], b[1]), b[2]), min(min(b[3], b[5]), min(min(b[6], b[7]), b[8])));
-        const int32_t best = min(min(min9(a), mid8 + 9), min(min9(c) + 18, self));
-        const uint32_t p = pxy_idx + plane * (uint32_t)pz;
+
+    auto emit = [&](int32_t pz, int32_t best) {
+        const uint32_t p = pxy_idx + plane_elems * (uint32_t)pz;
         int32_t id = RTSDF_EMPTY;
         if ((best >> 5) < kEmptyV) id = in[(uint32_t)((int32_t)p + tab[best & 31])];
         out[p] = id;
     };
 
-    Cand A[9], B[9], C[9];
-    load_plane(m0 - 1, A);
-    load_plane(m0, B);
-    // rotate the three plane buffers by unrolling three outputs per trip
-    for (int32_t m = m0; m < m1; m += 3) {
-        load_plane(m + 1, C);
-        emit(m, A, B, C);
-        if (m + 1 >= m1) break;
-        load_plane(m + 2, A);
-        emit(m + 1, B, C, A);
-        if (m + 2 >= m1) break;
-        load_plane(m + 3, B);
-        emit(m + 2, C, A, B);
+    const ZTasks zt = z_tasks(nz, k, kCh);
+    int32_t r0, r1, mlo, mhi;
+    if (zt.per_res > 1) {
+        r0 = bz / zt.per_res;
+        r1 = r0 + 1;
+        mlo = (bz - r0 * zt.per_res) * kCh;
+        mhi = mlo + kCh;
+    } else {
+        r0 = bz * zt.group;
+        r1 = min(r0 + zt.group, zt.res);
+        mlo = 0;
+        mhi = 0x7FFFFFFF;
     }
+#define RTSDF_PLANE(P, C, N, zz) plane<kRows, kCols, kSparse, P, C, N>(in, plane_elems, zz, k, c, a_prev, a_cur, a_next)
+    for (int32_t r = r0; r < r1; ++r) {
+        const int32_t mcount = (nz - r + k - 1) / k;  // lattice points z = r + m k < nz
+        const int32_t m0 = mlo, m1 = min(mhi, mcount);
+        if (m0 >= m1) continue;
+        // accumulators of outputs m - 1, m, m + 1 while plane m streams in
+        int32_t a_prev = kNoKey, a_cur = kNoKey, a_next = kNoKey;
+        if (m0 >= 1) {  // plane m0 - 1 is the ez = -1 plane of output m0
+            RTSDF_PLANE(false, false, true, r + (m0 - 1) * k);
+            a_cur = a_next;
+            a_next = kNoKey;
+        }
+        for (int32_t m = m0; m < m1; ++m) {
+            const int32_t z = r + m * k;
+            const bool first = m == m0, last = m + 1 == m1;
+            if (!first && !last) RTSDF_PLANE(true, true, true, z);
+            else if (first && last) RTSDF_PLANE(false, true, false, z);
+            else if (first) RTSDF_PLANE(false, true, true, z);
+            else RTSDF_PLANE(true, true, false, z);
+            if (!first) emit(z - k, a_prev);
+            a_prev = a_cur;
+            a_cur = a_next;
+            a_next = kNoKey;
+        }
+        // plane m1 is the ez = +1 plane of the chain's last output
+        if (m1 < mcount) RTSDF_PLANE(true, false, false, r + m1 * k);
+        emit(r + (m1 - 1) * k, a_prev);
+    }
+#undef RTSDF_PLANE
 }
 
-template <int kCh>
+// launch index -> task index: XCD x (= launch index mod 8) runs tasks [x per, (x+1) per)
+__device__ inline int64_t xcd_task(uint32_t b, uint32_t nblocks)
+{
+    const uint32_t per = nblocks / kXcds;  // the launch is padded to a multiple of 8
+    return (int64_t)(b % kXcds) * per + b / kXcds;
+}
+
+template <int kCh, int kRows, int kCols, bool kSparse>
 __global__ __launch_bounds__(kBX * kBY) void k_jfa_stream(const int32_t* __restrict__ in,
                                                           int32_t* __restrict__ out, int32_t nx,
-                                                          int32_t ny, int32_t nz, int32_t k,
-                                                          int32_t chunks_per_residue)
+                                                          int32_t ny, int32_t nz, int32_t k, int64_t tasks)
 {
+    const int64_t t = xcd_task(blockIdx.x, gridDim.x);
+    if (t >= tasks) return;  // padding (whole work-group)
     __shared__ int32_t tab[32];
     rank_table(tab, nx, ny, k);
     __syncthreads();
-    jfa_block<kCh>(in, out, nx, ny, nz, k, chunks_per_residue, blockIdx.x, blockIdx.y, blockIdx.z, tab);
+    jfa_block<kCh, kRows, kCols, kSparse>(in, out, nx, ny, nz, k, t, tab);
 }
 
-__host__ __device__ inline int32_t chunks_per_residue(int32_t nz, int32_t k, int32_t chunk = kChunk)
+// work-groups of a pass over one grid before padding
+__host__ __device__ inline int64_t pass_tasks(const rtsdf_grid& g, int32_t k, int32_t ch)
 {
-    return (int32_t)ceil_div(ceil_div(nz, k), chunk);
+    return ceil_div(g.nx, kBX) * ceil_div(g.ny, kBY) * z_tasks(g.nz, k, ch).count;
 }
 
-// One pass over every object still flooding: the flat work-group index picks the object
-// from this pass's prefix table, then the object's own geometry and offset; object o reads
-// the buffer holding its pass-p input (its start buffer alternates with p).
+// One pass over every object still flooding: the task index picks the object from this
+// pass's prefix table, then the object's own geometry and offset; object o reads the
+// buffer holding its pass-p input (its start buffer alternates with p).
+template <bool kSparse>
 __global__ __launch_bounds__(kBX * kBY) void k_jfa_batched(const char* __restrict__ plan, int32_t nobj,
                                                            int32_t pass, int32_t* __restrict__ seeds,
                                                            int32_t* __restrict__ scratch)
 {
     const BatchView v = batch_view(plan, nobj);
     const int32_t* prefix = v.pass_prefix + (int64_t)pass * (nobj + 1);
-    const int32_t b = blockIdx.x;
-    const int32_t o = find_object(prefix, nobj, b);
+    const int64_t b = xcd_task(blockIdx.x, gridDim.x);
+    if (b >= prefix[nobj]) return;  // padding (whole work-group)
+    const int32_t o = find_object(prefix, nobj, (int32_t)b);
     const BatchObject& ob = v.obj[o];
     const int32_t k = jfa_offset(ob.k0, ob.nhalf, pass);
     const int32_t nx = ob.g.nx, ny = ob.g.ny, nz = ob.g.nz;
-    const int32_t gx = (nx + kBX - 1) / kBX, gy = (ny + kBY - 1) / kBY;
-    const int32_t l = b - prefix[o];
     const bool from_scratch = (ob.flip ^ (pass & 1)) != 0;
     const int32_t* in = (from_scratch ? scratch : seeds) + ob.vox_off;
     int32_t* out = (from_scratch ? seeds : scratch) + ob.vox_off;
     __shared__ int32_t tab[32];
     rank_table(tab, nx, ny, k);
     __syncthreads();
-    jfa_block<kChunk>(in, out, nx, ny, nz, k, chunks_per_residue(nz, k), l % gx, (l / gx) % gy, l / (gx * gy), tab);
+    jfa_block<kChunk, 3, 3, kSparse>(in, out, nx, ny, nz, k, b - prefix[o], tab);
 }
+
+unsigned padded(int64_t tasks) { return (unsigned)(ceil_div(tasks, kXcds) * kXcds); }
 
 }  // namespace
 
-int64_t jfa_pass_blocks(const rtsdf_grid& g, int32_t k)
-{
-    return ceil_div(g.nx, kBX) * ceil_div(g.ny, kBY) * std::min<int64_t>(k, g.nz) * chunks_per_residue(g.nz, k);
-}
+int64_t jfa_pass_blocks(const rtsdf_grid& g, int32_t k) { return pass_tasks(g, k, kChunk); }
 
 hipError_t jfa_batched_pass(const BatchView& hv, const void* dplan, int32_t* seeds, int32_t* scratch, int32_t pass,
                             hipStream_t s)
 {
     const int32_t blocks = hv.h->pass_blocks[pass];
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_jfa_batched, dim3((unsigned)blocks), dim3(kBX, kBY), 0, s, (const char*)dplan,
-                       hv.h->nobj, pass, seeds, scratch);
+    if (pass < kSparsePasses)
+        hipLaunchKernelGGL(k_jfa_batched<true>, dim3(padded(blocks)), dim3(kBX, kBY), 0, s, (const char*)dplan,
+                           hv.h->nobj, pass, seeds, scratch);
+    else
+        hipLaunchKernelGGL(k_jfa_batched<false>, dim3(padded(blocks)), dim3(kBX, kBY), 0, s, (const char*)dplan,
+                           hv.h->nobj, pass, seeds, scratch);
     return hipGetLastError();
 }
 
-hipError_t jfa_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, hipStream_t s)
+namespace {
+
+template <int kCh, int kRows, int kCols>
+void launch_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, bool sparse, int64_t tasks,
+                 hipStream_t s)
 {
-    const int64_t residues = std::min<int64_t>(k, g.nz);
-    const bool few = jfa_pass_blocks(g, k) < kFewBlocks;  // small grids: shorter chunks, more blocks
-    const int64_t per_res = chunks_per_residue(g.nz, k, few ? kChunkSmall : kChunk);
-    dim3 grid((unsigned)ceil_div(g.nx, kBX), (unsigned)ceil_div(g.ny, kBY), (unsigned)(residues * per_res));
-    if (few)
-        hipLaunchKernelGGL(k_jfa_stream<kChunkSmall>, grid, dim3(kBX, kBY), 0, s, in, out, g.nx, g.ny, g.nz, k,
-                           (int32_t)per_res);
+    const dim3 grid(padded(tasks)), block(kBX, kBY);
+    if (sparse)
+        hipLaunchKernelGGL((k_jfa_stream<kCh, kRows, kCols, true>), grid, block, 0, s, in, out, g.nx, g.ny, g.nz, k,
+                           tasks);
     else
-        hipLaunchKernelGGL(k_jfa_stream<kChunk>, grid, dim3(kBX, kBY), 0, s, in, out, g.nx, g.ny, g.nz, k,
-                           (int32_t)per_res);
+        hipLaunchKernelGGL((k_jfa_stream<kCh, kRows, kCols, false>), grid, block, 0, s, in, out, g.nx, g.ny, g.nz,
+                           k, tasks);
+}
+
+template <int kCh>
+void launch_pass_modes(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, bool sparse, int64_t tasks,
+                       hipStream_t s)
+{
+    // neighbour rows (columns) at +-k lie outside the grid everywhere once k >= ny (nx)
+    const bool rows1 = k >= g.ny, cols1 = k >= g.nx;
+    if (rows1 && cols1) launch_pass<kCh, 1, 1>(in, out, g, k, sparse, tasks, s);
+    else if (rows1) launch_pass<kCh, 1, 3>(in, out, g, k, sparse, tasks, s);
+    else if (cols1) launch_pass<kCh, 3, 1>(in, out, g, k, sparse, tasks, s);
+    else launch_pass<kCh, 3, 3>(in, out, g, k, sparse, tasks, s);
+}
+
+}  // namespace
+
+hipError_t jfa_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, bool sparse, hipStream_t s)
+{
+    const bool few = pass_tasks(g, k, kChunk) < kFewBlocks;  // small grids: shorter chunks, more blocks
+    const int64_t tasks = pass_tasks(g, k, few ? kChunkSmall : kChunk);
+    if (few) launch_pass_modes<kChunkSmall>(in, out, g, k, sparse, tasks, s);
+    else launch_pass_modes<kChunk>(in, out, g, k, sparse, tasks, s);
     return hipGetLastError();
 }
 

@@ -63,10 +63,21 @@ def tuning():
 ROWS, CHUNK = tuning()["RTSDF_JFA_ROWS"], tuning()["RTSDF_JFA_CHUNK"]
 
 
+def z_tasks(nz, k):
+    """z tasks of a pass: chunks of CHUNK lattice points of one residue class, or, when the
+    classes are short, several whole classes per task -> (classes, chunks per class,
+    classes per task, tasks)."""
+    res = min(k, nz)
+    mmax = -(-nz // k)
+    per_res = -(-mmax // CHUNK)
+    group = 1 if per_res > 1 else max(1, CHUNK // mmax)
+    count = res * per_res if per_res > 1 else -(-res // group)
+    return res, per_res, group, count
+
+
 def jfa_blocks(n, k):
     nx, ny, nz = n
-    cpr = -(-(-(-nz // k)) // CHUNK)
-    return -(-nx // 64) * -(-ny // ROWS) * min(k, nz) * cpr
+    return -(-nx // 64) * -(-ny // ROWS) * z_tasks(nz, k)[3]
 
 
 def batch_scenes():
@@ -138,8 +149,9 @@ def test_plan_tables(R, which):
             nx, ny, nz = sc.dims
             gx, gy = -(-nx // 64), -(-ny // ROWS)
             bz = l // (gx * gy)
-            cpr = -(-(-(-nz // k)) // CHUNK)
-            assert l % gx < gx and (l // gx) % gy < gy and bz // cpr < min(k, nz)
+            res, per_res, group, count = z_tasks(nz, k)
+            assert l % gx < gx and (l // gx) % gy < gy and bz < count
+            assert (bz // per_res if per_res > 1 else bz * group) < res
             seen[o] += 1
         assert all(seen[o] > 0 for o in range(n) if counts[o] > 0)
     # mask / combine tiles: each lies in one object's range
@@ -179,3 +191,26 @@ def test_plan_validation(R):
     assert lib.rtsdf_jfa_batched(ctypes.cast(junk, ctypes.c_void_p), ctypes.c_void_p(0x10),
                                  ctypes.c_void_p(0x20), None) == -1
     assert b"not a batch plan" in lib.rtsdf_last_error()
+
+
+def test_jfa_tasks_cover_every_point_once():
+    """The z tasks of a pass, decoded the way the pass kernel decodes them, visit every z of
+    the grid exactly once (as lattice point m of residue class z mod k), for grids and
+    offsets that give long classes split into chunks, short classes grouped, and offsets
+    beyond the grid."""
+    for nz in (1, 2, 3, 7, 31, 32, 33, 64, 100, 200, 400, 1023):
+        for k in sorted({1, 2, 3, 4, 8, 16, 31, 32, 64, 128, 256, 512, 1024, nz, max(1, nz // 2)}):
+            res, per_res, group, count = z_tasks(nz, k)
+            seen = np.zeros(nz, np.int64)
+            for bz in range(count):
+                if per_res > 1:
+                    r0 = bz // per_res
+                    r1, mlo, mhi = r0 + 1, (bz - r0 * per_res) * CHUNK, (bz - r0 * per_res + 1) * CHUNK
+                else:
+                    r0 = bz * group
+                    r1, mlo, mhi = min(r0 + group, res), 0, 1 << 31
+                for r in range(r0, r1):
+                    mcount = (nz - r + k - 1) // k
+                    for m in range(mlo, min(mhi, mcount)):
+                        seen[r + m * k] += 1
+            assert (seen == 1).all(), (nz, k)
