@@ -122,8 +122,9 @@ def gpu_step(S, rtsdf, timer):
 
 def deform_bench(torch, rtsdf, synth):
     """Deforming torus knot (50k triangles) on the same grid: 60 frames, each re-voxelized,
-    re-flooded, re-masked, BVH rebuilt, 4 rays per masked voxel, Eq. 1 decay; every frame's
-    chain is a captured HIP graph, replayed in order (eager chain timed beside it)."""
+    re-flooded, re-masked, BVH rebuilt, 4 rays per masked voxel, Eq. 1 decay; the chain of
+    frames >= 1 is one HIP graph recorded once and replayed per frame with the frame index
+    in device memory (eager chain timed beside it)."""
     sc = synth.scene_deform()
     D = rtsdf.DeformSDF(sc.extra["frames"], sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays,
                         sc.extra["alpha"])

@@ -167,6 +167,21 @@ rtsdf_status rtsdf_raysample(const void* bvh, rtsdf_grid g, const int32_t* band_
                              void* work, size_t work_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * rtsdf_raysample_frame_device -- rtsdf_raysample with the frame index read from device
+ * memory (`frame`, one uint32, device pointer) when the kernel runs rather than passed by
+ * value, so that a per-frame chain recorded once into a HIP graph can be replayed for
+ * every frame of a sequence (section 2.5.1 updates the field each frame) with only the
+ * frame word changed between replays.  Results and errors as rtsdf_raysample (E_ARG also
+ * for a NULL frame).
+ * ------------------------------------------------------------------------------------- */
+rtsdf_status rtsdf_raysample_frame_device(const void* bvh, rtsdf_grid g, const int32_t* band_list,
+                                          const int32_t* band_count, int64_t band_capacity,
+                                          int32_t rays_per_voxel, uint64_t rng_key,
+                                          const uint32_t* frame, uint32_t obj, float* dmin,
+                                          uint32_t* hits, uint64_t* argmin, void* work,
+                                          size_t work_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * rtsdf_raysample_noalloc -- rtsdf_raysample without a work argument, for callers that
  * cannot allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  Same arguments (minus work / work_bytes), same

@@ -411,8 +411,30 @@ rtsdf_status rtsdf_raysample(const void* bvh, rtsdf_grid g, const int32_t* band_
         return fail(RTSDF_E_SIZE, "raysample work %zu < %zu bytes", work_bytes,
                     rtsdf::raysample_work_bytes(band_capacity, rays_per_voxel));
     return device(rtsdf::raysample(bvh, g, band_list, band_count, band_capacity, rays_per_voxel, rng_key,
-                                   frame, obj, dmin, hits, argmin, work, as_stream(stream)),
+                                   frame, nullptr, obj, dmin, hits, argmin, work, as_stream(stream)),
                   "raysample");
+}
+
+rtsdf_status rtsdf_raysample_frame_device(const void* bvh, rtsdf_grid g, const int32_t* band_list,
+                                          const int32_t* band_count, int64_t band_capacity, int32_t rays_per_voxel,
+                                          uint64_t rng_key, const uint32_t* frame, uint32_t obj, float* dmin,
+                                          uint32_t* hits, uint64_t* argmin, void* work, size_t work_bytes,
+                                          void* stream)
+{
+    if (rtsdf_status st = check_grid(g)) return st;
+    if (!bvh || !band_list || !band_count || !frame || !dmin || !hits || !work)
+        return fail(RTSDF_E_ARG, "NULL pointer");
+    if (rays_per_voxel < 1 || rays_per_voxel > RTSDF_MAX_RAYS)
+        return fail(RTSDF_E_RANGE, "rays_per_voxel %d outside [1, %d]", rays_per_voxel, RTSDF_MAX_RAYS);
+    if (band_capacity < 0 || band_capacity > rtsdf::nvox(g))
+        return fail(RTSDF_E_RANGE, "band_capacity outside [0, N]");
+    if (obj >= (1u << 24)) return fail(RTSDF_E_RANGE, "obj %u >= 2^24", obj);
+    if (work_bytes < rtsdf::raysample_work_bytes(band_capacity, rays_per_voxel))
+        return fail(RTSDF_E_SIZE, "raysample work %zu < %zu bytes", work_bytes,
+                    rtsdf::raysample_work_bytes(band_capacity, rays_per_voxel));
+    return device(rtsdf::raysample(bvh, g, band_list, band_count, band_capacity, rays_per_voxel, rng_key, 0u, frame,
+                                   obj, dmin, hits, argmin, work, as_stream(stream)),
+                  "raysample_frame_device");
 }
 
 rtsdf_status rtsdf_raysample_noalloc(const void* bvh, rtsdf_grid g, const int32_t* band_list,
@@ -434,7 +456,7 @@ rtsdf_status rtsdf_raysample_noalloc(const void* bvh, rtsdf_grid g, const int32_
     void* scratch = nullptr;
     if (rtsdf_status st = device(rtsdf::raysample_scratch(&scratch), "raysample scratch address")) return st;
     return device(rtsdf::raysample(bvh, g, band_list, band_count, band_capacity, rays_per_voxel, rng_key, frame,
-                                   obj, dmin, hits, argmin, scratch, as_stream(stream)),
+                                   nullptr, obj, dmin, hits, argmin, scratch, as_stream(stream)),
                   "raysample_noalloc");
 }
 

@@ -51,10 +51,12 @@ size_t raysample_work_bytes(int64_t capacity, int32_t x);
 // the allocation-free variant's work cursors: a static device array per GPU
 size_t raysample_scratch_bytes();
 hipError_t raysample_scratch(void** out);
+// frame_dev: when non-null, the frame index is read from it when the kernel runs (frame is
+// then ignored)
 hipError_t raysample(const void* bvh, const rtsdf_grid& g, const int32_t* list,
                      const int32_t* count, int64_t capacity, int32_t x, uint64_t key,
-                     uint32_t frame, uint32_t obj, float* dmin, uint32_t* hits, uint64_t* argmin,
-                     void* work, hipStream_t s);
+                     uint32_t frame, const uint32_t* frame_dev, uint32_t obj, float* dmin, uint32_t* hits,
+                     uint64_t* argmin, void* work, hipStream_t s);
 
 hipError_t combine(const int32_t* seeds, float* dmin, uint32_t* hits, const rtsdf_grid& g,
                    int32_t band_vox, float beta, float bias, int32_t mode, float alpha,

@@ -93,6 +93,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves<kBatch>) void k_raysample(const
                                                         const int32_t* __restrict__ list,
                                                         const int32_t* __restrict__ count_p, int32_t x,
                                                         uint32_t k0, uint32_t k1, uint32_t frame,
+                                                        const uint32_t* __restrict__ frame_dev,
                                                         uint32_t obj, float* __restrict__ dmin,
                                                         uint32_t* __restrict__ hits,
                                                         uint64_t* __restrict__ argmin,
@@ -145,6 +146,7 @@ __global__ __launch_bounds__(kThreads, kMinWaves<kBatch>) void k_raysample(const
     const int tid = threadIdx.x;
     const int lane = __lane_id();
     const uint64_t lt_mask = (1ull << lane) - 1ull;
+    if (frame_dev != nullptr) frame = *frame_dev;  // the frame index as of when the kernel runs
     const uint32_t code0 = frame * (uint32_t)x;
     // the range this wave takes units from: one of its own XCD's
     int rng = (int)(blockIdx.x % kXcds) * kSub + (int)((blockIdx.x / kXcds) % kSub);
@@ -409,8 +411,8 @@ hipError_t raysample_scratch(void** out)
 }
 
 hipError_t raysample(const void* bvh, const rtsdf_grid& g, const int32_t* list, const int32_t* count,
-                     int64_t capacity, int32_t x, uint64_t key, uint32_t frame, uint32_t obj,
-                     float* dmin, uint32_t* hits, uint64_t* argmin, void* work, hipStream_t s)
+                     int64_t capacity, int32_t x, uint64_t key, uint32_t frame, const uint32_t* frame_dev,
+                     uint32_t obj, float* dmin, uint32_t* hits, uint64_t* argmin, void* work, hipStream_t s)
 {
     if (capacity <= 0) return hipSuccess;
     int32_t* cursors = (int32_t*)work;
@@ -430,7 +432,8 @@ hipError_t raysample(const void* bvh, const rtsdf_grid& g, const int32_t* list, 
     const int64_t want = ceil_div(capacity, kThreads);
     const unsigned groups = (unsigned)std::max<int64_t>(kXcds, std::min<int64_t>(want, resident));
     hipLaunchKernelGGL(k_raysample<false>, dim3(groups), dim3(kThreads), 0, s, (const char*)bvh, g, list, count, x,
-                       (uint32_t)key, (uint32_t)(key >> 32), frame, obj, dmin, hits, argmin, cursors, nullptr, 0);
+                       (uint32_t)key, (uint32_t)(key >> 32), frame, frame_dev, obj, dmin, hits, argmin, cursors,
+                       nullptr, 0);
     return hipGetLastError();
 }
 
@@ -456,7 +459,7 @@ hipError_t raysample_batched(const BatchView& hv, const void* dplan, const void*
     const unsigned groups = (unsigned)std::max<int64_t>(kXcds, std::min<int64_t>(want, resident));
     const rtsdf_grid g0 = hv.obj[0].g;  // unused in batch mode
     hipLaunchKernelGGL(k_raysample<true>, dim3(groups), dim3(kThreads), 0, s, (const char*)bvh, g0, list, count, x,
-                       (uint32_t)key, (uint32_t)(key >> 32), frame, 0u, dmin, hits, argmin, cursors,
+                       (uint32_t)key, (uint32_t)(key >> 32), frame, nullptr, 0u, dmin, hits, argmin, cursors,
                        (const char*)dplan, hv.h->nobj);
     return hipGetLastError();
 }

@@ -121,6 +121,7 @@ def lib():
             "rtsdf_raysample_work_bytes": ([i64, i32], sz),
             "rtsdf_raysample": ([vp, Grid, vp, vp, i64, i32, u64, u32, u32, vp, vp, vp, vp, sz, vp], i32),
             "rtsdf_raysample_noalloc": ([vp, Grid, vp, vp, i64, i32, u64, u32, u32, vp, vp, vp, vp], i32),
+            "rtsdf_raysample_frame_device": ([vp, Grid, vp, vp, i64, i32, u64, vp, u32, vp, vp, vp, vp, sz, vp], i32),
             "rtsdf_combine": ([vp, vp, vp, Grid, i32, f32, f32, i32, f32, i32, i32, vp, vp, vp], i32),
             "rtsdf_refine_grid": ([Grid, i32, ctypes.POINTER(Grid)], i32),
             "rtsdf_band_refined_work_bytes": ([Grid, i32], sz),
@@ -158,7 +159,7 @@ def lib():
 EXPORTED = ["rtsdf_last_error", "rtsdf_abi_version", "rtsdf_voxelize_work_bytes", "rtsdf_voxelize",
             "rtsdf_jfa", "rtsdf_band_work_bytes", "rtsdf_band", "rtsdf_bvh_bytes", "rtsdf_bvh_work_bytes",
             "rtsdf_build_bvh", "rtsdf_reset_accum", "rtsdf_raysample_work_bytes", "rtsdf_raysample",
-            "rtsdf_raysample_noalloc",
+            "rtsdf_raysample_noalloc", "rtsdf_raysample_frame_device",
             "rtsdf_combine", "rtsdf_refine_grid", "rtsdf_band_refined_work_bytes", "rtsdf_band_refined",
             "rtsdf_combine_refined", "rtsdf_shadow_forward", "rtsdf_shadow_backward", "rtsdf_shadow_forward_ex",
             "rtsdf_shadow_backward_ex", "rtsdf_clipmap_levels", "rtsdf_clipmap_sample", "rtsdf_shadow_forward_clip",
@@ -265,6 +266,20 @@ def rtsdf_raysample(bvh, grid, band_list, band_count, rays_per_voxel, rng_key, f
                                  _ptr(argmin, torch.int64) if argmin is not None else None, _ptr(work),
                                  work.numel(), _stream(stream)),
            "rtsdf_raysample")
+
+
+def rtsdf_raysample_frame_device(bvh, grid, band_list, band_count, rays_per_voxel, rng_key, frame, dmin, hits, work,
+                                 argmin=None, obj=0, band_capacity=None, stream=None):
+    """rtsdf_raysample with the frame index read from `frame` (a one-element int32 device
+    tensor) when the kernel runs."""
+    cap = band_list.numel() if band_capacity is None else int(band_capacity)
+    _check(lib().rtsdf_raysample_frame_device(_ptr(bvh), grid, _ptr(band_list, torch.int32),
+                                              _ptr(band_count, torch.int32), cap, int(rays_per_voxel),
+                                              int(rng_key) & (2 ** 64 - 1), _ptr(frame, torch.int32), int(obj),
+                                              _ptr(dmin, torch.float32), _ptr(hits, torch.int32),
+                                              _ptr(argmin, torch.int64) if argmin is not None else None, _ptr(work),
+                                              work.numel(), _stream(stream)),
+           "rtsdf_raysample_frame_device")
 
 
 def rtsdf_raysample_noalloc(bvh, grid, band_list, band_count, rays_per_voxel, rng_key, frame, dmin, hits,
@@ -797,8 +812,12 @@ class DeformSDF:
     re-floods, re-masks, rebuilds the hierarchy, ray-samples the mask and folds the frame
     into the field with the decay rule of Eq. 1 (RTSDF_DECAY, `consume` resets the frame's
     ray accumulators).  All frames' vertices are resident on the device.  frame(f) only
-    enqueues kernels and never synchronizes, so capture() can record each frame's chain
-    into a HIP graph once and replay() runs it; frame 0 also clears the accumulators.
+    enqueues kernels and never synchronizes; frame 0 also clears the accumulators and starts
+    the decay from the coarse field.  capture() records the chain of frames >= 1 once into a
+    HIP graph in which everything that depends on the frame reads a one-word frame index in
+    device memory (the frame's vertices are gathered into a fixed buffer, ray sampling reads
+    the counter word there), so replay(f) only writes f into that word and replays the same
+    graph for every frame.
     ratio r > 1 is the paper's two-level configuration: `dims`/`h` are the coarse flooded
     grid `g`, rays and the field run on the grid `gf` refined by r (see StaticSDF).
     """
@@ -832,13 +851,20 @@ class DeformSDF:
                  rtsdf_bvh_work_bytes(nt))
         self.work = workspace(wb, device)
         self.ray_work = workspace(rtsdf_raysample_work_bytes(Nf, self.rays), device)
-        self.graphs = {}
+        self.graph = None
+        self.frame_dev = torch.zeros(1, dtype=torch.int32, device=device)
+        self.cur = torch.empty_like(self.verts[:1])  # the replayed graph's vertex buffer [1, V, 3]
         self.jfa_out = None
 
     def frame(self, f):
-        v = self.verts[f]
-        if f == 0:
+        self._chain(self.verts[f], f, None)
+
+    def _chain(self, v, f, frame_dev):
+        """One frame's chain on vertices v: frame f (frame_dev None) or the frame index held
+        in frame_dev (a frame >= 1)."""
+        if frame_dev is None and f == 0:
             rtsdf_reset_accum(self.dmin, self.hits)
+        first = frame_dev is None and f == 0
         rtsdf_voxelize(v, self.tris, self.g, self.seeds, self.work)
         self.jfa_out = rtsdf_jfa(self.seeds, self.scratch, self.g, self.steps)
         if self.ratio == 1:
@@ -847,22 +873,35 @@ class DeformSDF:
             rtsdf_band_refined(self.jfa_out, self.g, self.ratio, self.band, self.band_list, self.band_count,
                                self.work)
         rtsdf_build_bvh(v, self.tris, self.gf, self.bvh, self.work, self.bvh_method)
-        rtsdf_raysample(self.bvh, self.gf, self.band_list, self.band_count, self.rays, self.rng_key, f, self.dmin,
-                        self.hits, self.ray_work)
+        if frame_dev is None:
+            rtsdf_raysample(self.bvh, self.gf, self.band_list, self.band_count, self.rays, self.rng_key, f, self.dmin,
+                            self.hits, self.ray_work)
+        else:
+            rtsdf_raysample_frame_device(self.bvh, self.gf, self.band_list, self.band_count, self.rays, self.rng_key,
+                                         frame_dev, self.dmin, self.hits, self.ray_work)
         if self.ratio == 1:
             rtsdf_combine(self.jfa_out, self.dmin, self.hits, self.g, self.band, self.beta, self.bias, DECAY,
-                          self.fine, alpha=self.alpha, first_frame=(f == 0), consume=True, state=self.state)
+                          self.fine, alpha=self.alpha, first_frame=first, consume=True, state=self.state)
         else:
             rtsdf_combine_refined(self.jfa_out, self.dmin, self.hits, self.g, self.ratio, self.band, self.beta,
-                                  self.bias, DECAY, self.fine, alpha=self.alpha, first_frame=(f == 0), consume=True,
+                                  self.bias, DECAY, self.fine, alpha=self.alpha, first_frame=first, consume=True,
                                   state=self.state)
 
-    def capture(self, frames=None):
-        for f in (range(self.nframes) if frames is None else frames):
-            gr = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(gr):
-                self.frame(f)
-            self.graphs[f] = gr
+    def capture(self):
+        """Records the chain of a frame >= 1 once (vertices gathered by the device-side frame
+        index, ray counters read from it)."""
+        self.frame_dev.fill_(1)
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            torch.index_select(self.verts, 0, self.frame_dev, out=self.cur)
+            self._chain(self.cur[0], None, self.frame_dev)
+        self.graph = gr
 
     def replay(self, f):
-        self.graphs[f].replay()
+        """Frame f: frame 0 runs eagerly (it starts the decay); later frames replay the graph."""
+        if f == 0 or self.graph is None:
+            self.frame(f)
+            return
+        self.frame_dev.fill_(f)
+        self.graph.replay()

@@ -81,6 +81,13 @@ def test_host_validation(L):
                                fake(), lib.rtsdf_raysample_work_bytes(10, 4) - 1, None) == E_SIZE
     assert lib.rtsdf_raysample(fake(), g, fake(), fake(), 10, 4, 0, 0, 0, fake(), fake(), None,
                                None, 256, None) == E_ARG
+    # the device-side frame index variant: same checks, plus a NULL frame pointer
+    assert lib.rtsdf_raysample_frame_device(fake(), g, fake(), fake(), 10, 4, 0, None, 0, fake(), fake(), None,
+                                            fake(), 256, None) == E_ARG
+    assert lib.rtsdf_raysample_frame_device(fake(), g, fake(), fake(), 10, 0, 0, fake(), 0, fake(), fake(), None,
+                                            fake(), 256, None) == E_RANGE
+    assert lib.rtsdf_raysample_frame_device(fake(), g, fake(), fake(), 10, 4, 0, fake(), 0, fake(), fake(), None,
+                                            fake(), lib.rtsdf_raysample_work_bytes(10, 4) - 1, None) == E_SIZE
     # the allocation-free variant validates the same way, before it touches a device
     for rays in (0, 65536):
         assert lib.rtsdf_raysample_noalloc(fake(), g, fake(), fake(), 10, rays, 0, 0, 0, fake(), fake(), None,

@@ -4,8 +4,9 @@ HIP-graph replays of every frame vs the eager chain.
 A reduced grid (100 x 50 x 100 over the same world box) is compared element by element over
 a sequence of frames, including the Eq. 1 state carried from frame to frame.  At the full
 400 x 200 x 400 size, the first and last frames are compared stage by stage (seed ids, mask
-exact over every voxel; per-frame ray results on sampled masked voxels), and 60 graph
-replays (twice over) must equal the eager chain bit for bit.
+exact over every voxel; per-frame ray results on sampled masked voxels), and 60 frames
+replayed (twice over) from one HIP graph recorded once (the frame index in device memory)
+must equal the eager chain bit for bit.
 """
 import sys
 
