@@ -25,7 +25,7 @@ TUNE_DIR = os.path.join(HERE, "_build", "tune")
 TUNING_H = os.path.join(HERE, "csrc", "tuning.h")
 
 GROUPS = {
-    "jfa": {"RTSDF_JFA_CHUNK": [16, 32, 64], "RTSDF_JFA_ROWS": [2, 4, 8]},
+    "jfa": {"RTSDF_JFA_CHUNK": [16, 32, 64], "RTSDF_JFA_WAVES": [2, 4, 8]},
     "ray": {"RTSDF_RAY_START_BATCH": [8, 12, 16], "RTSDF_RAY_WAVES": [6, 7], "RTSDF_RAY_POP_TRIPS": [1, 2]},
     "tree": {"RTSDF_LEAF_MAX": [2, 3, 4], "RTSDF_PLOC_RADIUS": [16, 32]},
     "waves": {"RTSDF_RAY_WAVES": [6, 7]},

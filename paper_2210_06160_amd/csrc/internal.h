@@ -24,11 +24,10 @@ size_t voxelize_work_bytes(int32_t nt);
 hipError_t voxelize(const float* verts, const int32_t* tris, int32_t nt, const rtsdf_grid& g,
                     int32_t* seeds, void* work, hipStream_t s);
 
-// sparse: the input is mostly EMPTY (the first passes after voxelization); only speed
-// differs
-hipError_t jfa_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, bool sparse, hipStream_t s);
-// passes run with the all-EMPTY row test (the first ones after voxelization)
-constexpr int32_t kSparsePasses = 2;
+hipError_t jfa_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, hipStream_t s);
+// a pass whose input is mostly EMPTY (the offsets of at least a quarter of the longest side:
+// the first two after voxelization) tests each plane's loaded ids for all-EMPTY first
+bool jfa_sparse(const rtsdf_grid& g, int32_t k);
 int64_t jfa_pass_blocks(const rtsdf_grid& g, int32_t k);  // work-groups of one pass
 
 size_t band_work_bytes(const rtsdf_grid& g);

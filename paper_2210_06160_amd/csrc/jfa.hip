@@ -36,7 +36,8 @@
 //   - in the sparse early passes (most of the input EMPTY) a neighbour row whose three
 //     loaded columns are EMPTY on every lane.
 //
-// Work distribution.  A work-group is 64 x-columns x RTSDF_JFA_ROWS rows and a z task:
+// Work distribution.  A work-group is 64 RTSDF_JFA_WAVES consecutive columns of a plane
+// (in x-fastest order, across row ends) and a z task:
 // a chunk of one residue class's lattice points, or, when classes are short (large k),
 // several whole classes, so that per-group set-up is spread over about RTSDF_JFA_CHUNK
 // outputs per thread.  Work-groups are dealt to the 8 XCDs round-robin in launch order;
@@ -50,7 +51,7 @@ namespace rtsdf {
 
 namespace {
 
-constexpr int kBX = 64, kBY = RTSDF_JFA_ROWS;  // threads per block: 64 x-columns x kBY y-columns
+constexpr int kThreads = 64 * RTSDF_JFA_WAVES;  // threads (= consecutive columns of a plane) per work-group
 constexpr int kChunk = RTSDF_JFA_CHUNK;        // outputs per thread and work-group along z
 constexpr int kChunkSmall = 16;                // ... for passes that would launch few blocks
 constexpr int64_t kFewBlocks = 2048;           // below this many blocks, use kChunkSmall
@@ -88,7 +89,7 @@ __device__ inline int32_t min9(const int32_t* k)
 // rank 0 is the point itself, rank 1 + L the query L = 9 (ez+1) + 3 (ey+1) + (ex+1)
 __device__ inline void rank_table(int32_t* tab, int32_t nx, int32_t ny, int32_t k)
 {
-    const int t = threadIdx.x + threadIdx.y * kBX;
+    const int t = threadIdx.x;
     if (t < 28) {
         const int32_t L = t == 0 ? 13 : t - 1;
         const int32_t ez = L / 9 - 1, ey = (L / 3) % 3 - 1, ex = L % 3 - 1;
@@ -104,11 +105,14 @@ __device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const int32_t* in, uint32_t 
                                             0x00020000);
 }
 
-// z tasks of one pass: either chunks of kCh lattice points of one residue class
-// (per_res > 1 chunks per class, one class per task), or `group` whole classes per task
+// z tasks of one pass: either chunks of at most kCh lattice points of one residue class
+// (per_res > 1 chunks of equal length `len` per class, one class per task; equal lengths
+// keep the work of the XCDs' contiguous task ranges equal), or `group` whole classes per
+// task
 struct ZTasks {
     int32_t res;      // residue classes: min(k, nz)
     int32_t per_res;  // chunks per class (>= 1)
+    int32_t len;      // lattice points per chunk (when per_res > 1)
     int32_t group;    // classes per task (>= 1; > 1 only when per_res == 1)
     int32_t count;    // tasks
 };
@@ -119,6 +123,7 @@ __host__ __device__ inline ZTasks z_tasks(int32_t nz, int32_t k, int32_t ch)
     t.res = k < nz ? k : nz;
     const int32_t mmax = (nz + k - 1) / k;  // lattice points of class 0 (the longest)
     t.per_res = (mmax + ch - 1) / ch;
+    t.len = (mmax + t.per_res - 1) / t.per_res;
     t.group = t.per_res > 1 ? 1 : (ch / mmax > 1 ? ch / mmax : 1);
     t.count = t.per_res > 1 ? t.res * t.per_res : (t.res + t.group - 1) / t.group;
     return t;
@@ -183,21 +188,23 @@ __device__ __forceinline__ void plane(const int32_t* __restrict__ in, uint32_t p
     if (kNext) a_next = min(a_next, min9(kn));
 }
 
-// work-group `blk` (remapped task index) of a pass over one grid: x-columns bx*64..,
-// y-columns by*kBY.., z task bz; tab = rank_table(nx, ny, k)
+// work-group `blk` (remapped task index) of a pass over one grid: the plane's columns
+// c = x + nx y in [cb kThreads, (cb+1) kThreads) (waves take consecutive columns across row
+// ends, so no lane idles at the end of a row), z task bz; tab = rank_table(nx, ny, k)
 template <int kCh, int kRows, int kCols, bool kSparse>
 __device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_t* __restrict__ out, int32_t nx,
                                           int32_t ny, int32_t nz, int32_t k, int64_t blk, const int32_t* tab)
 {
-    const int32_t gx = (nx + kBX - 1) / kBX, gy = (ny + kBY - 1) / kBY;
-    const int32_t bx = (int32_t)(blk % gx), by = (int32_t)((blk / gx) % gy), bz = (int32_t)(blk / ((int64_t)gx * gy));
-    const int32_t x = bx * kBX + threadIdx.x;
-    const int32_t y = by * kBY + threadIdx.y;
-    if (x >= nx || y >= ny) return;
     const uint32_t plane_elems = (uint32_t)nx * (uint32_t)ny;  // grids hold at most 2^30 points
+    const int64_t gc = ceil_div(plane_elems, kThreads);
+    const int64_t cb = blk % gc;
+    const int32_t bz = (int32_t)(blk / gc);
+    const int64_t col = cb * kThreads + threadIdx.x;
+    if (col >= plane_elems) return;
+    const int32_t y = (int32_t)(col / nx), x = (int32_t)(col - (int64_t)y * nx);
 
     Column c;
-    const uint32_t own = 4u * ((uint32_t)x + (uint32_t)nx * (uint32_t)y);
+    const uint32_t own = 4u * (uint32_t)col;
 #pragma unroll
     for (int ey = -1; ey <= 1; ++ey)
 #pragma unroll
@@ -209,7 +216,7 @@ __device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_
             c.inv[q] = ok ? 0 : -1;
         }
     c.pxy = __builtin_bit_cast(short2_t, (uint32_t)x | ((uint32_t)y << 16));
-    const uint32_t pxy_idx = (uint32_t)x + (uint32_t)nx * (uint32_t)y;
+    const uint32_t pxy_idx = (uint32_t)col;
 
     auto emit = [&](int32_t pz, int32_t best) {
         const uint32_t p = pxy_idx + plane_elems * (uint32_t)pz;
@@ -223,8 +230,8 @@ __device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_
     if (zt.per_res > 1) {
         r0 = bz / zt.per_res;
         r1 = r0 + 1;
-        mlo = (bz - r0 * zt.per_res) * kCh;
-        mhi = mlo + kCh;
+        mlo = (bz - r0 * zt.per_res) * zt.len;
+        mhi = mlo + zt.len;
     } else {
         r0 = bz * zt.group;
         r1 = min(r0 + zt.group, zt.res);
@@ -270,7 +277,7 @@ __device__ inline int64_t xcd_task(uint32_t b, uint32_t nblocks)
 }
 
 template <int kCh, int kRows, int kCols, bool kSparse>
-__global__ __launch_bounds__(kBX * kBY) void k_jfa_stream(const int32_t* __restrict__ in,
+__global__ __launch_bounds__(kThreads) void k_jfa_stream(const int32_t* __restrict__ in,
                                                           int32_t* __restrict__ out, int32_t nx,
                                                           int32_t ny, int32_t nz, int32_t k, int64_t tasks)
 {
@@ -285,14 +292,14 @@ __global__ __launch_bounds__(kBX * kBY) void k_jfa_stream(const int32_t* __restr
 // work-groups of a pass over one grid before padding
 __host__ __device__ inline int64_t pass_tasks(const rtsdf_grid& g, int32_t k, int32_t ch)
 {
-    return ceil_div(g.nx, kBX) * ceil_div(g.ny, kBY) * z_tasks(g.nz, k, ch).count;
+    return ceil_div((int64_t)g.nx * g.ny, kThreads) * z_tasks(g.nz, k, ch).count;
 }
 
 // One pass over every object still flooding: the task index picks the object from this
 // pass's prefix table, then the object's own geometry and offset; object o reads the
 // buffer holding its pass-p input (its start buffer alternates with p).
 template <bool kSparse>
-__global__ __launch_bounds__(kBX * kBY) void k_jfa_batched(const char* __restrict__ plan, int32_t nobj,
+__global__ __launch_bounds__(kThreads) void k_jfa_batched(const char* __restrict__ plan, int32_t nobj,
                                                            int32_t pass, int32_t* __restrict__ seeds,
                                                            int32_t* __restrict__ scratch)
 {
@@ -324,11 +331,11 @@ hipError_t jfa_batched_pass(const BatchView& hv, const void* dplan, int32_t* see
 {
     const int32_t blocks = hv.h->pass_blocks[pass];
     if (blocks == 0) return hipSuccess;
-    if (pass < kSparsePasses)
-        hipLaunchKernelGGL(k_jfa_batched<true>, dim3(padded(blocks)), dim3(kBX, kBY), 0, s, (const char*)dplan,
+    if (pass < 2)  // the first two passes of the halving offsets (the sparse ones, as jfa_sparse)
+        hipLaunchKernelGGL(k_jfa_batched<true>, dim3(padded(blocks)), dim3(kThreads), 0, s, (const char*)dplan,
                            hv.h->nobj, pass, seeds, scratch);
     else
-        hipLaunchKernelGGL(k_jfa_batched<false>, dim3(padded(blocks)), dim3(kBX, kBY), 0, s, (const char*)dplan,
+        hipLaunchKernelGGL(k_jfa_batched<false>, dim3(padded(blocks)), dim3(kThreads), 0, s, (const char*)dplan,
                            hv.h->nobj, pass, seeds, scratch);
     return hipGetLastError();
 }
@@ -339,7 +346,7 @@ template <int kCh, int kRows, int kCols>
 void launch_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, bool sparse, int64_t tasks,
                  hipStream_t s)
 {
-    const dim3 grid(padded(tasks)), block(kBX, kBY);
+    const dim3 grid(padded(tasks)), block(kThreads);
     if (sparse)
         hipLaunchKernelGGL((k_jfa_stream<kCh, kRows, kCols, true>), grid, block, 0, s, in, out, g.nx, g.ny, g.nz, k,
                            tasks);
@@ -362,8 +369,11 @@ void launch_pass_modes(const int32_t* in, int32_t* out, const rtsdf_grid& g, int
 
 }  // namespace
 
-hipError_t jfa_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, bool sparse, hipStream_t s)
+bool jfa_sparse(const rtsdf_grid& g, int32_t k) { return 4 * (int64_t)k >= std::max(g.nx, std::max(g.ny, g.nz)); }
+
+hipError_t jfa_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, hipStream_t s)
 {
+    const bool sparse = jfa_sparse(g, k);
     const bool few = pass_tasks(g, k, kChunk) < kFewBlocks;  // small grids: shorter chunks, more blocks
     const int64_t tasks = pass_tasks(g, k, few ? kChunkSmall : kChunk);
     if (few) launch_pass_modes<kChunkSmall>(in, out, g, k, sparse, tasks, s);

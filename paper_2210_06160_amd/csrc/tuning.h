@@ -5,12 +5,13 @@
 // its candidate libraries that way).
 #pragma once
 
-// jump flooding: lattice points per work-group along z, and y-rows of 64 x-columns
+// jump flooding: lattice points per work-group along z, and waves per work-group (each wave
+// takes 64 consecutive columns of a plane)
 #ifndef RTSDF_JFA_CHUNK
 #define RTSDF_JFA_CHUNK 32
 #endif
-#ifndef RTSDF_JFA_ROWS
-#define RTSDF_JFA_ROWS 4
+#ifndef RTSDF_JFA_WAVES
+#define RTSDF_JFA_WAVES 4
 #endif
 
 // ray sampling: work units a wave takes per cursor atomic (raised so that one atomic

@@ -60,7 +60,7 @@ def tuning():
     return {m.group(1): int(m.group(2)) for m in re.finditer(r"#define (RTSDF_\w+) (\d+)", open(path).read())}
 
 
-ROWS, CHUNK = tuning()["RTSDF_JFA_ROWS"], tuning()["RTSDF_JFA_CHUNK"]
+WAVES, CHUNK = tuning()["RTSDF_JFA_WAVES"], tuning()["RTSDF_JFA_CHUNK"]
 
 
 def z_tasks(nz, k):
@@ -75,9 +75,16 @@ def z_tasks(nz, k):
     return res, per_res, group, count
 
 
+def chunk_len(nz, k):
+    """Lattice points per chunk when classes are split: equal lengths, each <= CHUNK."""
+    mmax = -(-nz // k)
+    per_res = -(-mmax // CHUNK)
+    return -(-mmax // per_res)
+
+
 def jfa_blocks(n, k):
     nx, ny, nz = n
-    return -(-nx // 64) * -(-ny // ROWS) * z_tasks(nz, k)[3]
+    return -(-(nx * ny) // (64 * WAVES)) * z_tasks(nz, k)[3]
 
 
 def batch_scenes():
@@ -147,10 +154,10 @@ def test_plan_tables(R, which):
             l = blk - pass_prefix[p][o]
             assert 0 <= l < counts[o]
             nx, ny, nz = sc.dims
-            gx, gy = -(-nx // 64), -(-ny // ROWS)
-            bz = l // (gx * gy)
+            gc = -(-(nx * ny) // (64 * WAVES))
+            bz = l // gc
             res, per_res, group, count = z_tasks(nz, k)
-            assert l % gx < gx and (l // gx) % gy < gy and bz < count
+            assert bz < count
             assert (bz // per_res if per_res > 1 else bz * group) < res
             seen[o] += 1
         assert all(seen[o] > 0 for o in range(n) if counts[o] > 0)
@@ -204,8 +211,10 @@ def test_jfa_tasks_cover_every_point_once():
             seen = np.zeros(nz, np.int64)
             for bz in range(count):
                 if per_res > 1:
+                    L = chunk_len(nz, k)
+                    assert L <= CHUNK
                     r0 = bz // per_res
-                    r1, mlo, mhi = r0 + 1, (bz - r0 * per_res) * CHUNK, (bz - r0 * per_res + 1) * CHUNK
+                    r1, mlo, mhi = r0 + 1, (bz - r0 * per_res) * L, (bz - r0 * per_res + 1) * L
                 else:
                     r0 = bz * group
                     r1, mlo, mhi = min(r0 + group, res), 0, 1 << 31
