@@ -69,6 +69,14 @@ constexpr int kPerTrip = 16;
     asm volatile(TWO(ins " %0, %0\n\t" ins " %1, %1\n\t" ins " %2, %2\n\t" ins " %3, %3\n\t" ins " %4, %4\n\t" ins \
                      " %5, %5\n\t" ins " %6, %6\n\t" ins " %7, %7\n\t")                               \
                  : OUTS8(a))
+// v_mad_u64_u32 dst64 = src0 * src1 + src2_64 (the 32 x 32 -> 64 products of Philox): 8
+// independent 64-bit accumulators would need 16 registers, so 4 are rotated twice per trip
+#define IMAD64(ins)                                                                                     \
+    asm volatile(TWO(TWO(ins " %0, s[0:1], %4, %5, %0\n\t" ins " %1, s[0:1], %4, %5, %1\n\t" ins           \
+                         " %2, s[0:1], %4, %5, %2\n\t" ins " %3, s[0:1], %4, %5, %3\n\t"))              \
+                 : "+v"(w64[0]), "+v"(w64[1]), "+v"(w64[2]), "+v"(w64[3])                            \
+                 : "v"(b), "v"(c)                                                                      \
+                 : "s0", "s1")
 // one chain: every instruction reads the previous result
 #define D2(ins) asm volatile(TWO(TWO(TWO(TWO(ins " %0, %0, %1\n\t")))) : "+v"(a[0]) : "v"(b))
 #define D3(ins) asm volatile(TWO(TWO(TWO(TWO(ins " %0, %0, %1, %2\n\t")))) : "+v"(a[0]) : "v"(b), "v"(c))
@@ -134,7 +142,10 @@ constexpr int kPerTrip = 16;
     X(56, "v_cndmask_b32_e64", ICNDS)              \
     X(57, "v_not_b32", INOT)                       \
     X(58, "v_cvt_f32_u32", INOT)                   \
-    X(59, "v_mov_b32", INOT)
+    X(59, "v_mov_b32", INOT)                       \
+    X(60, "v_cvt_f32_ubyte0", INOT)                \
+    X(61, "v_mul_hi_u32", I2)                      \
+    X(62, "v_mad_u64_u32", IMAD64)
 
 #define COUNT(i, n, s) +1
 constexpr int kOps = 0 PROBES(COUNT);
@@ -144,7 +155,11 @@ struct Probe;
 #define DEF(i, n, s)                                                                                     \
     template <>                                                                                          \
     struct Probe<i> {                                                                                    \
-        __device__ static inline void run(uint32_t (&a)[8], uint32_t b, uint32_t c, uint64_t m) { s(n); } \
+        __device__ static inline void run(uint32_t (&a)[8], uint64_t (&w64)[4], uint32_t b, uint32_t c, \
+                                          uint64_t m)                                                 \
+        {                                                                                              \
+            s(n);                                                                                      \
+        }                                                                                              \
     };
 PROBES(DEF)
 
@@ -157,10 +172,15 @@ __global__ __launch_bounds__(256) void k_valu(uint32_t* __restrict__ sink, int32
     for (int i = 0; i < 8; ++i) a[i] = seed ^ (t * 2654435761u + (uint32_t)i);
     const uint32_t b = (seed * 3u + 1u) | 1u, c = seed >> 3;
     const uint64_t m = 0x5555555555555555ull ^ (uint64_t)seed;  // a lane mask in SGPRs
-    for (int32_t i = 0; i < iters; ++i) Probe<kOp>::run(a, b, c, m);
+    uint64_t w64[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w64[i] = ((uint64_t)a[2 * i] << 32) | a[2 * i + 1];
+    for (int32_t i = 0; i < iters; ++i) Probe<kOp>::run(a, w64, b, c, m);
     uint32_t r = 0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) r ^= a[i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r ^= (uint32_t)w64[i] ^ (uint32_t)(w64[i] >> 32);
     if (r == 0x9E3779B9u) sink[t & 255u] = r;
 }
 
@@ -179,8 +199,8 @@ int valu_peak_per_trip(void) { return kPerTrip; }
 // Instruction mnemonic of probe `op`, and its form: I2 / I3 (dst = op(dst, b[, c]), 8
 // independent chains), INOT (dst = op(dst)), IACC (dst += op(b, c)), ICND (v_cndmask on
 // vcc), ICMPSEL (v_cmp_lt_u32 into vcc then the op reading it, 8 of each per trip), ICNDS
-// (v_cndmask on a mask in another SGPR pair), D2 / D3 (one dependent chain).  NULL for an
-// unknown op.
+// (v_cndmask on a mask in another SGPR pair), IMAD64 (64-bit accumulators), D2 / D3 (one
+// dependent chain).  NULL for an unknown op.
 const char* valu_peak_name(int32_t op) { return op >= 0 && op < kOps ? kNames[op] : nullptr; }
 const char* valu_peak_shape(int32_t op) { return op >= 0 && op < kOps ? kShapes[op] : nullptr; }
 
