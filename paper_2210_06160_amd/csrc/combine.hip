@@ -7,67 +7,14 @@ namespace rtsdf {
 namespace {
 
 constexpr int kBandThreads = 256;
-constexpr int kBandItems = 16;  // consecutive voxels per thread
+constexpr int kBandItems = 16;  // slices of kBandThreads consecutive voxels per work-group
 constexpr int kBandTile = kBandThreads * kBandItems;
+constexpr int kBandWaves = kBandThreads / kWave;
 
 __device__ inline int32_t seed_d2(int32_t s, int32_t x, int32_t y, int32_t z)
 {
     const int32_t dx = (s & 1023) - x, dy = ((s >> 10) & 1023) - y, dz = ((s >> 20) & 1023) - z;
     return dx * dx + dy * dy + dz * dz;
-}
-
-// Flags of the kBandItems grid points of this thread, as a bit mask.  (nx, ny) are the
-// dimensions of the masked grid.  With kRef it is refined by `r` over a coarse grid of
-// (cnx, cny) columns and rows: point (x, y, z) takes the flag of its parent
-// (x / r, y / r, z / r); without it r = 1 and the parent is the point itself.
-template <bool kRef>
-__device__ uint32_t band_bits(const int32_t* __restrict__ seeds, int64_t N, int32_t nx, int32_t ny,
-                              int32_t b2, int64_t first, int32_t r, int32_t cnx, int32_t cny)
-{
-    uint32_t bits = 0;
-    if (first >= N) return 0;
-    const int64_t row = first / nx;
-    int32_t x = (int32_t)(first - row * nx);
-    int32_t y = (int32_t)(row % ny);
-    int32_t z = (int32_t)(row / ny);
-    int32_t cx = x, cy = y, cz = z, rx = 0;
-    if (kRef) {
-        cx = x / r;
-        rx = x - cx * r;
-        cy = y / r;
-        cz = z / r;
-    } else {
-        cnx = nx;
-        cny = ny;
-    }
-    const int32_t* line = seeds + (int64_t)cnx * (cy + (int64_t)cny * cz);
-#pragma unroll
-    for (int i = 0; i < kBandItems; ++i) {
-        if (first + i < N) {
-            const int32_t s = line[cx];
-            if (s != RTSDF_EMPTY && seed_d2(s, cx, cy, cz) <= b2) bits |= 1u << i;
-        }
-        ++x;
-        if (kRef) {
-            if (++rx == r) {
-                rx = 0;
-                ++cx;
-            }
-        } else {
-            cx = x;
-        }
-        if (x == nx) {
-            x = cx = rx = 0;
-            if (++y == ny) {
-                y = 0;
-                ++z;
-            }
-            cy = kRef ? y / r : y;
-            cz = kRef ? z / r : z;
-            line = seeds + (int64_t)cnx * (cy + (int64_t)cny * cz);
-        }
-    }
-    return bits;
 }
 
 // The grid a mask work-group scans.  Single object: the arguments (a refined grid also
@@ -76,7 +23,7 @@ __device__ uint32_t band_bits(const int32_t* __restrict__ seeds, int64_t N, int3
 // added to the listed indices.
 struct BandGrid {
     const int32_t* seeds;
-    int64_t N, first, base;
+    int64_t N, tile, base;  // points of the grid, its first point of this tile, list index offset
     int32_t nx, ny, b2;
 };
 
@@ -91,52 +38,111 @@ template <bool kBatch>
 __device__ inline BandGrid band_grid(const BandArgs& a, const char* plan, int32_t nobj)
 {
     const int64_t tile = (int64_t)blockIdx.x * kBandTile;
-    if (!kBatch) return BandGrid{a.seeds, a.N, tile + (int64_t)threadIdx.x * kBandItems, 0, a.nx, a.ny, a.b2};
+    if (!kBatch) return BandGrid{a.seeds, a.N, tile, 0, a.nx, a.ny, a.b2};
     const BatchView v = batch_view(plan, nobj);
     const BatchObject& ob = v.obj[find_object(v.vox_prefix, nobj, tile)];
-    return BandGrid{a.seeds + ob.vox_off, nvox(ob.g), tile - ob.vox_off + (int64_t)threadIdx.x * kBandItems,
-                    ob.vox_off, ob.g.nx, ob.g.ny, ob.band_vox * ob.band_vox};
+    return BandGrid{a.seeds + ob.vox_off, nvox(ob.g), tile - ob.vox_off, ob.vox_off, ob.g.nx, ob.g.ny,
+                    ob.band_vox * ob.band_vox};
+}
+
+// The mask flags of one work-group's tile as wave ballots: slice i covers the kBandThreads
+// points tile + i kBandThreads ..; lane t of wave w flags point tile + i kBandThreads +
+// w 64 + t.  Loads are consecutive across the work-group.  (nx, ny) are the dimensions of
+// the masked grid; with kRef it is refined by r over a coarse grid of (cnx, cny) columns
+// and rows and point (x, y, z) takes the flag of its parent (x / r, y / r, z / r).
+template <bool kRef>
+__device__ void band_ballots(const BandGrid& bg, int32_t r, int32_t cnx, int32_t cny, uint64_t* ballot)
+{
+    int64_t p = bg.tile + threadIdx.x;
+    const int64_t row = p / bg.nx;
+    int32_t x = (int32_t)(p - row * bg.nx);
+    int32_t y = (int32_t)(row % bg.ny);
+    int32_t z = (int32_t)(row / bg.ny);
+    if (!kRef) {
+        r = 1;
+        cnx = bg.nx;
+        cny = bg.ny;
+    }
+#pragma unroll
+    for (int i = 0; i < kBandItems; ++i) {
+        bool in = false;
+        if (p < bg.N) {
+            const int32_t cx = kRef ? x / r : x, cy = kRef ? y / r : y, cz = kRef ? z / r : z;
+            const int32_t s = bg.seeds[cx + (int64_t)cnx * (cy + (int64_t)cny * cz)];
+            in = s != RTSDF_EMPTY && seed_d2(s, cx, cy, cz) <= bg.b2;
+        }
+        ballot[i] = __ballot(in);
+        // next slice: kBandThreads points on
+        p += kBandThreads;
+        x += kBandThreads;
+        if (x >= bg.nx) {
+            const int32_t qy = x / bg.nx;
+            x -= qy * bg.nx;
+            y += qy;
+            if (y >= bg.ny) {
+                const int32_t qz = y / bg.ny;
+                y -= qz * bg.ny;
+                z += qz;
+            }
+        }
+    }
 }
 
 template <bool kBatch, bool kRef>
 __global__ __launch_bounds__(kBandThreads) void k_band_count(const BandArgs a, uint32_t* __restrict__ counts,
-                                                             const char* plan, int32_t nobj)
+                                                             uint64_t* __restrict__ ballots, const char* plan,
+                                                             int32_t nobj)
 {
-    __shared__ uint32_t part[kBandThreads / kWave];
+    __shared__ uint32_t part[kBandWaves];
     const BandGrid bg = band_grid<kBatch>(a, plan, nobj);
-    uint32_t c = __popc(band_bits<kRef>(bg.seeds, bg.N, bg.nx, bg.ny, bg.b2, bg.first, a.r, a.cnx, a.cny));
-    for (int d = kWave / 2; d > 0; d >>= 1) c += __shfl_xor(c, d, kWave);
-    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = c;
+    uint64_t b[kBandItems];
+    band_ballots<kRef>(bg, a.r, a.cnx, a.cny, b);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < kBandItems; ++i) c += (uint32_t)__popcll(b[i]);
+    // lane i of each wave stores the wave's slice-i ballot: [tile][slice][wave]
+    uint64_t mine = 0;
+#pragma unroll
+    for (int i = 0; i < kBandItems; ++i) mine = lane == i ? b[i] : mine;
+    if (lane < kBandItems) ballots[((int64_t)blockIdx.x * kBandItems + lane) * kBandWaves + wave] = mine;
+    if (lane == 0) part[wave] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t t = 0;
-        for (int w = 0; w < kBandThreads / kWave; ++w) t += part[w];
+        for (int w = 0; w < kBandWaves; ++w) t += part[w];
         counts[blockIdx.x] = t;
     }
 }
 
-template <bool kBatch, bool kRef>
+// Lists the tile's flagged points in increasing order from the stored ballots: slice i's
+// points follow slices 0 .. i-1, and within a slice wave w's follow waves 0 .. w-1.
+template <bool kBatch>
 __global__ __launch_bounds__(kBandThreads) void k_band_write(const BandArgs a,
                                                              const uint32_t* __restrict__ offsets,
+                                                             const uint64_t* __restrict__ ballots,
                                                              int32_t* __restrict__ list, const char* plan,
                                                              int32_t nobj)
 {
-    __shared__ uint32_t part[kBandThreads / kWave];
-    const BandGrid bg = band_grid<kBatch>(a, plan, nobj);
-    const uint32_t bits = band_bits<kRef>(bg.seeds, bg.N, bg.nx, bg.ny, bg.b2, bg.first, a.r, a.cnx, a.cny);
-    const uint32_t c = __popc(bits);
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    uint32_t inc = c;
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t o = __shfl_up(inc, d, kWave);
-        if (lane >= d) inc += o;
+    __shared__ uint32_t pre[kBandItems * kBandWaves];  // list position of each (slice, wave)
+    const int64_t tile = (int64_t)blockIdx.x * kBandTile;
+    const uint64_t* tb = ballots + (int64_t)blockIdx.x * kBandItems * kBandWaves;
+    if (threadIdx.x == 0) {
+        uint32_t pos = offsets[blockIdx.x];
+        for (int j = 0; j < kBandItems * kBandWaves; ++j) {
+            pre[j] = pos;
+            pos += (uint32_t)__popcll(tb[j]);
+        }
     }
-    if (lane == kWave - 1) part[wave] = inc;
     __syncthreads();
-    uint32_t pos = offsets[blockIdx.x] + inc - c;
-    for (int w = 0; w < wave; ++w) pos += part[w];
-    for (int i = 0; i < kBandItems; ++i)
-        if (bits & (1u << i)) list[pos++] = (int32_t)(bg.base + bg.first + i);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int i = 0; i < kBandItems; ++i) {
+        const uint64_t bw = tb[i * kBandWaves + wave];
+        if ((bw >> lane) & 1ull)
+            list[pre[i * kBandWaves + wave] + (uint32_t)__popcll(bw & below)] =
+                (int32_t)(tile + (int64_t)i * kBandThreads + threadIdx.x);  // batch: the concatenated index
+    }
 }
 
 __global__ void k_store_count(const uint32_t* __restrict__ total, int32_t* __restrict__ count)
@@ -266,7 +272,8 @@ namespace {
 size_t band_work_points(int64_t N)
 {
     const int64_t nb = ceil_div(N, kBandTile);
-    return align256((size_t)nb * 4) + align256(4) + scan_work_bytes_u32(nb);
+    return align256((size_t)nb * 4) + align256((size_t)nb * kBandItems * kBandWaves * 8) + align256(4) +
+           scan_work_bytes_u32(nb);
 }
 
 // count, scan, write: the mask list of the grid `a` describes (or of a batch when `plan`)
@@ -277,14 +284,16 @@ hipError_t band_launch(const BandArgs& a, int64_t nb, const char* plan, int32_t 
     char* w = (char*)work;
     uint32_t* counts = (uint32_t*)w;
     w += align256((size_t)nb * 4);
+    uint64_t* ballots = (uint64_t*)w;
+    w += align256((size_t)nb * kBandItems * kBandWaves * 8);
     uint32_t* total = (uint32_t*)w;
     w += align256(4);
-    hipLaunchKernelGGL((k_band_count<kBatch, kRef>), dim3((unsigned)nb), dim3(kBandThreads), 0, s, a, counts, plan,
-                       nobj);
+    hipLaunchKernelGGL((k_band_count<kBatch, kRef>), dim3((unsigned)nb), dim3(kBandThreads), 0, s, a, counts,
+                       ballots, plan, nobj);
     hipError_t e = scan_exclusive_u32(counts, counts, nb, total, w, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_band_write<kBatch, kRef>), dim3((unsigned)nb), dim3(kBandThreads), 0, s, a,
-                       (const uint32_t*)counts, list, plan, nobj);
+    hipLaunchKernelGGL((k_band_write<kBatch>), dim3((unsigned)nb), dim3(kBandThreads), 0, s, a,
+                       (const uint32_t*)counts, (const uint64_t*)ballots, list, plan, nobj);
     hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, s, (const uint32_t*)total, count);
     return hipGetLastError();
 }
