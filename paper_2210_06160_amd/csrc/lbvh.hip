@@ -824,42 +824,56 @@ __global__ __launch_bounds__(256) void k_collapse4(Args a, const BinNode* __rest
     ((Bvh4Node*)(bvh + sg.bvh_off + 256))[i] = o;
 }
 
-// The 4-wide depth (nodes on the longest root-to-leaf path) of the collapsed hierarchy,
-// bottom-up over the binary tree like a refit: the second child to arrive at binary node p
-// takes 1 + the largest depth among the 4-wide children of the node collapsed at p (binary
-// descendants, all finished by then); the root's value goes into the header.  Non-root
-// binary nodes that the collapse skips get a value too, which nothing reads.
-__device__ inline int32_t ld_coherent_i32(const int32_t* p)
-{
-    return (int32_t)__hip_atomic_load((const uint32_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
+// The 4-wide depth (nodes on the longest root-to-leaf path) of the collapsed hierarchy.
+// Every binary subtree covers consecutive triangle positions (its first and count are in
+// its node), so each triangle walks down from the root, entering at each 4-wide node the
+// child node whose range holds its position, until a leaf range holds it; the deepest walk
+// is the depth, which goes into the header with one atomicMax per object and wave (the
+// header's depth starts at 0; a root that is a leaf range keeps it).
 template <bool kBatch>
-__global__ __launch_bounds__(256) void k_depth4(Args a, int32_t total, const int32_t* __restrict__ nparent,
-                                                const int32_t* __restrict__ lparent, uint32_t* flags, int32_t* d4,
-                                                char* bvh)
+__global__ __launch_bounds__(256) void k_depth4(Args a, const BinNode* __restrict__ bin, int32_t total, char* bvh)
 {
     const int32_t gt = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gt >= total) return;
-    const Seg s = seg_of_tri<kBatch>(a, gt);
-    if (s.nt <= kLeafMax) return;  // the root is a leaf range: depth 0, as k_header wrote
-    const Bvh4Node* n4 = (const Bvh4Node*)(bvh + s.bvh_off + 256);
-    int32_t p = lparent[gt];
-    for (int32_t guard = 0; p >= 0 && guard < s.nt; ++guard) {
-        const uint32_t old = __hip_atomic_fetch_add(&flags[s.tri_off + p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == 0u) return;  // the sibling will finish this node
-        const int4 c = n4[p].child;
-        int32_t d = 0;
-        if (c.x >= 0) d = max(d, ld_coherent_i32(&d4[s.tri_off + c.x]));
-        if (c.y >= 0) d = max(d, ld_coherent_i32(&d4[s.tri_off + c.y]));
-        if (c.z >= 0) d = max(d, ld_coherent_i32(&d4[s.tri_off + c.z]));
-        if (c.w >= 0) d = max(d, ld_coherent_i32(&d4[s.tri_off + c.w]));
-        __hip_atomic_store((uint32_t*)&d4[s.tri_off + p], (uint32_t)(d + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (p == 0) {
-            ((BvhHeader*)(bvh + s.bvh_off))->depth = d + 1;
-            return;
+    const bool live = gt < total;  // lanes past the end stay for the wave reduction below
+    int32_t depth = 0;
+    int32_t* slot = nullptr;
+    if (live) {
+        const Seg s = seg_of_tri<kBatch>(a, gt);
+        slot = &((BvhHeader*)(bvh + s.bvh_off))->depth;
+        if (s.nt > kLeafMax) {
+            const Bvh4Node* n4 = (const Bvh4Node*)(bvh + s.bvh_off + 256);
+            const BinNode* nodes = bin + s.tri_off;
+            const uint32_t pos = (uint32_t)(gt - s.tri_off);
+            int32_t p = 0;
+            depth = 1;
+            for (int32_t guard = 0; guard < s.nt; ++guard) {
+                const int4 c = n4[p].child;
+                const int32_t cc[4] = {c.x, c.y, c.z, c.w};
+                int32_t next = -1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (cc[q] >= 0) {
+                        const uint32_t first = (uint32_t)__float_as_int(nodes[cc[q]].a_hi.w);
+                        const uint32_t count = (uint32_t)__float_as_int(nodes[cc[q]].b_hi.w);
+                        if (pos - first < count) next = cc[q];
+                    }
+                if (next < 0) break;
+                p = next;
+                ++depth;
+            }
         }
-        p = nparent[s.tri_off + p];
+    }
+    // one atomic per wave when the wave's live triangles belong to one object
+    const uint64_t lives = __ballot(live);
+    if (lives == 0ull) return;
+    const int32_t first_lane = __ffsll((long long)lives) - 1;
+    const uintptr_t obj0 = (uintptr_t)__shfl((int64_t)(uintptr_t)slot, first_lane);
+    if (__ballot(live && (uintptr_t)slot != obj0) == 0ull) {
+        int32_t m = depth;  // 0 on the lanes past the end
+        for (int d = 32; d > 0; d >>= 1) m = max(m, __shfl_xor(m, d));
+        if (__lane_id() == first_lane) atomicMax(slot, m);
+    } else if (live) {
+        atomicMax(slot, depth);
     }
 }
 
@@ -989,9 +1003,7 @@ hipError_t build(Args a, int32_t nobj, int64_t n, int64_t tiles, const float* ve
                            w.posmap);
     }
     hipLaunchKernelGGL(k_collapse4<kBatch>, dim3(tb), dim3(256), 0, s, a, (const BinNode*)w.bin, total, bvh);
-    hipLaunchKernelGGL(k_fill_i32, dim3(std::min<unsigned>(tb, 2048u)), dim3(256), 0, s, (int32_t*)w.flags32, n, 0);
-    hipLaunchKernelGGL(k_depth4<kBatch>, dim3(tb), dim3(256), 0, s, a, total, (const int32_t*)w.nparent,
-                       (const int32_t*)w.lparent, w.flags32, w.nn, bvh);
+    hipLaunchKernelGGL(k_depth4<kBatch>, dim3(tb), dim3(256), 0, s, a, (const BinNode*)w.bin, total, bvh);
     return hipGetLastError();
 }
 
