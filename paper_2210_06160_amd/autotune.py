@@ -26,6 +26,7 @@ TUNING_H = os.path.join(HERE, "csrc", "tuning.h")
 
 GROUPS = {
     "jfa": {"RTSDF_JFA_CHUNK": [16, 32, 64], "RTSDF_JFA_WAVES": [2, 4, 8]},
+    "jfa_sparse": {"RTSDF_JFA_SPARSE": [0, 2, 4, 8]},
     "ray": {"RTSDF_RAY_START_BATCH": [8, 12, 16], "RTSDF_RAY_WAVES": [6, 7], "RTSDF_RAY_POP_TRIPS": [1, 2]},
     "tree": {"RTSDF_LEAF_MAX": [2, 3, 4], "RTSDF_PLOC_RADIUS": [16, 32]},
     "waves": {"RTSDF_RAY_WAVES": [6, 7]},
@@ -91,11 +92,11 @@ def time_candidate(group, path, reps):
                 out.append(a.elapsed_time(b))
         return statistics.median(out)
 
-    if group in ("jfa", "ray", "tree", "waves", "restart", "dist"):
+    if group in ("jfa", "jfa_sparse", "ray", "tree", "waves", "restart", "dist"):
         sc = synth.scene_static()
         S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
         S.voxelize()
-        if group == "jfa":
+        if group in ("jfa", "jfa_sparse"):
             return events(S.jfa)
         S.jfa()
         S.mask()

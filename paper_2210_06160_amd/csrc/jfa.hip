@@ -326,12 +326,18 @@ unsigned padded(int64_t tasks) { return (unsigned)(ceil_div(tasks, kXcds) * kXcd
 
 int64_t jfa_pass_blocks(const rtsdf_grid& g, int32_t k) { return pass_tasks(g, k, kChunk); }
 
+// pass p of an object's halving schedule has offset P / 2^(p+1), P the longest side n rounded
+// up to a power of two (n <= P < 2n); for a power-of-two RTSDF_JFA_SPARSE = S, S x offset >= n
+// then holds exactly for p < log2(S), the passes jfa_sparse picks for a single grid
+constexpr int ilog2(int v) { return v > 1 ? 1 + ilog2(v / 2) : 0; }
+constexpr int kSparsePasses = RTSDF_JFA_SPARSE > 0 ? ilog2(RTSDF_JFA_SPARSE) : 0;
+
 hipError_t jfa_batched_pass(const BatchView& hv, const void* dplan, int32_t* seeds, int32_t* scratch, int32_t pass,
                             hipStream_t s)
 {
     const int32_t blocks = hv.h->pass_blocks[pass];
     if (blocks == 0) return hipSuccess;
-    if (pass < 2)  // the first two passes of the halving offsets (the sparse ones, as jfa_sparse)
+    if (pass < kSparsePasses)  // an object's offsets halve from half its longest side: as jfa_sparse
         hipLaunchKernelGGL(k_jfa_batched<true>, dim3(padded(blocks)), dim3(kThreads), 0, s, (const char*)dplan,
                            hv.h->nobj, pass, seeds, scratch);
     else
@@ -369,7 +375,10 @@ void launch_pass_modes(const int32_t* in, int32_t* out, const rtsdf_grid& g, int
 
 }  // namespace
 
-bool jfa_sparse(const rtsdf_grid& g, int32_t k) { return 4 * (int64_t)k >= std::max(g.nx, std::max(g.ny, g.nz)); }
+bool jfa_sparse(const rtsdf_grid& g, int32_t k)
+{
+    return RTSDF_JFA_SPARSE > 0 && (int64_t)RTSDF_JFA_SPARSE * k >= std::max(g.nx, std::max(g.ny, g.nz));
+}
 
 hipError_t jfa_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, hipStream_t s)
 {

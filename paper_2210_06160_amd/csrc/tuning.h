@@ -13,6 +13,13 @@
 #ifndef RTSDF_JFA_WAVES
 #define RTSDF_JFA_WAVES 4
 #endif
+// ... a pass first tests a plane's loaded ids for all-EMPTY (a mostly EMPTY input: the large
+// offsets of the halving schedule) when RTSDF_JFA_SPARSE x offset >= the longest grid side
+// (0: never; a power of two)
+#ifndef RTSDF_JFA_SPARSE
+#define RTSDF_JFA_SPARSE 4
+#endif
+static_assert((RTSDF_JFA_SPARSE & (RTSDF_JFA_SPARSE - 1)) == 0, "RTSDF_JFA_SPARSE: 0 or a power of two");
 
 // ray sampling: work units a wave takes per cursor atomic (raised so that one atomic
 // covers at least RTSDF_RAY_CHUNK_RAYS rays), and idle lanes restarted together
