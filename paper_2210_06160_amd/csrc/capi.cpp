@@ -338,7 +338,7 @@ rtsdf_status rtsdf_jfa(int32_t* seeds, int32_t* scratch, rtsdf_grid g, const int
     int32_t* a = seeds;
     int32_t* b = scratch;
     for (int32_t i = 0; i < nsteps; ++i) {
-        hipError_t e = rtsdf::jfa_pass(a, b, g, steps[i], as_stream(stream));
+        hipError_t e = rtsdf::jfa_pass(a, b, g, steps[i], i == 0, i + 1 == nsteps, as_stream(stream));
         if (e != hipSuccess) return device(e, "jfa pass");
         std::swap(a, b);
     }

@@ -24,7 +24,11 @@ size_t voxelize_work_bytes(int32_t nt);
 hipError_t voxelize(const float* verts, const int32_t* tris, int32_t nt, const rtsdf_grid& g,
                     int32_t* seeds, void* work, hipStream_t s);
 
-hipError_t jfa_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, hipStream_t s);
+// One pass.  Between the first and the last pass of a call the buffers hold complemented ids
+// (~id, EMPTY = 0: a load past the grid returns it for free); in_plain / out_plain say that
+// the pass reads / writes the plain ids of the public format instead.
+hipError_t jfa_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, bool in_plain, bool out_plain,
+                    hipStream_t s);
 // a pass whose input is mostly EMPTY (the offsets of at least a quarter of the longest side:
 // the first two after voxelization) tests each plane's loaded ids for all-EMPTY first
 bool jfa_sparse(const rtsdf_grid& g, int32_t k);

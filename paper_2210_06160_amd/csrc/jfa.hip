@@ -27,23 +27,23 @@
 // three roles a plane has is fixed per work-group (first and last planes of a chain have
 // one or two), so each role set is its own instantiation.
 //
-// Work skipped without changing any result:
-//   - planes outside the grid (uniform per work-group);
-//   - neighbour rows y + ey k outside the grid (uniform per wave: a wave is one row of 64
-//     x-columns), and neighbour columns x + ex k outside the grid for every lane of the
-//     wave; a column valid for only some lanes reads EMPTY on the others (a select that
-//     only such waves run);
-//   - in the sparse early passes (most of the input EMPTY) a neighbour row whose three
-//     loaded columns are EMPTY on every lane.
+// Out-of-grid neighbours: a neighbour column (x + ex k, y + ey k) outside the grid loads the
+// thread's own column and is OR-ed with an all-ones mask, which makes it EMPTY (no select,
+// no branch); a plane outside the grid is never loaded (the chain's first and last planes
+// have fewer roles).  When k >= ny (or k >= nx) the ey = +-1 rows (ex = +-1 columns) are
+// outside for every point and are dropped at compile time.  In the sparse early passes
+// (mostly EMPTY input, RTSDF_JFA_SPARSE) a plane's arithmetic is skipped when every id it
+// loaded is EMPTY on every lane of the wave.  None of this changes any result.
 //
 // Work distribution.  A work-group is 64 RTSDF_JFA_WAVES consecutive columns of a plane
-// (in x-fastest order, across row ends) and a z task:
-// a chunk of one residue class's lattice points, or, when classes are short (large k),
-// several whole classes, so that per-group set-up is spread over about RTSDF_JFA_CHUNK
-// outputs per thread.  Work-groups are dealt to the 8 XCDs round-robin in launch order;
-// the launch index is remapped so that each XCD runs one contiguous range of tasks
-// (z-major), so the planes and rows that a task's neighbours read are fetched into one
-// XCD's L2 rather than into several.
+// (x fastest, across row ends, so no lane idles at the end of a row; rows taken in the
+// order of their residue mod k when rows k apart would otherwise be far apart in launch
+// order, see pass_row) and a z task: a chunk of one residue class's lattice points, or,
+// when classes are short (large k), several whole classes, so that per-group set-up is
+// spread over about RTSDF_JFA_CHUNK outputs per thread.  Work-groups are dealt to the 8
+// XCDs round-robin in launch order; the launch index is remapped so that each XCD runs one
+// contiguous range of tasks (z-major), so the planes and rows that a task's neighbours read
+// are fetched into one XCD's L2 rather than into several.
 #include "internal.h"
 #include "tuning.h"
 
@@ -56,28 +56,33 @@ constexpr int kChunk = RTSDF_JFA_CHUNK;        // outputs per thread and work-gr
 constexpr int kChunkSmall = 16;                // ... for passes that would launch few blocks
 constexpr int64_t kFewBlocks = 2048;           // below this many blocks, use kChunkSmall
 constexpr int kXcds = 8;
-constexpr int32_t kEmptyV = 8000000;    // v >= this only for EMPTY
 constexpr int32_t kNoKey = 0x7F000000;  // no candidate yet: above every key, and + 18 does not overflow
+constexpr uint32_t kOutside = 0x80000000u;  // buffer offset past every plane: the load returns 0
 
 struct Cand {
-    int32_t W;   // ((sx-px)^2 + (sy-py)^2 + sz^2) * 32 + 1 + q
-    int32_t sz;
+    int32_t W;   // ((cx-qx)^2 + (cy-qy)^2 + cz^2) * 32 + 1 + q, in complemented coordinates
+    int32_t cz;
 };
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
-// (dx, dy) as packed int16 (|d| <= 1023) so that dx^2 + dy^2 + sz^2 is one v_dot2c_i32_i16
-// on top of sz^2; all other factors are below 2^23, so the 24-bit multiplier is exact.
-__device__ inline Cand prep(int32_t s, short2_t pxy, int32_t q)
+// c = ~id of a loaded seed (0 for EMPTY): its fields are the complemented coordinates
+// (1023 - sx, 1023 - sy, 4095 - sz).  (dx, dy) as packed int16 (|d| <= 1023) so that
+// dx^2 + dy^2 + cz^2 is one v_dot2c_i32_i16 on top of cz^2; all other factors are below
+// 2^23, so the 24-bit multiplier is exact.
+__device__ inline Cand prep(uint32_t c, short2_t qxy, int32_t q)
 {
-    const uint32_t u = (uint32_t)s;
-    const int32_t sz = (int32_t)(u >> 20);
-    const short2_t sxy = __builtin_bit_cast(short2_t, (u & 1023u) | (((u >> 10) & 1023u) << 16));
-    const short2_t d = sxy - pxy;
-    return Cand{__builtin_amdgcn_sdot2(d, d, __mul24(sz, sz), false) * 32 + (1 + q), sz};
+    const int32_t cz = (int32_t)(c >> 20);
+    uint32_t cy = c & 0xFFC00u;
+    asm("" : "+v"(cy));  // keeps the double-rate AND before the shift (one v_lshl_or below)
+    const short2_t cxy = __builtin_bit_cast(short2_t, (cy << 6) | (c & 1023u));
+    const short2_t d = cxy - qxy;
+    return Cand{__builtin_amdgcn_sdot2(d, d, __mul24(cz, cz), false) * 32 + (1 + q), cz};
 }
 
-__device__ inline int32_t cand_key(Cand c, int32_t m64pz) { return c.W + __mul24(c.sz, m64pz); }
+// m = -64 (4095 - pz): the key W + cz m = (d^2 - (4095 - pz)^2) 32 + rank
+__device__ inline int32_t cand_key(Cand c, int32_t m) { return c.W + __mul24(c.cz, m); }
+__device__ inline int32_t key_factor(int32_t z) { return 64 * z - 64 * 4095; }
 
 __device__ inline int32_t min9(const int32_t* k)
 {
@@ -98,22 +103,49 @@ __device__ inline void rank_table(int32_t* tab, int32_t nx, int32_t ny, int32_t 
 }
 
 // One plane of the input as a buffer resource: a scalar base and 32-bit byte offsets, so
-// the gathers of a plane need no per-lane address arithmetic.
+// the gathers of a plane need no per-lane address arithmetic; its size is the plane's, so a
+// load at an offset past it (kOutside) returns 0 without touching memory.
 __device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const int32_t* in, uint32_t plane, int32_t z)
 {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)(in + (size_t)plane * (uint32_t)z), (short)0, 0x7FFFFFFF,
-                                            0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(in + (size_t)plane * (uint32_t)z), (short)0,
+                                            (int)(4u * plane), 0x00020000);
+}
+
+// Rows of a plane in the order a pass walks them: grouped by their residue mod k (rows rho,
+// rho + k, rho + 2k, ... one after the other), so that the work-groups reading a row as their
+// own and as their y -/+ k neighbour row run at about the same time on one XCD and share
+// its L2; in plain order they are k nx / kThreads work-groups apart.  Identity when k = 1 or
+// k >= ny, and kept plain when rows k apart lie within kNearBlocks work-groups anyway.
+constexpr int64_t kNearBlocks = 32;
+
+__device__ inline int32_t pass_row(int32_t i, int32_t nx, int32_t ny, int32_t k)
+{
+    if ((int64_t)k * nx <= kNearBlocks * kThreads || k >= ny) return i;
+    const int32_t c0 = ny / k, r = ny - c0 * k;  // residues rho < r have c0 + 1 rows, the others c0
+    const int32_t split = r * (c0 + 1);
+    int32_t rho, j;
+    if (i < split) {
+        rho = i / (c0 + 1);
+        j = i - rho * (c0 + 1);
+    } else {
+        const int32_t i2 = i - split;
+        rho = r + i2 / c0;
+        j = i2 - (rho - r) * c0;
+    }
+    return rho + j * k;
 }
 
 // z tasks of one pass: either chunks of at most kCh lattice points of one residue class
-// (per_res > 1 chunks of equal length `len` per class, one class per task; equal lengths
-// keep the work of the XCDs' contiguous task ranges equal), or `group` whole classes per
-// task
+// (per_res > 1 chunks of equal length `len` per class, one class per task), or about `group`
+// whole classes per task, task t taking classes t, t + count, t + 2 count, ...  Both keep
+// the work of the XCDs' contiguous task ranges equal: the classes r < nz mod k hold one
+// lattice point more than the others, and taking them in consecutive groups would hand
+// them all to the first XCDs.
 struct ZTasks {
     int32_t res;      // residue classes: min(k, nz)
     int32_t per_res;  // chunks per class (>= 1)
     int32_t len;      // lattice points per chunk (when per_res > 1)
-    int32_t group;    // classes per task (>= 1; > 1 only when per_res == 1)
+    int32_t group;    // classes per task, at most (>= 1; > 1 only when per_res == 1)
     int32_t count;    // tasks
 };
 
@@ -130,13 +162,15 @@ __host__ __device__ inline ZTasks z_tasks(int32_t nz, int32_t k, int32_t ch)
 }
 
 // What a thread knows about its column for one pass: for each of the 3 x 3 neighbour
-// columns q, its byte offset within a plane and a mask that is all ones when the column
-// lies outside the grid (OR-ed into the loaded id it makes that id EMPTY; its load reads
-// the thread's own column instead, which is always inside).
+// columns q, its byte offset within a plane, kOutside when the column lies outside the grid
+// (the load returns 0: EMPTY in complemented ids), and its complemented (x, y).  A pass
+// whose input holds plain ids loads its own column instead and ORs the mask inv (all ones
+// outside) into the id before complementing it, which gives 0 there too.
+template <bool kInC>
 struct Column {
     uint32_t off[9];
     int32_t inv[9];
-    short2_t pxy;
+    short2_t qxy;
 };
 
 // Neighbour rows / columns a pass can reach anywhere in the grid: 3, or only the middle one
@@ -150,31 +184,34 @@ struct Slots {
 // output z - k), their own plane (kCur: output z, with its stored seed) and their ez = -1
 // plane (kNext: output z + k).  kSparse: skip the plane's arithmetic when every id it
 // loaded is EMPTY on every lane of the wave.
-template <int kRows, int kCols, bool kSparse, bool kPrev, bool kCur, bool kNext>
+template <int kRows, int kCols, bool kSparse, bool kInC, bool kPrev, bool kCur, bool kNext>
 __device__ __forceinline__ void plane(const int32_t* __restrict__ in, uint32_t plane_elems, int32_t z, int32_t k,
-                                      const Column& c, int32_t& a_prev, int32_t& a_cur, int32_t& a_next)
+                                      const Column<kInC>& c, int32_t& a_prev, int32_t& a_cur, int32_t& a_next)
 {
     using S = Slots<kRows, kCols>;
     const __amdgpu_buffer_rsrc_t rs = plane_rsrc(in, plane_elems, z);
-    int32_t v[9];
+    uint32_t v[9];  // complemented ids
 #pragma unroll
     for (int q = 0; q < 9; ++q)
-        if (S::has(q)) v[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)c.off[q], 0, 0) | c.inv[q];
+        if (S::has(q)) {
+            const uint32_t raw = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)c.off[q], 0, 0);
+            v[q] = kInC ? raw : ~(raw | (uint32_t)c.inv[q]);
+        }
     if (kSparse) {
-        int32_t all = -1;
+        uint32_t any = 0;
 #pragma unroll
         for (int q = 0; q < 9; ++q)
-            if (S::has(q)) all &= v[q];
-        if (__builtin_amdgcn_readfirstlane((uint32_t)(__ballot(all != RTSDF_EMPTY) != 0ull)) == 0u) return;
+            if (S::has(q)) any |= v[q];
+        if (__builtin_amdgcn_readfirstlane((uint32_t)(__ballot(any != 0u) != 0ull)) == 0u) return;
     }
-    const int32_t m_cur = -64 * z, m_prev = -64 * (z - k), m_next = -64 * (z + k);
+    const int32_t m_cur = key_factor(z), m_prev = key_factor(z - k), m_next = key_factor(z + k);
     int32_t kp[9], kc[9], kn[9];
     int32_t self = kNoKey;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         kp[q] = kc[q] = kn[q] = kNoKey;
         if (!S::has(q)) continue;
-        Cand cd = prep(v[q], c.pxy, q);
+        Cand cd = prep(v[q], c.qxy, q);
         asm volatile("" : "+v"(cd.W));  // W once per seed; each key below is one multiply-add on it
         if (kPrev) kp[q] = cand_key(cd, m_prev);
         if (kCur) {
@@ -188,23 +225,27 @@ __device__ __forceinline__ void plane(const int32_t* __restrict__ in, uint32_t p
     if (kNext) a_next = min(a_next, min9(kn));
 }
 
-// work-group `blk` (remapped task index) of a pass over one grid: the plane's columns
-// c = x + nx y in [cb kThreads, (cb+1) kThreads) (waves take consecutive columns across row
-// ends, so no lane idles at the end of a row), z task bz; tab = rank_table(nx, ny, k)
-template <int kCh, int kRows, int kCols, bool kSparse>
+// work-group `blk` (remapped task index) of a pass over one grid: positions
+// [cb kThreads, (cb+1) kThreads) of the plane's columns in the pass's row order (x fastest,
+// waves take consecutive positions across row ends, so no lane idles at the end of a row),
+// z task bz; tab = rank_table(nx, ny, k)
+template <int kCh, int kRows, int kCols, bool kSparse, bool kInC>
 __device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_t* __restrict__ out, int32_t nx,
-                                          int32_t ny, int32_t nz, int32_t k, int64_t blk, const int32_t* tab)
+                                          int32_t ny, int32_t nz, int32_t k, int64_t blk, const int32_t* tab,
+                                          uint32_t omask)
 {
     const uint32_t plane_elems = (uint32_t)nx * (uint32_t)ny;  // grids hold at most 2^30 points
     const int64_t gc = ceil_div(plane_elems, kThreads);
     const int64_t cb = blk % gc;
     const int32_t bz = (int32_t)(blk / gc);
-    const int64_t col = cb * kThreads + threadIdx.x;
-    if (col >= plane_elems) return;
-    const int32_t y = (int32_t)(col / nx), x = (int32_t)(col - (int64_t)y * nx);
+    const int64_t pos = cb * kThreads + threadIdx.x;  // position in the pass's row order
+    if (pos >= plane_elems) return;
+    const int32_t i = (int32_t)(pos / nx), x = (int32_t)(pos - (int64_t)i * nx);
+    const int32_t y = pass_row(i, nx, ny, k);
+    const uint32_t col = (uint32_t)x + (uint32_t)nx * (uint32_t)y;  // element index within a plane
 
-    Column c;
-    const uint32_t own = 4u * (uint32_t)col;
+    Column<kInC> c;
+    const uint32_t own = 4u * col;
 #pragma unroll
     for (int ey = -1; ey <= 1; ++ey)
 #pragma unroll
@@ -212,17 +253,21 @@ __device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_
             const int q = 3 * (ey + 1) + (ex + 1);
             const int32_t qx = x + ex * k, qy = y + ey * k;
             const bool ok = qx >= 0 && qx < nx && qy >= 0 && qy < ny;
-            c.off[q] = ok ? 4u * ((uint32_t)qx + (uint32_t)nx * (uint32_t)qy) : own;  // bytes
+            const uint32_t off = 4u * ((uint32_t)qx + (uint32_t)nx * (uint32_t)qy);  // bytes
+            c.off[q] = ok ? off : (kInC ? kOutside : own);
             c.inv[q] = ok ? 0 : -1;
         }
-    c.pxy = __builtin_bit_cast(short2_t, (uint32_t)x | ((uint32_t)y << 16));
-    const uint32_t pxy_idx = (uint32_t)col;
+    c.qxy = __builtin_bit_cast(short2_t, (1023u - (uint32_t)x) | ((1023u - (uint32_t)y) << 16));
 
+    // the winner's id is reloaded from the query its rank names and stored complemented
+    // (omask 0) or plain (omask all ones); real candidates have keys below 0 (d^2 <= 3 1023^2
+    // against (4095 - pz)^2 >= 3072^2), EMPTY ones at least 0
+    const uint32_t xmask = (kInC ? 0u : ~0u) ^ omask;
     auto emit = [&](int32_t pz, int32_t best) {
-        const uint32_t p = pxy_idx + plane_elems * (uint32_t)pz;
-        int32_t id = RTSDF_EMPTY;
-        if ((best >> 5) < kEmptyV) id = in[(uint32_t)((int32_t)p + tab[best & 31])];
-        out[p] = id;
+        const uint32_t p = col + plane_elems * (uint32_t)pz;
+        uint32_t id = omask;
+        if (best < 0) id = (uint32_t)in[(uint32_t)((int32_t)p + tab[best & 31])] ^ xmask;
+        out[p] = (int32_t)id;
     };
 
     const ZTasks zt = z_tasks(nz, k, kCh);
@@ -233,13 +278,15 @@ __device__ __forceinline__ void jfa_block(const int32_t* __restrict__ in, int32_
         mlo = (bz - r0 * zt.per_res) * zt.len;
         mhi = mlo + zt.len;
     } else {
-        r0 = bz * zt.group;
-        r1 = min(r0 + zt.group, zt.res);
+        r0 = bz;  // classes bz, bz + count, ... (stride rstep)
+        r1 = zt.res;
         mlo = 0;
         mhi = 0x7FFFFFFF;
     }
-#define RTSDF_PLANE(P, C, N, zz) plane<kRows, kCols, kSparse, P, C, N>(in, plane_elems, zz, k, c, a_prev, a_cur, a_next)
-    for (int32_t r = r0; r < r1; ++r) {
+    const int32_t rstep = zt.per_res > 1 ? 1 : zt.count;
+#define RTSDF_PLANE(P, C, N, zz) \
+    plane<kRows, kCols, kSparse, kInC, P, C, N>(in, plane_elems, zz, k, c, a_prev, a_cur, a_next)
+    for (int32_t r = r0; r < r1; r += rstep) {
         const int32_t mcount = (nz - r + k - 1) / k;  // lattice points z = r + m k < nz
         const int32_t m0 = mlo, m1 = min(mhi, mcount);
         if (m0 >= m1) continue;
@@ -276,17 +323,20 @@ __device__ inline int64_t xcd_task(uint32_t b, uint32_t nblocks)
     return (int64_t)(b % kXcds) * per + b / kXcds;
 }
 
-template <int kCh, int kRows, int kCols, bool kSparse>
+// kInC: the input holds complemented ids (every pass of a call but the first); omask: all
+// ones when the output is to hold plain ids (the last pass), else 0
+template <int kCh, int kRows, int kCols, bool kSparse, bool kInC>
 __global__ __launch_bounds__(kThreads) void k_jfa_stream(const int32_t* __restrict__ in,
                                                           int32_t* __restrict__ out, int32_t nx,
-                                                          int32_t ny, int32_t nz, int32_t k, int64_t tasks)
+                                                          int32_t ny, int32_t nz, int32_t k, int64_t tasks,
+                                                          uint32_t omask)
 {
     const int64_t t = xcd_task(blockIdx.x, gridDim.x);
     if (t >= tasks) return;  // padding (whole work-group)
     __shared__ int32_t tab[32];
     rank_table(tab, nx, ny, k);
     __syncthreads();
-    jfa_block<kCh, kRows, kCols, kSparse>(in, out, nx, ny, nz, k, t, tab);
+    jfa_block<kCh, kRows, kCols, kSparse, kInC>(in, out, nx, ny, nz, k, t, tab, omask);
 }
 
 // work-groups of a pass over one grid before padding
@@ -298,7 +348,7 @@ __host__ __device__ inline int64_t pass_tasks(const rtsdf_grid& g, int32_t k, in
 // One pass over every object still flooding: the task index picks the object from this
 // pass's prefix table, then the object's own geometry and offset; object o reads the
 // buffer holding its pass-p input (its start buffer alternates with p).
-template <bool kSparse>
+template <bool kSparse, bool kInC>
 __global__ __launch_bounds__(kThreads) void k_jfa_batched(const char* __restrict__ plan, int32_t nobj,
                                                            int32_t pass, int32_t* __restrict__ seeds,
                                                            int32_t* __restrict__ scratch)
@@ -317,7 +367,8 @@ __global__ __launch_bounds__(kThreads) void k_jfa_batched(const char* __restrict
     __shared__ int32_t tab[32];
     rank_table(tab, nx, ny, k);
     __syncthreads();
-    jfa_block<kChunk, 3, 3, kSparse>(in, out, nx, ny, nz, k, b - prefix[o], tab);
+    const uint32_t omask = pass + 1 == ob.nsteps ? ~0u : 0u;  // the object's last pass stores plain ids
+    jfa_block<kChunk, 3, 3, kSparse, kInC>(in, out, nx, ny, nz, k, b - prefix[o], tab, omask);
 }
 
 unsigned padded(int64_t tasks) { return (unsigned)(ceil_div(tasks, kXcds) * kXcds); }
@@ -337,40 +388,62 @@ hipError_t jfa_batched_pass(const BatchView& hv, const void* dplan, int32_t* see
 {
     const int32_t blocks = hv.h->pass_blocks[pass];
     if (blocks == 0) return hipSuccess;
-    if (pass < kSparsePasses)  // an object's offsets halve from half its longest side: as jfa_sparse
-        hipLaunchKernelGGL(k_jfa_batched<true>, dim3(padded(blocks)), dim3(kThreads), 0, s, (const char*)dplan,
-                           hv.h->nobj, pass, seeds, scratch);
+    // pass 0 reads the voxelized (plain) ids, later passes complemented ones
+    const dim3 grid(padded(blocks)), block(kThreads);
+    if constexpr (kSparsePasses > 0) {
+        if (pass < kSparsePasses) {  // an object's offsets halve from half its longest side: as jfa_sparse
+            if (pass == 0)
+                hipLaunchKernelGGL((k_jfa_batched<true, false>), grid, block, 0, s, (const char*)dplan, hv.h->nobj,
+                                   pass, seeds, scratch);
+            else
+                hipLaunchKernelGGL((k_jfa_batched<true, true>), grid, block, 0, s, (const char*)dplan, hv.h->nobj,
+                                   pass, seeds, scratch);
+            return hipGetLastError();
+        }
+    }
+    if (pass == 0)
+        hipLaunchKernelGGL((k_jfa_batched<false, false>), grid, block, 0, s, (const char*)dplan, hv.h->nobj, pass,
+                           seeds, scratch);
     else
-        hipLaunchKernelGGL(k_jfa_batched<false>, dim3(padded(blocks)), dim3(kThreads), 0, s, (const char*)dplan,
-                           hv.h->nobj, pass, seeds, scratch);
+        hipLaunchKernelGGL((k_jfa_batched<false, true>), grid, block, 0, s, (const char*)dplan, hv.h->nobj, pass,
+                           seeds, scratch);
     return hipGetLastError();
 }
 
 namespace {
 
-template <int kCh, int kRows, int kCols>
-void launch_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, bool sparse, int64_t tasks,
-                 hipStream_t s)
+template <int kCh, int kRows, int kCols, bool kSparse>
+void launch_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, bool in_c, uint32_t omask,
+                 int64_t tasks, hipStream_t s)
 {
     const dim3 grid(padded(tasks)), block(kThreads);
-    if (sparse)
-        hipLaunchKernelGGL((k_jfa_stream<kCh, kRows, kCols, true>), grid, block, 0, s, in, out, g.nx, g.ny, g.nz, k,
-                           tasks);
+    if (in_c)
+        hipLaunchKernelGGL((k_jfa_stream<kCh, kRows, kCols, kSparse, true>), grid, block, 0, s, in, out, g.nx, g.ny,
+                           g.nz, k, tasks, omask);
     else
-        hipLaunchKernelGGL((k_jfa_stream<kCh, kRows, kCols, false>), grid, block, 0, s, in, out, g.nx, g.ny, g.nz,
-                           k, tasks);
+        hipLaunchKernelGGL((k_jfa_stream<kCh, kRows, kCols, kSparse, false>), grid, block, 0, s, in, out, g.nx, g.ny,
+                           g.nz, k, tasks, omask);
+}
+
+template <int kCh, int kRows, int kCols>
+void launch_pass_sparse(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, bool sparse, bool in_c,
+                        uint32_t omask, int64_t tasks, hipStream_t s)
+{
+    if constexpr (RTSDF_JFA_SPARSE > 0)
+        if (sparse) return launch_pass<kCh, kRows, kCols, true>(in, out, g, k, in_c, omask, tasks, s);
+    launch_pass<kCh, kRows, kCols, false>(in, out, g, k, in_c, omask, tasks, s);
 }
 
 template <int kCh>
-void launch_pass_modes(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, bool sparse, int64_t tasks,
-                       hipStream_t s)
+void launch_pass_modes(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, bool sparse, bool in_c,
+                       uint32_t omask, int64_t tasks, hipStream_t s)
 {
     // neighbour rows (columns) at +-k lie outside the grid everywhere once k >= ny (nx)
     const bool rows1 = k >= g.ny, cols1 = k >= g.nx;
-    if (rows1 && cols1) launch_pass<kCh, 1, 1>(in, out, g, k, sparse, tasks, s);
-    else if (rows1) launch_pass<kCh, 1, 3>(in, out, g, k, sparse, tasks, s);
-    else if (cols1) launch_pass<kCh, 3, 1>(in, out, g, k, sparse, tasks, s);
-    else launch_pass<kCh, 3, 3>(in, out, g, k, sparse, tasks, s);
+    if (rows1 && cols1) launch_pass_sparse<kCh, 1, 1>(in, out, g, k, sparse, in_c, omask, tasks, s);
+    else if (rows1) launch_pass_sparse<kCh, 1, 3>(in, out, g, k, sparse, in_c, omask, tasks, s);
+    else if (cols1) launch_pass_sparse<kCh, 3, 1>(in, out, g, k, sparse, in_c, omask, tasks, s);
+    else launch_pass_sparse<kCh, 3, 3>(in, out, g, k, sparse, in_c, omask, tasks, s);
 }
 
 }  // namespace
@@ -380,13 +453,15 @@ bool jfa_sparse(const rtsdf_grid& g, int32_t k)
     return RTSDF_JFA_SPARSE > 0 && (int64_t)RTSDF_JFA_SPARSE * k >= std::max(g.nx, std::max(g.ny, g.nz));
 }
 
-hipError_t jfa_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, hipStream_t s)
+hipError_t jfa_pass(const int32_t* in, int32_t* out, const rtsdf_grid& g, int32_t k, bool in_plain, bool out_plain,
+                    hipStream_t s)
 {
     const bool sparse = jfa_sparse(g, k);
     const bool few = pass_tasks(g, k, kChunk) < kFewBlocks;  // small grids: shorter chunks, more blocks
     const int64_t tasks = pass_tasks(g, k, few ? kChunkSmall : kChunk);
-    if (few) launch_pass_modes<kChunkSmall>(in, out, g, k, sparse, tasks, s);
-    else launch_pass_modes<kChunk>(in, out, g, k, sparse, tasks, s);
+    const uint32_t omask = out_plain ? ~0u : 0u;
+    if (few) launch_pass_modes<kChunkSmall>(in, out, g, k, sparse, !in_plain, omask, tasks, s);
+    else launch_pass_modes<kChunk>(in, out, g, k, sparse, !in_plain, omask, tasks, s);
     return hipGetLastError();
 }
 

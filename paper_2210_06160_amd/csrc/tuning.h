@@ -17,7 +17,7 @@
 // offsets of the halving schedule) when RTSDF_JFA_SPARSE x offset >= the longest grid side
 // (0: never; a power of two)
 #ifndef RTSDF_JFA_SPARSE
-#define RTSDF_JFA_SPARSE 4
+#define RTSDF_JFA_SPARSE 0
 #endif
 static_assert((RTSDF_JFA_SPARSE & (RTSDF_JFA_SPARSE - 1)) == 0, "RTSDF_JFA_SPARSE: 0 or a power of two");
 

@@ -204,7 +204,9 @@ def test_jfa_tasks_cover_every_point_once():
     """The z tasks of a pass, decoded the way the pass kernel decodes them, visit every z of
     the grid exactly once (as lattice point m of residue class z mod k), for grids and
     offsets that give long classes split into chunks, short classes grouped, and offsets
-    beyond the grid."""
+    beyond the grid.  For the halving offsets of a grid whose classes are grouped, every
+    task holds the same number of lattice points up to one class's (the XCDs run
+    contiguous task ranges, so unequal tasks would leave some of them idle)."""
     for nz in (1, 2, 3, 7, 31, 32, 33, 64, 100, 200, 400, 1023):
         for k in sorted({1, 2, 3, 4, 8, 16, 31, 32, 64, 128, 256, 512, 1024, nz, max(1, nz // 2)}):
             res, per_res, group, count = z_tasks(nz, k)
@@ -215,11 +217,50 @@ def test_jfa_tasks_cover_every_point_once():
                     assert L <= CHUNK
                     r0 = bz // per_res
                     r1, mlo, mhi = r0 + 1, (bz - r0 * per_res) * L, (bz - r0 * per_res + 1) * L
+                    rstep = 1
                 else:
-                    r0 = bz * group
-                    r1, mlo, mhi = min(r0 + group, res), 0, 1 << 31
-                for r in range(r0, r1):
+                    r0, r1, mlo, mhi, rstep = bz, res, 0, 1 << 31, count  # classes bz, bz + count, ...
+                for r in range(r0, r1, rstep):
                     mcount = (nz - r + k - 1) // k
                     for m in range(mlo, min(mhi, mcount)):
                         seen[r + m * k] += 1
             assert (seen == 1).all(), (nz, k)
+            if per_res == 1 and k & (k - 1) == 0 and 2 * k > nz // 2:
+                work = [sum((nz - r + k - 1) // k for r in range(bz, res, count)) for bz in range(count)]
+                assert max(work) - min(work) <= -(-nz // k), (nz, k, work)
+
+
+NEAR_BLOCKS = 32  # rows k apart within this many work-groups keep the plain order
+
+
+def pass_row(i, nx, ny, k):
+    """Row of a plane at position i of a pass's row order: rows grouped by residue mod k
+    (rho, rho + k, rho + 2k, ...) unless k = 1, k >= ny or rows k apart are near anyway."""
+    if k * nx <= NEAR_BLOCKS * 64 * WAVES or k >= ny:
+        return i
+    c0, r = divmod(ny, k)
+    split = r * (c0 + 1)
+    if i < split:
+        rho, j = divmod(i, c0 + 1)
+    else:
+        rho, j = divmod(i - split, c0)
+        rho += r
+    return rho + j * k
+
+
+def test_jfa_row_order_is_a_permutation_grouping_residues():
+    """The pass's row order visits every row of the plane once, and when it is not the plain
+    order, rows of one residue class mod k follow each other in ascending order, so a row's
+    y - k and y + k neighbour rows are the positions just before and after it."""
+    for nx in (1, 7, 64, 100, 400, 1000):
+        for ny in (1, 2, 5, 31, 64, 100, 200, 255, 401):
+            for k in sorted({1, 2, 3, 8, 16, 32, 33, 64, 128, 256, max(1, ny // 2), ny, ny + 1}):
+                rows = [pass_row(i, nx, ny, k) for i in range(ny)]
+                assert sorted(rows) == list(range(ny)), (nx, ny, k)
+                if rows == list(range(ny)):
+                    continue
+                for i, y in enumerate(rows):
+                    if y + k < ny:
+                        assert rows[i + 1] == y + k, (nx, ny, k, i)
+                    if y - k >= 0:
+                        assert rows[i - 1] == y - k, (nx, ny, k, i)
