@@ -6,18 +6,27 @@
 // increasing in that order: here rank 0 for the stored seed and 1 + L for the others,
 // L = 9 (ez+1) + 3 (ey+1) + (ex+1) (so 1..13 and 15..27).
 //
-// Keys.  For a seed s loaded at column slot q = 3 (ey+1) + (ex+1) of a thread's column
-// (px, py) the thread computes once
-//     W = ((sx - px)^2 + (sy - py)^2 + sz^2) * 32 + 1 + q,
-// and for an output at z = pz the candidate's signed 32-bit key is
-//     W + sz * (-64 pz) + 9 (ez+1) = (d2 - pz^2) * 32 + rank,
+// Internal ids.  Between the first and the last pass of a call the buffers hold the
+// complement c = ~id of each packed id (EMPTY = -1 becomes 0); its fields are the
+// complemented coordinates (cx, cy, cz) = (1023 - x, 1023 - y, 4095 - z), and distances
+// between complemented points equal the true ones.  A load past a plane returns 0, i.e.
+// EMPTY, so neighbours outside the grid cost nothing (see Column).  The first pass
+// complements what it loads, the last stores plain ids again.
+//
+// Keys.  For a seed c loaded at column slot q = 3 (ey+1) + (ex+1) of a thread's column,
+// complemented (qx, qy), the thread computes once
+//     W = ((cx - qx)^2 + (cy - qy)^2 + cz^2) * 32 + 1 + q,
+// and for an output at z = pz (complemented pz' = 4095 - pz) the candidate's signed 32-bit
+// key is
+//     W + cz * (-64 pz') + 9 (ez+1) = (d2 - pz'^2) * 32 + rank,
 // an order-preserving image of (d2, rank): one v_mad_i32_i24 per candidate.  A plane's
 // keys for one output are reduced (v_min3_i32) before that plane's rank offset 9 (ez+1)
 // is added once; the stored seed takes its mid-plane key minus 1 + 4 (rank 0).  The
 // winner's id is reloaded from the query its rank names (offsets from a 28-entry LDS
-// table per work-group).  EMPTY (-1) unpacks to (1023, 1023, 4095), whose key exceeds
-// 8.39e6 * 32 > any real d2 (<= 3 * 1023^2) for every output, so it never wins against a
-// seed.  Keys stay within +-2^30.
+// table per work-group).  Grids have at most 1024 points a side, so a real seed has
+// d2 <= 3 * 1023^2 < 3072^2 <= pz'^2 and a negative key, while EMPTY (c = 0, the point
+// (1023, 1023, 4095)) has d2 >= pz'^2 and a key >= 0: it never wins against a seed, and a
+// minimum >= 0 means no seed was seen.  Keys lie in (-2^30, 2^29.3).
 //
 // Streaming.  A pass with offset k couples only the z positions of one residue class
 // z = r + m k.  Each thread owns one (x, y) column and walks the lattice points m of a
