@@ -6,8 +6,9 @@ operation order, correctly rounded '/' and sqrt, no contraction).
 Sizes: the 32^3 icosphere; a 100x50x100 static scene compared element by element; and the
 full 400x200x400 static scene in the launch configuration the benchmark times, compared
 in full for the integer stages and on sampled voxels for the ray stages.  Edge cases: an
-empty mesh, one triangle (a single-leaf hierarchy), two triangles on a voxel face, and a
-grid of 128 coplanar triangles (hierarchy nodes flat on one axis).
+empty mesh, one triangle (a single-leaf hierarchy), two triangles on a voxel face, a grid
+of 128 coplanar triangles (hierarchy nodes flat on one axis), grids with the largest
+allowed side (1024) on each axis, and jump flooding with arbitrary offset lists on odd grids.
 """
 import sys
 
@@ -217,6 +218,9 @@ def test_deterministic(R):
     ((700, 97, 9), [256, 128, 64, 48, 33, 17, 12, 5, 2, 1]),   # rows walked in residue order for k = 12 ... 64
     ((430, 250, 7), [512, 300, 200, 129, 64, 31, 1]),           # k >= nx, k >= ny, odd row counts per residue
     ((37, 1001, 5), [600, 257, 64, 1]),                         # one-row-per-residue and tall planes
+    ((1024, 6, 5), [512, 256, 3, 1]),                           # the largest side on each axis: ids with
+    ((5, 1024, 6), [512, 100, 1]),                              # coordinates up to 1023
+    ((6, 5, 1024), [1024, 512, 256, 128, 7, 1]),
 ])
 def test_jfa_offsets_and_row_orders(R, orc, dims, steps):
     """Arbitrary offset lists on grids whose passes take every work layout (rows in residue
@@ -242,3 +246,26 @@ def test_jfa_offsets_and_row_orders(R, orc, dims, steps):
         got = res.cpu().numpy()
         assert np.array_equal(got, ref), "k=%d: %d ids differ" % (k, (got != ref).sum())
         cur, nxt = res, cur
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_max_side_pipeline(R, orc, axis):
+    """The whole chain on a grid whose side along `axis` is the largest allowed (1024 points,
+    coordinates up to 1023) and a few points across: a slab through the icosphere, compared
+    element by element (seeds, flood, mask, hits, distances, argmin records, fine values)."""
+    sc = synth.scene_tiny()
+    dims = [6, 5, 7]
+    dims[axis] = 1024
+    sc.h = 1.0 / 1024
+    org = [0.5 - 3 * sc.h, 0.5 - 2.5 * sc.h, 0.5 - 3.5 * sc.h]
+    org[axis] = 0.0
+    sc.dims, sc.org = tuple(dims), tuple(org)
+    sc.steps = orc.jfa_steps(sc.dims, 1)
+    log("case: max side", sc.dims)
+    G = gpu_pipeline(R, sc)
+    O = oracle_pipeline(orc, sc)
+    assert (O["seeds0"] != -1).sum() > 0 and len(O["band"]) > 0
+    assert np.array_equal(G["seeds0"], O["seeds0"]) and np.array_equal(G["jfa"], O["jfa"])
+    assert np.array_equal(G["band"], O["band"])
+    compare_rays(G, O, O["vids"])
+    np.testing.assert_allclose(G["fine"], O["fine"], rtol=RTOL, atol=0)
