@@ -11,6 +11,16 @@ constexpr int kBandItems = 16;  // slices of kBandThreads consecutive voxels per
 constexpr int kBandTile = kBandThreads * kBandItems;
 constexpr int kBandWaves = kBandThreads / kWave;
 
+// v / r for a fine coordinate v < 1024 and a refinement ratio r in [1, 1024]:
+// trunc(v RN(1/r) + RN(0.5/r)) in binary32 with one rounding is exact over that whole range
+// (checked exhaustively on the host), and costs a few instructions instead of an integer
+// division.
+struct ParentOf {
+    float inv, half;
+    __device__ explicit ParentOf(int32_t r) : inv(1.0f / (float)r), half(0.5f * inv) {}
+    __device__ int32_t operator()(int32_t v) const { return (int32_t)fmaf((float)v, inv, half); }
+};
+
 __device__ inline int32_t seed_d2(int32_t s, int32_t x, int32_t y, int32_t z)
 {
     const int32_t dx = (s & 1023) - x, dy = ((s >> 10) & 1023) - y, dz = ((s >> 20) & 1023) - z;
@@ -45,46 +55,70 @@ __device__ inline BandGrid band_grid(const BandArgs& a, const char* plan, int32_
                     ob.band_vox * ob.band_vox};
 }
 
+// (x, y, z) of a point of an nx x ny plane grid advanced by kBandThreads points: the step
+// split into planes, rows and columns once, then added with carries (no division per step)
+struct SliceStep {
+    int32_t nx, ny, dx, dy, dz;
+    __device__ SliceStep(int32_t nx_, int32_t ny_) : nx(nx_), ny(ny_)
+    {
+        const int32_t plane = nx * ny;  // at most 2^20
+        dz = kBandThreads / plane;
+        const int32_t rem = kBandThreads - dz * plane;
+        dy = rem / nx;
+        dx = rem - dy * nx;
+    }
+    __device__ void advance(int32_t& x, int32_t& y, int32_t& z) const
+    {
+        x += dx;
+        const int32_t cx = x >= nx ? 1 : 0;  // dx < nx, so one carry at most
+        x -= cx * nx;
+        y += dy + cx;
+        const int32_t cy = y >= ny ? 1 : 0;  // dy < ny
+        y -= cy * ny;
+        z += dz + cy;
+    }
+};
+
 // The mask flags of one work-group's tile as wave ballots: slice i covers the kBandThreads
 // points tile + i kBandThreads ..; lane t of wave w flags point tile + i kBandThreads +
-// w 64 + t.  Loads are consecutive across the work-group.  (nx, ny) are the dimensions of
-// the masked grid; with kRef it is refined by r over a coarse grid of (cnx, cny) columns
-// and rows and point (x, y, z) takes the flag of its parent (x / r, y / r, z / r).
+// w 64 + t.  Loads are consecutive across the work-group, and all kBandItems of a thread
+// are issued before the first is tested, so they are in flight together.  (nx, ny) are
+// the dimensions of the masked grid; with kRef it is refined by r over a coarse grid of
+// (cnx, cny) columns and rows and point (x, y, z) takes the flag of its parent
+// (x / r, y / r, z / r).
 template <bool kRef>
 __device__ void band_ballots(const BandGrid& bg, int32_t r, int32_t cnx, int32_t cny, uint64_t* ballot)
 {
-    int64_t p = bg.tile + threadIdx.x;
-    const int64_t row = p / bg.nx;
-    int32_t x = (int32_t)(p - row * bg.nx);
-    int32_t y = (int32_t)(row % bg.ny);
-    int32_t z = (int32_t)(row / bg.ny);
+    const ParentOf parent(r);
+    const int64_t p0 = bg.tile + threadIdx.x;
+    const SliceStep st(bg.nx, bg.ny);
+    const int64_t row = p0 / bg.nx;
+    const int32_t x0 = (int32_t)(p0 - row * bg.nx), y0 = (int32_t)(row % bg.ny), z0 = (int32_t)(row / bg.ny);
+    int32_t s[kBandItems];
     if (!kRef) {
-        r = 1;
-        cnx = bg.nx;
-        cny = bg.ny;
+#pragma unroll
+        for (int i = 0; i < kBandItems; ++i) {
+            const int64_t p = p0 + (int64_t)i * kBandThreads;
+            s[i] = p < bg.N ? bg.seeds[p] : RTSDF_EMPTY;
+        }
+    } else {
+        int32_t x = x0, y = y0, z = z0;
+#pragma unroll
+        for (int i = 0; i < kBandItems; ++i) {
+            const int64_t p = p0 + (int64_t)i * kBandThreads;
+            s[i] = p < bg.N ? bg.seeds[parent(x) + (int64_t)cnx * (parent(y) + (int64_t)cny * parent(z))]
+                            : RTSDF_EMPTY;
+            st.advance(x, y, z);
+        }
     }
+    int32_t x = x0, y = y0, z = z0;
 #pragma unroll
     for (int i = 0; i < kBandItems; ++i) {
-        bool in = false;
-        if (p < bg.N) {
-            const int32_t cx = kRef ? x / r : x, cy = kRef ? y / r : y, cz = kRef ? z / r : z;
-            const int32_t s = bg.seeds[cx + (int64_t)cnx * (cy + (int64_t)cny * cz)];
-            in = s != RTSDF_EMPTY && seed_d2(s, cx, cy, cz) <= bg.b2;
-        }
+        const int32_t cx = kRef ? parent(x) : x, cy = kRef ? parent(y) : y, cz = kRef ? parent(z) : z;
+        // points past the grid's end loaded EMPTY
+        const bool in = s[i] != RTSDF_EMPTY && seed_d2(s[i], cx, cy, cz) <= bg.b2;
         ballot[i] = __ballot(in);
-        // next slice: kBandThreads points on
-        p += kBandThreads;
-        x += kBandThreads;
-        if (x >= bg.nx) {
-            const int32_t qy = x / bg.nx;
-            x -= qy * bg.nx;
-            y += qy;
-            if (y >= bg.ny) {
-                const int32_t qz = y / bg.ny;
-                y -= qz * bg.ny;
-                z += qz;
-            }
-        }
+        st.advance(x, y, z);
     }
 }
 
@@ -124,21 +158,29 @@ __global__ __launch_bounds__(kBandThreads) void k_band_write(const BandArgs a,
                                                              int32_t* __restrict__ list, const char* plan,
                                                              int32_t nobj)
 {
-    __shared__ uint32_t pre[kBandItems * kBandWaves];  // list position of each (slice, wave)
+    static_assert(kBandItems * kBandWaves == kWave, "one ballot per lane of the first wave");
+    __shared__ uint32_t pre[kWave];      // list position of each (slice, wave)
+    __shared__ uint64_t bal[kWave];
     const int64_t tile = (int64_t)blockIdx.x * kBandTile;
     const uint64_t* tb = ballots + (int64_t)blockIdx.x * kBandItems * kBandWaves;
-    if (threadIdx.x == 0) {
-        uint32_t pos = offsets[blockIdx.x];
-        for (int j = 0; j < kBandItems * kBandWaves; ++j) {
-            pre[j] = pos;
-            pos += (uint32_t)__popcll(tb[j]);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    if (wave == 0) {  // exclusive scan of the 64 ballots' counts, one per lane
+        const uint64_t bw = tb[lane];
+        const uint32_t n = (uint32_t)__popcll(bw);
+        uint32_t incl = n;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, d);
+            if (lane >= d) incl += o;
         }
+        pre[lane] = offsets[blockIdx.x] + incl - n;
+        bal[lane] = bw;
     }
     __syncthreads();
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
     for (int i = 0; i < kBandItems; ++i) {
-        const uint64_t bw = tb[i * kBandWaves + wave];
+        const uint64_t bw = bal[i * kBandWaves + wave];
         if ((bw >> lane) & 1ull)
             list[pre[i * kBandWaves + wave] + (uint32_t)__popcll(bw & below)] =
                 (int32_t)(tile + (int64_t)i * kBandThreads + threadIdx.x);  // batch: the concatenated index
@@ -179,7 +221,8 @@ __global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ see
     const int32_t z = blockIdx.z;
     if (x >= fnx || y >= fny) return;
     const int64_t p = x + (int64_t)fnx * (y + (int64_t)fny * z);
-    const int32_t cx = kRef ? x / r : x, cy = kRef ? y / r : y, cz = kRef ? z / r : z;
+    const ParentOf parent(r);
+    const int32_t cx = kRef ? parent(x) : x, cy = kRef ? parent(y) : y, cz = kRef ? parent(z) : z;
     const int32_t s = seeds[cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz)];
     float u = __int_as_float(0x7f800000);
     bool inband = false;
