@@ -4,8 +4,9 @@
 // 2. one thread per triangle: snap vertices to 1/256 voxel, count the voxels of the
 //    triangle's closed-cell range (a candidate box)
 // 3. exclusive scan of the counts (64-bit; a big triangle can cover the whole grid)
-// 4. one thread per (triangle, candidate voxel), found by binary search in the offsets:
-//    exact integer separating-axis test of the triangle against the closed voxel cube;
+// 4. one lane per (triangle, candidate voxel), dealt in runs of consecutive candidates so
+//    that a lane's triangle changes rarely (see k_candidates): exact integer
+//    separating-axis test of the triangle against the closed voxel cube;
 //    on overlap the voxel writes its own id.  Every writer of a voxel writes the same
 //    value, so the result does not depend on scheduling.
 #include "internal.h"
@@ -173,6 +174,15 @@ __device__ bool overlaps(const Snapped& S, int32_t i, int32_t j, int32_t k)
     return true;
 }
 
+// Candidates are dealt to lanes in runs of consecutive ones (a wave takes 64 runs at a
+// time): a lane's next candidate is in the same triangle unless it crosses the triangle's
+// end (triangles hold hundreds of candidates on average at fine resolutions, a few at
+// coarse ones), so the triangle is found by a forward step rather than a search per
+// candidate, and the voxel coordinates advance by one with carries instead of divisions.
+// Runs are kCandRun long when there are that many candidates per lane of the launch, and
+// shorter when there are fewer, so that every lane still has work.
+constexpr int kCandRun = 16;
+
 template <bool kBatch>
 __global__ __launch_bounds__(256) void k_candidates(const float* __restrict__ verts,
                                                     const int32_t* __restrict__ tris, int32_t nt,
@@ -183,33 +193,64 @@ __global__ __launch_bounds__(256) void k_candidates(const float* __restrict__ ve
                                                     int32_t nobj, int32_t* __restrict__ scratch)
 {
     const uint64_t total = *total_p;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    int32_t cur = -1;
+    const int lane = threadIdx.x & 63;
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / 64);
+    const uint64_t run = min((uint64_t)kCandRun, max((uint64_t)1, total / (nwaves * 64)));
+    const uint64_t chunk = 64 * run;
+    int32_t cur = 0;
+    uint64_t tri_lo = 1, tri_hi = 0;  // candidates [tri_lo, tri_hi) of triangle cur (none yet)
     Snapped S;
     TriSource src;
-    int32_t ex = 0, ey = 0;
-    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += stride) {
-        // triangle owning candidate c: last t with offsets[t] <= c
-        int32_t lo = 0, hi = nt - 1;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (offsets[mid] <= c) lo = mid;
-            else hi = mid - 1;
+    int32_t ex = 1, ey = 1;          // the triangle's candidate box extents on x and y
+    int32_t li = 0, lj = 0, lk = 0;  // the candidate's position in the box
+    for (uint64_t base = wave * chunk; base < total; base += nwaves * chunk) {
+        const uint64_t first = base + (uint64_t)lane * run;
+        const uint64_t end = min(first + run, total);
+        bool carried = false;  // li, lj, lk hold the position of c - 1 in the same triangle
+        for (uint64_t c = first; c < end; ++c) {
+            if (c < tri_lo || c >= tri_hi) {
+                // triangle owning c: the last t with offsets[t] <= c (candidates only grow, so
+                // from the current one: a forward step within a run, a search between runs)
+                int32_t lo = cur, hi = nt - 1;
+                if (carried) {
+                    while (lo < hi && offsets[lo + 1] <= c) ++lo;
+                } else {
+                    while (lo < hi) {
+                        const int32_t mid = (lo + hi + 1) >> 1;
+                        if (offsets[mid] <= c) lo = mid;
+                        else hi = mid - 1;
+                    }
+                }
+                cur = lo;
+                tri_lo = offsets[cur];
+                tri_hi = cur + 1 < nt ? offsets[cur + 1] : total;
+                src = tri_source<kBatch>(verts, tris, cur, g, seeds, plan, nobj, scratch);
+                snap_triangle(src.verts, src.tris, src.t, src.g, S);
+                ex = S.hi[0] - S.lo[0] + 1;
+                ey = S.hi[1] - S.lo[1] + 1;
+                carried = false;
+            }
+            if (carried) {
+                if (++li == ex) {
+                    li = 0;
+                    if (++lj == ey) {
+                        lj = 0;
+                        ++lk;
+                    }
+                }
+            } else {
+                const uint32_t local = (uint32_t)(c - tri_lo);  // a box holds at most 2^30 voxels
+                const uint32_t q = local / (uint32_t)ex;
+                li = (int32_t)(local - q * (uint32_t)ex);
+                lk = (int32_t)(q / (uint32_t)ey);
+                lj = (int32_t)q - lk * ey;
+            }
+            carried = true;
+            const int32_t i = S.lo[0] + li, j = S.lo[1] + lj, k = S.lo[2] + lk;
+            if (overlaps(S, i, j, k))
+                src.out[i + (int64_t)src.g.nx * (j + (int64_t)src.g.ny * k)] = i | (j << 10) | (k << 20);
         }
-        if (lo != cur) {
-            cur = lo;
-            src = tri_source<kBatch>(verts, tris, cur, g, seeds, plan, nobj, scratch);
-            snap_triangle(src.verts, src.tris, src.t, src.g, S);
-            ex = S.hi[0] - S.lo[0] + 1;
-            ey = S.hi[1] - S.lo[1] + 1;
-        }
-        const uint64_t local = c - offsets[cur];
-        const int32_t i = S.lo[0] + (int32_t)(local % (uint64_t)ex);
-        const uint64_t rest = local / (uint64_t)ex;
-        const int32_t j = S.lo[1] + (int32_t)(rest % (uint64_t)ey);
-        const int32_t k = S.lo[2] + (int32_t)(rest / (uint64_t)ey);
-        if (overlaps(S, i, j, k))
-            src.out[i + (int64_t)src.g.nx * (j + (int64_t)src.g.ny * k)] = i | (j << 10) | (k << 20);
     }
 }
 
