@@ -141,37 +141,102 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v)
         p[i] = v;
 }
 
+// Per-object centroid bounds.  A work-group reduces kBoundsItems x 256 consecutive
+// triangles (lane registers, then the wave, then the group through LDS) and updates an
+// object's six bound words once: atomics on one address serialise across the chip, and one
+// set per wave cost a few hundred serialised updates per large object.  A thread whose
+// triangles cross into another object (rare: objects hold thousands) updates the first
+// object's bounds itself; a wave or group spanning objects falls back to one set per lane.
+constexpr int kBoundsItems = 16;
+
 template <bool kBatch>
 __global__ __launch_bounds__(256) void k_bounds(Args a, const float* __restrict__ v, const int32_t* __restrict__ t,
                                                 int32_t total, uint32_t* __restrict__ bounds)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = i < total;
-    const Seg s = seg_of_tri<kBatch>(a, valid ? i : total - 1);
+    __shared__ uint32_t part[256 / kWave][6];
+    __shared__ int32_t part_o[256 / kWave];
     uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0u, 0u, 0u};
-    if (valid) {
-        const float3 c = tri_centroid(v + 3 * (int64_t)s.vert_off, t + 3 * (int64_t)s.tri_off, i - s.tri_off);
-        mn[0] = mx[0] = f2o(c.x);
-        mn[1] = mx[1] = f2o(c.y);
-        mn[2] = mx[2] = f2o(c.z);
-    }
-    // one atomic per wave when the wave lies in one object, else one per lane
-    const int32_t o0 = __shfl(s.o, 0);
-    if (__ballot(s.o != o0) == 0ull) {
-        for (int d = kWave / 2; d > 0; d >>= 1)
-            for (int q = 0; q < 3; ++q) {
-                mn[q] = min(mn[q], (uint32_t)__shfl_xor((int)mn[q], d, kWave));
-                mx[q] = max(mx[q], (uint32_t)__shfl_xor((int)mx[q], d, kWave));
-            }
-        if ((threadIdx.x & (kWave - 1)) == 0)
-            for (int q = 0; q < 3; ++q) {
-                atomicMin(&bounds[6 * o0 + q], mn[q]);
-                atomicMax(&bounds[6 * o0 + 3 + q], mx[q]);
-            }
-    } else if (valid) {
+    int32_t o = -1;  // object of the triangles in mn / mx (-1: none yet)
+    auto update = [&](int32_t obj) {
         for (int q = 0; q < 3; ++q) {
-            atomicMin(&bounds[6 * s.o + q], mn[q]);
-            atomicMax(&bounds[6 * s.o + 3 + q], mx[q]);
+            atomicMin(&bounds[6 * obj + q], mn[q]);
+            atomicMax(&bounds[6 * obj + 3 + q], mx[q]);
+        }
+    };
+    const int64_t first = (int64_t)blockIdx.x * 256 * kBoundsItems + threadIdx.x;
+    for (int j = 0; j < kBoundsItems; ++j) {
+        const int64_t i = first + (int64_t)j * 256;
+        if (i >= total) break;
+        const Seg s = seg_of_tri<kBatch>(a, (int32_t)i);
+        if (s.o != o) {
+            if (o >= 0) update(o);
+            o = s.o;
+            for (int q = 0; q < 3; ++q) {
+                mn[q] = 0xFFFFFFFFu;
+                mx[q] = 0u;
+            }
+        }
+        const float3 c = tri_centroid(v + 3 * (int64_t)s.vert_off, t + 3 * (int64_t)s.tri_off, (int32_t)i - s.tri_off);
+        const uint32_t e[3] = {f2o(c.x), f2o(c.y), f2o(c.z)};
+        for (int q = 0; q < 3; ++q) {
+            mn[q] = min(mn[q], e[q]);
+            mx[q] = max(mx[q], e[q]);
+        }
+    }
+    // lanes without triangles (o < 0) hold the neutral values; the wave reduces when every
+    // other lane ends in one object
+    const uint64_t has = __ballot(o >= 0);
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    int32_t wo = -1;
+    if (has != 0ull) {
+        const int32_t o0 = __shfl(o, __ffsll((long long)has) - 1);
+        if (__ballot(o >= 0 && o != o0) == 0ull) {
+            for (int d = kWave / 2; d > 0; d >>= 1)
+                for (int q = 0; q < 3; ++q) {
+                    mn[q] = min(mn[q], (uint32_t)__shfl_xor((int)mn[q], d, kWave));
+                    mx[q] = max(mx[q], (uint32_t)__shfl_xor((int)mx[q], d, kWave));
+                }
+            wo = o0;
+        } else if (o >= 0) {
+            update(o);  // a wave spanning objects
+        }
+    }
+    if (lane == 0) {
+        part_o[wave] = wo;
+        for (int q = 0; q < 3; ++q) {
+            part[wave][q] = mn[q];
+            part[wave][3 + q] = mx[q];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t go = -1;
+        bool one = true;
+        for (int w = 0; w < 256 / kWave; ++w) {
+            if (part_o[w] < 0) continue;
+            if (go < 0) go = part_o[w];
+            else if (part_o[w] != go) one = false;
+        }
+        if (go >= 0 && one) {
+            // only the waves that reduced to one object (part_o >= 0) are merged
+            uint32_t gmn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, gmx[3] = {0u, 0u, 0u};
+            for (int w = 0; w < 256 / kWave; ++w)
+                if (part_o[w] >= 0)
+                    for (int q = 0; q < 3; ++q) {
+                        gmn[q] = min(gmn[q], part[w][q]);
+                        gmx[q] = max(gmx[q], part[w][3 + q]);
+                    }
+            for (int q = 0; q < 3; ++q) {
+                atomicMin(&bounds[6 * go + q], gmn[q]);
+                atomicMax(&bounds[6 * go + 3 + q], gmx[q]);
+            }
+        } else {
+            for (int w = 0; w < 256 / kWave; ++w)
+                if (part_o[w] >= 0)
+                    for (int q = 0; q < 3; ++q) {
+                        atomicMin(&bounds[6 * part_o[w] + q], part[w][q]);
+                        atomicMax(&bounds[6 * part_o[w] + 3 + q], part[w][3 + q]);
+                    }
         }
     }
 }
@@ -828,13 +893,13 @@ __global__ __launch_bounds__(256) void k_collapse4(Args a, const BinNode* __rest
 // Every binary subtree covers consecutive triangle positions (its first and count are in
 // its node), so each triangle walks down from the root, entering at each 4-wide node the
 // child node whose range holds its position, until a leaf range holds it; the deepest walk
-// is the depth, which goes into the header with one atomicMax per object and wave (the
-// header's depth starts at 0; a root that is a leaf range keeps it).
+// is the depth, which goes into the header with one atomicMax per object and work-group
+// (the header's depth starts at 0; a root that is a leaf range keeps it).
 template <bool kBatch>
 __global__ __launch_bounds__(256) void k_depth4(Args a, const BinNode* __restrict__ bin, int32_t total, char* bvh)
 {
     const int32_t gt = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = gt < total;  // lanes past the end stay for the wave reduction below
+    const bool live = gt < total;  // lanes past the end stay for the reductions below
     int32_t depth = 0;
     int32_t* slot = nullptr;
     if (live) {
@@ -863,17 +928,45 @@ __global__ __launch_bounds__(256) void k_depth4(Args a, const BinNode* __restric
             }
         }
     }
-    // one atomic per wave when the wave's live triangles belong to one object
+    // one atomic per work-group when its live triangles belong to one object (atomics on one
+    // address serialise across the chip), else one per wave or lane
+    __shared__ int32_t* wslot[256 / kWave];
+    __shared__ int32_t wdepth[256 / kWave];
+    const int wave = threadIdx.x / kWave;
     const uint64_t lives = __ballot(live);
-    if (lives == 0ull) return;
-    const int32_t first_lane = __ffsll((long long)lives) - 1;
-    const uintptr_t obj0 = (uintptr_t)__shfl((int64_t)(uintptr_t)slot, first_lane);
-    if (__ballot(live && (uintptr_t)slot != obj0) == 0ull) {
-        int32_t m = depth;  // 0 on the lanes past the end
-        for (int d = 32; d > 0; d >>= 1) m = max(m, __shfl_xor(m, d));
-        if (__lane_id() == first_lane) atomicMax(slot, m);
-    } else if (live) {
-        atomicMax(slot, depth);
+    int32_t* ws = nullptr;
+    int32_t m = depth;  // 0 on the lanes past the end
+    if (lives != 0ull) {
+        const int32_t first_lane = __ffsll((long long)lives) - 1;
+        const uintptr_t obj0 = (uintptr_t)__shfl((int64_t)(uintptr_t)slot, first_lane);
+        if (__ballot(live && (uintptr_t)slot != obj0) == 0ull) {
+            for (int d = 32; d > 0; d >>= 1) m = max(m, __shfl_xor(m, d));
+            ws = (int32_t*)obj0;
+        } else if (live) {
+            atomicMax(slot, depth);
+        }
+    }
+    if (__lane_id() == 0) {
+        wslot[wave] = ws;
+        wdepth[wave] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t* gs = nullptr;
+        bool one = true;
+        int32_t gm = 0;
+        for (int w = 0; w < 256 / kWave; ++w) {
+            if (wslot[w] == nullptr) continue;
+            if (gs == nullptr) gs = wslot[w];
+            else if (wslot[w] != gs) one = false;
+            gm = max(gm, wdepth[w]);
+        }
+        if (gs != nullptr && one) {
+            atomicMax(gs, gm);
+        } else {
+            for (int w = 0; w < 256 / kWave; ++w)
+                if (wslot[w] != nullptr) atomicMax(wslot[w], wdepth[w]);
+        }
     }
 }
 
@@ -960,7 +1053,8 @@ hipError_t build(Args a, int32_t nobj, int64_t n, int64_t tiles, const float* ve
     hipLaunchKernelGGL(k_init<kBatch>, dim3(ob), dim3(256), 0, s, a, w.bounds, w.cseg0, w.base, n);
     hipLaunchKernelGGL(k_fill_i32, dim3(std::min<unsigned>(tb, 2048u)), dim3(256), 0, s, w.nparent, n, -1);
     hipLaunchKernelGGL(k_fill_i32, dim3(std::min<unsigned>(tb, 2048u)), dim3(256), 0, s, w.lparent, n, -1);
-    hipLaunchKernelGGL(k_bounds<kBatch>, dim3(tb), dim3(256), 0, s, a, verts, tris, total, w.bounds);
+    hipLaunchKernelGGL(k_bounds<kBatch>, dim3((unsigned)ceil_div(total, 256 * kBoundsItems)), dim3(256), 0, s, a, verts,
+                       tris, total, w.bounds);
     hipLaunchKernelGGL(k_morton<kBatch>, dim3(tb), dim3(256), 0, s, a, verts, tris, total, (const uint32_t*)w.bounds,
                        w.k0, w.v0);
     uint32_t *ka = w.k0, *va = w.v0, *kb = w.k1, *vb = w.v1;
