@@ -177,8 +177,8 @@ __device__ bool overlaps(const Snapped& S, int32_t i, int32_t j, int32_t k)
 // Candidates are dealt to lanes in runs of consecutive ones (a wave takes 64 runs at a
 // time): a lane's next candidate is in the same triangle unless it crosses the triangle's
 // end (triangles hold hundreds of candidates on average at fine resolutions, a few at
-// coarse ones), so the triangle is found by a forward step rather than a search per
-// candidate, and the voxel coordinates advance by one with carries instead of divisions.
+// coarse ones), so the triangle is found by a short forward search rather than a full one
+// per candidate, and the voxel coordinates advance by one with carries instead of divisions.
 // Runs are kCandRun long when there are that many candidates per lane of the launch, and
 // shorter when there are fewer, so that every lane still has work.
 constexpr int kCandRun = 16;
@@ -210,17 +210,24 @@ __global__ __launch_bounds__(256) void k_candidates(const float* __restrict__ ve
         bool carried = false;  // li, lj, lk hold the position of c - 1 in the same triangle
         for (uint64_t c = first; c < end; ++c) {
             if (c < tri_lo || c >= tri_hi) {
-                // triangle owning c: the last t with offsets[t] <= c (candidates only grow, so
-                // from the current one: a forward step within a run, a search between runs)
+                // triangle owning c: the last t with offsets[t] <= c, searched from the current
+                // one (candidates only grow); within a run c has just passed the current
+                // triangle's end, so the search gallops forward (steps 1, 2, 4, ..) before
+                // bisecting: a few loads for the next triangle, and O(log) ones across long
+                // stretches of triangles without candidates
                 int32_t lo = cur, hi = nt - 1;
                 if (carried) {
-                    while (lo < hi && offsets[lo + 1] <= c) ++lo;
-                } else {
-                    while (lo < hi) {
-                        const int32_t mid = (lo + hi + 1) >> 1;
-                        if (offsets[mid] <= c) lo = mid;
-                        else hi = mid - 1;
+                    int32_t step = 1;
+                    while (lo + step <= hi && offsets[lo + step] <= c) {
+                        lo += step;
+                        step <<= 1;
                     }
+                    hi = min(hi, lo + step - 1);
+                }
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (offsets[mid] <= c) lo = mid;
+                    else hi = mid - 1;
                 }
                 cur = lo;
                 tri_lo = offsets[cur];
