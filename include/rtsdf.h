@@ -89,6 +89,9 @@ rtsdf_status rtsdf_voxelize(const float* verts, int32_t nv, const int32_t* tris,
  *   scratch  [N] int32 ping-pong buffer, must not alias seeds
  *   steps    HOST int32[nsteps], each in [1, 1024]; nsteps in [0, 64]
  *   result_in_scratch  HOST int32 out: 1 if the result is in scratch (nsteps odd), else 0
+ * The result holds packed ids and RTSDF_EMPTY like the input; the other buffer is left with
+ * an intermediate pass's output in an internal encoding (the bitwise complement of each
+ * id) and means nothing to the caller.
  * Errors: E_ARG (null / aliased pointers, bad grid, step < 1), E_RANGE (dims, nsteps).
  * ------------------------------------------------------------------------------------- */
 rtsdf_status rtsdf_jfa(int32_t* seeds, int32_t* scratch, rtsdf_grid g, const int32_t* steps,
@@ -424,7 +427,8 @@ rtsdf_status rtsdf_voxelize_batched(const void* plan_host, const float* verts, c
                                     int32_t* seeds, int32_t* scratch, void* work, size_t work_bytes,
                                     void* stream);
 /* As rtsdf_jfa per object with its own offsets; one launch per pass over every object
- * still flooding; the results end in `seeds` (see rtsdf_voxelize_batched). */
+ * still flooding; the results end in `seeds` (see rtsdf_voxelize_batched), and `scratch`
+ * is left with intermediate passes in an internal encoding (as for rtsdf_jfa). */
 rtsdf_status rtsdf_jfa_batched(const void* plan_host, int32_t* seeds, int32_t* scratch, void* stream);
 /* As rtsdf_band per object with its own mask width; one list over the concatenated grid
  * points, increasing.  band_list [sizes.voxels] int32, band_count [1] int32 (device). */
