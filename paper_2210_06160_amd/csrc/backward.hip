@@ -11,7 +11,10 @@
 // One lane per listed grid point (grid-stride); a closest-hit traversal of the 4-wide
 // hierarchy with a per-lane stack in LDS that spills to private memory, in the iteration
 // structure of ray sampling; the gradient is scattered to the three vertices with binary32
-// atomic adds.
+// atomic adds.  Device-scope atomics are the slow part (they serialise at the memory side),
+// and neighbouring list entries mostly hit the same triangles (their closest rays run to the
+// nearest surface), so the lanes of a wave that hit one triangle first sum their nine values
+// in LDS and one of them issues the triangle's nine atomics.
 #include "traverse.h"
 
 namespace rtsdf {
@@ -32,6 +35,7 @@ __global__ __launch_bounds__(kThreads) void k_sdf_backward(
     float* __restrict__ grad_verts, const char* plan, int32_t nobj)
 {
     __shared__ uint64_t s_stk[kLdsDepth][kThreads];  // child keys: (entry t bits << 32) | code
+    __shared__ float s_acc[9][kThreads];             // a group leader's sums (3 vertices x 3)
     // spilled entries as two 32-bit arrays: a 64-bit array would let the compiler merge its
     // reads with the LDS reads into one flat load, which occupies the vector-memory path
     // even for LDS addresses
@@ -185,31 +189,66 @@ __global__ __launch_bounds__(kThreads) void k_sdf_backward(
                 sp = top;
             }
         }
-        if (bpos < 0) continue;
-
-        const float4 a = tris[bpos].v0, b = tris[bpos].v1, c = tris[bpos].v2;
-        const float3 v0 = make_float3(a.x, a.y, a.z);
-        const float3 e1 = make_float3(b.x - a.x, b.y - a.y, b.z - a.z);
-        const float3 e2 = make_float3(c.x - a.x, c.y - a.y, c.z - a.z);
-        const float3 n = cross3(e1, e2);
-        const float nw = dot3(n, w);
-        // barycentrics of the hit (Moller-Trumbore u, v)
-        const float3 P = cross3(w, e2);
-        const float inv_det = 1.0f / dot3(e1, P);
-        const float3 T = make_float3(o.x - v0.x, o.y - v0.y, o.z - v0.z);
-        const float u = dot3(T, P) * inv_det;
-        const float v = dot3(w, cross3(T, e1)) * inv_det;
-        const float bary[3] = {(1.0f - u) - v, u, v};
-        const float sign = (hc >> 16) > (hc & 0xFFFFu) ? -1.0f : 1.0f;
-        const float scale = gf * sign / nw;
-        const int32_t* tv = ltri + 3 * (int64_t)bid;
+        // lanes whose ray hit nothing (bpos < 0) stay for the wave's aggregation below
+        const bool valid = bpos >= 0;
+        float val[9];
+        int32_t gtri = -1;                 // the hit triangle across the batch
+        const int32_t* tv = nullptr;
+        if (valid) {
+            const float4 a = tris[bpos].v0, b = tris[bpos].v1, c = tris[bpos].v2;
+            const float3 v0 = make_float3(a.x, a.y, a.z);
+            const float3 e1 = make_float3(b.x - a.x, b.y - a.y, b.z - a.z);
+            const float3 e2 = make_float3(c.x - a.x, c.y - a.y, c.z - a.z);
+            const float3 n = cross3(e1, e2);
+            const float nw = dot3(n, w);
+            // barycentrics of the hit (Moller-Trumbore u, v)
+            const float3 P = cross3(w, e2);
+            const float inv_det = 1.0f / dot3(e1, P);
+            const float3 T = make_float3(o.x - v0.x, o.y - v0.y, o.z - v0.z);
+            const float u = dot3(T, P) * inv_det;
+            const float v = dot3(w, cross3(T, e1)) * inv_det;
+            const float bary[3] = {(1.0f - u) - v, u, v};
+            const float sign = (hc >> 16) > (hc & 0xFFFFu) ? -1.0f : 1.0f;
+            const float scale = gf * sign / nw;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            float* gv = lgv + 3 * (int64_t)tv[k];
-            const float s = scale * bary[k];
-            unsafeAtomicAdd(gv + 0, s * n.x);
-            unsafeAtomicAdd(gv + 1, s * n.y);
-            unsafeAtomicAdd(gv + 2, s * n.z);
+            for (int k = 0; k < 3; ++k) {
+                const float sk = scale * bary[k];
+                val[3 * k + 0] = sk * n.x;
+                val[3 * k + 1] = sk * n.y;
+                val[3 * k + 2] = sk * n.z;
+            }
+            gtri = (int32_t)((ltri - tri_index) / 3) + bid;
+            tv = ltri + 3 * (int64_t)bid;
+        }
+        // group the wave's lanes by hit triangle: each lane learns its group's first lane
+        const int lane = tid & (kWave - 1), wbase = tid - lane;
+        int leader = lane;
+        uint64_t pending = __ballot(valid);
+        while (pending != 0ull) {
+            const int l = __ffsll((long long)pending) - 1;
+            const int32_t kl = __shfl(gtri, l);
+            const bool mine = valid && gtri == kl;
+            if (mine) leader = l;
+            pending &= ~__ballot(mine);
+        }
+        // leaders clear their slots, every member adds into its leader's (LDS atomics; LDS
+        // operations of one wave complete in order), leaders scatter the sums
+        if (valid && leader == lane)
+            for (int i = 0; i < 9; ++i) s_acc[i][tid] = 0.0f;
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+        __builtin_amdgcn_wave_barrier();
+        if (valid)
+            for (int i = 0; i < 9; ++i) atomicAdd(&s_acc[i][wbase + leader], val[i]);
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+        __builtin_amdgcn_wave_barrier();
+        if (valid && leader == lane) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                float* gv = lgv + 3 * (int64_t)tv[k];
+                unsafeAtomicAdd(gv + 0, s_acc[3 * k + 0][tid]);
+                unsafeAtomicAdd(gv + 1, s_acc[3 * k + 1][tid]);
+                unsafeAtomicAdd(gv + 2, s_acc[3 * k + 2][tid]);
+            }
         }
     }
 }
