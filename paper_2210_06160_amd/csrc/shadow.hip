@@ -108,19 +108,48 @@ __device__ inline float trilinear(const float* __restrict__ f, const Cell& c, fl
     return y0 + fz * (y1 - y0);
 }
 
-__device__ inline void scatter(float* __restrict__ gf, const Cell& c, float w)
+// Adds w times the trilinear weights of sample cell c to its eight corners of gf.  The lanes
+// of a wave often sample the same cell (neighbouring pixels march side by side, several per
+// voxel) and device-scope atomics serialise at the memory side, so the active lanes are
+// grouped by cell (lower corner and clamped axes), members add their eight corner values
+// into their group leader's LDS slots, and each leader issues the eight atomics once.
+// acc: [8][64] LDS; the block is one wave.
+__device__ inline void scatter_wave(float* __restrict__ gf, const Cell& c, float w, float (*acc)[64])
 {
+    const int lane = (int)threadIdx.x;
     const float fx = c.ax.fr, fy = c.ay.fr, fz = c.az.fr;
     const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
-    float* p = gf + c.base;
-    unsafeAtomicAdd(p, w * (gx * gy * gz));
-    unsafeAtomicAdd(p + c.sx, w * (fx * gy * gz));
-    unsafeAtomicAdd(p + c.sy, w * (gx * fy * gz));
-    unsafeAtomicAdd(p + c.sy + c.sx, w * (fx * fy * gz));
-    unsafeAtomicAdd(p + c.sz, w * (gx * gy * fz));
-    unsafeAtomicAdd(p + c.sz + c.sx, w * (fx * gy * fz));
-    unsafeAtomicAdd(p + c.sz + c.sy, w * (gx * fy * fz));
-    unsafeAtomicAdd(p + c.sz + c.sy + c.sx, w * (fx * fy * fz));
+    const float v[8] = {w * (gx * gy * gz), w * (fx * gy * gz), w * (gx * fy * gz), w * (fx * fy * gz),
+                        w * (gx * gy * fz), w * (fx * gy * fz), w * (gx * fy * fz), w * (fx * fy * fz)};
+    const int64_t key = c.base * 8 + (c.sx != 0 ? 1 : 0) + (c.sy != 0 ? 2 : 0) + (c.sz != 0 ? 4 : 0);
+    int leader = lane;
+    uint64_t pending = __ballot(1);  // the lanes taking part
+    while (pending != 0ull) {
+        const int l = __ffsll((long long)pending) - 1;
+        const int64_t kl = __shfl(key, l);
+        const bool mine = key == kl;
+        if (mine) leader = l;
+        pending &= ~__ballot(mine);
+    }
+    // LDS operations of one wave complete in order; the waits make that explicit
+    if (leader == lane)
+        for (int i = 0; i < 8; ++i) acc[i][lane] = 0.0f;
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    for (int i = 0; i < 8; ++i) atomicAdd(&acc[i][leader], v[i]);
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
+    if (leader == lane) {
+        float* p = gf + c.base;
+        unsafeAtomicAdd(p, acc[0][lane]);
+        unsafeAtomicAdd(p + c.sx, acc[1][lane]);
+        unsafeAtomicAdd(p + c.sy, acc[2][lane]);
+        unsafeAtomicAdd(p + c.sy + c.sx, acc[3][lane]);
+        unsafeAtomicAdd(p + c.sz, acc[4][lane]);
+        unsafeAtomicAdd(p + c.sz + c.sx, acc[5][lane]);
+        unsafeAtomicAdd(p + c.sz + c.sy, acc[6][lane]);
+        unsafeAtomicAdd(p + c.sz + c.sy + c.sx, acc[7][lane]);
+    }
 }
 
 // Everything a launch needs besides the field: the receiver lattice and march constants,
@@ -253,6 +282,7 @@ __global__ __launch_bounds__(kTX* kTY) void k_shadow_backward(const float* __res
                                                                   float* __restrict__ grad_fine)
 {
     extern __shared__ float s_t[];  // [steps][64]: t_m, negative when clamp(s_m) was active
+    __shared__ float s_acc[8][64];  // scatter_wave's group sums
     const rtsdf_shadow& s = M.s;
     int a, b;
     if (!pixel_of(s, tiles_x, a, b)) return;
@@ -313,7 +343,7 @@ __global__ __launch_bounds__(kTX* kTY) void k_shadow_backward(const float* __res
         const Cell c = F.cell(make_float3(P.x + tm * L.x, P.y + tm * L.y, P.z + tm * L.z));
         float3 gr;
         trilinear(fine, c, &gr);
-        scatter(grad_fine, c, sbar);
+        scatter_wave(grad_fine, c, sbar, s_acc);
         tbar += sbar * ((gr.x * L.x + gr.y * L.y) + gr.z * L.z);
         if (m == 0) break;
         // t_m = t_{m-1} + clamp(s_{m-1}): s_{m-1} receives tbar where the clamp is inactive
