@@ -32,7 +32,7 @@ constexpr int kSortThreads = 256;
 constexpr int kSortRounds = kBvhSortTile / kSortThreads;
 constexpr int kPlocRadius = RTSDF_PLOC_RADIUS;
 constexpr int kPlocThreads = 256;
-constexpr int kPlocWide = 24;
+constexpr int kPlocWide = RTSDF_PLOC_WIDE;
 constexpr int kFinishThreads = 1024;
 
 // ---- objects ------------------------------------------------------------------------------

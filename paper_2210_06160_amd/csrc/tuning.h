@@ -60,6 +60,12 @@ static_assert((RTSDF_JFA_SPARSE & (RTSDF_JFA_SPARSE - 1)) == 0, "RTSDF_JFA_SPARS
 #define RTSDF_SHADOW_TILE_X 4
 #endif
 
+// PLOC iterations run across all clusters of all objects before one work-group per object
+// finishes the rest (the same step either way, so the tree does not depend on it)
+#ifndef RTSDF_PLOC_WIDE
+#define RTSDF_PLOC_WIDE 24
+#endif
+
 // hierarchy shape: most triangles in a leaf of the 4-wide tree, and the PLOC neighbourhood
 // radius (positions searched on each side for a cluster's nearest neighbour)
 #ifndef RTSDF_LEAF_MAX
