@@ -638,11 +638,50 @@ __global__ __launch_bounds__(256) void k_ploc_compact(Args a, const Cluster* __r
     cout[pos] = merge_cluster(me, other, id);
 }
 
+// Exclusive scans of keep and mrg over a work-group of kFinishThreads (one value per
+// thread); returns this thread's prefixes and writes the totals into tot.
+__device__ inline void finish_scan(uint32_t keep, uint32_t mrg, uint32_t* s_keep, uint32_t* s_merge, uint32_t& pk,
+                                   uint32_t& pm, uint32_t& tk, uint32_t& tm)
+{
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    uint32_t ik = keep, im = mrg;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t xk = __shfl_up(ik, d, kWave), xm = __shfl_up(im, d, kWave);
+        if (lane >= d) {
+            ik += xk;
+            im += xm;
+        }
+    }
+    if (lane == kWave - 1) {
+        s_keep[wave] = ik;
+        s_merge[wave] = im;
+    }
+    __syncthreads();
+    pk = ik - keep;
+    pm = im - mrg;
+    tk = 0;
+    tm = 0;
+    for (int w = 0; w < kFinishThreads / kWave; ++w) {
+        if (w < wave) {
+            pk += s_keep[w];
+            pm += s_merge[w];
+        }
+        tk += s_keep[w];
+        tm += s_merge[w];
+    }
+    __syncthreads();  // s_keep / s_merge are reused by the next scan
+}
+
 // One work-group per object finishes its clusters [start, start + n) of buffer A, using
 // the same segment of buffer B as the other half of the ping-pong, `nnw` for the nearest
-// neighbours and LDS scans for the compaction.  Every iteration merges at least one pair
-// (the least (area, position) pair of the object is mutual), so it ends after at most n - 1
-// iterations.
+// neighbours and LDS scans for the compaction; once at most kFinishLds clusters remain they
+// move to LDS and the remaining iterations run there (every read of an iteration happens
+// before a barrier, every write after it, so the compaction is in place).  Every iteration
+// merges at least one pair (the least (area, position) pair of the object is mutual), so it
+// ends after at most n - 1 iterations.
+constexpr int32_t kFinishLds = 1792;  // 56 KB of clusters + 7 KB of neighbour indices
+static_assert(kFinishLds <= 2 * kFinishThreads, "two clusters per thread in the LDS phase");
+
 template <bool kBatch>
 __global__ __launch_bounds__(kFinishThreads) void k_ploc_finish(Args a, Cluster* ca, Cluster* cb,
                                                                 const int32_t* __restrict__ cseg, const int32_t* base_in,
@@ -652,6 +691,8 @@ __global__ __launch_bounds__(kFinishThreads) void k_ploc_finish(Args a, Cluster*
 {
     __shared__ uint32_t s_keep[kFinishThreads / kWave], s_merge[kFinishThreads / kWave];
     __shared__ uint32_t s_tot[2];
+    __shared__ Cluster s_cl[kFinishLds];
+    __shared__ int32_t s_nn[kFinishLds];
     const int32_t o = blockIdx.x;
     const Seg s = seg_of_obj<kBatch>(a, o);
     const int32_t start = cseg[o];
@@ -660,7 +701,8 @@ __global__ __launch_bounds__(kFinishThreads) void k_ploc_finish(Args a, Cluster*
     Cluster* cur = ca;
     Cluster* nxt = cb;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    for (int32_t guard = 0; n > 1 && guard < s.nt; ++guard) {
+    int32_t guard = 0;
+    for (; n > kFinishLds && guard < s.nt; ++guard) {
         for (int32_t i = tid; i < n; i += kFinishThreads)
             nnw[start + i] = nearest(cur + start, i, max(i - kPlocRadius, 0), min(i + kPlocRadius, n - 1), 0);
         __syncthreads();
@@ -719,6 +761,45 @@ __global__ __launch_bounds__(kFinishThreads) void k_ploc_finish(Args a, Cluster*
         cur = nxt;
         nxt = tmp;
         __syncthreads();
+    }
+    if (n <= 1) return;
+    // LDS phase: at most kFinishLds clusters, two per thread
+    for (int32_t i = tid; i < n; i += kFinishThreads) s_cl[i] = cur[start + i];
+    __syncthreads();
+    for (; n > 1 && guard < s.nt; ++guard) {
+        for (int32_t i = tid; i < n; i += kFinishThreads)
+            s_nn[i] = nearest(s_cl, i, max(i - kPlocRadius, 0), min(i + kPlocRadius, n - 1), 0);
+        __syncthreads();
+        Cluster me[2], other[2];
+        uint32_t keep[2] = {0u, 0u}, mrg[2] = {0u, 0u};
+        for (int r = 0; r < 2; ++r) {
+            const int32_t i = r * kFinishThreads + tid;
+            if (i < n) {
+                const int32_t j = s_nn[i];
+                const bool mutual = j >= 0 && s_nn[j] == i;
+                keep[r] = (!mutual || i < j) ? 1u : 0u;
+                mrg[r] = (mutual && i < j) ? 1u : 0u;
+                me[r] = s_cl[i];
+                if (mrg[r]) other[r] = s_cl[j];
+            }
+        }
+        uint32_t pk0, pm0, tk0, tm0, pk1, pm1, tk1, tm1;
+        finish_scan(keep[0], mrg[0], s_keep, s_merge, pk0, pm0, tk0, tm0);  // its barriers end the reads
+        finish_scan(keep[1], mrg[1], s_keep, s_merge, pk1, pm1, tk1, tm1);
+        const uint32_t pk[2] = {pk0, tk0 + pk1}, pm[2] = {pm0, tm0 + pm1};
+        for (int r = 0; r < 2; ++r) {
+            if (!keep[r]) continue;
+            if (mrg[r]) {
+                const int32_t id = s.nt - 2 - (merges + (int32_t)pm[r]);
+                write_node<kBatch>(s, id, me[r], other[r], bin, ncount, nparent, lparent);
+                s_cl[pk[r]] = merge_cluster(me[r], other[r], id);
+            } else {
+                s_cl[pk[r]] = me[r];
+            }
+        }
+        __syncthreads();
+        merges += (int32_t)(tm0 + tm1);
+        n = (int32_t)(tk0 + tk1);
     }
 }
 
