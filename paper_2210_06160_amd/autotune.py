@@ -27,14 +27,14 @@ TUNING_H = os.path.join(HERE, "csrc", "tuning.h")
 GROUPS = {
     "jfa": {"RTSDF_JFA_CHUNK": [16, 32, 64], "RTSDF_JFA_WAVES": [2, 4, 8]},
     "jfa_sparse": {"RTSDF_JFA_SPARSE": [0, 2, 4, 8]},
-    "ray": {"RTSDF_RAY_START_BATCH": [8, 12, 16], "RTSDF_RAY_WAVES": [6, 7], "RTSDF_RAY_POP_TRIPS": [1, 2]},
+    "ray": {"RTSDF_RAY_START_BATCH": [6, 8, 12], "RTSDF_RAY_WAVES": [6, 7], "RTSDF_RAY_POP_TRIPS": [1, 2]},
     "tree": {"RTSDF_LEAF_MAX": [2, 3, 4], "RTSDF_PLOC_RADIUS": [16, 32]},
     "waves": {"RTSDF_RAY_WAVES": [6, 7]},
-    "restart": {"RTSDF_RAY_START_BATCH": [10, 12, 16], "RTSDF_RAY_POP_TRIPS": [1, 2, 3]},
+    "restart": {"RTSDF_RAY_START_BATCH": [4, 6, 8, 12], "RTSDF_RAY_POP_TRIPS": [1, 2, 3]},
+    "slots": {"RTSDF_RAY_SLOTS": [8, 16, 32]},
     "dist": {"RTSDF_RAY_CHUNK": [16, 32, 64], "RTSDF_RAY_RANGES": [8, 16]},
     "shadow": {"RTSDF_SHADOW_TILE_X": [1, 2, 4, 8]},
-    "ray_small": {"RTSDF_RAY_RANGES": [8, 32, 64], "RTSDF_RAY_CHUNK_SMALL": [16, 32, 128],
-                  "RTSDF_RAY_CHUNK_RAYS": [32, 64, 128]},
+    "ray_small": {"RTSDF_RAY_RANGES": [8, 32, 64], "RTSDF_RAY_CHUNK": [16, 32]},
 }
 
 
@@ -92,7 +92,7 @@ def time_candidate(group, path, reps):
                 out.append(a.elapsed_time(b))
         return statistics.median(out)
 
-    if group in ("jfa", "jfa_sparse", "ray", "tree", "waves", "restart", "dist"):
+    if group in ("jfa", "jfa_sparse", "ray", "tree", "waves", "restart", "slots", "dist"):
         sc = synth.scene_static()
         S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
         S.voxelize()

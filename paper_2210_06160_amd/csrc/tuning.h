@@ -21,33 +21,30 @@
 #endif
 static_assert((RTSDF_JFA_SPARSE & (RTSDF_JFA_SPARSE - 1)) == 0, "RTSDF_JFA_SPARSE: 0 or a power of two");
 
-// ray sampling: work units a wave takes per cursor atomic (raised so that one atomic
-// covers at least RTSDF_RAY_CHUNK_RAYS rays), and idle lanes restarted together
+// ray sampling: listed voxels a wave takes per cursor atomic (at most; fewer when the
+// mask is small, so that every wave gets work), the number of voxel ranges (each with its
+// own cursor; a multiple of the 8 XCDs), the voxel slots per wave (a power of two; a pool
+// fill starts at most half of them), and idle lanes restarted together
 #ifndef RTSDF_RAY_CHUNK
 #define RTSDF_RAY_CHUNK 32
-#endif
-#ifndef RTSDF_RAY_CHUNK_RAYS
-#define RTSDF_RAY_CHUNK_RAYS 64
-#endif
-// ... units per cursor atomic when there are fewer than 8 units per lane, and the number of
-// unit ranges (each with its own cursor; a multiple of the 8 XCDs)
-#ifndef RTSDF_RAY_CHUNK_SMALL
-#define RTSDF_RAY_CHUNK_SMALL 16
 #endif
 #ifndef RTSDF_RAY_RANGES
 #define RTSDF_RAY_RANGES 8
 #endif
+#ifndef RTSDF_RAY_SLOTS
+#define RTSDF_RAY_SLOTS 16
+#endif
 #ifndef RTSDF_RAY_START_BATCH
-#define RTSDF_RAY_START_BATCH 12
+#define RTSDF_RAY_START_BATCH 8
 #endif
 // ... waves per SIMD the single-object and the batched kernel are built for (their register
 // budgets, and the depth of their per-lane LDS stacks, which share the CU's 160 KB among that
 // many waves)
 #ifndef RTSDF_RAY_WAVES
-#define RTSDF_RAY_WAVES 7
+#define RTSDF_RAY_WAVES 6
 #endif
 #ifndef RTSDF_RAY_WAVES_BATCH
-#define RTSDF_RAY_WAVES_BATCH 6
+#define RTSDF_RAY_WAVES_BATCH 5
 #endif
 // ... and the most stack entries a lane pops per loop iteration (0: until it finds work); a
 // lane that needs more pops carries on in the next iteration

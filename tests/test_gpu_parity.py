@@ -135,6 +135,30 @@ def test_static_reduced_full_parity(R, orc, case):
     np.testing.assert_allclose(G["fine"], O["fine"], rtol=RTOL, atol=0)
 
 
+@pytest.mark.parametrize("case", ["x1", "x3", "x7", "x100", "x5_large", "x9_large"])
+def test_rays_per_voxel_pool_boundaries(R, orc, case):
+    """Ray counts that split a wave's pool of 64 rays unevenly: fills with more voxels than
+    LDS slots (x < 8: those voxels' rays add to the global accumulators themselves), voxels
+    continued from one fill to the next (x not dividing 64, on a mask large enough for
+    chunks longer than one fill), and a voxel spanning several fills (x > 64).  Small grids
+    are compared at every masked voxel, the larger ones at 4000 sampled voxels."""
+    x = int(case[1:].split("_")[0])
+    if case.endswith("_large"):
+        sc = synth.scene_static(dims=(160, 80, 160), nprims=60, seed=6)
+        sc.frames, sc.rays, sc.band = 1, x, 4
+        sample = 4000
+    else:
+        sc = synth.scene_static(dims=(60, 40, 60), nprims=12, seed=4)
+        sc.frames, sc.rays, sc.band = (1 if x > 64 else 2), x, 3
+        sample = None
+    log("case:", case, "tris", len(sc.tris), "rays", x)
+    G = gpu_pipeline(R, sc, key=77)
+    O = oracle_pipeline(orc, sc, key=77, sample=sample, rng=np.random.default_rng(5))
+    log("  masked voxels", len(G["band"]))
+    assert np.array_equal(G["band"], O["band"])
+    compare_rays(G, O, O["vids"])
+
+
 def test_paper_scale_static(R, orc):
     """400x200x400, ~102k triangles, 10 passes, 4-voxel mask, 8 rays x 16 frames."""
     sc = synth.scene_static()
