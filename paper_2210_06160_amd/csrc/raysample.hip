@@ -73,8 +73,9 @@ template <bool kBatch>
 constexpr int kSlotBytes = kWaves * kSlots * (int)(sizeof(VoxelSlot) + (kBatch ? sizeof(int32_t) : 0));
 // LDS stack entries per lane (6 bytes each: a child code and the top 16 bits of its entry
 // t): what the work-group's slots leave of its share of the CU's 160 KB (kMinWaves
-// work-groups of 4 waves per CU), the share rounded down to whole KiB (LDS is allocated in
-// KiB granules: a work-group 512 bytes over its share leaves one work-group fewer per CU)
+// work-groups of 4 waves per CU), the share rounded down to whole KiB (LDS behaves as if
+// allocated in KiB granules: a work-group of 27,136 bytes, within its 27,306-byte share but
+// not a whole number of KiB, ran as if one work-group fewer fitted per CU)
 template <bool kBatch>
 constexpr int kGroupLds = (163840 / kMinWaves<kBatch>) / 1024 * 1024;
 template <bool kBatch>
