@@ -31,6 +31,7 @@ GROUPS = {
     "tree": {"RTSDF_LEAF_MAX": [2, 3, 4], "RTSDF_PLOC_RADIUS": [16, 32]},
     "waves": {"RTSDF_RAY_WAVES": [6, 7]},
     "restart": {"RTSDF_RAY_START_BATCH": [4, 6, 8, 12], "RTSDF_RAY_POP_TRIPS": [1, 2, 3]},
+    "visits": {"RTSDF_RAY_VISITS": [1, 2, 3], "RTSDF_RAY_POP_TRIPS": [1, 2]},
     "slots": {"RTSDF_RAY_SLOTS": [8, 16, 32]},
     "dist": {"RTSDF_RAY_CHUNK": [16, 32, 64], "RTSDF_RAY_RANGES": [8, 16]},
     "shadow": {"RTSDF_SHADOW_TILE_X": [1, 2, 4, 8]},
@@ -92,7 +93,7 @@ def time_candidate(group, path, reps):
                 out.append(a.elapsed_time(b))
         return statistics.median(out)
 
-    if group in ("jfa", "jfa_sparse", "ray", "tree", "waves", "restart", "slots", "dist"):
+    if group in ("jfa", "jfa_sparse", "ray", "tree", "waves", "restart", "visits", "slots", "dist"):
         sc = synth.scene_static()
         S = rtsdf.StaticSDF(sc.verts, sc.tris, sc.dims, sc.org, sc.h, sc.steps, sc.band, sc.rays, sc.frames)
         S.voxelize()

@@ -20,7 +20,8 @@
 // The loop touches no cold memory: directions are drawn in registers and accumulators are
 // updated in LDS or with fire-and-forget atomics, because on CDNA loads retire in order and
 // one HBM-latency load would stall every later node fetch of the wave.
-// Each loop iteration does at most one node visit and one triangle test per lane.
+// Each loop iteration does at most RTSDF_RAY_VISITS node visits and one triangle test per
+// lane.
 //
 // Traversal of the 4-wide hierarchy: the four child boxes are tested at once, the hits are
 // sorted by entry distance (packed into uint keys with the slot in the two low bits, the
@@ -49,7 +50,10 @@ constexpr int kWaves = kThreads / kWave;  // waves per work-group
 // latter keeps its object's hierarchy per lane, and needs more registers)
 template <bool kBatch>
 constexpr int kMinWaves = kBatch ? RTSDF_RAY_WAVES_BATCH : RTSDF_RAY_WAVES;
-constexpr int kPopTrips = RTSDF_RAY_POP_TRIPS;  // stack pops per lane and iteration (0: no limit)
+constexpr int kPopTrips = RTSDF_RAY_POP_TRIPS;  // stack pops per lane and node visit (0: no limit)
+constexpr int kVisits = RTSDF_RAY_VISITS;       // node visits per lane and loop iteration
+constexpr int kTestRound = kVisits > 1 ? 1 : 0;  // the triangle test runs before this visit
+static_assert(kVisits >= 1, "at least one node visit per iteration");
 
 // A voxel's results while its rays are traced (one slot per voxel in a per-wave ring).
 struct alignas(16) VoxelSlot {
@@ -412,83 +416,91 @@ __global__ __launch_bounds__(kThreads, kMinWaves<kBatch>) void k_raysample(const
         }
         if (!more && __ballot(active) == 0ull) break;
         if (!active) continue;
-        // at most one triangle test ...
-        if (pcount > 0) {
-            test_leaf(tris, pfirst, o, w, pad, tb, bid, bfr);
-            ++pfirst;
-            --pcount;
-            if (pcount == 0) {
-                pfirst = pfirst2;
-                pcount = pcount2;
-                pcount2 = 0;
-            }
-        }
-        // ... and one node visit per iteration
-        if (node >= 0) {
-            ChildKey s0, s1, s2, s3;
-            node_keys(fetch_node(nodes, (uint32_t)node), np, inv, oinv, tb, s0, s1, s2, s3);
-            sort4(s0, s1, s2, s3);
-            // entered boxes sort first, so they are a prefix: push the entered ones of s1..s3,
-            // farthest first; with room in LDS all three slots are written unconditionally
-            // (slots past the new top are dead) and only the top moves
-            const int nv = (int)entered(s1) + (int)entered(s2) + (int)entered(s3);
-            if (sp + 3 <= kDepth) {
-                put(sp, nv == 3 ? s3 : (nv == 2 ? s2 : s1));
-                put(sp + 1, nv == 3 ? s2 : s1);
-                put(sp + 2, s1);
-                sp += nv;
-            } else {
-                if (entered(s3)) push(s3);
-                if (entered(s2)) push(s2);
-                if (entered(s1)) push(s1);
-            }
-            node = -1;
-            if (entered(s0)) {
-                const int32_t c0 = s0.code;
-                if (c0 >= 0) {
-                    node = c0;
-                } else if (pcount == 0) {
-                    pfirst = leaf_first(c0);
-                    pcount = leaf_count(c0);
-                } else if (pcount2 == 0) {
-                    pfirst2 = leaf_first(c0);
-                    pcount2 = leaf_count(c0);
-                } else {
-                    push(s0);
+        // kVisits rounds of (node visit, stack pops) per iteration, with the triangle test
+        // after the first: visits outnumber triangle tests about two to one per ray, and the
+        // iteration's fixed costs (restart check, loop control) are paid once per round pair
+#pragma unroll
+        for (int round = 0; round < kVisits; ++round) {
+            if (round == kTestRound) {
+                // the iteration's triangle test
+                if (pcount > 0) {
+                    test_leaf(tris, pfirst, o, w, pad, tb, bid, bfr);
+                    ++pfirst;
+                    --pcount;
+                    if (pcount == 0) {
+                        pfirst = pfirst2;
+                        pcount = pcount2;
+                        pcount2 = 0;
+                    }
                 }
             }
-        }
-        // refill node / pending leaf from the stack
-        int trips = 0;
-        while (node < 0 && sp > 0 && (kPopTrips == 0 || trips++ < kPopTrips)) {
-            const int top = sp - 1;
-            uint32_t tbits;
-            int32_t e;
-            if (top < kDepth) {
-                tbits = (uint32_t)s_t16[top][tid] << 16;
-                e = s_code[top][tid];
-            } else {
-                const uint64_t w = p_key[top - kDepth];
-                tbits = (uint32_t)(w >> 32);
-                e = word_code(w);
+            // a node visit ...
+            if (node >= 0) {
+                ChildKey s0, s1, s2, s3;
+                node_keys(fetch_node(nodes, (uint32_t)node), np, inv, oinv, tb, s0, s1, s2, s3);
+                sort4(s0, s1, s2, s3);
+                // entered boxes sort first, so they are a prefix: push the entered ones of s1..s3,
+                // farthest first; with room in LDS all three slots are written unconditionally
+                // (slots past the new top are dead) and only the top moves
+                const int nv = (int)entered(s1) + (int)entered(s2) + (int)entered(s3);
+                if (sp + 3 <= kDepth) {
+                    put(sp, nv == 3 ? s3 : (nv == 2 ? s2 : s1));
+                    put(sp + 1, nv == 3 ? s2 : s1);
+                    put(sp + 2, s1);
+                    sp += nv;
+                } else {
+                    if (entered(s3)) push(s3);
+                    if (entered(s2)) push(s2);
+                    if (entered(s1)) push(s1);
+                }
+                node = -1;
+                if (entered(s0)) {
+                    const int32_t c0 = s0.code;
+                    if (c0 >= 0) {
+                        node = c0;
+                    } else if (pcount == 0) {
+                        pfirst = leaf_first(c0);
+                        pcount = leaf_count(c0);
+                    } else if (pcount2 == 0) {
+                        pfirst2 = leaf_first(c0);
+                        pcount2 = leaf_count(c0);
+                    } else {
+                        push(s0);
+                    }
+                }
             }
-            if (__uint_as_float(tbits) > tb) {
-                sp = top;
-                continue;
-            }
-            if (e >= 0) {
-                node = e;
-                sp = top;
-            } else if (pcount == 0) {
-                pfirst = leaf_first(e);
-                pcount = leaf_count(e);
-                sp = top;
-            } else if (pcount2 == 0) {
-                pfirst2 = leaf_first(e);
-                pcount2 = leaf_count(e);
-                sp = top;
-            } else {
-                break;
+            // ... and at most kPopTrips stack pops to refill the node or a pending leaf range
+            int trips = 0;
+            while (node < 0 && sp > 0 && (kPopTrips == 0 || trips++ < kPopTrips)) {
+                const int top = sp - 1;
+                uint32_t tbits;
+                int32_t e;
+                if (top < kDepth) {
+                    tbits = (uint32_t)s_t16[top][tid] << 16;
+                    e = s_code[top][tid];
+                } else {
+                    const uint64_t w = p_key[top - kDepth];
+                    tbits = (uint32_t)(w >> 32);
+                    e = word_code(w);
+                }
+                if (__uint_as_float(tbits) > tb) {
+                    sp = top;
+                    continue;
+                }
+                if (e >= 0) {
+                    node = e;
+                    sp = top;
+                } else if (pcount == 0) {
+                    pfirst = leaf_first(e);
+                    pcount = leaf_count(e);
+                    sp = top;
+                } else if (pcount2 == 0) {
+                    pfirst2 = leaf_first(e);
+                    pcount2 = leaf_count(e);
+                    sp = top;
+                } else {
+                    break;
+                }
             }
         }
         if (node < 0 && pcount == 0 && sp == 0) active = false;
