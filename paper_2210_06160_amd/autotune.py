@@ -28,7 +28,7 @@ GROUPS = {
     "jfa": {"RTSDF_JFA_CHUNK": [16, 32, 64], "RTSDF_JFA_WAVES": [2, 4, 8]},
     "jfa_sparse": {"RTSDF_JFA_SPARSE": [0, 2, 4, 8]},
     "ray": {"RTSDF_RAY_START_BATCH": [6, 8, 12], "RTSDF_RAY_WAVES": [6, 7], "RTSDF_RAY_POP_TRIPS": [1, 2]},
-    "tree": {"RTSDF_LEAF_MAX": [2, 3, 4], "RTSDF_PLOC_RADIUS": [16, 32]},
+    "tree": {"RTSDF_LEAF_MAX": [1, 2, 3], "RTSDF_PLOC_RADIUS": [16, 32]},
     "waves": {"RTSDF_RAY_WAVES": [6, 7]},
     "restart": {"RTSDF_RAY_START_BATCH": [4, 6, 8, 12], "RTSDF_RAY_POP_TRIPS": [1, 2, 3]},
     "visits": {"RTSDF_RAY_VISITS": [1, 2, 3], "RTSDF_RAY_POP_TRIPS": [1, 2]},

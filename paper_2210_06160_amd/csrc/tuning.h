@@ -70,7 +70,7 @@ static_assert((RTSDF_JFA_SPARSE & (RTSDF_JFA_SPARSE - 1)) == 0, "RTSDF_JFA_SPARS
 // hierarchy shape: most triangles in a leaf of the 4-wide tree, and the PLOC neighbourhood
 // radius (positions searched on each side for a cluster's nearest neighbour)
 #ifndef RTSDF_LEAF_MAX
-#define RTSDF_LEAF_MAX 2
+#define RTSDF_LEAF_MAX 1
 #endif
 #ifndef RTSDF_PLOC_RADIUS
 #define RTSDF_PLOC_RADIUS 16
