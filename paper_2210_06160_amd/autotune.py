@@ -31,7 +31,7 @@ GROUPS = {
     "tree": {"RTSDF_LEAF_MAX": [1, 2, 3], "RTSDF_PLOC_RADIUS": [16, 32]},
     "waves": {"RTSDF_RAY_WAVES": [6, 7]},
     "restart": {"RTSDF_RAY_START_BATCH": [4, 6, 8, 12], "RTSDF_RAY_POP_TRIPS": [1, 2, 3]},
-    "visits": {"RTSDF_RAY_VISITS": [1, 2, 3], "RTSDF_RAY_POP_TRIPS": [1, 2]},
+    "visits": {"RTSDF_RAY_VISITS": [2, 4, 6, 8], "RTSDF_RAY_START_BATCH": [4, 8]},
     "slots": {"RTSDF_RAY_SLOTS": [8, 16, 32]},
     "dist": {"RTSDF_RAY_CHUNK": [16, 32, 64], "RTSDF_RAY_RANGES": [8, 16]},
     "shadow": {"RTSDF_SHADOW_TILE_X": [1, 2, 4, 8]},

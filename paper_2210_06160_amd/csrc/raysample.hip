@@ -20,8 +20,8 @@
 // The loop touches no cold memory: directions are drawn in registers and accumulators are
 // updated in LDS or with fire-and-forget atomics, because on CDNA loads retire in order and
 // one HBM-latency load would stall every later node fetch of the wave.
-// Each loop iteration does at most RTSDF_RAY_VISITS node visits and one triangle test per
-// lane.
+// Each loop iteration does at most RTSDF_RAY_VISITS node visits per lane, with a triangle
+// test after every second one.
 //
 // Traversal of the 4-wide hierarchy: the four child boxes are tested at once, the hits are
 // sorted by entry distance (packed into uint keys with the slot in the two low bits, the
@@ -51,9 +51,11 @@ constexpr int kWaves = kThreads / kWave;  // waves per work-group
 template <bool kBatch>
 constexpr int kMinWaves = kBatch ? RTSDF_RAY_WAVES_BATCH : RTSDF_RAY_WAVES;
 constexpr int kPopTrips = RTSDF_RAY_POP_TRIPS;  // stack pops per lane and node visit (0: no limit)
-constexpr int kVisits = RTSDF_RAY_VISITS;       // node visits per lane and loop iteration
-constexpr int kTestRound = kVisits > 1 ? 1 : 0;  // the triangle test runs before this visit
+constexpr int kVisits = RTSDF_RAY_VISITS;  // node visits per lane and loop iteration
 static_assert(kVisits >= 1, "at least one node visit per iteration");
+// the rounds (node visit, stack pops) that a triangle test precedes: every second one from
+// the second on (the first, with one round per iteration)
+__device__ constexpr bool test_before(int round) { return kVisits > 1 ? round % 2 == 1 : round == 0; }
 
 // A voxel's results while its rays are traced (one slot per voxel in a per-wave ring).
 struct alignas(16) VoxelSlot {
@@ -416,13 +418,13 @@ __global__ __launch_bounds__(kThreads, kMinWaves<kBatch>) void k_raysample(const
         }
         if (!more && __ballot(active) == 0ull) break;
         if (!active) continue;
-        // kVisits rounds of (node visit, stack pops) per iteration, with the triangle test
-        // after the first: visits outnumber triangle tests about two to one per ray, and the
-        // iteration's fixed costs (restart check, loop control) are paid once per round pair
+        // kVisits rounds of (node visit, stack pops) per iteration, with a triangle test after
+        // every second visit: visits outnumber triangle tests about two to one per ray, and the
+        // iteration's fixed costs (restart check, loop control) are paid once per kVisits visits
 #pragma unroll
         for (int round = 0; round < kVisits; ++round) {
-            if (round == kTestRound) {
-                // the iteration's triangle test
+            if (test_before(round)) {
+                // a triangle test
                 if (pcount > 0) {
                     test_leaf(tris, pfirst, o, w, pad, tb, bid, bfr);
                     ++pfirst;

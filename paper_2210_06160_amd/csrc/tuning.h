@@ -46,11 +46,11 @@ static_assert((RTSDF_JFA_SPARSE & (RTSDF_JFA_SPARSE - 1)) == 0, "RTSDF_JFA_SPARS
 #ifndef RTSDF_RAY_WAVES_BATCH
 #define RTSDF_RAY_WAVES_BATCH 5
 #endif
-// ... the node visits per loop iteration (the triangle test runs after the first), and the
-// most stack entries a lane pops after a node visit (0: until it finds work); a lane that
+// ... the node visits per loop iteration (a triangle test runs after every second one), and
+// the most stack entries a lane pops after a node visit (0: until it finds work); a lane that
 // needs more pops carries on at the next visit
 #ifndef RTSDF_RAY_VISITS
-#define RTSDF_RAY_VISITS 2
+#define RTSDF_RAY_VISITS 6
 #endif
 #ifndef RTSDF_RAY_POP_TRIPS
 #define RTSDF_RAY_POP_TRIPS 1
