@@ -399,16 +399,6 @@ __global__ __launch_bounds__(256) void k_tree(Args a, const uint32_t* __restrict
     else lparent[s.tri_off + ~right] = i;
 }
 
-__device__ inline float ld_coherent(const float* p)
-{
-    return __uint_as_float(__hip_atomic_load((const uint32_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-}
-
-__device__ inline void st_coherent(float* p, float v)
-{
-    __hip_atomic_store((uint32_t*)p, __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 template <bool kBatch>
 __device__ inline BvhTri* blob_tris(char* bvh, const Seg& s)
 {
@@ -429,14 +419,75 @@ __device__ inline BvhTri leaf_record(const float* __restrict__ v, const int32_t*
     return tri;
 }
 
-// LBVH: write the leaf records in sorted order and refit boxes bottom-up (the second child
-// to arrive at a node merges both boxes)
+// ---- LBVH boxes -------------------------------------------------------------------------
+// Radix-tree node i covers the consecutive sorted leaves [first, first + count) (k_tree
+// stores them in its a_hi.w / b_hi.w), so its box is the union of those leaves' boxes: no
+// bottom-up chain of arrivals is needed.  Level 0 of a box pyramid holds the leaf boxes
+// (global sorted positions), level k + 1 the unions of kBoxFan consecutive level-k entries;
+// a range query reads the partial blocks at both ends of each level and moves up through
+// the whole blocks, so it reads at most 2 (kBoxFan - 1) entries per level.  A block that
+// straddles two objects of a batch is never read: a node's range lies within one object and
+// only blocks inside the range are used.
+constexpr int kBoxFan = 64;
+constexpr int kBoxLevels = 6;  // kBoxFan^5 >= kBvhMaxTris
+struct LeafBox {
+    float4 lo, hi;  // .w unused
+};
+struct BoxPyramid {
+    const LeafBox* lev[kBoxLevels];
+    int32_t nlev;  // levels in use; the last holds at most kBoxFan entries
+};
+
+__device__ inline void grow(float3& lo, float3& hi, const LeafBox& b)
+{
+    lo = make_float3(fminf(lo.x, b.lo.x), fminf(lo.y, b.lo.y), fminf(lo.z, b.lo.z));
+    hi = make_float3(fmaxf(hi.x, b.hi.x), fmaxf(hi.y, b.hi.y), fmaxf(hi.z, b.hi.z));
+}
+
+// union of the level-0 entries [lo, hi] (inclusive)
+__device__ inline void range_box(const BoxPyramid& P, int64_t lo, int64_t hi, float3& blo, float3& bhi)
+{
+    for (int k = 0; lo <= hi; ++k) {
+        const LeafBox* __restrict__ c = P.lev[k];
+        if (k + 1 == P.nlev) {
+#pragma unroll 4
+            for (int64_t e = lo; e <= hi; ++e) grow(blo, bhi, c[e]);
+            break;
+        }
+        const int64_t head = min(hi + 1, (lo + kBoxFan - 1) / kBoxFan * kBoxFan);  // first block boundary
+#pragma unroll 4
+        for (int64_t e = lo; e < head; ++e) grow(blo, bhi, c[e]);
+        if (head > hi) break;
+        const int64_t tail = max(head, (hi + 1) / kBoxFan * kBoxFan);  // last block boundary
+#pragma unroll 4
+        for (int64_t e = tail; e <= hi; ++e) grow(blo, bhi, c[e]);
+        lo = head / kBoxFan;
+        hi = tail / kBoxFan - 1;
+    }
+}
+
+// child slot of node `parent` whose code is `code`: its box components (x, y, z of lo and hi)
+// are written one by one, leaving the .w fields that k_tree filled
+__device__ inline void set_child_box(BinNode* node, int32_t code, float3 lo, float3 hi)
+{
+    const bool is_a = __float_as_int(node->a_lo.w) == code;
+    float* slo = is_a ? &node->a_lo.x : &node->b_lo.x;
+    float* shi = is_a ? &node->a_hi.x : &node->b_hi.x;
+    slo[0] = lo.x;
+    slo[1] = lo.y;
+    slo[2] = lo.z;
+    shi[0] = hi.x;
+    shi[1] = hi.y;
+    shi[2] = hi.z;
+}
+
+// LBVH leaves: the triangle records in sorted order, the leaf boxes (level 0), and each
+// leaf's box in its parent's child slot
 template <bool kBatch>
-__global__ __launch_bounds__(256) void k_leaves_refit(Args a, const float* __restrict__ v,
-                                                      const int32_t* __restrict__ t, int32_t total,
-                                                      const uint32_t* __restrict__ order, BinNode* bin, char* bvh,
-                                                      const int32_t* __restrict__ nparent,
-                                                      const int32_t* __restrict__ lparent, uint32_t* flags)
+__global__ __launch_bounds__(256) void k_lbvh_leaves(Args a, const float* __restrict__ v,
+                                                     const int32_t* __restrict__ t, int32_t total,
+                                                     const uint32_t* __restrict__ order, BinNode* bin, char* bvh,
+                                                     const int32_t* __restrict__ lparent, LeafBox* __restrict__ boxes)
 {
     const int32_t gp = blockIdx.x * blockDim.x + threadIdx.x;
     if (gp >= total) return;
@@ -444,37 +495,49 @@ __global__ __launch_bounds__(256) void k_leaves_refit(Args a, const float* __res
     const int32_t pos = gp - s.tri_off;
     const int32_t id = (int32_t)order[gp] - s.tri_off;
     blob_tris<kBatch>(bvh, s)[pos] = leaf_record<kBatch>(v, t, s, id);
-    if (s.nt == 1) return;
     float3 blo, bhi;
     tri_box(v + 3 * (int64_t)s.vert_off, t + 3 * (int64_t)s.tri_off, id, s.pad, blo, bhi);
-    int32_t me = ~pos;
-    int32_t p = lparent[gp];
-    BinNode* nodes = bin + s.tri_off;
-    while (true) {
-        BinNode* node = &nodes[p];
-        const bool is_a = __float_as_int(node->a_lo.w) == me;
-        float* slo = is_a ? &node->a_lo.x : &node->b_lo.x;
-        float* shi = is_a ? &node->a_hi.x : &node->b_hi.x;
-        st_coherent(slo, blo.x);
-        st_coherent(slo + 1, blo.y);
-        st_coherent(slo + 2, blo.z);
-        st_coherent(shi, bhi.x);
-        st_coherent(shi + 1, bhi.y);
-        st_coherent(shi + 2, bhi.z);
-        const uint32_t old = __hip_atomic_fetch_add(&flags[s.tri_off + p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == 0u) return;  // the sibling will finish this node
-        const float* alo = &node->a_lo.x;
-        const float* ahi = &node->a_hi.x;
-        const float* bl = &node->b_lo.x;
-        const float* bh = &node->b_hi.x;
-        blo = make_float3(fminf(ld_coherent(alo), ld_coherent(bl)), fminf(ld_coherent(alo + 1), ld_coherent(bl + 1)),
-                          fminf(ld_coherent(alo + 2), ld_coherent(bl + 2)));
-        bhi = make_float3(fmaxf(ld_coherent(ahi), ld_coherent(bh)), fmaxf(ld_coherent(ahi + 1), ld_coherent(bh + 1)),
-                          fmaxf(ld_coherent(ahi + 2), ld_coherent(bh + 2)));
-        if (p == 0) return;
-        me = p;
-        p = nparent[s.tri_off + p];
+    boxes[gp] = LeafBox{make_float4(blo.x, blo.y, blo.z, 0.0f), make_float4(bhi.x, bhi.y, bhi.z, 0.0f)};
+    if (s.nt > 1) set_child_box(bin + s.tri_off + lparent[gp], ~pos, blo, bhi);
+}
+
+// level k + 1 of the box pyramid: one wave per block of kBoxFan level-k entries
+__global__ __launch_bounds__(256) void k_box_level(const LeafBox* __restrict__ below, int64_t nbelow,
+                                                   LeafBox* __restrict__ above, int64_t nabove)
+{
+    const int64_t blk = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (blk >= nabove) return;  // whole waves leave together (nabove is a count of waves)
+    const int64_t e = blk * kBoxFan + __lane_id();
+    const float inf = __int_as_float(0x7f800000);
+    float3 lo = make_float3(inf, inf, inf), hi = make_float3(-inf, -inf, -inf);
+    if (e < nbelow) grow(lo, hi, below[e]);
+    for (int m = kWave / 2; m >= 1; m >>= 1) {
+        lo = make_float3(fminf(lo.x, __shfl_xor(lo.x, m)), fminf(lo.y, __shfl_xor(lo.y, m)),
+                         fminf(lo.z, __shfl_xor(lo.z, m)));
+        hi = make_float3(fmaxf(hi.x, __shfl_xor(hi.x, m)), fmaxf(hi.y, __shfl_xor(hi.y, m)),
+                         fmaxf(hi.z, __shfl_xor(hi.z, m)));
     }
+    if (__lane_id() == 0)
+        above[blk] = LeafBox{make_float4(lo.x, lo.y, lo.z, 0.0f), make_float4(hi.x, hi.y, hi.z, 0.0f)};
+}
+
+// LBVH internal nodes: each node's box from its leaf range, into its parent's child slot
+template <bool kBatch>
+__global__ __launch_bounds__(256) void k_lbvh_nodes(Args a, int32_t total, BinNode* bin,
+                                                    const int32_t* __restrict__ nparent, BoxPyramid P)
+{
+    const int32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= total) return;
+    const Seg s = seg_of_tri<kBatch>(a, gi);
+    const int32_t i = gi - s.tri_off;
+    if (i == 0 || i >= s.nt - 1) return;  // the root has no parent; nt - 1 internal nodes
+    const BinNode* node = bin + gi;
+    const int64_t first = (int64_t)s.tri_off + __float_as_int(node->a_hi.w);
+    const int64_t count = __float_as_int(node->b_hi.w);
+    const float inf = __int_as_float(0x7f800000);
+    float3 lo = make_float3(inf, inf, inf), hi = make_float3(-inf, -inf, -inf);
+    range_box(P, first, first + count - 1, lo, hi);
+    set_child_box(bin + s.tri_off + nparent[gi], i, lo, hi);
 }
 
 // ---- PLOC ------------------------------------------------------------------------------
@@ -483,6 +546,7 @@ __global__ __launch_bounds__(256) void k_leaves_refit(Args a, const float* __res
 struct Cluster {
     float4 lo, hi;
 };
+static_assert(sizeof(Cluster) == sizeof(LeafBox), "the LBVH box pyramid reuses the cluster arrays");
 
 __device__ inline float union_area(const Cluster& x, const Cluster& y)
 {
@@ -1070,7 +1134,7 @@ __global__ void k_header(Args a, char* bvh)
 
 // ---- workspace ----------------------------------------------------------------------------
 struct Work {
-    uint32_t *k0, *v0, *k1, *v1, *counts, *bounds, *flags32;
+    uint32_t *k0, *v0, *k1, *v1, *counts, *bounds;
     Cluster *ca, *cb;
     int32_t *nn, *ncount, *nparent, *lparent, *posmap, *cseg0, *cseg1, *base, *mrank0, *mbase;
     uint64_t* flags;
@@ -1093,7 +1157,6 @@ Work carve(void* work, int64_t n, int64_t tiles, int32_t nobj)
     w.v1 = (uint32_t*)take(4 * n);
     w.counts = (uint32_t*)take(4 * 256 * tiles);
     w.bounds = (uint32_t*)take(4 * 6 * (size_t)nobj);
-    w.flags32 = (uint32_t*)take(4 * n);
     w.ca = (Cluster*)take(sizeof(Cluster) * n);
     w.cb = (Cluster*)take(sizeof(Cluster) * n);
     w.nn = (int32_t*)take(4 * n);
@@ -1115,7 +1178,7 @@ Work carve(void* work, int64_t n, int64_t tiles, int32_t nobj)
 size_t carve_bytes(int64_t n, int64_t tiles, int32_t nobj)
 {
     const size_t head = 4 * align256(4 * n) + align256(4 * 256 * tiles) + align256(4 * 6 * (size_t)nobj) +
-                        align256(4 * n) + 2 * align256(sizeof(Cluster) * n) + 5 * align256(4 * n) +
+                        2 * align256(sizeof(Cluster) * n) + 5 * align256(4 * n) +
                         2 * align256(4 * ((size_t)nobj + 1)) + 3 * align256(4 * (size_t)nobj) + align256(8 * (n + 1)) +
                         align256(sizeof(BinNode) * n);
     return head + std::max(scan_work_bytes_u32(256 * tiles), scan_work_bytes_u64(n + 1));
@@ -1149,10 +1212,24 @@ hipError_t build(Args a, int32_t nobj, int64_t n, int64_t tiles, const float* ve
         std::swap(va, vb);
     }
     if (method == RTSDF_BVH_LBVH) {
-        hipLaunchKernelGGL(k_fill_i32, dim3(std::min<unsigned>(tb, 2048u)), dim3(256), 0, s, (int32_t*)w.flags32, n, 0);
+        // the radix tree, then its boxes from a box pyramid over the sorted leaves (the PLOC
+        // cluster arrays hold the pyramid: level 0 in ca, the upper levels in cb)
         hipLaunchKernelGGL(k_tree<kBatch>, dim3(tb), dim3(256), 0, s, a, ka, total, w.bin, w.nparent, w.lparent);
-        hipLaunchKernelGGL(k_leaves_refit<kBatch>, dim3(tb), dim3(256), 0, s, a, verts, tris, total, va, w.bin, bvh,
-                           w.nparent, w.lparent, w.flags32);
+        BoxPyramid P{};
+        P.lev[0] = (const LeafBox*)w.ca;
+        P.nlev = 1;
+        hipLaunchKernelGGL(k_lbvh_leaves<kBatch>, dim3(tb), dim3(256), 0, s, a, verts, tris, total, va, w.bin, bvh,
+                           w.lparent, (LeafBox*)w.ca);
+        LeafBox* up = (LeafBox*)w.cb;  // levels 1.. take ceil(n/64) + ceil(n/64^2) + ... <= n entries
+        for (int64_t cnt = n; cnt > kBoxFan && P.nlev < kBoxLevels; ++P.nlev) {
+            const int64_t nup = ceil_div(cnt, kBoxFan);
+            hipLaunchKernelGGL(k_box_level, dim3((unsigned)ceil_div(nup * kWave, 256)), dim3(256), 0, s,
+                               P.lev[P.nlev - 1], cnt, up, nup);
+            P.lev[P.nlev] = up;
+            up += nup;
+            cnt = nup;
+        }
+        hipLaunchKernelGGL(k_lbvh_nodes<kBatch>, dim3(tb), dim3(256), 0, s, a, total, w.bin, w.nparent, P);
     } else {
         hipLaunchKernelGGL(k_ploc_init<kBatch>, dim3(tb), dim3(256), 0, s, a, verts, tris, total, va, w.ca);
         Cluster *cin = w.ca, *cout = w.cb;
