@@ -68,16 +68,19 @@ def compare_object(R, B, S, o):
     assert torch.equal(B.view(B.fine, o).view(torch.int32), S.fine.view(torch.int32)), "object %d: fine differs" % o
 
 
-@pytest.mark.parametrize("frames,key", [(1, 0), (2, 9)])
-def test_batched_equals_single_calls(R, frames, key):
+@pytest.mark.parametrize("frames,key,rays", [(1, 0, 8), (2, 9, 8), (1, 3, 3), (2, 4, 1)])
+def test_batched_equals_single_calls(R, frames, key, rays):
+    """Also with fewer than 8 rays per voxel, where ray sampling's pool fills span more voxels
+    than they have LDS slots for (a separate kernel instance in both the batched and the
+    single-object case)."""
     import torch
     objs = mixed_batch()
-    log("case: mixed batch of %d objects, frames %d, key %d" % (len(objs), frames, key))
-    B = R.BatchSDF(objs, rays=8, frames=frames, rng_key=key)
+    log("case: mixed batch of %d objects, frames %d, key %d, rays %d" % (len(objs), frames, key, rays))
+    B = R.BatchSDF(objs, rays=rays, frames=frames, rng_key=key)
     B.run()
     torch.cuda.synchronize()
     for o, sc in enumerate(objs):
-        S = single(R, sc, o, 8, key, frames)
+        S = single(R, sc, o, rays, key, frames)
         torch.cuda.synchronize()
         compare_object(R, B, S, o)
     assert int(B.band_count.item()) > 0
