@@ -135,7 +135,7 @@ def test_static_reduced_full_parity(R, orc, case):
     np.testing.assert_allclose(G["fine"], O["fine"], rtol=RTOL, atol=0)
 
 
-@pytest.mark.parametrize("case", ["x1", "x3", "x7", "x100", "x5_large", "x9_large"])
+@pytest.mark.parametrize("case", ["x1", "x3", "x7", "x100", "x1_large", "x5_large", "x9_large"])
 def test_rays_per_voxel_pool_boundaries(R, orc, case):
     """Ray counts that split a wave's pool of 64 rays unevenly: fills with more voxels than
     LDS slots (x < 8: those voxels' rays add to the global accumulators themselves), voxels
