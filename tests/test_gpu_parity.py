@@ -135,12 +135,13 @@ def test_static_reduced_full_parity(R, orc, case):
     np.testing.assert_allclose(G["fine"], O["fine"], rtol=RTOL, atol=0)
 
 
-@pytest.mark.parametrize("case", ["x1", "x3", "x7", "x100", "x1_large", "x5_large", "x9_large"])
+@pytest.mark.parametrize("case", ["x1", "x3", "x7", "x64", "x65", "x100", "x1_large", "x5_large", "x9_large"])
 def test_rays_per_voxel_pool_boundaries(R, orc, case):
     """Ray counts that split a wave's pool of 64 rays unevenly: fills with more voxels than
     LDS slots (x < 8: those voxels' rays add to the global accumulators themselves), voxels
     continued from one fill to the next (x not dividing 64, on a mask large enough for
-    chunks longer than one fill), and a voxel spanning several fills (x > 64).  Small grids
+    chunks longer than one fill), a voxel filling a pool exactly (x = 64), and a voxel
+    spanning several fills (x = 65, x = 100).  Small grids
     are compared at every masked voxel, the larger ones at 4000 sampled voxels."""
     x = int(case[1:].split("_")[0])
     if case.endswith("_large"):
